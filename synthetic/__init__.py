@@ -1,0 +1,194 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the HIP path.
+
+This module only draws random numbers and lays them out as arrays: camera
+descriptions, MLP weights, rigid-transform parameters (R, T, s), light
+positions, training rays and pixel subsets.  It holds none of the rendering
+method's arithmetic (no ray generation, no encoding, no network evaluation, no
+compositing), so that the oracle and the GPU path stay independent.
+
+Every generator is a NumPy PCG64 stream seeded with
+``4669 + 1000 * config + stream`` so that a (config, stream) pair always gives
+the same bytes.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 4669
+
+
+def rng(config: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * config + stream))
+
+
+# --------------------------------------------------------------------------
+# camera and scene descriptions (plain parameters)
+# --------------------------------------------------------------------------
+@dataclass
+class Camera:
+    eye: tuple
+    at: tuple
+    up: tuple
+    fov_y_deg: float
+    width: int
+    height: int
+
+    @property
+    def n_rays(self) -> int:
+        return self.width * self.height
+
+
+@dataclass
+class MLPWeights:
+    """Fully connected layers, PyTorch convention: W[i] is [out, in] float32."""
+    W: list
+    b: list
+
+    @property
+    def dims(self):
+        return [self.W[0].shape[1]] + [w.shape[0] for w in self.W]
+
+
+@dataclass
+class Model:
+    """One object model.  ``kind`` names the density field family:
+
+    * ``sphere``  analytic sigma_max * sigmoid((radius - |x|) / width)
+    * ``slab``    sigma0 inside z0 <= z <= z1
+    * ``mlp``     density MLP on gamma_L(x); ``sigma_mode`` is ``softplus``
+                  (optionally masked to |x| <= bound) or ``sdf`` (SDF-biased)
+    * ``nerf``    density trunk as ``mlp`` plus an RGB branch
+    * ``nedf``    ray -> (mu_hat, hit logit) network on gamma_L(Pluecker)
+    """
+    kind: str
+    bound: float = 1.0
+    params: dict = field(default_factory=dict)
+    trunk: MLPWeights | None = None
+    rgb: MLPWeights | None = None
+
+
+@dataclass
+class Instance:
+    model: int
+    R: np.ndarray      # 3x3 float64 rotation
+    T: np.ndarray      # 3 float64 translation
+    s: float           # uniform scale
+
+
+def normal_mlp(g: np.random.Generator, dims, head_std_fan_in: bool = True,
+               hidden_gain: float = 1.0) -> MLPWeights:
+    """Weights N(0, gain/fan_in) as float32, biases zero."""
+    W, b = [], []
+    n = len(dims) - 1
+    for i in range(n):
+        fan_in, fan_out = dims[i], dims[i + 1]
+        gain = hidden_gain if i < n - 1 else 1.0
+        w = g.standard_normal((fan_out, fan_in)) * math.sqrt(gain / fan_in)
+        W.append(w.astype(np.float32))
+        b.append(np.zeros(fan_out, dtype=np.float32))
+    return MLPWeights(W, b)
+
+
+def shoemake_rotation(g: np.random.Generator) -> np.ndarray:
+    """Uniform rotation from a uniform unit quaternion (Shoemake, Graphics
+    Gems III, 1992), returned as a float64 3x3 matrix."""
+    u1, u2, u3 = g.random(3)
+    a, b = math.sqrt(1.0 - u1), math.sqrt(u1)
+    qx, qy = a * math.sin(2 * math.pi * u2), a * math.cos(2 * math.pi * u2)
+    qz, qw = b * math.sin(2 * math.pi * u3), b * math.cos(2 * math.pi * u3)
+    return np.array([
+        [1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw), 2 * (qx * qz + qy * qw)],
+        [2 * (qx * qy + qz * qw), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw)],
+        [2 * (qx * qz - qy * qw), 2 * (qy * qz + qx * qw), 1 - 2 * (qx * qx + qy * qy)],
+    ], dtype=np.float64)
+
+
+def pixel_subset(config: int, n_pixels: int, n: int, stream: int = 7) -> np.ndarray:
+    """Sorted seeded subset of pixel indices (without replacement)."""
+    g = rng(config, stream)
+    n = min(n, n_pixels)
+    return np.sort(g.choice(n_pixels, size=n, replace=False)).astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+SPHERE_A = dict(sigma_max=50.0, radius=0.5, width=0.01)
+
+
+def config1_camera(width: int = 32, height: int = 32) -> Camera:
+    return Camera(eye=(0.0, 0.0, 4.0), at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+                  fov_y_deg=40.0, width=width, height=height)
+
+
+def config1_models():
+    """Density A (analytic sphere) and density B (gamma_6 -> 3x64 ReLU ->
+    softplus, N(0, 1/fan_in) float32 weights, seed stream 1)."""
+    a = Model(kind="sphere", bound=1.0, params=dict(SPHERE_A))
+    g = rng(1, 1)
+    trunk = normal_mlp(g, [39, 64, 64, 64, 1])
+    b = Model(kind="mlp", bound=1.0, trunk=trunk,
+              params=dict(enc_L=6, sigma_mode="softplus", masked=False))
+    return a, b
+
+
+def nerf_model(config: int, stream: int, sigma_mode: str = "softplus", sdf_shape: int = 0,
+               width: int = 256, depth: int = 8, enc_L: int = 10, dir_L: int = 4,
+               rgb_width: int = 128) -> Model:
+    """A NeRF-shaped object: gamma_L(x) -> depth x width ReLU -> sigma head,
+    plus concat(h, gamma_dirL(d)) -> rgb_width ReLU -> 3 (sigmoid).
+    Hidden weights N(0, 1/fan_in), biases zero."""
+    g = rng(config, stream)
+    d_in = 3 * (1 + 2 * enc_L)
+    trunk = normal_mlp(g, [d_in] + [width] * depth + [1])
+    d_dir = 3 * (1 + 2 * dir_L)
+    rgb = normal_mlp(g, [width + d_dir, rgb_width, 3])
+    params = dict(enc_L=enc_L, dir_L=dir_L, sigma_mode=sigma_mode, masked=True)
+    if sigma_mode == "sdf":
+        params.update(sdf_shape=sdf_shape, sigma_max=50.0, width=0.01)
+    return Model(kind="nerf", bound=1.0, trunk=trunk, rgb=rgb, params=params)
+
+
+def config2_scene(n_objects: int = 16, width: int = 800, height: int = 800):
+    """16 as-stated NeRFs (masked to |x| <= 1), random rigid placement
+    (Shoemake rotation, T ~ U[-3,3]^3, s ~ U[0.5,1.5], stream 900), camera at
+    (0,0,13) looking at the origin, one point light at (6,10,8)."""
+    models = [nerf_model(2, k) for k in range(n_objects)]
+    g = rng(2, 900)
+    insts = []
+    for k in range(n_objects):
+        R = shoemake_rotation(g)
+        T = g.uniform(-3.0, 3.0, size=3)
+        s = float(g.uniform(0.5, 1.5))
+        insts.append(Instance(model=k, R=R, T=T, s=s))
+    cam = Camera(eye=(0.0, 0.0, 13.0), at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+                 fov_y_deg=40.0, width=width, height=height)
+    light = np.array([6.0, 10.0, 8.0])
+    return models, insts, cam, [light]
+
+
+def scene_extent(insts, bounds) -> float:
+    """Diameter of the smallest sphere centred at the centroid of the instance
+    bounding-sphere centres that contains every instance bounding sphere."""
+    c = np.mean([i.T for i in insts], axis=0)
+    r = max(np.linalg.norm(i.T - c) + i.s * bounds[i.model] for i in insts)
+    return 2.0 * float(r)
+
+
+def training_rays(config: int, stream: int, n: int, radius: float = 4.0,
+                  aim_radius: float = 1.2):
+    """Local-space training rays: origin uniform on the sphere of the given
+    radius, aimed at a point uniform in the ball of radius ``aim_radius``.
+    Returns float32 (o [n,3], d [n,3]) with unit d."""
+    g = rng(config, stream)
+    v = g.standard_normal((n, 3))
+    o = radius * v / np.linalg.norm(v, axis=1, keepdims=True)
+    w = g.standard_normal((n, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    p = w * aim_radius * g.random((n, 1)) ** (1.0 / 3.0)
+    d = p - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return o.astype(np.float32), d.astype(np.float32)
