@@ -1,0 +1,159 @@
+"""Throughput benchmark of the depth+ID hot path on one MI355X.
+
+Workload (the plain-marcher composition scene): 16 NeRF-shaped objects
+(gamma_10(x) -> 8 x 256 ReLU -> sigma, masked to the unit ball) under random
+rigid transforms, 800 x 800 pinhole rays, 192 midpoint samples per
+(ray, instance) pair, per-pixel min-depth into depth/ID buffers.  A step is
+one frame: float64 transform composition, culling/binning, the matrix-core
+marcher and the buffer finalisation, all in the HIP library.  Inputs are
+seeded synthetic weights and placements (no trained models or datasets).
+
+Prints one JSON line.  ``roofline`` is computed for the dominant kernel
+(march.mlp) from library-side HIP events over the timed region;
+``cpu_baseline`` times the FP64 oracle on a bounded pixel sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s depth+ID (NeDF vs plain marcher, ≤1% depth err); MFMA util"
+PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+# trunk multiply-adds per sample: 63x256 + 7 x 256x256 + 256 (sigma head)
+MAC_PER_SAMPLE = 63 * 256 + 7 * 256 * 256 + 256
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
+    p.add_argument("--samples", type=int, default=192)
+    p.add_argument("--size", type=int, default=800)
+    p.add_argument("--f32-steps", type=int, default=2)
+    p.add_argument("--cpu-pixels", type=int, default=6000)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(n_pixels: int, n_samples: int, size: int):
+    """FP64 oracle marcher on a seeded pixel subset of the same frame."""
+    import synthetic as syn
+    from oracle import camera_rays, march_compose
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    models, insts, cam, _ = syn.config2_scene(width=size, height=size)
+    # half of the sample on pixels covered by some bounding sphere, half uniform
+    pix = syn.pixel_subset(2, cam.n_rays, n_pixels)
+    o, d = camera_rays(cam, pix)
+    t0 = time.perf_counter()
+    march_compose(models, insts, o, d, n_samples)
+    dt = time.perf_counter() - t0
+    return {"value": n_pixels / dt, "unit": "rays/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n_pixels} seeded pixels of the same {size}x{size} frame, {n_samples} samples/pair, "
+                      f"FP64 NumPy, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
+              f"design note, not a build target", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synthetic as syn
+    from paper_2308_04669_amd import api
+
+    torch.cuda.set_device(0)
+    models, insts, cam, _ = syn.config2_scene(width=args.size, height=args.size)
+    rays = api.camera_rays(cam)
+    n = cam.n_rays
+
+    def build_scene(dtype):
+        objs = [api.object_from_model(m, dtype) for m in models]
+        return api.make_scene(objs, insts)
+
+    def run(dtype, steps, warmup, profile):
+        sc = build_scene(dtype)
+        ws = api.Workspace()
+        out = (torch.empty(n, dtype=torch.float32, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"),
+               None)
+
+        def step():
+            sc.inst_w2l = api.compose_transforms(sc.inst_G)
+            api.march_depth(sc, rays, n_samples=args.samples, dtype=dtype, opacity=False, ws=ws, out=out)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            api.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        stages = api.profile_read() if profile else {}
+        api.profile_enable(False)
+        pairs, items = api.ws_counters(ws)
+        assert api.check_status(ws) == 0
+        return ms, stages, pairs
+
+    ms, stages, pairs = run(args.dtype, args.steps, args.warmup, True)
+    mlp_ms, mlp_cnt = stages.get("march.mlp", (0.0, 1))
+    avg_mlp = mlp_ms / max(mlp_cnt, 1)
+    flops = 2.0 * MAC_PER_SAMPLE * args.samples * pairs
+    achieved = flops / (avg_mlp * 1e-3) / 1e12 if avg_mlp > 0 else 0.0
+    peak = PEAK_TFLOPS[args.dtype]
+    extra = {}
+    if args.dtype != "f32" and args.f32_steps > 0:
+        ms32, st32, _ = run("f32", args.f32_steps, 1, True)
+        m32, c32 = st32.get("march.mlp", (0.0, 1))
+        a32 = flops / (m32 / max(c32, 1) * 1e-3) / 1e12 if m32 > 0 else 0.0
+        extra["f32_marcher"] = {"rays_per_s": n / (ms32 * 1e-3), "ms_per_step": ms32,
+                                "mlp_tflops": a32, "mlp_frac_of_f32_peak": a32 / PEAK_TFLOPS["f32"]}
+    line = {
+        "metric": METRIC,
+        "value": n / (ms * 1e-3),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded random-init NeRF-shaped MLPs and placements)",
+        "config": {"workload": f"plain-marcher composition: 16 NeRF objects (gamma10 xyz, 8x256 ReLU, sigma head), "
+                               f"{args.size}x{args.size} rays, {args.samples} samples per pair, depth+ID",
+                   "pairs_per_frame": pairs, "samples_per_pair": args.samples, "path": "plain marcher"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "march.mlp", "avg_launch_ms": avg_mlp,
+                     "flop_per_launch": flops},
+        "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+    }
+    line.update(extra)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_pixels, args.samples, args.size)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * nedf.h -- C ABI of the MI355X (gfx950) NeDF composition library.
+ *
+ * The library renders depth/ID buffers of many rigidly transformed neural
+ * objects as in Gao et al., "A General Implicit Framework for Fast NeRF
+ * Composition and Rendering" (AAAI 2024, arXiv 2308.04669):
+ *   - nedf_march_depth     plain volume-rendered depth (Eq. 5) + Alg. 1 step 1
+ *   - nedf_infer_depth_id  NeDF depth (Eq. 1, 2, 7) + Alg. 1 step 1, marcher
+ *                          fallback for uncertain rays, secant refinement
+ *   - nedf_shade_deferred  deferred shading (Eq. 8, Alg. 1 step 2)
+ *   - nedf_shadow          shadow step (Alg. 2) and final composite
+ *   - nedf_train_step      one forward/backward/Adam step of an intersection
+ *                          network (Eq. 6 in regression form)
+ *
+ * Conventions for every entry point
+ *   Ownership   Array arguments are DEVICE pointers owned by the caller unless
+ *               the comment says "host".  The library never frees caller
+ *               memory and never allocates device memory inside a call.
+ *   Workspace   Calls that need scratch take (void* ws, size_t ws_bytes), a
+ *               device buffer sized by nedf_workspace_size() for the same
+ *               arguments.  Its first 256 bytes hold a device status word
+ *               (read by nedf_check_status).
+ *   Streams     Work is enqueued on `stream` (a hipStream_t; NULL = the
+ *               default stream) and the call returns without synchronising.
+ *               Host-side argument validation happens before anything is
+ *               enqueued; a call that returns an error enqueued nothing.
+ *   Errors      Every call returns an nedf_status; nedf_last_error() gives a
+ *               thread-local message for the last failing call.
+ *   Layout      Rays, points and directions are float32 [n][3] row-major;
+ *               image buffers are row-major with pixel p = row * width + col,
+ *               row 0 at the top.
+ *   Alignment   Device pointers must be 16-byte aligned (NEDF_ERR_ALIGN).
+ *   Concurrency Calls are reentrant; calls that share a workspace buffer
+ *               must be ordered on one stream.
+ */
+#ifndef NEDF_H
+#define NEDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* nedf_stream_t; /* hipStream_t */
+
+typedef enum nedf_status {
+  NEDF_OK = 0,
+  NEDF_ERR_NULL = 1,        /* required pointer is NULL */
+  NEDF_ERR_SHAPE = 2,       /* bad size, count or network shape */
+  NEDF_ERR_DTYPE = 3,       /* unknown or unsupported precision */
+  NEDF_ERR_ALIGN = 4,       /* device pointer not 16-byte aligned */
+  NEDF_ERR_WORKSPACE = 5,   /* workspace smaller than nedf_workspace_size() */
+  NEDF_ERR_CAPACITY = 6,    /* a device-side list overflowed (nedf_check_status) */
+  NEDF_ERR_HIP = 7,         /* HIP runtime error */
+  NEDF_ERR_UNSUPPORTED = 8  /* option combination not implemented */
+} nedf_status;
+
+typedef enum nedf_dtype {
+  NEDF_F32 = 0,   /* float32 matrix cores (v_mfma_f32_32x32x2_f32) */
+  NEDF_BF16 = 1,  /* bfloat16 inputs, float32 accumulate */
+  NEDF_FP8 = 2    /* OCP E4M3FN inputs with per-layer scales, float32 accumulate */
+} nedf_dtype;
+
+/* Density field families of an object (local/canonical space). */
+typedef enum nedf_field {
+  NEDF_FIELD_SPHERE = 0,  /* sigma_max * sigmoid((radius - |x|) / width); param = {sigma_max, radius, width} */
+  NEDF_FIELD_SLAB = 1,    /* sigma0 where z0 <= z <= z1; param = {sigma0, z0, z1} */
+  NEDF_FIELD_MLP = 2      /* density network on gamma_L(x), see nedf_sigma_mode */
+} nedf_field;
+
+typedef enum nedf_sigma_mode {
+  NEDF_SIGMA_SOFTPLUS = 0,         /* sigma = softplus(u) */
+  NEDF_SIGMA_SOFTPLUS_MASKED = 1,  /* softplus(u), zero outside |x| <= bound */
+  NEDF_SIGMA_SDF = 2               /* sigma_max * sigmoid(u - sdf_shape(x) / width);
+                                      param = {sigma_max, width, shape} */
+} nedf_sigma_mode;
+
+typedef enum nedf_input_kind {
+  NEDF_IN_XYZ = 0,       /* gamma_L(x), 3 (1 + 2L) features (density / NeRF trunk) */
+  NEDF_IN_PLUECKER = 1   /* gamma_L(d, o x d), 6 (1 + 2L) features (intersection network) */
+} nedf_input_kind;
+
+/*
+ * Shape of a ReLU multilayer perceptron:
+ *   in (encoded) -> n_hidden x [Linear(width) + ReLU] -> Linear(n_out)
+ * and, when rgb_width > 0, a colour branch
+ *   concat(h_last, gamma_dirL(d)) -> Linear(rgb_width) + ReLU -> Linear(3) -> sigmoid.
+ * Supported: width in {64, 256}; n_hidden 1..16; n_out 1..2; rgb_width in {0, 128}.
+ */
+typedef struct nedf_mlp_shape {
+  int32_t in_kind;    /* nedf_input_kind */
+  int32_t enc_L;      /* encoding levels of the input */
+  int32_t width;
+  int32_t n_hidden;
+  int32_t n_out;
+  int32_t rgb_width;  /* 0 = no colour branch */
+  int32_t dir_L;      /* direction encoding levels of the colour branch */
+} nedf_mlp_shape;
+
+/* A packed network: a device blob written by nedf_pack_mlp (after upload). */
+typedef struct nedf_mlp {
+  nedf_mlp_shape shape;
+  int32_t dtype;       /* nedf_dtype the blob was packed for */
+  const void* blob;    /* device */
+} nedf_mlp;
+
+/* One object model: its density field in local space (marcher, fallback,
+ * refinement, shading density), optional NeRF colour branch (inside the
+ * density network), and optional intersection network F_Phi. */
+typedef struct nedf_object {
+  int32_t field;       /* nedf_field */
+  int32_t sigma_mode;  /* nedf_sigma_mode (NEDF_FIELD_MLP) */
+  float bound;         /* local bounding-sphere radius l (> 0) */
+  float param[6];      /* field parameters, see nedf_field / nedf_sigma_mode */
+  nedf_mlp density;    /* NEDF_FIELD_MLP: density network (blob may carry the colour branch) */
+  nedf_mlp nedf;       /* intersection network (blob NULL when absent); in_kind PLUECKER, n_out 2 */
+} nedf_object;
+
+/* Instances of objects.  Rigid map G(q) = s R q + T (Eq. 7). */
+typedef struct nedf_scene {
+  int32_t n_objects;
+  const nedf_object* objects;  /* host array of n_objects (at most NEDF_MAX_OBJECTS) */
+  int32_t n_inst;
+  const int32_t* inst_object;  /* device [n_inst]: object index of each instance */
+  const float* inst_w2l;       /* device [n_inst][16]: world->local records from nedf_compose_transforms */
+} nedf_scene;
+
+#define NEDF_MAX_OBJECTS 32
+#define NEDF_W2L_FLOATS 16
+
+/* Rays: generated from a pinhole camera in-kernel, or explicit arrays. */
+typedef struct nedf_camera {
+  double eye[3], at[3], up[3];
+  double fov_y_deg;        /* vertical field of view */
+  int32_t width, height;   /* pixel centres; unit directions */
+} nedf_camera;
+
+typedef struct nedf_rays {
+  int32_t kind;            /* 0 = camera, 1 = explicit arrays */
+  nedf_camera camera;      /* kind 0: n = width * height */
+  const float* origins;    /* kind 1: device [n][3] */
+  const float* dirs;       /* kind 1: device [n][3], unit length */
+  int64_t n;               /* kind 1: number of rays */
+} nedf_rays;
+
+typedef struct nedf_march_opts {
+  int32_t n_samples;       /* midpoint samples per (ray, instance) pair, 1..4096 */
+  int32_t clip_to_bound;   /* 1: march the chord of the local bounding sphere;
+                              0: march the fixed world interval [t_near, t_far] */
+  float t_near, t_far;
+  float hit_threshold;     /* hit iff opacity >= hit_threshold (default 0.5) */
+  int32_t dtype;           /* precision of MLP fields */
+} nedf_march_opts;
+
+/* ---------------------------------------------------------------- helpers */
+const char* nedf_version(void);
+const char* nedf_last_error(void);
+const char* nedf_status_string(int32_t status);
+
+/*
+ * Bytes of the packed blob of a network (nedf_pack_mlp).  0 when the shape
+ * or dtype is unsupported (nedf_last_error says why).
+ */
+size_t nedf_mlp_packed_bytes(const nedf_mlp_shape* shape, int32_t dtype);
+
+/*
+ * Pack float32 weights into the blob layout the GPU kernels read (matrix-core
+ * fragment order, per-lane bias and head tables).  HOST only: W[i]/b[i] are
+ * HOST pointers to layer i in PyTorch layout [out][in] / [out], layers in
+ * order (hidden layers, head, then colour-branch hidden and colour head).
+ * `out` is a HOST buffer of nedf_mlp_packed_bytes() bytes; the caller uploads
+ * it to the device.  For NEDF_FP8, `fp8_scales` (host, 2 per hidden layer:
+ * weight scale, activation scale) is required; otherwise it is ignored.
+ */
+int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, const float* const* W,
+                      const float* const* b, const float* fp8_scales, void* out, size_t out_bytes);
+
+/*
+ * World->local records of the instances (Sec. "Manipulating Objects", Eq. 7),
+ * composed in float64 on the GPU and rounded to float32:
+ *   in  inst_G   device float64 [n][13] = R (row-major 3x3), T (3), s
+ *   out inst_w2l device float32 [n][16] = R^T (9), -R^T T / s (3), s, 1/s, 0, 0
+ * so that o_l = R^T o / s + c and d_l = R^T d.
+ */
+int32_t nedf_compose_transforms(const double* inst_G, int32_t n, float* inst_w2l,
+                                nedf_stream_t stream);
+
+typedef enum nedf_op {
+  NEDF_OP_MARCH = 0,
+  NEDF_OP_INFER = 1,
+  NEDF_OP_SHADE = 2,
+  NEDF_OP_SHADOW = 3
+} nedf_op;
+
+/* Workspace bytes needed by an entry point for these arguments. */
+/* pair_capacity <= 0 sizes the (ray, instance) pair list for the worst case
+ * n_rays * n_inst; a smaller explicit capacity is reported as NEDF_ERR_CAPACITY
+ * by nedf_check_status when exceeded (results are then incomplete). */
+size_t nedf_workspace_size(int32_t op, const nedf_scene* scene, const nedf_rays* rays,
+                           int64_t pair_capacity);
+
+/*
+ * Synchronise `stream` and return the device status word of `ws`
+ * (NEDF_OK, or NEDF_ERR_CAPACITY when a pair list overflowed).
+ */
+int32_t nedf_check_status(const void* ws, nedf_stream_t stream);
+
+/*
+ * Stage timing.  nedf_profile_enable(1) clears the record list and makes every
+ * later call bracket its kernel launches with HIP events on its stream, under
+ * stage names ("march.cull", "march.mlp", ...); nedf_profile_enable(0) stops
+ * recording.  nedf_profile_read synchronises on the recorded events and
+ * returns, per stage in first-seen order, the summed elapsed milliseconds and
+ * the number of brackets: names is a host buffer of max_stages x 64 chars.
+ */
+int32_t nedf_profile_enable(int32_t on);
+int32_t nedf_profile_read(int32_t max_stages, char* names, double* total_ms, int32_t* counts,
+                          int32_t* n_stages);
+
+/*
+ * Counters of the last call that used `ws` (synchronises `stream`):
+ * out[0] = (ray, instance) pairs after culling, out[1] = network work items.
+ */
+int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out2);
+
+/* ------------------------------------------------------------- hot path */
+
+/*
+ * Plain volume-rendering marcher (Eq. 5) composed over all instances
+ * (Alg. 1 step 1).  For every (ray, instance) pair whose ray meets the
+ * instance's bounding sphere (or every pair, clip_to_bound = 0), the local
+ * ray is marched with N midpoint samples, giving opacity A = sum w_i and
+ * depth D = s * sum w_i t_i / A.  The pair hits when A >= hit_threshold.
+ *   depth    [n] float32: minimum hit depth over instances, +inf if none
+ *   id       [n] int32: instance of that minimum (lowest index on ties), -1 if none
+ *   opacity  [n] float32 or NULL: max over instances of A
+ */
+int32_t nedf_march_depth(const nedf_scene* scene, const nedf_rays* rays,
+                         const nedf_march_opts* opts, float* depth, int32_t* id,
+                         float* opacity, void* ws, size_t ws_bytes, nedf_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEDF_H */

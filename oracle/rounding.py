@@ -28,7 +28,7 @@ def round_bf16(x):
     x = np.asarray(x, np.float64)
     r = _round_sig(x, 8, -126)
     big = (2.0 - 2.0 ** -8) * 2.0 ** 127
-    r = np.where(np.abs(x) >= big, np.sign(x) * np.inf, r)
+    r = np.where(np.abs(x) >= big, np.copysign(np.inf, x), r)
     return np.where(np.isnan(x), np.nan, r)
 
 

@@ -1,0 +1,221 @@
+// Host-side packing of float32 network weights into the blob layout read by
+// the matrix-core kernels (see blob_layout.h for the register layout).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "blob_layout.h"
+#include "nedf.h"
+#include "runtime.h"
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+struct Plan {
+  nedf_blob_header h;
+  bool ok = false;
+  std::string why;
+};
+
+int in_components(int in_kind) { return in_kind == NEDF_IN_PLUECKER ? 6 : 3; }
+
+Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
+  Plan p;
+  std::memset(&p.h, 0, sizeof(p.h));
+  if (!s) { p.why = "shape is NULL"; return p; }
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) { p.why = "dtype not supported by the packer"; return p; }
+  if (s->in_kind != NEDF_IN_XYZ && s->in_kind != NEDF_IN_PLUECKER) { p.why = "bad in_kind"; return p; }
+  if (s->width != 64 && s->width != 256) { p.why = "width must be 64 or 256"; return p; }
+  if (s->n_hidden < 2 || s->n_hidden > NEDF_MAX_LAYERS) { p.why = "n_hidden must be 2..16"; return p; }
+  if (s->n_out < 1 || s->n_out > 2) { p.why = "n_out must be 1 or 2"; return p; }
+  if (s->enc_L < 0 || s->enc_L > 12) { p.why = "enc_L must be 0..12"; return p; }
+  if (s->rgb_width != 0 && s->rgb_width != 128) { p.why = "rgb_width must be 0 or 128"; return p; }
+  if (s->rgb_width && (s->dir_L < 0 || s->dir_L > 8)) { p.why = "dir_L must be 0..8"; return p; }
+  if (s->rgb_width && s->in_kind != NEDF_IN_XYZ) { p.why = "colour branch needs an xyz input"; return p; }
+  nedf_blob_header& h = p.h;
+  const bool bf = dtype == NEDF_BF16;
+  const int n = in_components(s->in_kind);
+  h.magic = NEDF_BLOB_MAGIC;
+  h.version = NEDF_BLOB_VERSION;
+  h.dtype = uint32_t(dtype);
+  h.in_kind = uint32_t(s->in_kind);
+  h.enc_L = uint32_t(s->enc_L);
+  h.width = uint32_t(s->width);
+  h.n_hidden = uint32_t(s->n_hidden);
+  h.n_out = uint32_t(s->n_out);
+  h.rgb_width = uint32_t(s->rgb_width);
+  h.dir_L = uint32_t(s->dir_L);
+  h.n_in = uint32_t(n * (1 + 2 * s->enc_L));
+  h.n_dir = s->rgb_width ? uint32_t(3 * (1 + 2 * s->dir_L)) : 0u;
+  const int slots = nedf_enc_slots(n, s->enc_L);
+  auto round4 = [](int x) { return (x + 3) / 4 * 4; };
+  h.ks_in = bf ? uint32_t((slots + 7) / 8) : uint32_t(round4(slots));
+  h.ks_hidden = bf ? uint32_t(s->width / 16) : uint32_t(s->width / 2);
+  if (s->rgb_width) {
+    const int dslots = nedf_enc_slots(3, s->dir_L);
+    h.ks_rgb = h.ks_hidden + (bf ? uint32_t((dslots + 7) / 8) : uint32_t(round4(dslots)));
+  }
+  h.frag_bytes = bf ? 1024u : 256u;
+  const size_t fbn = size_t(s->width / 32);
+  size_t off = align256(sizeof(nedf_blob_header));
+  for (int i = 0; i < s->n_hidden; ++i) {
+    const size_t ks = i == 0 ? h.ks_in : h.ks_hidden;
+    const size_t heads = i == s->n_hidden - 1 ? size_t(s->n_out) : 0;
+    h.chunk_bytes[i] = uint32_t(ks * h.frag_bytes + 128 * (1 + heads));
+    h.off_layer[i] = off;
+    off = align256(off + fbn * h.chunk_bytes[i]);
+  }
+  h.off_head_b = off;
+  off = align256(off + 16);
+  if (s->rgb_width) {
+    const size_t rfb = size_t(s->rgb_width / 32);
+    h.rgb_chunk_bytes = uint32_t(h.ks_rgb * h.frag_bytes + 128 * (1 + 3));
+    h.off_rgb = off;
+    off = align256(off + rfb * h.rgb_chunk_bytes);
+    h.off_rgbh_b = off;
+    off = align256(off + 16);
+  }
+  h.off_scales = off;
+  off = align256(off + NEDF_MAX_LAYERS * 2 * 4);
+  h.total_bytes = off;
+  p.ok = true;
+  return p;
+}
+
+// Actual input feature (or -1) of logical K index k.
+//   part: 0 = encoded network input, 1 = previous hidden layer,
+//         2 = colour layer (hidden features, then the direction encoding)
+int logical_to_feature(const nedf_blob_header& h, int part, int k) {
+  const bool bf = h.dtype == NEDF_BF16;
+  int ks, hh, j;
+  if (bf) { ks = k / 16; hh = (k % 16) / 8; j = k % 8; }
+  else { ks = k / 2; hh = k % 2; j = 0; }
+  const int n = h.in_kind == NEDF_IN_PLUECKER ? 6 : 3;
+  if (part == 0) {
+    const int a = bf ? 8 * ks + j : ks;
+    if (a >= nedf_enc_slots(n, int(h.enc_L))) return -1;
+    return nedf_enc_feature(n, int(h.enc_L), a, hh);
+  }
+  if (part == 2 && ks >= int(h.ks_hidden)) {
+    const int kd = ks - int(h.ks_hidden);
+    const int a = bf ? 8 * kd + j : kd;
+    if (a >= nedf_enc_slots(3, int(h.dir_L))) return -1;
+    const int f = nedf_enc_feature(3, int(h.dir_L), a, hh);
+    return f < 0 ? -1 : int(h.width) + f;
+  }
+  const int fb = bf ? ks / 2 : ks / 16;
+  const int r = bf ? (ks % 2) * 8 + j : ks % 16;
+  return nedf_acc_feature(fb, hh, r);
+}
+
+// Write the fragments of one Linear layer W [rows][cols] (row-major).
+void pack_fragments(const nedf_blob_header& h, int part, const float* W, int rows, int cols,
+                    int ks_count, size_t chunk_bytes, uint8_t* dst) {
+  const bool bf = h.dtype == NEDF_BF16;
+  const int fbn = rows / 32;
+  for (int fb = 0; fb < fbn; ++fb)
+    for (int ks = 0; ks < ks_count; ++ks) {
+      uint8_t* frag = dst + size_t(fb) * chunk_bytes + size_t(ks) * h.frag_bytes;
+      for (int l = 0; l < 64; ++l) {
+        const int row = 32 * fb + (l % 32);
+        if (bf) {
+          uint16_t* out = reinterpret_cast<uint16_t*>(frag) + l * 8;
+          for (int jj = 0; jj < 8; ++jj) {
+            const int k = 16 * ks + 8 * (l / 32) + jj;
+            const int f = logical_to_feature(h, part, k);
+            out[jj] = (f >= 0 && f < cols) ? bf16_rne(W[size_t(row) * cols + f]) : uint16_t(0);
+          }
+        } else {
+          // F32: four consecutive K-steps share one 16-byte lane word
+          float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks / 4) * 1024 +
+                                                size_t(l) * 16 + size_t(ks % 4) * 4);
+          const int k = 2 * ks + (l / 32);
+          const int f = logical_to_feature(h, part, k);
+          *out = (f >= 0 && f < cols) ? W[size_t(row) * cols + f] : 0.0f;
+        }
+      }
+    }
+}
+
+// Bias of every output block, placed after the block's fragments.
+void pack_bias(const float* b, int rows, int ks_count, int frag_bytes, size_t chunk_bytes, uint8_t* dst) {
+  for (int fb = 0; fb < rows / 32; ++fb) {
+    float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes);
+    for (int hh = 0; hh < 2; ++hh)
+      for (int r = 0; r < 16; ++r) out[hh * 16 + r] = b[nedf_acc_feature(fb, hh, r)];
+  }
+}
+
+// Narrow head W [n_out][in_width]: row o's weights of input block fb follow
+// that block's bias, [h][16] in accumulator order.
+void pack_head(const float* W, int n_out, int in_width, int ks_count, int frag_bytes, size_t chunk_bytes,
+               uint8_t* dst) {
+  for (int fb = 0; fb < in_width / 32; ++fb)
+    for (int o = 0; o < n_out; ++o) {
+      float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes +
+                                            128 * (1 + o));
+      for (int hh = 0; hh < 2; ++hh)
+        for (int r = 0; r < 16; ++r) out[hh * 16 + r] = W[size_t(o) * in_width + nedf_acc_feature(fb, hh, r)];
+    }
+}
+
+}  // namespace
+
+extern "C" size_t nedf_mlp_packed_bytes(const nedf_mlp_shape* shape, int32_t dtype) {
+  Plan p = plan_blob(shape, dtype);
+  if (!p.ok) {
+    nedf::set_error(p.why);
+    return 0;
+  }
+  return size_t(p.h.total_bytes);
+}
+
+extern "C" int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, const float* const* W,
+                                 const float* const* b, const float* fp8_scales, void* out,
+                                 size_t out_bytes) {
+  (void)fp8_scales;
+  if (!shape || !W || !b || !out) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: NULL argument");
+  if (dtype == NEDF_FP8) return nedf::fail(NEDF_ERR_UNSUPPORTED, "nedf_pack_mlp: FP8 packing not available");
+  Plan p = plan_blob(shape, dtype);
+  if (!p.ok) return nedf::fail(dtype == NEDF_F32 || dtype == NEDF_BF16 ? NEDF_ERR_SHAPE : NEDF_ERR_DTYPE,
+                               "nedf_pack_mlp: " + p.why);
+  const nedf_blob_header& h = p.h;
+  if (out_bytes < h.total_bytes) return nedf::fail(NEDF_ERR_WORKSPACE, "nedf_pack_mlp: output buffer too small");
+  const int n_layers = shape->n_hidden + 1 + (shape->rgb_width ? 2 : 0);
+  for (int i = 0; i < n_layers; ++i)
+    if (!W[i] || !b[i]) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: NULL layer pointer");
+  uint8_t* base = static_cast<uint8_t*>(out);
+  std::memset(base, 0, h.total_bytes);
+  std::memcpy(base, &h, sizeof(h));
+  const int Wd = shape->width;
+  const int fragb = int(h.frag_bytes);
+  for (int i = 0; i < shape->n_hidden; ++i) {
+    const int cols = i == 0 ? int(h.n_in) : Wd;
+    const int ks = int(i == 0 ? h.ks_in : h.ks_hidden);
+    uint8_t* dst = base + h.off_layer[i];
+    pack_fragments(h, i == 0 ? 0 : 1, W[i], Wd, cols, ks, h.chunk_bytes[i], dst);
+    pack_bias(b[i], Wd, ks, fragb, h.chunk_bytes[i], dst);
+    if (i == shape->n_hidden - 1)
+      pack_head(W[shape->n_hidden], shape->n_out, Wd, ks, fragb, h.chunk_bytes[i], dst);
+  }
+  std::memcpy(base + h.off_head_b, b[shape->n_hidden], sizeof(float) * shape->n_out);
+  if (shape->rgb_width) {
+    const int rw = shape->rgb_width;
+    uint8_t* dst = base + h.off_rgb;
+    pack_fragments(h, 2, W[shape->n_hidden + 1], rw, Wd + int(h.n_dir), int(h.ks_rgb), h.rgb_chunk_bytes, dst);
+    pack_bias(b[shape->n_hidden + 1], rw, int(h.ks_rgb), fragb, h.rgb_chunk_bytes, dst);
+    pack_head(W[shape->n_hidden + 2], 3, rw, int(h.ks_rgb), fragb, h.rgb_chunk_bytes, dst);
+    std::memcpy(base + h.off_rgbh_b, b[shape->n_hidden + 2], sizeof(float) * 3);
+  }
+  return NEDF_OK;
+}

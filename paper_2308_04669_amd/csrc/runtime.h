@@ -1,0 +1,14 @@
+// Host runtime helpers shared by the C-ABI translation units.
+#pragma once
+#include <stdint.h>
+#include <string>
+
+namespace nedf {
+void set_error(const std::string& msg);
+int32_t fail(int32_t code, const std::string& msg);
+
+// Kernel-level timing (nedf_profile_enable): when on, launches are bracketed
+// by HIP events recorded on the launch stream under a stage name.
+bool prof_on();
+void prof_mark(const char* name, void* stream, bool begin);
+}  // namespace nedf

@@ -1,0 +1,160 @@
+"""GPU parity of nedf_march_depth / nedf_compose_transforms against the FP64
+oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import camera_rays, march_compose, inverse_transform
+from tests.gpu_util import need_gpu, gpu_scene, per_instance, compare_depth_id, log
+
+pytestmark = pytest.mark.gpu
+
+IDENT = syn.Instance(0, np.eye(3), np.zeros(3), 1.0)
+
+
+def _run(scene, rays, **kw):
+    import torch
+    from paper_2308_04669_amd import api
+    d, i, o = api.march_depth(scene, rays, **kw)
+    torch.cuda.synchronize()
+    return d.cpu().numpy().astype(np.float64), i.cpu().numpy(), (None if o is None else o.cpu().numpy().astype(np.float64))
+
+
+def test_compose_transforms_matches_oracle():
+    need_gpu()
+    import torch
+    from paper_2308_04669_amd import api
+    g = syn.rng(0, 70)
+    insts = [syn.Instance(0, syn.shoemake_rotation(g), g.uniform(-3, 3, 3), float(g.uniform(0.5, 1.5)))
+             for _ in range(37)]
+    sc = api.make_scene([api.ObjectSpec("sphere", 1.0, (50, 0.5, 0.01))], insts)
+    w2l = sc.inst_w2l.cpu().numpy().astype(np.float64)
+    for k, inst in enumerate(insts):
+        M, c = inverse_transform(inst.R, inst.T, inst.s)
+        assert np.allclose(w2l[k, 0:9].reshape(3, 3), inst.R.T, rtol=0, atol=1e-7)
+        assert np.allclose(w2l[k, 9:12], c, rtol=1e-6, atol=1e-6)
+        assert abs(w2l[k, 12] - inst.s) <= 1e-7 * inst.s and abs(w2l[k, 13] - 1 / inst.s) <= 1e-7 / inst.s
+
+
+@pytest.mark.parametrize("n_samples", [128, 100])
+def test_march_config1_sphere_f32(n_samples):
+    need_gpu()
+    from paper_2308_04669_amd import api
+    a, _ = syn.config1_models()
+    cam = syn.config1_camera()
+    log(f"case: config1 sphere A f32 N={n_samples}")
+    sc = gpu_scene([a], [IDENT], "f32")
+    depth, ident, opac = _run(sc, api.camera_rays(cam), n_samples=n_samples, clip_to_bound=False,
+                              t_near=2.0, t_far=6.0)
+    o, d = camera_rays(cam)
+    As, Ds, _ = per_instance([a], [IDENT], o, d, n_samples, interval=(2.0, 6.0))
+    st = compare_depth_id(depth, ident, opac, As, Ds, 1e-4, 1e-5, 1e-5, 1e-5, "cfg1 A")
+    assert st["hits"] > 60
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_march_config1_density_b(dtype):
+    need_gpu()
+    from paper_2308_04669_amd import api
+    _, b = syn.config1_models()
+    cam = syn.config1_camera()
+    log(f"case: config1 density B {dtype}")
+    sc = gpu_scene([b], [IDENT], dtype)
+    depth, ident, opac = _run(sc, api.camera_rays(cam), n_samples=128, clip_to_bound=False, t_near=2.0,
+                              t_far=6.0, dtype=dtype)
+    o, d = camera_rays(cam)
+    gemm = "bf16" if dtype == "bf16" else None
+    As, Ds, _ = per_instance([b], [IDENT], o, d, 128, interval=(2.0, 6.0), gemm=gemm)
+    if dtype == "f32":
+        compare_depth_id(depth, ident, opac, As, Ds, 1e-4, 1e-5, 1e-5, 1e-5, "cfg1 B f32")
+    else:
+        compare_depth_id(depth, ident, opac, As, Ds, 5e-3, 1e-2, 5e-3, 1e-2, "cfg1 B bf16")
+
+
+def test_march_slab_closed_form():
+    need_gpu()
+    from paper_2308_04669_amd import api
+    import torch
+    slab = syn.Model(kind="slab", params=dict(sigma0=3.0, z0=-0.5, z1=0.5))
+    sc = gpu_scene([slab], [IDENT], "f32")
+    o = torch.tensor([[0.0, 0.0, 4.0]] * 5, device="cuda")
+    d = torch.tensor([[0.0, 0.0, -1.0]] * 5, device="cuda")
+    depth, ident, opac = _run(sc, api.array_rays(o, d), n_samples=128, clip_to_bound=False, t_near=2.0,
+                              t_far=6.0)
+    assert np.allclose(opac, 1 - math.exp(-3.0), atol=2e-6)
+    cont = 3.5 + 1 / 3.0 - math.exp(-3.0) / (1 - math.exp(-3.0))
+    assert np.all(np.abs(depth - cont) < 2 * 4.0 / 128) and np.all(ident == 0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_march_config2_scene_small(dtype):
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, insts, cam, _ = syn.config2_scene(width=40, height=36)
+    log(f"case: config2 16 NeRF objects 40x36 {dtype} N=192")
+    sc = gpu_scene(models, insts, dtype)
+    depth, ident, opac = _run(sc, api.camera_rays(cam), n_samples=192, dtype=dtype)
+    o, d = camera_rays(cam)
+    gemm = "bf16" if dtype == "bf16" else None
+    As, Ds, _ = per_instance(models, insts, o, d, 192, gemm=gemm)
+    if dtype == "f32":
+        st = compare_depth_id(depth, ident, opac, As, Ds, 1e-4, 1e-5, 1e-5, 1e-5, "cfg2 small f32")
+    else:
+        st = compare_depth_id(depth, ident, opac, As, Ds, 5e-3, 1e-2, 5e-3, 1e-2, "cfg2 small bf16")
+    assert st["hits"] > 50
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_march_config2_full_size_sampled(dtype):
+    """Full 800x800 frame, 192 samples, in the benchmark's launch
+    configuration; a seeded subset of pixels is checked one by one."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, insts, cam, _ = syn.config2_scene()
+    log(f"case: config2 full 800x800 {dtype}")
+    sc = gpu_scene(models, insts, dtype)
+    depth, ident, opac = _run(sc, api.camera_rays(cam), n_samples=192, dtype=dtype)
+    pix = syn.pixel_subset(2, cam.n_rays, 300)
+    # bias the subset towards covered pixels so that it exercises hits
+    hitpix = np.nonzero(ident >= 0)[0]
+    extra = hitpix[syn.rng(2, 8).choice(hitpix.size, size=min(200, hitpix.size), replace=False)]
+    pix = np.unique(np.concatenate([pix, extra]))
+    o, d = camera_rays(cam, pix)
+    gemm = "bf16" if dtype == "bf16" else None
+    As, Ds, _ = per_instance(models, insts, o, d, 192, gemm=gemm)
+    if dtype == "f32":
+        compare_depth_id(depth[pix], ident[pix], opac[pix], As, Ds, 1e-4, 1e-5, 1e-5, 1e-5, "cfg2 full f32")
+    else:
+        compare_depth_id(depth[pix], ident[pix], opac[pix], As, Ds, 5e-3, 1e-2, 5e-3, 1e-2, "cfg2 full bf16")
+    # every pixel outside all bounding spheres is a miss with zero opacity
+    assert np.all(opac >= 0)
+
+
+def test_march_edge_cases():
+    need_gpu()
+    import torch
+    from paper_2308_04669_amd import api, _abi as A
+    a, _ = syn.config1_models()
+    sc = gpu_scene([a], [IDENT], "f32")
+    # zero rays
+    z = torch.zeros((0, 3), device="cuda")
+    d, i, o = api.march_depth(sc, api.array_rays(z, z), n_samples=64)
+    assert d.numel() == 0
+    # rays that miss the bound, point away, or start inside it
+    o = torch.tensor([[0, 0, 4.0], [0, 0, 4.0], [0, 0, 0.2], [5, 5, 5]], device="cuda")
+    dd = torch.tensor([[0, 0, -1.0], [0, 0, 1.0], [0, 0, -1.0], [1, 0, 0]], device="cuda")
+    d, i, op = api.march_depth(sc, api.array_rays(o, dd), n_samples=64)
+    torch.cuda.synchronize()
+    d, i = d.cpu().numpy(), i.cpu().numpy()
+    assert i[0] == 0 and abs(d[0] - 3.5) < 0.05
+    assert i[1] == -1 and np.isinf(d[1]) and i[3] == -1
+    assert i[2] == 0 and d[2] < 0.4      # origin inside the object: hit right away
+    # argument errors are reported before anything is enqueued
+    with pytest.raises(A.NedfError) as e:
+        api.march_depth(sc, api.array_rays(o, dd), n_samples=0)
+    assert e.value.status == 2
+    with pytest.raises(A.NedfError) as e:
+        api.march_depth(sc, api.array_rays(o, dd), n_samples=64, dtype="fp8")
+    assert e.value.status in (3, 8)
