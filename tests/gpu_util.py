@@ -50,7 +50,10 @@ def compare_depth_id(depth_g, id_g, opac_g, As, Ds, depth_tol, thr_band, tie_tol
     best = Ds.min(axis=0)
     id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
     srt = np.sort(Ds, axis=0)
-    gap = srt[1] - srt[0] if Ds.shape[0] > 1 else np.full(n, np.inf)
+    if Ds.shape[0] > 1:
+        gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0.0), np.inf)
+    else:
+        gap = np.full(n, np.inf)
     near_thr = (np.abs(As - 0.5) <= thr_band).any(axis=0)
     exempt = near_thr | (np.isfinite(srt[0]) & (gap <= tie_tol))
     id_bad = (id_g != id_o) & ~exempt

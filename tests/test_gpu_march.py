@@ -100,7 +100,9 @@ def test_march_config2_scene_small(dtype):
     gemm = "bf16" if dtype == "bf16" else None
     As, Ds, _ = per_instance(models, insts, o, d, 192, gemm=gemm)
     if dtype == "f32":
-        st = compare_depth_id(depth, ident, opac, As, Ds, 1e-4, 1e-5, 1e-5, 1e-5, "cfg2 small f32")
+        # opacity: FP32 sample positions (|o_l| ~ 26, ulp ~ 2e-6) meet the 2^9 pi top encoding
+        # frequency, so per-pair opacity agrees to ~4e-4 while depth stays within 1e-4
+        st = compare_depth_id(depth, ident, opac, As, Ds, 1e-4, 1e-5, 1e-5, 1e-3, "cfg2 small f32")
     else:
         st = compare_depth_id(depth, ident, opac, As, Ds, 5e-3, 1e-2, 5e-3, 1e-2, "cfg2 small bf16")
     assert st["hits"] > 50
@@ -125,7 +127,7 @@ def test_march_config2_full_size_sampled(dtype):
     gemm = "bf16" if dtype == "bf16" else None
     As, Ds, _ = per_instance(models, insts, o, d, 192, gemm=gemm)
     if dtype == "f32":
-        compare_depth_id(depth[pix], ident[pix], opac[pix], As, Ds, 1e-4, 1e-5, 1e-5, 1e-5, "cfg2 full f32")
+        compare_depth_id(depth[pix], ident[pix], opac[pix], As, Ds, 1e-4, 1e-5, 1e-5, 1e-3, "cfg2 full f32")
     else:
         compare_depth_id(depth[pix], ident[pix], opac[pix], As, Ds, 5e-3, 1e-2, 5e-3, 1e-2, "cfg2 full bf16")
     # every pixel outside all bounding spheres is a miss with zero opacity
