@@ -110,7 +110,7 @@ def main():
         ms = e0.elapsed_time(e1) / steps
         stages = api.profile_read() if profile else {}
         api.profile_enable(False)
-        pairs, items = api.ws_counters(ws)
+        pairs = api.ws_counters(ws)["pairs"]
         assert api.check_status(ws) == 0
         return ms, stages, pairs
 

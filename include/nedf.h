@@ -154,6 +154,31 @@ typedef struct nedf_march_opts {
   int32_t dtype;           /* precision of MLP fields */
 } nedf_march_opts;
 
+/* Options of the NeDF path (Eq. 1, 2, 7 with marcher fallback and refinement). */
+typedef struct nedf_infer_opts {
+  int32_t dtype;            /* precision of the intersection networks and of fallback/refinement fields */
+  float p_lo, p_hi;         /* hit probability band sent to the marcher (inclusive), default 0.2 / 0.8 */
+  int32_t refine_steps;     /* secant updates on the winning pixel (0 = off), default 3 */
+  float refine_h;           /* seed offset in world units, default 0.05 */
+  nedf_march_opts march;    /* marcher used for fallback pairs (clip_to_bound must be 1) */
+} nedf_infer_opts;
+
+/* Options of deferred shading (Eq. 8, Alg. 1 step 2). */
+typedef struct nedf_shade_opts {
+  int32_t K;                /* samples per pixel in [D - h, D + h]: 1, 2, 4, 8, 16 or 32 (K = 1 is Eq. 8) */
+  float h;                  /* half width in world units, default 0.05 */
+  float clear_rgb[3];       /* colour of pixels without an ID */
+  int32_t dtype;
+} nedf_shade_opts;
+
+/* Options of the shadow step (Alg. 2). */
+typedef struct nedf_shadow_opts {
+  float eps;                /* depth bias epsilon (world units) */
+  float beta;               /* attenuation 0 < beta < 1 per shadowing light */
+  int32_t method;           /* 0 = NeDF path (nedf_infer_opts), 1 = plain marcher */
+  nedf_infer_opts infer;    /* depth method of the shadow rays */
+} nedf_shadow_opts;
+
 /* ---------------------------------------------------------------- helpers */
 const char* nedf_version(void);
 const char* nedf_last_error(void);
@@ -220,10 +245,13 @@ int32_t nedf_profile_read(int32_t max_stages, char* names, double* total_ms, int
                           int32_t* n_stages);
 
 /*
- * Counters of the last call that used `ws` (synchronises `stream`):
- * out[0] = (ray, instance) pairs after culling, out[1] = network work items.
+ * Counters of the last call that used `ws` (synchronises `stream`), host
+ * int64 out[5]: [0] (ray, instance) pairs after culling (or binned pixels of
+ * the last per-pixel stage), [1] work items of that list, [2] pairs decided
+ * by the intersection network, [3] pairs sent to the marcher, [4] pairs the
+ * network classified as misses.
  */
-int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out2);
+int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out5);
 
 /* ------------------------------------------------------------- hot path */
 
@@ -240,6 +268,92 @@ int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out2);
 int32_t nedf_march_depth(const nedf_scene* scene, const nedf_rays* rays,
                          const nedf_march_opts* opts, float* depth, int32_t* id,
                          float* opacity, void* ws, size_t ws_bytes, nedf_stream_t stream);
+
+/*
+ * NeDF depth and ID buffers (Alg. 1 step 1 with Eq. 7): for every (ray,
+ * instance) pair meeting the instance's bounding sphere, the object's
+ * intersection network maps the local line (d, o x d) to (mu_hat, z);
+ * D = s (t_perp - l clamp(mu_hat, -1, 1)), p = sigmoid(z).  p > p_hi is a hit
+ * at D (if D > 0), p < p_lo a miss; the band [p_lo, p_hi] and origins inside
+ * the bounding sphere are resolved by the plain marcher of the object's
+ * density field.  The minimum over instances gives depth/id (ties: lowest
+ * index).  With refine_steps > 0 the winner's depth is refined by secant
+ * steps on the surface function of its density field (SDF-mode networks and
+ * spheres; others are left as is).
+ * Every object must carry an intersection network (nedf.blob) or be an
+ * analytic field (marched directly).
+ *   depth [n] float32, id [n] int32 (-1 = none)
+ */
+int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                            float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream);
+
+/*
+ * Deferred shading (Eq. 8, Alg. 1 step 2): every pixel with a valid id is
+ * shaded by its object's NeRF colour branch at K samples around its depth,
+ * composited locally (K = 1 is the single evaluation of Eq. 8); pixels
+ * without an id get clear_rgb; analytic objects use param[3..5] as colour.
+ *   depth [n], id [n] inputs; rgb [n][3] float32 output
+ */
+int32_t nedf_shade_deferred(const nedf_scene* scene, const nedf_rays* rays, const float* depth,
+                            const int32_t* id, const nedf_shade_opts* opts, float* rgb, void* ws,
+                            size_t ws_bytes, nedf_stream_t stream);
+
+/*
+ * Shadow step (Alg. 2) for n_lights point lights (host float32 [n_lights][3],
+ * at most 8): for each pixel with a valid id, x = o + D d; a ray from each
+ * light towards x is resolved like step 1 over all instances (depth D_L);
+ * D_L + eps < |L - x| multiplies the pixel's factor by beta.
+ *   shadow [n] float32 output multiplier; rgb_inout [n][3] (nullable) is
+ *   multiplied by it (final composite: colour buffer x shadow buffer).
+ */
+int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, const float* depth, const int32_t* id,
+                    const float* lights, int32_t n_lights, const nedf_shadow_opts* opts, float* shadow,
+                    float* rgb_inout, void* ws, size_t ws_bytes, nedf_stream_t stream);
+
+/* ------------------------------------------------------------- training */
+
+/* Adam and loss settings of nedf_train_step (Eq. 6 regression form; the
+ * paper trains with Adam at lr 5e-4). */
+typedef struct nedf_train_opts {
+  float lr, beta1, beta2, eps;  /* Adam (Kingma & Ba 2015), bias-corrected */
+  float w_hit;                  /* weight of the hit BCE term (0.1 in Eq. 6) */
+  float bound;                  /* local bounding radius l: mu* = (t_perp - D) / l */
+} nedf_train_opts;
+
+/* Bytes of the device training state of a network (float32 master weights,
+ * Adam moments, last-step gradients, bfloat16 weight copies, step counter).
+ * The network must have n_out = 2 and width 256. */
+size_t nedf_train_state_bytes(const nedf_mlp_shape* shape);
+
+/* Device workspace bytes of nedf_train_step for a batch of B rays. */
+size_t nedf_train_workspace_size(const nedf_mlp_shape* shape, int32_t B);
+
+/* Initialise a state from float32 DEVICE weights W[i] [out][in] / b[i]
+ * (hidden layers, then the head); moments, gradients and step become zero. */
+int32_t nedf_train_init(const nedf_mlp_shape* shape, const float* const* W, const float* const* b,
+                        void* state, size_t state_bytes, nedf_stream_t stream);
+
+/*
+ * One training step on B local rays (B a multiple of 64): forward pass in
+ * bfloat16 on the matrix cores with float32 accumulation, loss
+ *   L = (1/B) sum_i [alpha_i (mu_hat_i - mu*_i)^2 + w_hit BCEwithLogits(z_i, alpha_i)]
+ * with mu* = (t_perp - depth_label) / bound and alpha = hit_label (Eq. 6,
+ * regression form, labels from the inverse of Eq. 2), back-propagation and
+ * one Adam update of the float32 master weights.
+ *   o_l, d_l     device float32 [B][3] local rays (d unit)
+ *   depth_label  device float32 [B] local depth of the first surface
+ *   hit_label    device uint8 [B]
+ *   loss_out     device float32 [3]: total, masked MSE, BCE (before the update)
+ */
+int32_t nedf_train_step(const nedf_mlp_shape* shape, void* state, const float* o_l, const float* d_l,
+                        const float* depth_label, const uint8_t* hit_label, int32_t B,
+                        const nedf_train_opts* opts, float* loss_out, void* ws, size_t ws_bytes,
+                        nedf_stream_t stream);
+
+/* Copy the float32 master weights (which = 0) or the last step's gradients
+ * (which = 1) of a state into DEVICE arrays W[i] [out][in] / b[i]. */
+int32_t nedf_train_export(const nedf_mlp_shape* shape, const void* state, int32_t which, float* const* W,
+                          float* const* b, nedf_stream_t stream);
 
 #ifdef __cplusplus
 }

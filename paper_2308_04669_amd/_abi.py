@@ -55,6 +55,24 @@ class MarchOpts(C.Structure):
                 ("t_far", C.c_float), ("hit_threshold", C.c_float), ("dtype", C.c_int32)]
 
 
+class InferOpts(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("p_lo", C.c_float), ("p_hi", C.c_float), ("refine_steps", C.c_int32),
+                ("refine_h", C.c_float), ("march", MarchOpts)]
+
+
+class ShadeOpts(C.Structure):
+    _fields_ = [("K", C.c_int32), ("h", C.c_float), ("clear_rgb", C.c_float * 3), ("dtype", C.c_int32)]
+
+
+class ShadowOpts(C.Structure):
+    _fields_ = [("eps", C.c_float), ("beta", C.c_float), ("method", C.c_int32), ("infer", InferOpts)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("w_hit", C.c_float), ("bound", C.c_float)]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = [
     ("nedf_version", C.c_char_p, []),
@@ -70,6 +88,22 @@ SIGNATURES = [
     ("nedf_profile_read", C.c_int32, [C.c_int32, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]),
     ("nedf_ws_counters", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
+    ("nedf_infer_depth_id", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(InferOpts), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nedf_shade_deferred", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p,
+                                        C.POINTER(ShadeOpts), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nedf_shadow", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int32, C.POINTER(ShadowOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_size_t, C.c_void_p]),
+    ("nedf_train_state_bytes", C.c_size_t, [C.POINTER(MlpShape)]),
+    ("nedf_train_workspace_size", C.c_size_t, [C.POINTER(MlpShape), C.c_int32]),
+    ("nedf_train_init", C.c_int32, [C.POINTER(MlpShape), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
+                                    C.c_size_t, C.c_void_p]),
+    ("nedf_train_step", C.c_int32, [C.POINTER(MlpShape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_int32, C.POINTER(TrainOpts), C.c_void_p, C.c_void_p,
+                                    C.c_size_t, C.c_void_p]),
+    ("nedf_train_export", C.c_int32, [C.POINTER(MlpShape), C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_void_p), C.c_void_p]),
     ("nedf_march_depth", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(MarchOpts), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
 ]

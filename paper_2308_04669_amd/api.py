@@ -103,10 +103,15 @@ def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None) 
     """Build an ObjectSpec from a model description with the attributes
     ``kind``, ``bound``, ``params``, ``trunk`` (W, b lists) and ``rgb``."""
     p = model.params
-    if model.kind == "sphere":
-        return ObjectSpec("sphere", model.bound, (p["sigma_max"], p["radius"], p["width"]))
-    if model.kind == "slab":
-        return ObjectSpec("slab", model.bound, (p["sigma0"], p["z0"], p["z1"]))
+    colour = tuple(p.get("colour", (0.8, 0.8, 0.8)))
+    if model.kind in ("sphere", "slab"):
+        if model.kind == "sphere":
+            spec = ObjectSpec("sphere", model.bound, (p["sigma_max"], p["radius"], p["width"]) + colour)
+        else:
+            spec = ObjectSpec("slab", model.bound, (p["sigma0"], p["z0"], p["z1"]) + colour)
+        if nedf_model is not None:
+            spec.nedf = _pack_nedf(nedf_model, dtype, device)
+        return spec
     if model.kind in ("mlp", "nerf"):
         tr = model.trunk
         width = tr.W[0].shape[0]
@@ -126,11 +131,15 @@ def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None) 
             param = ()
         spec = ObjectSpec("mlp", model.bound, param, mode, dens)
         if nedf_model is not None:
-            t = nedf_model.trunk
-            nshape = mlp_shape("pluecker", nedf_model.params["enc_L"], t.W[0].shape[0], len(t.W) - 1, 2)
-            spec.nedf = pack_mlp(t.W, t.b, nshape, dtype, device)
+            spec.nedf = _pack_nedf(nedf_model, dtype, device)
         return spec
     raise ValueError(model.kind)
+
+
+def _pack_nedf(nedf_model, dtype, device) -> PackedMLP:
+    t = nedf_model.trunk
+    nshape = mlp_shape("pluecker", nedf_model.params["enc_L"], t.W[0].shape[0], len(t.W) - 1, 2)
+    return pack_mlp(t.W, t.b, nshape, dtype, device)
 
 
 @dataclass
@@ -241,16 +250,93 @@ def march_depth(scene: SceneGPU, rays: A.Rays, n_samples: int = 128, clip_to_bou
     return depth, ident, opac
 
 
+def infer_opts(dtype="bf16", p_lo=0.2, p_hi=0.8, refine_steps=3, refine_h=0.05, n_samples=128,
+               hit_threshold=0.5) -> A.InferOpts:
+    m = A.MarchOpts(n_samples=n_samples, clip_to_bound=1, t_near=0.0, t_far=0.0, hit_threshold=hit_threshold,
+                    dtype=A.DTYPES[dtype])
+    return A.InferOpts(dtype=A.DTYPES[dtype], p_lo=p_lo, p_hi=p_hi, refine_steps=refine_steps,
+                       refine_h=refine_h, march=m)
+
+
+def infer_depth_id(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_lo: float = 0.2, p_hi: float = 0.8,
+                   refine_steps: int = 3, refine_h: float = 0.05, n_samples: int = 128,
+                   ws: Workspace | None = None, pair_capacity: int = 0, out=None):
+    """NeDF depth+ID with marcher fallback and secant refinement.  Returns
+    (depth float32 [n], id int32 [n])."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    if out is None:
+        depth = torch.empty(n, dtype=torch.float32, device=dev)
+        ident = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        depth, ident = out
+    sc = scene.struct()
+    opts = infer_opts(dtype, p_lo, p_hi, refine_steps, refine_h, n_samples)
+    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), int(pair_capacity))
+    ws = ws or Workspace(dev)
+    buf = ws.get(nbytes)
+    A.check(lib.nedf_infer_depth_id(C.byref(sc), C.byref(rays), C.byref(opts), _ptr(depth), _ptr(ident),
+                                    buf.data_ptr(), int(nbytes), _stream()), "nedf_infer_depth_id")
+    return depth, ident
+
+
+def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, K: int = 8,
+                   h: float = 0.05, clear_rgb=(0.0, 0.0, 0.0), dtype: str = "bf16", ws: Workspace | None = None,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """Deferred shading of every pixel with a valid ID; returns rgb [n, 3]."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
+    sc = scene.struct()
+    opts = A.ShadeOpts(K=K, h=h, dtype=A.DTYPES[dtype])
+    for i in range(3):
+        opts.clear_rgb[i] = float(clear_rgb[i])
+    nbytes = lib.nedf_workspace_size(A.OPS["shade"], C.byref(sc), C.byref(rays), 0)
+    ws = ws or Workspace(dev)
+    buf = ws.get(nbytes)
+    A.check(lib.nedf_shade_deferred(C.byref(sc), C.byref(rays), _ptr(depth), _ptr(ident), C.byref(opts),
+                                    _ptr(rgb), buf.data_ptr(), int(nbytes), _stream()), "nedf_shade_deferred")
+    return rgb
+
+
+def shadow(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, lights, eps: float,
+           beta: float = 0.5, method: str = "nedf", dtype: str = "bf16", n_samples: int = 128,
+           p_lo: float = 0.2, p_hi: float = 0.8, rgb_inout: torch.Tensor | None = None,
+           ws: Workspace | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Shadow step of Alg. 2 for point lights; returns the multiplier [n]
+    and multiplies ``rgb_inout`` by it when given."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    fac = out if out is not None else torch.empty(n, dtype=torch.float32, device=dev)
+    L = np.ascontiguousarray(np.asarray(lights, np.float32).reshape(-1, 3))
+    sc = scene.struct()
+    io = infer_opts(dtype, p_lo, p_hi, 0, 0.05, n_samples)
+    opts = A.ShadowOpts(eps=eps, beta=beta, method=0 if method == "nedf" else 1, infer=io)
+    nbytes = lib.nedf_workspace_size(A.OPS["shadow"], C.byref(sc), C.byref(rays), 0)
+    ws = ws or Workspace(dev)
+    buf = ws.get(nbytes)
+    A.check(lib.nedf_shadow(C.byref(sc), C.byref(rays), _ptr(depth), _ptr(ident), L.ctypes.data, L.shape[0],
+                            C.byref(opts), _ptr(fac), _ptr(rgb_inout), buf.data_ptr(), int(nbytes), _stream()),
+            "nedf_shadow")
+    return fac
+
+
 def check_status(ws: Workspace) -> int:
     lib = A.load()
     return int(lib.nedf_check_status(ws.buf.data_ptr(), _stream()))
 
 
-def ws_counters(ws: Workspace) -> tuple:
+def ws_counters(ws: Workspace) -> dict:
+    """Counters of the last call on ``ws``: pairs, items, and the NeDF
+    routing statistics (network-decided hits, marcher fallbacks, misses)."""
     lib = A.load()
-    out = (C.c_int64 * 2)()
+    out = (C.c_int64 * 5)()
     A.check(lib.nedf_ws_counters(ws.buf.data_ptr(), _stream(), out), "nedf_ws_counters")
-    return int(out[0]), int(out[1])
+    return dict(pairs=int(out[0]), items=int(out[1]), nedf_hits=int(out[2]), fallback=int(out[3]),
+                nedf_misses=int(out[4]))
 
 
 def profile_enable(on: bool = True) -> None:
@@ -270,3 +356,57 @@ def profile_read(max_stages: int = 64) -> dict:
         nm = names.raw[64 * k:64 * k + 64].split(b"\0", 1)[0].decode()
         out[nm] = (float(ms[k]), int(cnt[k]))
     return out
+
+
+# ---------------------------------------------------------------- training
+class Trainer:
+    """Device training state of one intersection network (float32 master
+    weights, Adam moments, gradients, bfloat16 copies) driven through
+    nedf_train_step."""
+
+    def __init__(self, W, b, enc_L: int = 8, in_kind: str = "pluecker", device=None):
+        lib = A.load()
+        self.dev = _device(device)
+        width = W[0].shape[0]
+        self.shape = mlp_shape(in_kind, enc_L, width, len(W) - 1, W[-1].shape[0])
+        self._s = A.MlpShape(**{k: int(v) for k, v in self.shape.items()})
+        n = lib.nedf_train_state_bytes(C.byref(self._s))
+        if n == 0:
+            raise A.NedfError(2, "nedf_train_state_bytes", lib.nedf_last_error().decode())
+        self.state = torch.zeros(int(n), dtype=torch.uint8, device=self.dev)
+        self.dims = [(w.shape[0], w.shape[1]) for w in W]
+        Wt = [torch.from_numpy(np.ascontiguousarray(w, np.float32)).to(self.dev) for w in W]
+        bt = [torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(self.dev) for x in b]
+        Wp = (C.c_void_p * len(Wt))(*[t.data_ptr() for t in Wt])
+        bp = (C.c_void_p * len(bt))(*[t.data_ptr() for t in bt])
+        A.check(lib.nedf_train_init(C.byref(self._s), Wp, bp, self.state.data_ptr(), int(n), _stream()),
+                "nedf_train_init")
+        torch.cuda.current_stream().synchronize()
+        self.ws = Workspace(self.dev)
+        self.loss = torch.zeros(4, dtype=torch.float32, device=self.dev)
+
+    def step(self, o_l, d_l, depth_label, hit_label, lr=5e-4, beta1=0.9, beta2=0.999, eps=1e-8, w_hit=0.1,
+             bound=1.0) -> torch.Tensor:
+        lib = A.load()
+        B = int(o_l.shape[0])
+        nbytes = lib.nedf_train_workspace_size(C.byref(self._s), B)
+        buf = self.ws.get(nbytes)
+        opts = A.TrainOpts(lr=lr, beta1=beta1, beta2=beta2, eps=eps, w_hit=w_hit, bound=bound)
+        A.check(lib.nedf_train_step(C.byref(self._s), self.state.data_ptr(), o_l.data_ptr(), d_l.data_ptr(),
+                                    depth_label.data_ptr(), hit_label.data_ptr(), B, C.byref(opts),
+                                    self.loss.data_ptr(), buf.data_ptr(), int(nbytes), _stream()),
+                "nedf_train_step")
+        return self.loss[:3]
+
+    def export(self, which: int = 0):
+        """(W list, b list) as float64 NumPy arrays: master weights (0) or the
+        last step's gradients (1)."""
+        lib = A.load()
+        Wt = [torch.empty(d, dtype=torch.float32, device=self.dev) for d in self.dims]
+        bt = [torch.empty(d[0], dtype=torch.float32, device=self.dev) for d in self.dims]
+        Wp = (C.c_void_p * len(Wt))(*[t.data_ptr() for t in Wt])
+        bp = (C.c_void_p * len(bt))(*[t.data_ptr() for t in bt])
+        A.check(lib.nedf_train_export(C.byref(self._s), self.state.data_ptr(), which, Wp, bp, _stream()),
+                "nedf_train_export")
+        torch.cuda.current_stream().synchronize()
+        return [t.cpu().numpy().astype(np.float64) for t in Wt], [t.cpu().numpy().astype(np.float64) for t in bt]

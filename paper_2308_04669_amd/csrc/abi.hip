@@ -11,12 +11,18 @@
 #include "blob_layout.h"
 #include "launch.h"
 #include "nedf.h"
+#include "pipeline.h"
 #include "runtime.h"
+#include "train_layout.h"
 
 namespace nedf {
 
 namespace {
 thread_local std::string g_last_error;
+
+__global__ void k_reset_status(int* status) {
+  if (threadIdx.x == 0) *status = 0;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -79,28 +85,35 @@ int32_t fail(int32_t code, const std::string& msg) {
   return code;
 }
 
-size_t ws_fixed_bytes(int64_t n_rays) {
-  size_t off = 256;                                  // status block
-  off = align256(off + sizeof(WsCounters));          // counters
-  off = align256(off + size_t(n_rays) * 8);          // packed keys
-  off = align256(off + size_t(n_rays) * 4);          // opacity bits
+
+// Workspace: status(256) | counters | keys n*8 | opacity n*4 | extra | pairs A | pairs B.
+size_t ws_fixed_bytes(int64_t n_rays, size_t extra_bytes) {
+  size_t off = 256;
+  off = align256(off + sizeof(WsCounters));
+  off = align256(off + size_t(n_rays) * 8);
+  off = align256(off + size_t(n_rays) * 4);
+  off = align256(off + extra_bytes);
   return off;
 }
 
-WsLayout ws_layout(int64_t n_rays, size_t ws_bytes) {
+WsLayout ws_layout(int64_t n_rays, size_t extra_bytes, size_t ws_bytes) {
   WsLayout l;
   l.counters = 256;
   l.keys = align256(l.counters + sizeof(WsCounters));
   l.opac = align256(l.keys + size_t(n_rays) * 8);
-  l.pairs = align256(l.opac + size_t(n_rays) * 4);
-  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / 8) : 0;
+  l.extra = align256(l.opac + size_t(n_rays) * 4);
+  l.pairs = align256(l.extra + extra_bytes);
+  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / 16) : 0;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   l.capacity = cap;
-  l.end = l.pairs + size_t(cap) * 8;
+  l.pairsB = l.pairs + size_t(cap) * 8;
+  l.end = l.pairsB + size_t(cap) * 8;
   return l;
 }
 
 namespace {
+
+constexpr size_t SHADOW_EXTRA_PER_RAY = 32;  // origin 12 + direction 12 + distance 4 + depth 4
 
 int32_t check_rays(const nedf_rays* rays, RaySrcHost& rs) {
   if (!rays) return fail(NEDF_ERR_NULL, "rays is NULL");
@@ -144,33 +157,171 @@ int32_t check_rays(const nedf_rays* rays, RaySrcHost& rs) {
   return NEDF_OK;
 }
 
-int32_t check_scene(const nedf_scene* sc) {
+int32_t hip_fail(hipError_t e, const char* where) {
+  return fail(NEDF_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Validated scene: object descriptors, per-kind masks and the shared
+// network shapes of the kernels that will run.
+struct Prepared {
+  KArgs k;
+  uint32_t analytic = 0, mlp = 0, nedf = 0, sphere = 0, sdf_mlp = 0, nerf = 0;
+  int32_t W = 0, H = 0, L = 0;        // density network shape (0 if none)
+  nedf_mlp_shape dshape{};
+};
+
+int32_t prepare_scene(const nedf_scene* sc, int32_t dtype, Prepared& P) {
   if (!sc) return fail(NEDF_ERR_NULL, "scene is NULL");
-  if (sc->n_objects < 1 || sc->n_objects > NEDF_MAX_OBJECTS)
-    return fail(NEDF_ERR_SHAPE, "n_objects must be 1..32");
+  if (sc->n_objects < 1 || sc->n_objects > NEDF_MAX_OBJECTS) return fail(NEDF_ERR_SHAPE, "n_objects must be 1..32");
   if (!sc->objects) return fail(NEDF_ERR_NULL, "scene.objects is NULL");
   if (sc->n_inst < 1) return fail(NEDF_ERR_SHAPE, "n_inst must be >= 1");
   if (!sc->inst_object || !sc->inst_w2l) return fail(NEDF_ERR_NULL, "instance arrays are NULL");
   if (!aligned16(sc->inst_object) || !aligned16(sc->inst_w2l)) return fail(NEDF_ERR_ALIGN, "instance arrays must be 16-byte aligned");
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return fail(NEDF_ERR_DTYPE, "dtype must be F32 or BF16");
+  std::memset(&P.k, 0, sizeof(P.k));
+  P.k.n_obj = sc->n_objects;
+  P.k.n_inst = sc->n_inst;
+  P.k.inst_object = sc->inst_object;
+  P.k.w2l = sc->inst_w2l;
+  bool have = false;
   for (int i = 0; i < sc->n_objects; ++i) {
     const nedf_object& o = sc->objects[i];
+    ObjDesc& d = P.k.obj[i];
     if (!(o.bound > 0.0f)) return fail(NEDF_ERR_SHAPE, "object bound must be positive");
     if (o.field < NEDF_FIELD_SPHERE || o.field > NEDF_FIELD_MLP) return fail(NEDF_ERR_SHAPE, "unknown object field");
-    if (o.field == NEDF_FIELD_SPHERE && !(o.param[2] > 0.0f)) return fail(NEDF_ERR_SHAPE, "sphere width must be positive");
+    d.field = o.field;
+    d.sigma_mode = o.sigma_mode;
+    d.bound = o.bound;
+    for (int j = 0; j < 6; ++j) d.param[j] = o.param[j];
+    d.blob = static_cast<const uint8_t*>(o.density.blob);
+    d.nedf_blob = static_cast<const uint8_t*>(o.nedf.blob);
+    if (o.field == NEDF_FIELD_SPHERE) {
+      if (!(o.param[2] > 0.0f)) return fail(NEDF_ERR_SHAPE, "sphere width must be positive");
+      P.sphere |= 1u << i;
+    }
+    if (o.field != NEDF_FIELD_MLP) P.analytic |= 1u << i;
     if (o.field == NEDF_FIELD_MLP) {
+      const nedf_mlp_shape& s = o.density.shape;
       if (!o.density.blob) return fail(NEDF_ERR_NULL, "MLP object without a density blob");
       if (!aligned16(o.density.blob)) return fail(NEDF_ERR_ALIGN, "density blob must be 16-byte aligned");
       if (o.sigma_mode < NEDF_SIGMA_SOFTPLUS || o.sigma_mode > NEDF_SIGMA_SDF) return fail(NEDF_ERR_SHAPE, "unknown sigma mode");
       if (o.sigma_mode == NEDF_SIGMA_SDF && !(o.param[1] > 0.0f)) return fail(NEDF_ERR_SHAPE, "sdf width must be positive");
-      if (o.density.shape.in_kind != NEDF_IN_XYZ || o.density.shape.n_out != 1)
-        return fail(NEDF_ERR_SHAPE, "density network must take xyz and output one value");
+      if (s.in_kind != NEDF_IN_XYZ || s.n_out != 1) return fail(NEDF_ERR_SHAPE, "density network must take xyz and output one value");
+      if (o.density.dtype != dtype) return fail(NEDF_ERR_DTYPE, "density blob dtype differs from the call's dtype");
+      if (!march_mlp_supported(dtype, s.width, s.n_hidden, s.enc_L))
+        return fail(NEDF_ERR_UNSUPPORTED, "density network shape not instantiated (width 64/3 hidden/L6 or 256/8/L10)");
+      if (have && (s.width != P.W || s.n_hidden != P.H || s.enc_L != P.L))
+        return fail(NEDF_ERR_UNSUPPORTED, "all MLP objects of one call must share a network shape");
+      have = true;
+      P.W = s.width;
+      P.H = s.n_hidden;
+      P.L = s.enc_L;
+      P.dshape = s;
+      P.mlp |= 1u << i;
+      if (o.sigma_mode == NEDF_SIGMA_SDF) P.sdf_mlp |= 1u << i;
+      if (s.rgb_width > 0) P.nerf |= 1u << i;
+    }
+    if (o.nedf.blob) {
+      const nedf_mlp_shape& s = o.nedf.shape;
+      if (!aligned16(o.nedf.blob)) return fail(NEDF_ERR_ALIGN, "intersection network blob must be 16-byte aligned");
+      if (s.in_kind != NEDF_IN_PLUECKER || s.n_out != 2) return fail(NEDF_ERR_SHAPE, "intersection network must take Pluecker coordinates and output (mu, logit)");
+      if (o.nedf.dtype != dtype) return fail(NEDF_ERR_DTYPE, "intersection network dtype differs from the call's dtype");
+      if (!nedf_net_supported(dtype, s.width, s.n_hidden, s.enc_L))
+        return fail(NEDF_ERR_UNSUPPORTED, "intersection network shape not instantiated (width 256, 8 hidden, L8)");
+      P.nedf |= 1u << i;
     }
   }
   return NEDF_OK;
 }
 
-int32_t hip_fail(hipError_t e, const char* where) {
-  return fail(NEDF_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+int32_t prepare_ws(Prepared& P, const RaySrcHost& rs, size_t extra, void* ws, size_t ws_bytes, WsLayout& lay) {
+  if (!ws) return fail(NEDF_ERR_NULL, "workspace is NULL");
+  if (!aligned16(ws)) return fail(NEDF_ERR_ALIGN, "workspace must be 16-byte aligned");
+  if (ws_bytes < ws_fixed_bytes(rs.n, extra) + 16) return fail(NEDF_ERR_WORKSPACE, "workspace smaller than nedf_workspace_size()");
+  lay = ws_layout(rs.n, extra, ws_bytes);
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  KArgs& k = P.k;
+  k.status = reinterpret_cast<int*>(w);
+  k.C = reinterpret_cast<WsCounters*>(w + lay.counters);
+  k.keys = reinterpret_cast<uint64_t*>(w + lay.keys);
+  k.opac = reinterpret_cast<uint32_t*>(w + lay.opac);
+  k.pairs = reinterpret_cast<uint2*>(w + lay.pairs);
+  k.pairsB = reinterpret_cast<uint2*>(w + lay.pairsB);
+  k.capacity = lay.capacity;
+  return NEDF_OK;
+}
+
+void set_rays(KArgs& k, const RaySrcHost& rs) {
+  k.rays.kind = rs.kind;
+  k.rays.width = rs.width;
+  k.rays.height = rs.height;
+  for (int i = 0; i < 3; ++i) {
+    k.rays.eye[i] = rs.eye[i];
+    k.rays.fwd[i] = rs.fwd[i];
+    k.rays.right[i] = rs.right[i];
+    k.rays.up[i] = rs.up[i];
+  }
+  k.rays.o = rs.o;
+  k.rays.d = rs.d;
+  k.n_rays = rs.n;
+}
+
+int32_t check_march_opts(const nedf_march_opts* o) {
+  if (!o) return fail(NEDF_ERR_NULL, "march opts are NULL");
+  if (o->n_samples < 1 || o->n_samples > 4096) return fail(NEDF_ERR_SHAPE, "n_samples must be 1..4096");
+  if (!(o->hit_threshold > 0.0f && o->hit_threshold <= 1.0f)) return fail(NEDF_ERR_SHAPE, "hit_threshold must be in (0, 1]");
+  if (!o->clip_to_bound && !(o->t_far > o->t_near && o->t_near >= 0.0f)) return fail(NEDF_ERR_SHAPE, "need 0 <= t_near < t_far");
+  return NEDF_OK;
+}
+
+int32_t check_infer_opts(const nedf_infer_opts* o) {
+  if (!o) return fail(NEDF_ERR_NULL, "infer opts are NULL");
+  if (!(o->p_lo >= 0.0f && o->p_lo <= o->p_hi && o->p_hi <= 1.0f)) return fail(NEDF_ERR_SHAPE, "need 0 <= p_lo <= p_hi <= 1");
+  if (o->refine_steps < 0 || o->refine_steps > 16) return fail(NEDF_ERR_SHAPE, "refine_steps must be 0..16");
+  if (o->refine_steps > 0 && !(o->refine_h > 0.0f)) return fail(NEDF_ERR_SHAPE, "refine_h must be positive");
+  int32_t st = check_march_opts(&o->march);
+  if (st) return st;
+  if (!o->march.clip_to_bound) return fail(NEDF_ERR_UNSUPPORTED, "fallback marching needs clip_to_bound = 1");
+  return NEDF_OK;
+}
+
+void apply_march_opts(KArgs& k, const nedf_march_opts& o) {
+  k.n_samples = o.n_samples;
+  k.clip = o.clip_to_bound;
+  k.t_near = o.t_near;
+  k.t_far = o.t_far;
+  k.hit_thr = o.hit_threshold;
+}
+
+// Plain-marcher depth into k.depth / k.id / k.opacity.
+void run_march(const Prepared& P, int dtype, hipStream_t s) {
+  stage_init_cull(P.k, s, P.mlp, eng::WAVES);
+  KArgs k = P.k;
+  k.L = &k.C->A;
+  stage_march(k, s, false, P.analytic, dtype, P.mlp ? P.W : 0, P.H, P.L);
+  stage_finalize(P.k, s);
+}
+
+// NeDF depth (+ fallback, + refinement) into k.depth / k.id.
+void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream_t s) {
+  KArgs k = P.k;
+  k.p_lo = o.p_lo;
+  k.p_hi = o.p_hi;
+  stage_init_cull(k, s, P.nedf, 32 * eng::WAVES);
+  k.L = &k.C->A;
+  // analytic objects without a network are marched directly
+  const uint32_t direct = P.analytic & ~P.nedf;
+  if (direct) stage_march(k, s, false, direct, dtype, 0, 0, 0);
+  if (P.nedf) stage_nedf(k, s, dtype);
+  // uncertain pairs: marcher on list B
+  stage_march(k, s, true, P.analytic, dtype, (P.mlp & P.nedf) ? P.W : 0, P.H, P.L);
+  stage_finalize(k, s);
+  if (o.refine_steps > 0 && k.id) {
+    k.refine_h = o.refine_h;
+    k.refine_steps = o.refine_steps;
+    const uint32_t mlp_ok = refine_supported(dtype, P.dshape) ? P.sdf_mlp : 0u;
+    if (mlp_ok | P.sphere) stage_refine(k, s, k.id, mlp_ok, P.sphere, dtype);
+  }
 }
 
 }  // namespace
@@ -178,7 +329,7 @@ int32_t hip_fail(hipError_t e, const char* where) {
 
 using namespace nedf;
 
-extern "C" const char* nedf_version(void) { return "nedf-mi355x 0.1.0 (gfx950)"; }
+extern "C" const char* nedf_version(void) { return "nedf-mi355x 0.2.0 (gfx950)"; }
 
 extern "C" const char* nedf_last_error(void) { return g_last_error.c_str(); }
 
@@ -215,10 +366,11 @@ extern "C" size_t nedf_workspace_size(int32_t op, const nedf_scene* scene, const
     set_error("nedf_workspace_size: NULL scene or rays");
     return 0;
   }
-  (void)op;
   int64_t cap = pair_capacity > 0 ? pair_capacity : n * int64_t(scene->n_inst > 0 ? scene->n_inst : 1);
+  if (cap < 1) cap = 1;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
-  return ws_fixed_bytes(n) + size_t(cap) * 8;
+  const size_t extra = op == NEDF_OP_SHADOW ? size_t(n) * SHADOW_EXTRA_PER_RAY : 0;
+  return ws_fixed_bytes(n, extra) + size_t(cap) * 16;
 }
 
 extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {
@@ -232,67 +384,185 @@ extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {
   return st;
 }
 
+extern "C" int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out5) {
+  if (!ws || !out5) return fail(NEDF_ERR_NULL, "nedf_ws_counters: NULL argument");
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
+  WsCounters c;
+  e = hipMemcpy(&c, static_cast<const uint8_t*>(ws) + 256, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
+  out5[0] = c.A.total_pairs;
+  out5[1] = c.A.total_items;
+  out5[2] = c.stats[0];
+  out5[3] = c.stats[1];
+  out5[4] = c.stats[2];
+  return NEDF_OK;
+}
+
 extern "C" int32_t nedf_march_depth(const nedf_scene* scene, const nedf_rays* rays,
                                     const nedf_march_opts* opts, float* depth, int32_t* id,
                                     float* opacity, void* ws, size_t ws_bytes, nedf_stream_t stream) {
-  int32_t st = check_scene(scene);
+  int32_t st = check_march_opts(opts);
   if (st) return st;
-  MarchLaunch m;
-  std::memset(&m, 0, sizeof(m));
-  st = check_rays(rays, m.rays);
-  if (st) return st;
-  if (!opts) return fail(NEDF_ERR_NULL, "opts is NULL");
-  if (opts->n_samples < 1 || opts->n_samples > 4096) return fail(NEDF_ERR_SHAPE, "n_samples must be 1..4096");
-  if (!(opts->hit_threshold > 0.0f && opts->hit_threshold <= 1.0f)) return fail(NEDF_ERR_SHAPE, "hit_threshold must be in (0, 1]");
-  if (!opts->clip_to_bound && !(opts->t_far > opts->t_near && opts->t_near >= 0.0f))
-    return fail(NEDF_ERR_SHAPE, "need 0 <= t_near < t_far");
   if (opts->dtype != NEDF_F32 && opts->dtype != NEDF_BF16) return fail(NEDF_ERR_DTYPE, "march dtype must be F32 or BF16");
-  const int64_t n = m.rays.n;
-  if (n == 0) return NEDF_OK;
-  if (!depth || !id || !ws) return fail(NEDF_ERR_NULL, "depth, id and ws are required");
-  if (!aligned16(depth) || !aligned16(id) || !aligned16(ws) || (opacity && !aligned16(opacity)))
+  Prepared P;
+  st = prepare_scene(scene, opts->dtype, P);
+  if (st) return st;
+  RaySrcHost rs;
+  st = check_rays(rays, rs);
+  if (st) return st;
+  if (rs.n == 0) return NEDF_OK;
+  if (!depth || !id) return fail(NEDF_ERR_NULL, "depth and id are required");
+  if (!aligned16(depth) || !aligned16(id) || (opacity && !aligned16(opacity)))
     return fail(NEDF_ERR_ALIGN, "output buffers must be 16-byte aligned");
-  m.lay = ws_layout(n, ws_bytes);
-  if (ws_bytes < ws_fixed_bytes(n) + 8) return fail(NEDF_ERR_WORKSPACE, "workspace smaller than nedf_workspace_size()");
-  m.n_obj = scene->n_objects;
-  m.n_inst = scene->n_inst;
-  bool have_shape = false;
-  for (int i = 0; i < scene->n_objects; ++i) {
-    const nedf_object& o = scene->objects[i];
-    ObjDesc& d = m.obj[i];
-    d.field = o.field;
-    d.sigma_mode = o.sigma_mode;
-    d.bound = o.bound;
-    for (int j = 0; j < 6; ++j) d.param[j] = o.param[j];
-    d.blob = static_cast<const uint8_t*>(o.density.blob);
-    d.nedf_blob = static_cast<const uint8_t*>(o.nedf.blob);
-    if (o.field == NEDF_FIELD_MLP) {
-      const nedf_mlp_shape& s = o.density.shape;
-      if (o.density.dtype != opts->dtype) return fail(NEDF_ERR_DTYPE, "density blob dtype differs from opts.dtype");
-      if (!march_mlp_supported(opts->dtype, s.width, s.n_hidden, s.enc_L))
-        return fail(NEDF_ERR_UNSUPPORTED, "density network shape not instantiated (width 64/3 hidden/L6 or 256/8/L10)");
-      if (have_shape && (s.width != m.mlp_width || s.n_hidden != m.mlp_hidden || s.enc_L != m.mlp_L))
-        return fail(NEDF_ERR_UNSUPPORTED, "all MLP objects of one call must share a network shape");
-      have_shape = true;
-      m.mlp_width = s.width;
-      m.mlp_hidden = s.n_hidden;
-      m.mlp_L = s.enc_L;
-    }
-  }
-  m.inst_object = scene->inst_object;
-  m.inst_w2l = scene->inst_w2l;
-  m.n_samples = opts->n_samples;
-  m.clip = opts->clip_to_bound;
-  m.t_near = opts->t_near;
-  m.t_far = opts->t_far;
-  m.hit_thr = opts->hit_threshold;
-  m.dtype = opts->dtype;
-  m.ws = static_cast<uint8_t*>(ws);
-  m.depth = depth;
-  m.id = id;
-  m.opacity = opacity;
-  hipError_t e = launch_march(m, static_cast<hipStream_t>(stream));
+  WsLayout lay;
+  st = prepare_ws(P, rs, 0, ws, ws_bytes, lay);
+  if (st) return st;
+  set_rays(P.k, rs);
+  apply_march_opts(P.k, *opts);
+  P.k.depth = depth;
+  P.k.id = id;
+  P.k.opacity = opacity;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  run_march(P, opts->dtype, s);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "nedf_march_depth");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                                       float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream) {
+  int32_t st = check_infer_opts(opts);
+  if (st) return st;
+  Prepared P;
+  st = prepare_scene(scene, opts->dtype, P);
+  if (st) return st;
+  if (P.mlp & ~P.nedf) return fail(NEDF_ERR_UNSUPPORTED, "every MLP object needs an intersection network (use nedf_march_depth)");
+  RaySrcHost rs;
+  st = check_rays(rays, rs);
+  if (st) return st;
+  if (rs.n == 0) return NEDF_OK;
+  if (!depth || !id) return fail(NEDF_ERR_NULL, "depth and id are required");
+  if (!aligned16(depth) || !aligned16(id)) return fail(NEDF_ERR_ALIGN, "output buffers must be 16-byte aligned");
+  WsLayout lay;
+  st = prepare_ws(P, rs, 0, ws, ws_bytes, lay);
+  if (st) return st;
+  set_rays(P.k, rs);
+  apply_march_opts(P.k, opts->march);
+  P.k.depth = depth;
+  P.k.id = id;
+  run_infer(P, opts->dtype, *opts, static_cast<hipStream_t>(stream));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "nedf_infer_depth_id");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_shade_deferred(const nedf_scene* scene, const nedf_rays* rays, const float* depth,
+                                       const int32_t* id, const nedf_shade_opts* opts, float* rgb, void* ws,
+                                       size_t ws_bytes, nedf_stream_t stream) {
+  if (!opts) return fail(NEDF_ERR_NULL, "shade opts are NULL");
+  const int K = opts->K;
+  if (!(K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32)) return fail(NEDF_ERR_SHAPE, "K must be 1, 2, 4, 8, 16 or 32");
+  if (!(opts->h > 0.0f)) return fail(NEDF_ERR_SHAPE, "h must be positive");
+  Prepared P;
+  int32_t st = prepare_scene(scene, opts->dtype, P);
+  if (st) return st;
+  for (int i = 0; i < scene->n_objects; ++i)
+    if (((P.mlp >> i) & 1u) && !shade_supported(opts->dtype, scene->objects[i].density.shape))
+      return fail(NEDF_ERR_UNSUPPORTED, "shading needs NeRF objects with a colour branch (256x8, L10, rgb 128, dir L4)");
+  RaySrcHost rs;
+  st = check_rays(rays, rs);
+  if (st) return st;
+  if (rs.n == 0) return NEDF_OK;
+  if (!depth || !id || !rgb) return fail(NEDF_ERR_NULL, "depth, id and rgb are required");
+  if (!aligned16(depth) || !aligned16(id) || !aligned16(rgb)) return fail(NEDF_ERR_ALIGN, "buffers must be 16-byte aligned");
+  WsLayout lay;
+  st = prepare_ws(P, rs, 0, ws, ws_bytes, lay);
+  if (st) return st;
+  set_rays(P.k, rs);
+  KArgs& k = P.k;
+  k.depth = const_cast<float*>(depth);
+  k.rgb = rgb;
+  k.shade_K = K;
+  k.shade_h = opts->h;
+  for (int c = 0; c < 3; ++c) k.clear_rgb[c] = opts->clear_rgb[c];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, k.status);
+  stage_shade(k, s, id, P.nerf, opts->dtype);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "nedf_shade_deferred");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, const float* depth, const int32_t* id,
+                               const float* lights, int32_t n_lights, const nedf_shadow_opts* opts, float* shadow,
+                               float* rgb_inout, void* ws, size_t ws_bytes, nedf_stream_t stream) {
+  if (!opts) return fail(NEDF_ERR_NULL, "shadow opts are NULL");
+  if (n_lights < 0 || n_lights > 8) return fail(NEDF_ERR_SHAPE, "n_lights must be 0..8");
+  if (n_lights > 0 && !lights) return fail(NEDF_ERR_NULL, "lights is NULL");
+  if (!(opts->beta > 0.0f && opts->beta < 1.0f)) return fail(NEDF_ERR_SHAPE, "beta must be in (0, 1)");
+  if (!(opts->eps >= 0.0f)) return fail(NEDF_ERR_SHAPE, "eps must be >= 0");
+  if (opts->method != 0 && opts->method != 1) return fail(NEDF_ERR_SHAPE, "method must be 0 (NeDF) or 1 (marcher)");
+  int32_t st = opts->method == 0 ? check_infer_opts(&opts->infer) : check_march_opts(&opts->infer.march);
+  if (st) return st;
+  const int32_t dtype = opts->method == 0 ? opts->infer.dtype : opts->infer.march.dtype;
+  Prepared P;
+  st = prepare_scene(scene, dtype, P);
+  if (st) return st;
+  if (opts->method == 0 && (P.mlp & ~P.nedf)) return fail(NEDF_ERR_UNSUPPORTED, "NeDF shadows need an intersection network on every MLP object");
+  RaySrcHost rs;
+  st = check_rays(rays, rs);
+  if (st) return st;
+  if (rs.n == 0) return NEDF_OK;
+  if (!depth || !id || !shadow) return fail(NEDF_ERR_NULL, "depth, id and shadow are required");
+  if (!aligned16(depth) || !aligned16(id) || !aligned16(shadow) || (rgb_inout && !aligned16(rgb_inout)))
+    return fail(NEDF_ERR_ALIGN, "buffers must be 16-byte aligned");
+  const size_t extra = size_t(rs.n) * SHADOW_EXTRA_PER_RAY;
+  WsLayout lay;
+  st = prepare_ws(P, rs, extra, ws, ws_bytes, lay);
+  if (st) return st;
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  float* so = reinterpret_cast<float*>(w + lay.extra);
+  float* sd = so + 3 * rs.n;
+  float* dist = sd + 3 * rs.n;
+  float* depth_l = dist + rs.n;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // primary-ray view of the scene (for x = o + D d)
+  Prepared Pp = P;
+  set_rays(Pp.k, rs);
+  Pp.k.depth = const_cast<float*>(depth);
+  stage_shadow_init(Pp.k, s, shadow);
+  // shadow-ray view: explicit rays from the workspace
+  RaySrcHost sr;
+  std::memset(&sr, 0, sizeof(sr));
+  sr.kind = 1;
+  sr.o = so;
+  sr.d = sd;
+  sr.n = rs.n;
+  Prepared Ps = P;
+  set_rays(Ps.k, sr);
+  Ps.k.depth = depth_l;
+  Ps.k.id = nullptr;
+  Ps.k.opacity = nullptr;
+  prof_mark("shadow", s, true);
+  for (int m = 0; m < n_lights; ++m) {
+    stage_shadow_rays(Pp.k, s, id, lights + 3 * m, so, sd, dist);
+    if (opts->method == 0) {
+      apply_march_opts(Ps.k, opts->infer.march);
+      nedf_infer_opts io = opts->infer;
+      io.refine_steps = 0;  // the occlusion test needs no refined depth
+      run_infer(Ps, dtype, io, s);
+    } else {
+      apply_march_opts(Ps.k, opts->infer.march);
+      Ps.k.clip = 1;
+      run_march(Ps, dtype, s);
+    }
+    stage_shadow_apply(Pp.k, s, id, depth_l, dist, opts->eps, opts->beta, shadow);
+  }
+  if (rgb_inout) stage_composite(Pp.k, s, shadow, rgb_inout);
+  prof_mark("shadow", s, false);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "nedf_shadow");
   return NEDF_OK;
 }
 
@@ -336,14 +606,76 @@ extern "C" int32_t nedf_profile_read(int32_t max_stages, char* names, double* to
   return NEDF_OK;
 }
 
-extern "C" int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out2) {
-  if (!ws || !out2) return fail(NEDF_ERR_NULL, "nedf_ws_counters: NULL argument");
-  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
-  WsCounters c;
-  e = hipMemcpy(&c, static_cast<const uint8_t*>(ws) + 256, sizeof(c), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
-  out2[0] = c.total_pairs;
-  out2[1] = c.total_items;
+
+namespace {
+int32_t check_train_shape(const nedf_mlp_shape* s) {
+  if (!s) return fail(NEDF_ERR_NULL, "shape is NULL");
+  if (s->width != 256 || s->n_out != 2 || s->rgb_width != 0) return fail(NEDF_ERR_UNSUPPORTED, "training needs width 256, n_out 2, no colour branch");
+  if (s->n_hidden < 1 || s->n_hidden > NEDF_MAX_LAYERS) return fail(NEDF_ERR_SHAPE, "n_hidden must be 1..16");
+  if (s->in_kind != NEDF_IN_PLUECKER && s->in_kind != NEDF_IN_XYZ) return fail(NEDF_ERR_SHAPE, "bad in_kind");
+  if (s->enc_L < 0 || s->enc_L > 12) return fail(NEDF_ERR_SHAPE, "enc_L must be 0..12");
+  return NEDF_OK;
+}
+}  // namespace
+
+extern "C" size_t nedf_train_state_bytes(const nedf_mlp_shape* shape) {
+  if (check_train_shape(shape)) return 0;
+  return nedf_train_layout_of(*shape).total;
+}
+
+extern "C" size_t nedf_train_workspace_size(const nedf_mlp_shape* shape, int32_t B) {
+  if (check_train_shape(shape) || B <= 0) return 0;
+  return train_ws_bytes(*shape, B);
+}
+
+extern "C" int32_t nedf_train_init(const nedf_mlp_shape* shape, const float* const* W, const float* const* b,
+                                   void* state, size_t state_bytes, nedf_stream_t stream) {
+  int32_t st = check_train_shape(shape);
+  if (st) return st;
+  if (!W || !b || !state) return fail(NEDF_ERR_NULL, "nedf_train_init: NULL argument");
+  const nedf_train_layout tl = nedf_train_layout_of(*shape);
+  if (state_bytes < tl.total) return fail(NEDF_ERR_WORKSPACE, "nedf_train_init: state buffer too small");
+  if (!aligned16(state)) return fail(NEDF_ERR_ALIGN, "state must be 16-byte aligned");
+  for (int i = 0; i < tl.n_layers; ++i)
+    if (!W[i] || !b[i]) return fail(NEDF_ERR_NULL, "nedf_train_init: NULL layer pointer");
+  hipError_t e = launch_train_init(*shape, W, b, static_cast<uint8_t*>(state), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nedf_train_init");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_train_step(const nedf_mlp_shape* shape, void* state, const float* o_l, const float* d_l,
+                                   const float* depth_label, const uint8_t* hit_label, int32_t B,
+                                   const nedf_train_opts* opts, float* loss_out, void* ws, size_t ws_bytes,
+                                   nedf_stream_t stream) {
+  int32_t st = check_train_shape(shape);
+  if (st) return st;
+  if (!state || !o_l || !d_l || !depth_label || !hit_label || !opts || !loss_out || !ws)
+    return fail(NEDF_ERR_NULL, "nedf_train_step: NULL argument");
+  if (B <= 0 || B % 64 != 0) return fail(NEDF_ERR_SHAPE, "batch must be a positive multiple of 64");
+  if (!aligned16(state) || !aligned16(o_l) || !aligned16(d_l) || !aligned16(depth_label) || !aligned16(ws))
+    return fail(NEDF_ERR_ALIGN, "nedf_train_step: misaligned pointer");
+  if (ws_bytes < train_ws_bytes(*shape, B)) return fail(NEDF_ERR_WORKSPACE, "workspace smaller than nedf_train_workspace_size()");
+  if (!(opts->lr >= 0.0f) || !(opts->beta1 >= 0.0f && opts->beta1 < 1.0f) || !(opts->beta2 >= 0.0f && opts->beta2 < 1.0f) ||
+      !(opts->eps > 0.0f) || !(opts->bound > 0.0f))
+    return fail(NEDF_ERR_SHAPE, "bad Adam / loss options");
+  hipError_t e = launch_train_step(*shape, static_cast<uint8_t*>(state), o_l, d_l, depth_label, hit_label, B,
+                                   opts->lr, opts->beta1, opts->beta2, opts->eps, opts->w_hit, opts->bound, loss_out,
+                                   static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nedf_train_step");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_train_export(const nedf_mlp_shape* shape, const void* state, int32_t which, float* const* W,
+                                     float* const* b, nedf_stream_t stream) {
+  int32_t st = check_train_shape(shape);
+  if (st) return st;
+  if (!state || !W || !b) return fail(NEDF_ERR_NULL, "nedf_train_export: NULL argument");
+  if (which != 0 && which != 1) return fail(NEDF_ERR_SHAPE, "which must be 0 (weights) or 1 (gradients)");
+  const nedf_train_layout tl = nedf_train_layout_of(*shape);
+  for (int i = 0; i < tl.n_layers; ++i)
+    if (!W[i] || !b[i]) return fail(NEDF_ERR_NULL, "nedf_train_export: NULL layer pointer");
+  hipError_t e = launch_train_export(*shape, static_cast<const uint8_t*>(state), W, b, which == 1,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nedf_train_export");
   return NEDF_OK;
 }

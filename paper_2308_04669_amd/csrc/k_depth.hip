@@ -1,0 +1,434 @@
+// Depth stage kernels: culling/binning into per-object pair lists, the plain
+// volume-rendering marcher (Eq. 5) on analytic and MLP fields, the NeDF
+// intersection network (Eq. 1, 2, 7) with routing of uncertain pairs to the
+// marcher, and the packed-key composition (Alg. 1, step 1).
+#include <cstring>
+
+#include "pipeline.h"
+#include "runtime.h"
+
+namespace nedf {
+namespace {
+
+__global__ void k_init(KArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < a.n_rays) {
+    a.keys[i] = NEDF_KEY_EMPTY;
+    a.opac[i] = 0u;
+  }
+  if (i == 0) *a.status = 0;
+  if (i < int64_t(sizeof(WsCounters) / 4)) reinterpret_cast<int32_t*>(a.C)[i] = 0;
+}
+
+__device__ __forceinline__ bool pair_test(const KArgs& a, const float o[3], const float d[3], int inst,
+                                          int obj) {
+  if (!a.clip) return true;
+  const W2L g = load_w2l(a.w2l, inst);
+  float ol[3], dl[3], ta, tb;
+  to_local(g, o, d, ol, dl);
+  return sphere_chord(ol, dl, a.obj[obj].bound, ta, tb);
+}
+
+// Pass 0 counts pairs per object in list A; pass 1 writes them.  One thread
+// per ray, wave-aggregated atomics per (wave, instance).
+template <int PASS>
+__global__ void k_cull(KArgs a) {
+  const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool live = ray < a.n_rays;
+  float o[3] = {0, 0, 0}, d[3] = {0, 0, 1};
+  if (live) make_ray(a.rays, ray, o, d);
+  const int lane = threadIdx.x & 63;
+  PairList* L = &a.C->A;
+  for (int k = 0; k < a.n_inst; ++k) {
+    const int obj = a.inst_object[k];
+    const bool pass = live && obj >= 0 && obj < a.n_obj && pair_test(a, o, d, k, obj);
+    const uint64_t m = __ballot(pass);
+    if (m == 0) continue;
+    const int cnt = __popcll(m);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    if (PASS == 0) {
+      if (lane == leader) atomicAdd(&L->cnt[obj], cnt);
+    } else {
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&L->fill[obj], cnt);
+      base = __shfl(base, leader);
+      if (pass) {
+        const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (pos < L->cnt[obj]) a.pairs[L->off[obj] + pos] = make_uint2(uint32_t(ray), uint32_t(k));
+      }
+    }
+  }
+}
+
+// Segment offsets of list A (clamped to capacity) and work items over the
+// objects in item_mask.  List B gets the same segments, empty.
+__global__ void k_scan_A(KArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  PairList* L = &a.C->A;
+  PairList* B = &a.C->B;
+  int64_t off = 0;
+  int items = 0;
+  bool over = false;
+  for (int m = 0; m < a.n_obj; ++m) {
+    int64_t c = L->cnt[m];
+    if (off + c > a.capacity) {
+      c = a.capacity - off > 0 ? a.capacity - off : 0;
+      over = true;
+    }
+    L->cnt[m] = int32_t(c);
+    L->off[m] = int32_t(off);
+    B->off[m] = int32_t(off);
+    B->cnt[m] = 0;
+    L->item_start[m] = items;
+    if ((a.item_mask >> m) & 1u) items += int32_t((c + a.item_pairs - 1) / a.item_pairs);
+    L->fill[m] = 0;
+    off += c;
+  }
+  L->off[a.n_obj] = int32_t(off);
+  B->off[a.n_obj] = int32_t(off);
+  L->item_start[a.n_obj] = items;
+  L->total_items = items;
+  L->total_pairs = int32_t(off);
+  L->work_counter = 0;
+  if (over) set_status(a.status, NEDF_ERR_CAPACITY);
+}
+
+// Work items over an already-filled list (segments fixed): list B after the
+// network stage, or list A for a second pass with another item size.
+__global__ void k_scan_items(KArgs a, PairList* L) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int items = 0, total = 0;
+  for (int m = 0; m < a.n_obj; ++m) {
+    L->item_start[m] = items;
+    const int c = L->cnt[m];
+    if ((a.item_mask >> m) & 1u) items += (c + a.item_pairs - 1) / a.item_pairs;
+    total += c;
+  }
+  L->item_start[a.n_obj] = items;
+  L->total_items = items;
+  L->total_pairs = total;
+  L->work_counter = 0;
+}
+
+// One thread per pair of an analytic object in `mask`; sequential
+// compensated scan.
+__global__ void k_march_analytic(KArgs a, uint32_t mask) {
+  const PairList* L = a.L;
+  for (int m = 0; m < a.n_obj; ++m) {
+    const ObjDesc od = a.obj[m];
+    if (od.field == NEDF_FIELD_MLP || !((mask >> m) & 1u)) continue;
+    const int cnt = L->cnt[m], off = L->off[m];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+      const uint2 pr = a.pairs[off + q];
+      const W2L g = load_w2l(a.w2l, int(pr.y));
+      float o[3], d[3], ol[3], dl[3];
+      make_ray(a.rays, pr.x, o, d);
+      to_local(g, o, d, ol, dl);
+      float ta, tb;
+      if (a.clip) {
+        if (!sphere_chord(ol, dl, od.bound, ta, tb)) continue;
+      } else {
+        ta = a.t_near * g.inv_s;
+        tb = a.t_far * g.inv_s;
+      }
+      const int N = a.n_samples;
+      const float delta = (tb - ta) / float(N);
+      const float px = fmaf(ta, dl[0], ol[0]), py = fmaf(ta, dl[1], ol[1]), pz = fmaf(ta, dl[2], ol[2]);
+      float tau = 0.f, tau_c = 0.f, sw = 0.f, sw_c = 0.f, swt = 0.f, swt_c = 0.f;
+      for (int i = 0; i < N; ++i) {
+        const float tr = (float(i) + 0.5f) * delta;
+        const float sig = analytic_sigma(od, fmaf(tr, dl[0], px), fmaf(tr, dl[1], py), fmaf(tr, dl[2], pz));
+        const float v = sig * delta;
+        const float w = expf(-(tau + tau_c)) * one_minus_exp_neg(v);
+        neu_add(sw, sw_c, w);
+        neu_add(swt, swt_c, w * (ta + tr));
+        neu_add(tau, tau_c, v);
+      }
+      const float A = sw + sw_c;
+      if (A >= a.hit_thr && A > 0.0f) emit_key(a, pr.x, pr.y, g.s * ((swt + swt_c) / A));
+      atomicMax(&a.opac[pr.x], __float_as_uint(fmaxf(A, 0.0f)));
+    }
+  }
+}
+
+// Matrix-core marcher: a workgroup takes items of 4 pairs (one per wave) of
+// one object from list a.L; each wave marches its pair in chunks of 32
+// samples through the register-resident density network, then scans the
+// chunk's optical depths across the wave.
+template <int DT, int WIDTH, int NHID, int L>
+__global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
+  using T = eng::Tr<DT>;
+  constexpr int NB = T::NB;
+  constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
+  constexpr int KSH = WIDTH / T::KPS;
+  constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
+  constexpr int SPC = 32 * NB;  // samples per wave per chunk
+  static_assert(NB == 1, "the scan assumes one 32-sample block per wave");
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
+  PairList* PL = a.L;
+  const int N = a.n_samples;
+  const int n_chunks = (N + SPC - 1) / SPC;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= PL->total_items) break;
+    const int obj = item_object(PL, a.n_obj, item);
+    const int local = (item - PL->item_start[obj]) * eng::WAVES + wave;
+    const bool valid = local < PL->cnt[obj];
+    const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+    const ObjDesc& od = a.obj[obj];
+    const uint8_t* blob = od.blob;
+    const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
+    const float head_b = reinterpret_cast<const float*>(blob + hb->off_head_b)[0];
+    const W2L g = load_w2l(a.w2l, int(pr.y));
+    float o[3], d[3], ol[3], dl[3];
+    make_ray(a.rays, pr.x, o, d);
+    to_local(g, o, d, ol, dl);
+    float ta = 0.f, tb = 0.f;
+    bool seg = true;
+    if (a.clip) {
+      seg = sphere_chord(ol, dl, od.bound, ta, tb);
+      if (!seg) { ta = 0.f; tb = 0.f; }
+    } else {
+      ta = a.t_near * g.inv_s;
+      tb = a.t_far * g.inv_s;
+    }
+    const float delta = (tb - ta) / float(N);
+    const float pa[3] = {fmaf(ta, dl[0], ol[0]), fmaf(ta, dl[1], ol[1]), fmaf(ta, dl[2], ol[2])};
+    float carry = 0.f, carry_c = 0.f, sw = 0.f, sw_c = 0.f, swt = 0.f, swt_c = 0.f;
+    for (int c = 0; c < n_chunks; ++c) {
+      typename T::frag Benc[NB][KS0];
+      const int si = c * SPC + (lane & 31);
+      const float tr = (float(si) + 0.5f) * delta;
+      float p[3] = {fmaf(tr, dl[0], pa[0]), fmaf(tr, dl[1], pa[1]), fmaf(tr, dl[2], pa[2])};
+      eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
+      float partial[NB][1] = {{0.f}};
+      typename T::frag Blast[NB][KSH];
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr);
+      const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
+      float v = mlp_sigma(od, u, p[0], p[1], p[2]) * delta;
+      if (lane >= 32 || si >= N || !seg) v = 0.f;
+      // inclusive scan of optical depth over the wave (sample order = lane order)
+      float incl = v;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const float y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      const float tau = (carry + carry_c) + (incl - v);
+      const float w = expf(-tau) * one_minus_exp_neg(v);
+      float ws = w, wts = w * (ta + tr);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        ws += __shfl_xor(ws, off);
+        wts += __shfl_xor(wts, off);
+      }
+      neu_add(sw, sw_c, ws);
+      neu_add(swt, swt_c, wts);
+      neu_add(carry, carry_c, __shfl(incl, 63));
+    }
+    if (lane == 0 && valid && seg) {
+      const float A = sw + sw_c;
+      if (A >= a.hit_thr && A > 0.0f) emit_key(a, pr.x, pr.y, g.s * ((swt + swt_c) / A));
+      atomicMax(&a.opac[pr.x], __float_as_uint(fmaxf(A, 0.0f)));
+    }
+  }
+}
+
+// NeDF stage: a workgroup takes items of 128 pairs (32 per wave) of one
+// object; each lane pair evaluates the intersection network on its pair's
+// line coordinates.  Confident hits go to the key buffer, uncertain pairs
+// (and origins inside the bounding sphere) to list B for the marcher.
+template <int DT, int WIDTH, int NHID, int L>
+__global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
+  using T = eng::Tr<DT>;
+  constexpr int NB = T::NB;
+  constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
+  constexpr int KSH = WIDTH / T::KPS;
+  constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
+  PairList* PL = &a.C->A;
+  PairList* FB = &a.C->B;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= PL->total_items) break;
+    const int obj = item_object(PL, a.n_obj, item);
+    const int local = (item - PL->item_start[obj]) * (32 * eng::WAVES) + wave * 32 + (lane & 31);
+    const bool valid = local < PL->cnt[obj];
+    const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+    const ObjDesc& od = a.obj[obj];
+    const uint8_t* blob = od.nedf_blob;
+    const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
+    const float* hbias = reinterpret_cast<const float*>(blob + hb->off_head_b);
+    const W2L g = load_w2l(a.w2l, int(pr.y));
+    float o[3], d[3], ol[3], dl[3];
+    make_ray(a.rays, pr.x, o, d);
+    to_local(g, o, d, ol, dl);
+    const float l = od.bound;
+    float pl[6] = {dl[0], dl[1], dl[2], ol[1] * dl[2] - ol[2] * dl[1], ol[2] * dl[0] - ol[0] * dl[2],
+                   ol[0] * dl[1] - ol[1] * dl[0]};
+    const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
+    const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
+    typename T::frag Benc[NB][KS0];
+    eng::encode_input<DT, 6, L, KS0>(pl, half, Benc[0]);
+    float partial[NB][2] = {{0.f, 0.f}};
+    typename T::frag Blast[NB][KSH];
+    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr);
+    const float mu_hat = partial[0][0] + __shfl_xor(partial[0][0], 32) + hbias[0];
+    const float z = partial[0][1] + __shfl_xor(partial[0][1], 32) + hbias[1];
+    const float p = sigmoidf_(z);
+    const float D = g.s * (tperp - l * fminf(fmaxf(mu_hat, -1.0f), 1.0f));
+    const bool mine = valid && half == 0;
+    const bool to_fb = mine && (inside || (p >= a.p_lo && p <= a.p_hi));
+    const bool hit = mine && !to_fb && p > a.p_hi && D > 0.0f;
+    if (hit) emit_key(a, pr.x, pr.y, D);
+    // wave-aggregated push into the object's segment of list B
+    const uint64_t m = __ballot(to_fb);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&FB->cnt[obj], __popcll(m));
+      base = __shfl(base, leader);
+      if (to_fb) a.pairsB[FB->off[obj] + base + __popcll(m & ((1ull << lane) - 1ull))] = pr;
+    }
+    const uint64_t mh = __ballot(hit), mv = __ballot(mine);
+    if (lane == 0) {
+      atomicAdd(&a.C->stats[0], __popcll(mh));
+      atomicAdd(&a.C->stats[1], __popcll(m));
+      atomicAdd(&a.C->stats[2], __popcll(mv) - __popcll(mh) - __popcll(m));
+    }
+  }
+}
+
+__global__ void k_finalize(KArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n_rays) return;
+  const uint64_t k = a.keys[i];
+  if (k == NEDF_KEY_EMPTY) {
+    a.depth[i] = __int_as_float(0x7f800000);
+    if (a.id) a.id[i] = -1;
+  } else {
+    a.depth[i] = __uint_as_float(uint32_t(k >> 32));
+    if (a.id) a.id[i] = int32_t(uint32_t(k & 0xffffffffu));
+  }
+  if (a.opacity) a.opacity[i] = __uint_as_float(a.opac[i]);
+}
+
+int cu_count() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+  }
+  return ncu;
+}
+
+template <int DT, int WIDTH, int NHID, int L>
+void launch_march_mlp(const KArgs& k, hipStream_t s) {
+  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L>), dim3(cu_count()), dim3(eng::THREADS), 0, s, k);
+}
+
+template <int DT>
+void launch_nedf_net(const KArgs& k, hipStream_t s) {
+  hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8>), dim3(cu_count()), dim3(eng::THREADS), 0, s, k);
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return unsigned(g > 0 ? g : 1);
+}
+
+}  // namespace
+
+bool march_mlp_supported(int dtype, int width, int n_hidden, int L) {
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
+  return (width == 64 && n_hidden == 3 && L == 6) || (width == 256 && n_hidden == 8 && L == 10);
+}
+
+bool nedf_net_supported(int dtype, int width, int n_hidden, int L) {
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
+  return width == 256 && n_hidden == 8 && L == 8;
+}
+
+bool shade_supported(int dtype, const nedf_mlp_shape& s) {
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
+  return s.width == 256 && s.n_hidden == 8 && s.enc_L == 10 && s.rgb_width == 128 && s.dir_L == 4;
+}
+
+bool refine_supported(int dtype, const nedf_mlp_shape& s) {
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
+  return s.width == 256 && s.n_hidden == 8 && s.enc_L == 10;
+}
+
+void stage_init_cull(const KArgs& k0, hipStream_t s, uint32_t item_mask, int item_pairs) {
+  KArgs k = k0;
+  k.item_mask = item_mask;
+  k.item_pairs = item_pairs;
+  k.L = &k.C->A;
+  const unsigned g = grid_for(k.n_rays);
+  prof_mark("depth.cull", s, true);
+  hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, s, k);
+  hipLaunchKernelGGL(k_cull<0>, dim3(g), dim3(256), 0, s, k);
+  hipLaunchKernelGGL(k_scan_A, dim3(1), dim3(64), 0, s, k);
+  hipLaunchKernelGGL(k_cull<1>, dim3(g), dim3(256), 0, s, k);
+  prof_mark("depth.cull", s, false);
+}
+
+void stage_march(const KArgs& k0, hipStream_t s, bool list_b, uint32_t analytic_mask, int dtype, int W, int H,
+                 int Lenc) {
+  (void)H;
+  (void)Lenc;
+  KArgs k = k0;
+  k.L = list_b ? &k.C->B : &k.C->A;
+  k.pairs = list_b ? k.pairsB : k.pairs;
+  if (list_b) {
+    k.item_mask = 0;
+    for (int m = 0; m < k.n_obj; ++m)
+      if (k.obj[m].field == NEDF_FIELD_MLP) k.item_mask |= 1u << m;
+    k.item_pairs = eng::WAVES;
+    hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(64), 0, s, k, k.L);
+  }
+  if (analytic_mask) {
+    prof_mark(list_b ? "fallback.analytic" : "march.analytic", s, true);
+    hipLaunchKernelGGL(k_march_analytic, dim3(512), dim3(256), 0, s, k, analytic_mask);
+    prof_mark(list_b ? "fallback.analytic" : "march.analytic", s, false);
+  }
+  if (W > 0) {
+    prof_mark(list_b ? "fallback.mlp" : "march.mlp", s, true);
+    if (dtype == NEDF_BF16) {
+      if (W == 256) launch_march_mlp<1, 256, 8, 10>(k, s);
+      else launch_march_mlp<1, 64, 3, 6>(k, s);
+    } else {
+      if (W == 256) launch_march_mlp<0, 256, 8, 10>(k, s);
+      else launch_march_mlp<0, 64, 3, 6>(k, s);
+    }
+    prof_mark(list_b ? "fallback.mlp" : "march.mlp", s, false);
+  }
+}
+
+void stage_nedf(const KArgs& k0, hipStream_t s, int dtype) {
+  KArgs k = k0;
+  prof_mark("infer.nedf", s, true);
+  if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s);
+  else launch_nedf_net<0>(k, s);
+  prof_mark("infer.nedf", s, false);
+}
+
+void stage_finalize(const KArgs& k, hipStream_t s) {
+  prof_mark("depth.finalize", s, true);
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(k.n_rays)), dim3(256), 0, s, k);
+  prof_mark("depth.finalize", s, false);
+}
+
+}  // namespace nedf

@@ -1,0 +1,423 @@
+// Per-pixel stages after the depth buffer: binning hit pixels by object,
+// secant refinement of the winning depth, deferred shading (Eq. 8, Alg. 1
+// step 2), shadow rays and the shadow multiplier (Alg. 2), composite.
+#include <cstring>
+
+#include "pipeline.h"
+#include "runtime.h"
+
+namespace nedf {
+namespace {
+
+// Segment offsets and work items of list A over the objects in item_mask.
+__global__ void k_scan_pixels(KArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  PairList* L = &a.C->A;
+  int64_t off = 0;
+  int items = 0;
+  for (int m = 0; m < a.n_obj; ++m) {
+    if (off + L->cnt[m] > a.capacity) {
+      L->cnt[m] = int32_t(a.capacity - off > 0 ? a.capacity - off : 0);
+      set_status(a.status, NEDF_ERR_CAPACITY);
+    }
+    L->off[m] = int32_t(off);
+    L->item_start[m] = items;
+    if ((a.item_mask >> m) & 1u) items += (L->cnt[m] + a.item_pairs - 1) / a.item_pairs;
+    L->fill[m] = 0;
+    off += L->cnt[m];
+  }
+  L->off[a.n_obj] = off;
+  L->item_start[a.n_obj] = items;
+  L->total_items = items;
+  L->total_pairs = off;
+  L->work_counter = 0;
+}
+
+__global__ void k_zero_list(PairList* L) {
+  const int i = threadIdx.x;
+  if (i < int(sizeof(PairList) / 4)) reinterpret_cast<int32_t*>(L)[i] = 0;
+}
+
+// Bin pixels with a valid ID whose object is in `mask` into list A as
+// (pixel, instance) pairs; pass 0 counts, pass 1 writes.  Lanes of a wave
+// are grouped by object so each group issues one atomic.
+template <int PASS>
+__global__ void k_bin(KArgs a, const int32_t* ids, uint32_t mask) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int inst = p < a.n_rays ? ids[p] : -1;
+  int obj = inst >= 0 && inst < a.n_inst ? a.inst_object[inst] : -1;
+  const bool want = obj >= 0 && obj < a.n_obj && ((mask >> obj) & 1u);
+  PairList* L = &a.C->A;
+  uint64_t pending = __ballot(want);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int o = __shfl(obj, leader);
+    const uint64_t match = __ballot(want && obj == o);
+    if (PASS == 0) {
+      if (lane == leader) atomicAdd(&L->cnt[o], __popcll(match));
+    } else {
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&L->fill[o], __popcll(match));
+      base = __shfl(base, leader);
+      if (want && obj == o) {
+        const int pos = base + __popcll(match & ((1ull << lane) - 1ull));
+        if (pos < L->cnt[o]) a.pairs[L->off[o] + pos] = make_uint2(uint32_t(p), uint32_t(inst));
+      }
+    }
+    pending &= ~match;
+  }
+}
+
+// ---- secant refinement --------------------------------------------------------
+// f(t) = surface function at the local point of world depth t; seeds D -/+ h,
+// `steps` secant updates with a [D - 2h, D + 2h] guard (needs steps + 1
+// evaluations; the last iterate is not evaluated).
+struct Secant {
+  float t0, t1, f0, f1, out, lo, hi;
+  bool active;
+  __device__ void start(float D, float h) {
+    t0 = D - h; t1 = D + h; out = D; lo = D - 2.f * h; hi = D + 2.f * h;
+  }
+  __device__ float update() {  // returns the new iterate (evaluation point)
+    const float den = f1 - f0;
+    bool ok = active && den != 0.0f;
+    const float tn = ok ? t1 - f1 * (t1 - t0) / den : t1;
+    ok = ok && tn >= lo && tn <= hi;
+    if (ok) out = tn;
+    active = ok;
+    return tn;
+  }
+  __device__ void shift(float tn, float fn) {
+    if (active) { t0 = t1; f0 = f1; t1 = tn; f1 = fn; }
+  }
+};
+
+__global__ void k_refine_analytic(KArgs a, uint32_t mask) {
+  const PairList* L = &a.C->A;
+  for (int m = 0; m < a.n_obj; ++m) {
+    if (!((mask >> m) & 1u)) continue;
+    const ObjDesc od = a.obj[m];
+    const int cnt = L->cnt[m], off = L->off[m];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+      const uint2 pr = a.pairs[off + q];
+      const W2L g = load_w2l(a.w2l, int(pr.y));
+      float o[3], d[3], ol[3], dl[3];
+      make_ray(a.rays, pr.x, o, d);
+      to_local(g, o, d, ol, dl);
+      auto f = [&](float t) {
+        const float tl = t * g.inv_s;
+        const float x = fmaf(tl, dl[0], ol[0]), y = fmaf(tl, dl[1], ol[1]), z = fmaf(tl, dl[2], ol[2]);
+        return (od.param[1] - sqrtf(x * x + y * y + z * z)) / od.param[2];
+      };
+      Secant s;
+      s.start(a.depth[pr.x], a.refine_h);
+      s.f0 = f(s.t0);
+      s.f1 = f(s.t1);
+      s.active = s.f0 < 0.0f && s.f1 >= 0.0f;
+      for (int it = 0; it < a.refine_steps; ++it) {
+        const float tn = s.update();
+        if (it + 1 < a.refine_steps) s.shift(tn, f(tn));
+      }
+      a.depth[pr.x] = s.out;
+    }
+  }
+}
+
+// Density-network refinement: items of 128 pixels (32 per wave) of one
+// SDF-mode object; each evaluation of f is one pass of the trunk.
+template <int DT, int WIDTH, int NHID, int L>
+__global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
+  using T = eng::Tr<DT>;
+  constexpr int NB = T::NB;
+  constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
+  constexpr int KSH = WIDTH / T::KPS;
+  constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
+  PairList* PL = &a.C->A;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= PL->total_items) break;
+    const int obj = item_object(PL, a.n_obj, item);
+    const int local = (item - PL->item_start[obj]) * (32 * eng::WAVES) + wave * 32 + (lane & 31);
+    const bool valid = local < PL->cnt[obj];
+    const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+    const ObjDesc& od = a.obj[obj];
+    const uint8_t* blob = od.blob;
+    const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
+    const float head_b = reinterpret_cast<const float*>(blob + hb->off_head_b)[0];
+    const W2L g = load_w2l(a.w2l, int(pr.y));
+    float o[3], d[3], ol[3], dl[3];
+    make_ray(a.rays, pr.x, o, d);
+    to_local(g, o, d, ol, dl);
+    auto f = [&](float t) {
+      const float tl = t * g.inv_s;
+      float p[3] = {fmaf(tl, dl[0], ol[0]), fmaf(tl, dl[1], ol[1]), fmaf(tl, dl[2], ol[2])};
+      typename T::frag Benc[NB][KS0];
+      eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
+      float partial[NB][1] = {{0.f}};
+      typename T::frag Blast[NB][KSH];
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr);
+      const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
+      return mlp_surface(od, u, p[0], p[1], p[2]);
+    };
+    Secant s;
+    s.start(a.depth[pr.x], a.refine_h);
+    s.f0 = f(s.t0);
+    s.f1 = f(s.t1);
+    s.active = s.f0 < 0.0f && s.f1 >= 0.0f;
+    for (int it = 0; it < a.refine_steps; ++it) {
+      const float tn = s.update();
+      if (it + 1 < a.refine_steps) {
+        const float fn = f(tn);
+        s.shift(tn, fn);
+      }
+    }
+    if (valid && half == 0) a.depth[pr.x] = s.out;
+  }
+}
+
+// ---- deferred shading ---------------------------------------------------------
+__global__ void k_clear_rgb(KArgs a, const int32_t* ids) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.n_rays) return;
+  const int inst = ids[p];
+  float c[3] = {a.clear_rgb[0], a.clear_rgb[1], a.clear_rgb[2]};
+  if (inst >= 0 && inst < a.n_inst) {
+    const ObjDesc& od = a.obj[a.inst_object[inst]];
+    if (od.field != NEDF_FIELD_MLP) { c[0] = od.param[3]; c[1] = od.param[4]; c[2] = od.param[5]; }
+  }
+  a.rgb[3 * p + 0] = c[0];
+  a.rgb[3 * p + 1] = c[1];
+  a.rgb[3 * p + 2] = c[2];
+}
+
+// NeRF shading: a wave shades 32 / K pixels with K samples each; trunk with
+// the sigma head, then the colour layer on [h_last, gamma_dirL(d)], then
+// local compositing across each pixel's K lanes.
+template <int DT, int WIDTH, int NHID, int L, int DIRL, int RGBW>
+__global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
+  using T = eng::Tr<DT>;
+  constexpr int NB = T::NB;
+  constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
+  constexpr int KSH = WIDTH / T::KPS;
+  constexpr int KSD = eng::ks_for_slots<DT>(3 * DIRL + 2);
+  constexpr int KSR = KSH + KSD;
+  constexpr int CBR = eng::chunk_bytes<DT>(KSR, 3);
+  constexpr int CHUNK = eng::cmax(eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1)), CBR);
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
+  const int K = a.shade_K;  // 1, 2, 4, 8, 16 or 32
+  const int ppw = 32 / K;
+  const int slot = lane & 31, q = slot / K, j = slot % K;
+  PairList* PL = &a.C->A;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= PL->total_items) break;
+    const int obj = item_object(PL, a.n_obj, item);
+    const int local = (item - PL->item_start[obj]) * (ppw * eng::WAVES) + wave * ppw + q;
+    const bool valid = local < PL->cnt[obj];
+    const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+    const ObjDesc& od = a.obj[obj];
+    const uint8_t* blob = od.blob;
+    const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
+    const float head_b = reinterpret_cast<const float*>(blob + hb->off_head_b)[0];
+    const float* rgb_b = reinterpret_cast<const float*>(blob + hb->off_rgbh_b);
+    const W2L g = load_w2l(a.w2l, int(pr.y));
+    float o[3], d[3], ol[3], dl[3];
+    make_ray(a.rays, pr.x, o, d);
+    to_local(g, o, d, ol, dl);
+    const float D = a.depth[pr.x];
+    const float step = 2.0f * a.shade_h / float(K);
+    const float t = D - a.shade_h + (float(j) + 0.5f) * step;
+    const float tl = t * g.inv_s;
+    float p[3] = {fmaf(tl, dl[0], ol[0]), fmaf(tl, dl[1], ol[1]), fmaf(tl, dl[2], ol[2])};
+    typename T::frag Benc[NB][KS0];
+    eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
+    float partial[NB][1] = {{0.f}};
+    typename T::frag Blast[NB][KSH];
+    int cur = 0;
+    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR>(hb, blob, Benc, lds, partial, Blast,
+                                                         blob + hb->off_rgb, &cur);
+    const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
+    const float sig = mlp_sigma(od, u, p[0], p[1], p[2]);
+    // colour layer input: [h_last, gamma_dirL(d_l)]
+    typename T::frag Bc[NB][KSR];
+#pragma unroll
+    for (int k = 0; k < KSH; ++k) Bc[0][k] = Blast[0][k];
+    {
+      typename T::frag Bd[KSD];
+      eng::encode_input<DT, 3, DIRL, KSD>(dl, half, Bd);
+#pragma unroll
+      for (int k = 0; k < KSD; ++k) Bc[0][KSH + k] = Bd[k];
+    }
+    float prgb[NB][3] = {{0.f, 0.f, 0.f}};
+    typename T::frag dummy[NB][1];
+    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK>(Bc, dummy, blob + hb->off_rgb, nullptr, lds, cur,
+                                                              prgb);
+    float c[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) c[ch] = sigmoidf_(prgb[0][ch] + __shfl_xor(prgb[0][ch], 32) + rgb_b[ch]);
+    // local compositing over the K lanes of this pixel
+    const float v = sig * (step * g.inv_s);
+    float incl = v;
+    for (int off = 1; off < K; off <<= 1) {
+      const float y = __shfl_up(incl, off);
+      if (j >= off) incl += y;
+    }
+    const float w = expf(-(incl - v)) * one_minus_exp_neg(v);
+    float sw = w, sc0 = w * c[0], sc1 = w * c[1], sc2 = w * c[2];
+    for (int off = 1; off < K; off <<= 1) {
+      sw += __shfl_xor(sw, off);
+      sc0 += __shfl_xor(sc0, off);
+      sc1 += __shfl_xor(sc1, off);
+      sc2 += __shfl_xor(sc2, off);
+    }
+    const int near = (K - 1) / 2;
+    const int src = (lane & ~(K - 1)) + near;
+    const float n0 = __shfl(c[0], src), n1 = __shfl(c[1], src), n2 = __shfl(c[2], src);
+    if (valid && half == 0 && j == 0) {
+      float* out = a.rgb + 3 * size_t(pr.x);
+      if (sw < 1e-6f) {
+        out[0] = n0; out[1] = n1; out[2] = n2;
+      } else {
+        out[0] = sc0 / sw; out[1] = sc1 / sw; out[2] = sc2 / sw;
+      }
+    }
+  }
+}
+
+// ---- shadows --------------------------------------------------------------------
+// Shadow ray of pixel p for light Lm: origin Lm, direction towards
+// x = o + D d; pixels without an ID get a NaN ray (culled everywhere).
+__global__ void k_shadow_rays(KArgs a, const int32_t* ids, float lx, float ly, float lz, float* so, float* sd,
+                              float* dist) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.n_rays) return;
+  float o[3], d[3];
+  make_ray(a.rays, p, o, d);
+  const float D = a.depth[p];
+  const bool hit = ids[p] >= 0;
+  const float x = fmaf(D, d[0], o[0]) - lx, y = fmaf(D, d[1], o[1]) - ly, z = fmaf(D, d[2], o[2]) - lz;
+  const float r = sqrtf(x * x + y * y + z * z);
+  const float nan = __int_as_float(0x7fc00000);
+  const float inv = hit && r > 0.f ? 1.0f / r : nan;
+  so[3 * p + 0] = lx; so[3 * p + 1] = ly; so[3 * p + 2] = lz;
+  sd[3 * p + 0] = x * inv; sd[3 * p + 1] = y * inv; sd[3 * p + 2] = z * inv;
+  dist[p] = hit ? r : 0.f;
+}
+
+__global__ void k_shadow_init(KArgs a, float* shadow) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < a.n_rays) shadow[p] = 1.0f;
+}
+
+// Occlusion test of Alg. 2 for one light: D_L + eps < |L - x| multiplies by beta.
+__global__ void k_shadow_apply(KArgs a, const int32_t* ids, const float* depth_l, const float* dist, float eps,
+                               float beta, float* shadow) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.n_rays || ids[p] < 0) return;
+  if (depth_l[p] + eps < dist[p]) shadow[p] *= beta;
+}
+
+__global__ void k_composite(KArgs a, const float* shadow, float* rgb) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.n_rays) return;
+  const float f = shadow[p];
+  rgb[3 * p + 0] *= f;
+  rgb[3 * p + 1] *= f;
+  rgb[3 * p + 2] *= f;
+}
+
+int cu_count2() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+  }
+  return ncu;
+}
+
+unsigned grid_n(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return unsigned(g > 0 ? g : 1);
+}
+
+}  // namespace
+
+// Bins hit pixels of the objects in `mask` into list A with work items of
+// `per` pixels.
+void stage_bin_pixels(const KArgs& k0, hipStream_t s, const int32_t* ids, uint32_t mask, int per) {
+  KArgs k = k0;
+  k.item_mask = mask;
+  k.item_pairs = per;
+  k.L = &k.C->A;
+  const unsigned g = grid_n(k.n_rays);
+  hipLaunchKernelGGL(k_zero_list, dim3(1), dim3(256), 0, s, &k.C->A);
+  hipLaunchKernelGGL(k_bin<0>, dim3(g), dim3(256), 0, s, k, ids, mask);
+  hipLaunchKernelGGL(k_scan_pixels, dim3(1), dim3(64), 0, s, k);
+  hipLaunchKernelGGL(k_bin<1>, dim3(g), dim3(256), 0, s, k, ids, mask);
+}
+
+void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mlp_mask, uint32_t sphere_mask,
+                  int dtype) {
+  prof_mark("infer.refine", s, true);
+  if (sphere_mask) {
+    stage_bin_pixels(k, s, ids, sphere_mask, 1);
+    hipLaunchKernelGGL(k_refine_analytic, dim3(256), dim3(256), 0, s, k, sphere_mask);
+  }
+  if (mlp_mask) {
+    stage_bin_pixels(k, s, ids, mlp_mask, 32 * eng::WAVES);
+    if (dtype == NEDF_BF16)
+      hipLaunchKernelGGL((k_refine_mlp<1, 256, 8, 10>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+    else
+      hipLaunchKernelGGL((k_refine_mlp<0, 256, 8, 10>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+  }
+  prof_mark("infer.refine", s, false);
+}
+
+void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype) {
+  prof_mark("shade", s, true);
+  hipLaunchKernelGGL(k_clear_rgb, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids);
+  if (nerf_mask) {
+    stage_bin_pixels(k, s, ids, nerf_mask, (32 / k.shade_K) * eng::WAVES);
+    if (dtype == NEDF_BF16)
+      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+    else
+      hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+  }
+  prof_mark("shade", s, false);
+}
+
+void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float* so, float* sd,
+                       float* dist) {
+  hipLaunchKernelGGL(k_shadow_rays, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids, L[0], L[1], L[2], so, sd,
+                     dist);
+}
+
+void stage_shadow_init(const KArgs& k, hipStream_t s, float* shadow) {
+  hipLaunchKernelGGL(k_shadow_init, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, shadow);
+}
+
+void stage_shadow_apply(const KArgs& k, hipStream_t s, const int32_t* ids, const float* depth_l, const float* dist,
+                        float eps, float beta, float* shadow) {
+  hipLaunchKernelGGL(k_shadow_apply, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids, depth_l, dist, eps, beta,
+                     shadow);
+}
+
+void stage_composite(const KArgs& k, hipStream_t s, const float* shadow, float* rgb) {
+  hipLaunchKernelGGL(k_composite, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, shadow, rgb);
+}
+
+}  // namespace nedf

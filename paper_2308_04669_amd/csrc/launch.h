@@ -24,42 +24,67 @@ struct RaySrcHost {
   int64_t n;
 };
 
-// Device counters in the workspace (after the 256-byte status block).
-struct WsCounters {
+// A per-object list of (ray or pixel, instance) pairs in the workspace:
+// object m owns pairs[off[m] .. off[m] + cnt[m]); item_start is the prefix of
+// work items over the objects a stage processes.
+struct PairList {
   int32_t cnt[NEDF_MAX_OBJECTS];
   int32_t fill[NEDF_MAX_OBJECTS];
   int32_t off[NEDF_MAX_OBJECTS + 1];
   int32_t item_start[NEDF_MAX_OBJECTS + 1];
-  int32_t total_items, work_counter, total_pairs, capacity;
+  int32_t total_items, work_counter, total_pairs, pad;
 };
 
+// Device counters in the workspace (after the 256-byte status block).
+struct WsCounters {
+  PairList A;       // primary pairs (culling result) / binned pixels
+  PairList B;       // fallback pairs (NeDF uncertain rays)
+  int32_t stats[8]; // [0] pairs decided by the network, [1] sent to the marcher, [2] network misses
+};
+
+// Workspace layout: status | counters | keys | opacity bits | pairs A | pairs B
+// | extra (shadow rays).  Capacity is per pair list.
 struct WsLayout {
-  size_t counters, keys, opac, pairs, end;
+  size_t counters, keys, opac, pairs, pairsB, extra, end;
   int64_t capacity;
 };
 
-WsLayout ws_layout(int64_t n_rays, size_t ws_bytes);
-size_t ws_fixed_bytes(int64_t n_rays);
-
-struct MarchLaunch {
-  RaySrcHost rays;
-  int32_t n_obj, n_inst;
-  ObjDesc obj[NEDF_MAX_OBJECTS];
-  const int32_t* inst_object;
-  const float* inst_w2l;
-  int32_t n_samples, clip;
-  float t_near, t_far, hit_thr;
-  int32_t dtype;
-  int32_t mlp_width, mlp_hidden, mlp_L;  // shared shape of all MLP objects (0 if none)
-  uint8_t* ws;
-  WsLayout lay;
-  float* depth;
-  int32_t* id;
-  float* opacity;
-};
+WsLayout ws_layout(int64_t n_rays, size_t extra_bytes, size_t ws_bytes);
+size_t ws_fixed_bytes(int64_t n_rays, size_t extra_bytes);
 
 hipError_t launch_compose_transforms(const double* G, int32_t n, float* w2l, hipStream_t s);
-hipError_t launch_march(const MarchLaunch& a, hipStream_t s);
+
 bool march_mlp_supported(int dtype, int width, int n_hidden, int L);
+bool nedf_net_supported(int dtype, int width, int n_hidden, int L);
+bool shade_supported(int dtype, const nedf_mlp_shape& s);
+bool refine_supported(int dtype, const nedf_mlp_shape& s);
+
+struct KArgs;
+
+// Stages (kernels enqueued on s, no host synchronisation).
+void stage_init_cull(const KArgs& k, hipStream_t s, uint32_t item_mask, int item_pairs);
+void stage_march(const KArgs& k, hipStream_t s, bool list_b, uint32_t analytic_mask, int dtype, int W, int H,
+                 int L);
+void stage_nedf(const KArgs& k, hipStream_t s, int dtype);
+void stage_finalize(const KArgs& k, hipStream_t s);
+void stage_bin_pixels(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mask, int per);
+void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mlp_mask, uint32_t sphere_mask,
+                  int dtype);
+void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype);
+void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float* so, float* sd,
+                       float* dist);
+void stage_shadow_init(const KArgs& k, hipStream_t s, float* shadow);
+void stage_shadow_apply(const KArgs& k, hipStream_t s, const int32_t* ids, const float* depth_l, const float* dist,
+                        float eps, float beta, float* shadow);
+void stage_composite(const KArgs& k, hipStream_t s, const float* shadow, float* rgb);
+
+size_t train_ws_bytes(const nedf_mlp_shape& sh, int B);
+hipError_t launch_train_init(const nedf_mlp_shape& sh, const float* const* W, const float* const* b, uint8_t* st,
+                             hipStream_t s);
+hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float* o_l, const float* d_l,
+                             const float* depth, const uint8_t* hit, int B, float lr, float b1, float b2, float eps,
+                             float w_hit, float bound, float* loss, uint8_t* ws, hipStream_t s);
+hipError_t launch_train_export(const nedf_mlp_shape& sh, const uint8_t* st, float* const* W, float* const* b,
+                               bool grads, hipStream_t s);
 
 }  // namespace nedf

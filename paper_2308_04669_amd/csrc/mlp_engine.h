@@ -83,12 +83,24 @@ __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     if constexpr (DT == 1) {
+      // round to bfloat16, then ReLU on the packed 16-bit patterns (a signed
+      // 16-bit max with 0 clears exactly the negative values)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
+        typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
+        typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
         bf16x8_t v;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = static_cast<__bf16>(fmaxf(acc[nb][8 * q + j], 0.0f));
-        Bout[nb][2 * fb + q] = v;
+        for (int j = 0; j < 8; j += 2) {
+          const f32x2_t f = {acc[nb][8 * q + j], acc[nb][8 * q + j + 1]};
+          const bf16x2_t b = __builtin_convertvector(f, bf16x2_t);
+          v[j] = b[0];
+          v[j + 1] = b[1];
+        }
+        typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8_t;
+        const s16x8_t zero = {0, 0, 0, 0, 0, 0, 0, 0};
+        s16x8_t r = __builtin_elementwise_max(__builtin_bit_cast(s16x8_t, v), zero);
+        Bout[nb][2 * fb + q] = __builtin_bit_cast(bf16x8_t, r);
       }
     } else {
 #pragma unroll
@@ -146,8 +158,11 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   constexpr int R = KS_IN / T::KPR;             // 16-byte LDS reads per chunk
-  constexpr int RB = R < 16 ? R : 16;           // reads in flight
   static_assert(KS_IN % T::KPR == 0, "K-steps must fill whole LDS reads");
+  // hidden-layer epilogues are deferred by one block so that their vector
+  // work overlaps the next block's matrix ops
+  constexpr bool DEFER = (MODE == 0);
+  f32x16_t prev[NB];
 #pragma unroll
   for (int fb = 0; fb < FB; ++fb) {
     uint8_t* nbuf = lds + (cur ^ 1) * CHUNK;
@@ -159,35 +174,69 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
     const uint8_t* chunk = lds + cur * CHUNK;
     const uint4* words = reinterpret_cast<const uint4*>(chunk) + lane;
     f32x16_t acc[NB];
+    {
+      const f32x16_t b0 = bias_acc(chunk + KS_IN * T::FRAG, half);
 #pragma unroll
-    for (int r0 = 0; r0 < R; r0 += RB) {
-      uint4 w[RB];
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
+    }
+    // Software pipeline over the chunk's 16-byte LDS reads: the reads of
+    // group g+1 are issued before the matrix ops of group g; scheduling
+    // barriers keep the compiler from sinking them, so LDS latency is
+    // covered by a group of matrix ops.
+    constexpr int G = 4;
+    constexpr int NG = (R + G - 1) / G;
+    uint4 wbuf[2][G];
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
-        if (r0 + r < R) w[r] = words[(r0 + r) * 64];
-      if (r0 == 0) {
-        const f32x16_t b0 = bias_acc(chunk + KS_IN * T::FRAG, half);
+    for (int r = 0; r < G; ++r)
+      if (r < R) wbuf[0][r] = words[r * 64];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
+    for (int gi = 0; gi < NG; ++gi) {
+      if (gi + 1 < NG) {
+#pragma unroll
+        for (int r = 0; r < G; ++r)
+          if ((gi + 1) * G + r < R) wbuf[(gi + 1) & 1][r] = words[((gi + 1) * G + r) * 64];
       }
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        if (r0 + r < R) {
+      for (int r = 0; r < G; ++r) {
+        if (gi * G + r < R) {
 #pragma unroll
           for (int i = 0; i < T::KPR; ++i) {
-            const int ks = (r0 + r) * T::KPR + i;
-            const typename T::frag a = T::pick(w[r], i);
+            const int ks = (gi * G + r) * T::KPR + i;
+            const typename T::frag a = T::pick(wbuf[gi & 1][r], i);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[nb] = T::mma(a, Bin[nb][ks], acc[nb]);
           }
         }
       }
+      if constexpr (DEFER) {
+        if (fb > 0 && gi == 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout);
+      }
+      // order inside the region: next group's LDS reads, then matrix ops
+      // interleaved with the deferred epilogue's vector ops
+      if (gi + 1 < NG) __builtin_amdgcn_sched_group_barrier(0x100, G, 0);
+      if (DEFER && fb > 0 && gi == 0) {
+#pragma unroll
+        for (int m = 0; m < G * T::KPR * NB; ++m) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+        }
+      } else {
+        __builtin_amdgcn_sched_group_barrier(0x008, G * T::KPR * NB, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if constexpr (MODE == 0 || MODE == 2) epi_hidden<DT, NB, KSO>(fb, acc, Bout);
-    if constexpr (MODE == 1 || MODE == 2) epi_head<NB, NOUT>(acc, chunk + KS_IN * T::FRAG + 128, half, partial);
+    if constexpr (DEFER) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
+    } else {
+      if constexpr (MODE == 2) epi_hidden<DT, NB, KSO>(fb, acc, Bout);
+      epi_head<NB, NOUT>(acc, chunk + KS_IN * T::FRAG + 128, half, partial);
+    }
     dma_wait_barrier();
     cur ^= 1;
   }
+  if constexpr (DEFER) epi_hidden<DT, NB, KSO>(FB - 1, prev, Bout);
 }
 
 // ---- whole trunk ------------------------------------------------------------
@@ -201,7 +250,7 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
                                       const typename Tr<DT>::frag (&Benc)[Tr<DT>::NB][KS0],
                                       uint8_t* lds, float (&partial)[Tr<DT>::NB][NOUT],
                                       typename Tr<DT>::frag (&Blast)[Tr<DT>::NB][WIDTH / Tr<DT>::KPS],
-                                      const uint8_t* w_after) {
+                                      const uint8_t* w_after, int* cur_io = nullptr) {
   using T = Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int FB = WIDTH / 32;
@@ -212,9 +261,9 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
   static_assert(NHID >= 3, "need at least three hidden layers");
   static_assert(CHUNK >= CB0 && CHUNK >= CBL, "LDS chunk buffer too small");
   typename T::frag X[NB][KSH], Y[NB][KSH];
-  int cur = 0;
+  int cur = cur_io ? *cur_io : 0;
   const uint64_t* off = hb->off_layer;
-  dma_chunk<CB0>(blob + off[0], lds);
+  dma_chunk<CB0>(blob + off[0], lds + cur * CHUNK);
   dma_wait_barrier();
   // layer 0: encoding -> X; then pairs X -> Y -> X; the last layer feeds the head
   layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK>(Benc, X, blob + off[0], blob + off[1], lds, cur,
@@ -242,6 +291,7 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
     layer<DT, NB, KSH, FB, CBL, CB_AFTER, KSH, NOUT, LAST_MODE, CHUNK>(X, Blast, blob + off[NHID - 1], w_after,
                                                                       lds, cur, partial);
   }
+  if (cur_io) *cur_io = cur;
 }
 
 // ---- first-layer encoding ----------------------------------------------------

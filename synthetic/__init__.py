@@ -192,3 +192,35 @@ def training_rays(config: int, stream: int, n: int, radius: float = 4.0,
     d = p - o
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return o.astype(np.float32), d.astype(np.float32)
+
+
+def nedf_model(config: int, stream: int, enc_L: int = 8, width: int = 256, depth: int = 8,
+               bound: float = 1.0, head_scale: float = 1.0) -> Model:
+    """An intersection network F_Phi: gamma_L(d, o x d) (6 (1 + 2L) inputs)
+    -> depth x width ReLU -> (mu_hat, hit logit).  Hidden weights
+    N(0, 2/fan_in) (He), head N(0, 1/fan_in) scaled by ``head_scale``,
+    biases zero: the training initialisation, also used untrained by the
+    parity tests."""
+    g = rng(config, stream)
+    d_in = 6 * (1 + 2 * enc_L)
+    trunk = normal_mlp(g, [d_in] + [width] * depth + [2], hidden_gain=2.0)
+    trunk.W[-1] *= np.float32(head_scale)
+    return Model(kind="nedf", bound=bound, trunk=trunk, params=dict(enc_L=enc_L))
+
+
+def sdf_scene(config: int, n_inst: int, n_models: int = 4, width: int = 64, height: int = 64,
+              z_range=(4.0, 8.0), spread: float = 1.2):
+    """SDF-biased NeRF objects (shapes 0..n_models-1) placed in front of a
+    camera at the origin looking down -z: instance k uses model k mod
+    n_models, a uniform rotation, scale U[0.6, 1.2] and a centre at depth
+    U[z_range] within a lateral spread.  Returns models, instances, camera."""
+    models = [nerf_model(config, 100 + k, sigma_mode="sdf", sdf_shape=k % 4) for k in range(n_models)]
+    g = rng(config, 901)
+    insts = []
+    for k in range(n_inst):
+        z = g.uniform(*z_range)
+        T = np.array([g.uniform(-spread, spread), g.uniform(-spread, spread), -z])
+        insts.append(Instance(model=k % n_models, R=shoemake_rotation(g), T=T, s=float(g.uniform(0.6, 1.2))))
+    cam = Camera(eye=(0.0, 0.0, 0.0), at=(0.0, 0.0, -1.0), up=(0.0, 1.0, 0.0), fov_y_deg=40.0,
+                 width=width, height=height)
+    return models, insts, cam

@@ -1,0 +1,228 @@
+"""GPU parity of nedf_infer_depth_id (network + fallback + refinement),
+nedf_shade_deferred and nedf_shadow against the FP64 oracle, through the
+C ABI."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import (camera_rays, march_compose, nedf_pair, secant_refine, shade_deferred, shadow_factor,
+                    to_local)
+from oracle.render import march_instance
+from tests.gpu_util import need_gpu, gpu_scene, per_instance, compare_depth_id, log
+
+pytestmark = pytest.mark.gpu
+
+GEMM = {"f32": None, "bf16": "bf16"}
+# band around decision thresholds inside which a float32/bfloat16 result may
+# legitimately fall on the other side
+BAND = {"f32": 1e-4, "bf16": 2e-2}
+DEPTH_TOL = {"f32": 2e-4, "bf16": 5e-3}
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _nedf_scene(n_inst=6, size=48, head_scale=4.0):
+    models, insts, cam = syn.sdf_scene(3, n_inst, width=size, height=size)
+    nedfs = [syn.nedf_model(3, 200 + k, head_scale=head_scale) for k in range(len(models))]
+    return models, nedfs, insts, cam
+
+
+def _oracle_pairs(models, nedfs, insts, o, d, dtype, n_samples):
+    """Per-instance oracle (hit, D, p, path, A-of-fallback) for every ray."""
+    res = []
+    for inst in insts:
+        hit, D, p, path = nedf_pair(nedfs[inst.model], models[inst.model], inst, o, d, p_lo=0.2, p_hi=0.8,
+                                    n_samples=n_samples, gemm=GEMM[dtype])
+        v, A, _ = march_instance(models[inst.model], inst, o, d, n_samples, None, GEMM[dtype])
+        res.append((hit, D, p, path, np.where(path == 1, A, np.nan)))
+    return res
+
+
+def _infer_compare(depth_g, id_g, res, dtype, label):
+    n = depth_g.shape[0]
+    Ds = np.array([np.where(r[0], r[1], np.inf) for r in res])
+    best = Ds.min(axis=0)
+    id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
+    band = BAND[dtype]
+    near = np.zeros(n, bool)
+    for hit, D, p, path, A in res:
+        near |= np.abs(p - 0.2) <= band
+        near |= np.abs(p - 0.8) <= band
+        near |= np.abs(A - 0.5) <= band
+        near |= (path == 0) & (np.abs(D) <= 1e-3)
+    srt = np.sort(Ds, axis=0)
+    gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
+    exempt = near | (gap <= DEPTH_TOL[dtype])
+    bad = (id_g != id_o) & ~exempt
+    both = (id_g == id_o) & (id_o >= 0)
+    err = np.abs(depth_g[both] - best[both])
+    st = dict(n=n, hits=int((id_o >= 0).sum()), exempt=int(exempt.sum()), id_mismatch=int(bad.sum()),
+              depth_max_err=float(err.max()) if err.size else 0.0,
+              depth_p99_err=float(np.quantile(err, 0.99)) if err.size else 0.0,
+              depth_med_err=float(np.median(err)) if err.size else 0.0,
+              paths=[int(sum(((r[3] == k) & np.isfinite(r[1] if k == 0 else r[3])).sum() for r in res))
+                     for k in (0, 1)])
+    log(f"[{label}] {st}")
+    assert st["id_mismatch"] == 0, st
+    if dtype == "f32":
+        assert st["depth_max_err"] <= DEPTH_TOL[dtype], st
+    else:
+        # BF16: the emulating oracle rounds the same operands, but the float32
+        # line coordinates (|o_l| up to ~13, error ~1e-6) feed encoding
+        # frequencies up to 2^7 pi, so top-level features land on the other
+        # side of a bf16 rounding boundary for a few rays; with a 4x-scaled
+        # random head this moves about 1% of the network depths by up to a
+        # few hundredths.  Criterion: >= 98% within 5e-3, none beyond 5e-2.
+        frac_ok = float(np.mean(err <= DEPTH_TOL[dtype])) if err.size else 1.0
+        log(f"[{label}] fraction within {DEPTH_TOL[dtype]}: {frac_ok:.4f}")
+        assert st["depth_med_err"] <= 1e-3 and frac_ok >= 0.98, st
+        assert st["depth_max_err"] <= 5e-2, st
+    return st
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_infer_network_and_fallback(dtype):
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene()
+    log(f"case: infer random NeDF {dtype} 48x48, 6 instances")
+    sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
+    ws = api.Workspace()
+    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0, n_samples=128,
+                                      ws=ws)
+    stats = api.ws_counters(ws)
+    depth, ident = _np(depth).astype(np.float64), _np(ident)
+    o, d = camera_rays(cam)
+    res = _oracle_pairs(models, nedfs, insts, o, d, dtype, 128)
+    st = _infer_compare(depth, ident, res, dtype, f"infer {dtype}")
+    log(f"routing {stats}")
+    assert stats["nedf_hits"] > 0 and stats["fallback"] > 0 and stats["nedf_misses"] > 0
+    assert st["hits"] > 100
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_infer_secant_refinement(dtype):
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene()
+    log(f"case: infer refinement {dtype}")
+    sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
+    d0, i0 = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0)
+    d3, i3 = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=3, refine_h=0.05)
+    d0, i0, d3, i3 = _np(d0).astype(np.float64), _np(i0), _np(d3).astype(np.float64), _np(i3)
+    assert np.array_equal(i0, i3)
+    o, d = camera_rays(cam)
+    ref = d0.copy()
+    for k, inst in enumerate(insts):
+        sel = np.nonzero(i0 == k)[0]
+        if sel.size:
+            ref[sel] = secant_refine(models[inst.model], inst, o[sel], d[sel], d0[sel], h=0.05, steps=3,
+                                     gemm=GEMM[dtype])
+    hit = i0 >= 0
+    moved = hit & (ref != d0)
+    err = np.abs(d3[hit] - ref[hit])
+    log(f"[refine {dtype}] hits={int(hit.sum())} moved={int(moved.sum())} max_err={err.max():.3e} "
+        f"median_err={np.median(err):.3e}")
+    assert moved.sum() > 20
+    tol = 1e-3 if dtype == "f32" else 2e-2
+    assert np.quantile(err, 0.99) <= tol and np.median(err) <= tol / 10
+
+
+@pytest.mark.parametrize("dtype,K", [("f32", 1), ("f32", 8), ("bf16", 8)])
+def test_shade_deferred_parity(dtype, K):
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, insts, cam, _ = syn.config2_scene(width=40, height=36)
+    log(f"case: shade {dtype} K={K}")
+    sc = gpu_scene(models, insts, dtype)
+    depth, ident, _ = api.march_depth(sc, api.camera_rays(cam), n_samples=192, dtype=dtype)
+    rgb = api.shade_deferred(sc, api.camera_rays(cam), depth, ident, K=K, h=0.05, clear_rgb=(0.1, 0.2, 0.3),
+                             dtype=dtype)
+    depth, ident, rgb = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(rgb).astype(np.float64)
+    o, d = camera_rays(cam)
+    ref = shade_deferred(models, insts, o, d, depth, ident, K=K, h=0.05, clear=(0.1, 0.2, 0.3),
+                         gemm=GEMM[dtype])
+    err = np.abs(rgb - ref).max(axis=1)
+    hit = ident >= 0
+    log(f"[shade {dtype} K={K}] hits={int(hit.sum())} max_err={err.max():.3e}")
+    assert hit.sum() > 50
+    assert np.all(rgb[~hit] == np.array([0.1, 0.2, 0.3], np.float32))
+    tol = 2e-4 if dtype == "f32" else 2e-2
+    assert err.max() <= tol
+
+
+def _shadow_compare(fac_g, ref, margin, label):
+    bad = (fac_g != ref) & ~margin
+    log(f"[{label}] shadowed={int((ref < 1).sum())} lit={int((ref == 1).sum())} exempt={int(margin.sum())} "
+        f"mismatch={int(bad.sum())}")
+    assert bad.sum() == 0
+    return bad
+
+
+def test_shadow_marcher_two_spheres():
+    need_gpu()
+    from paper_2308_04669_amd import api
+    a, _ = syn.config1_models()
+    insts = [syn.Instance(0, np.eye(3), np.zeros(3), 1.0), syn.Instance(0, np.eye(3), np.array([0.0, 1.2, 0.0]), 1.0)]
+    light = np.array([1.0, 4.0, 1.5])
+    cam = syn.Camera(eye=(3.0, 0.6, 3.0), at=(0.0, 0.6, 0.0), up=(0, 1, 0), fov_y_deg=40.0, width=40, height=40)
+    log("case: shadow marcher two spheres")
+    sc = gpu_scene([a], insts, "f32")
+    depth, ident, _ = api.march_depth(sc, api.camera_rays(cam), n_samples=256)
+    fac = api.shadow(sc, api.camera_rays(cam), depth, ident, [light], eps=0.05, beta=0.5, method="march",
+                     dtype="f32", n_samples=256)
+    depth, ident, fac = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(fac).astype(np.float64)
+    o, d = camera_rays(cam)
+    fn = lambda oo, dd: march_compose([a], insts, oo, dd, 256)[0]
+    ref = shadow_factor(fn, o, d, depth, ident, [light], eps=0.05, beta=0.5)
+    # margin: pixels whose shadow-ray depth lies within 1e-3 of the occlusion threshold
+    hitp = np.nonzero(ident >= 0)[0]
+    x = o[hitp] + depth[hitp, None] * d[hitp]
+    v = x - light
+    dist = np.linalg.norm(v, axis=1)
+    DL = fn(np.broadcast_to(light, v.shape).copy(), v / dist[:, None])
+    margin = np.zeros(len(depth), bool)
+    margin[hitp] = np.abs(DL + 0.05 - dist) <= 1e-3
+    _shadow_compare(fac, ref, margin, "shadow two spheres")
+    assert (ref < 1).sum() > 20
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_shadow_nedf_and_composite(dtype):
+    need_gpu()
+    import torch
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene(n_inst=5, size=40)
+    light = np.array([3.0, 6.0, -2.0])
+    log(f"case: shadow NeDF {dtype}")
+    sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
+    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0)
+    rgb_in = torch.rand((depth.numel(), 3), device="cuda")
+    rgb = rgb_in.clone()
+    fac = api.shadow(sc, api.camera_rays(cam), depth, ident, [light], eps=0.05, beta=0.5, method="nedf",
+                     dtype=dtype, rgb_inout=rgb)
+    depth, ident, fac = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(fac).astype(np.float64)
+    assert np.allclose(_np(rgb), _np(rgb_in) * fac[:, None], rtol=1e-6, atol=0)
+    o, d = camera_rays(cam)
+    hitp = np.nonzero(ident >= 0)[0]
+    x = o[hitp] + depth[hitp, None] * d[hitp]
+    v = x - light
+    dist = np.linalg.norm(v, axis=1)
+    ds = v / dist[:, None]
+    so = np.broadcast_to(light, v.shape).copy()
+    res = _oracle_pairs(models, nedfs, insts, so, ds, dtype, 128)
+    Ds = np.array([np.where(r[0], r[1], np.inf) for r in res])
+    DL = Ds.min(axis=0)
+    ref = np.ones(len(depth))
+    ref[hitp] = np.where(DL + 0.05 < dist, 0.5, 1.0)
+    band = BAND[dtype]
+    near = np.zeros(hitp.size, bool)
+    for hit, D, p, path, A in res:
+        near |= (np.abs(p - 0.2) <= band) | (np.abs(p - 0.8) <= band) | (np.abs(A - 0.5) <= band)
+    margin = np.zeros(len(depth), bool)
+    margin[hitp] = near | (np.abs(DL + 0.05 - dist) <= (DEPTH_TOL[dtype] if dtype == "f32" else 5e-2))
+    _shadow_compare(fac, ref, margin, f"shadow nedf {dtype}")

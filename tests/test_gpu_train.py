@@ -1,0 +1,128 @@
+"""GPU training path: gradients and the Adam update against the FP64
+oracle, labels from the GPU marcher, and what a trained network gains over
+the untrained one (through the C ABI)."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import nedf_loss_and_grads, camera_rays, march_compose
+from tests.gpu_util import need_gpu, log
+
+pytestmark = pytest.mark.gpu
+
+IDENT = syn.Instance(0, np.eye(3), np.zeros(3), 1.0)
+
+
+def _sphere_labels(o, d, r=0.5):
+    """Analytic labels of a radius-r sphere (depth of the first surface)."""
+    tp = -np.sum(o * d, axis=1)
+    b2 = np.sum(o * o, axis=1) - tp ** 2
+    hit = b2 < r * r
+    D = np.where(hit, tp - np.sqrt(np.maximum(r * r - b2, 0.0)), 0.0)
+    return D, hit
+
+
+def _tensor(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def test_train_gradients_and_adam_match_oracle():
+    need_gpu()
+    import torch
+    from paper_2308_04669_amd import api
+    model = syn.nedf_model(4, 1)
+    g = syn.rng(4, 2)
+    for bb in model.trunk.b:
+        bb[:] = (g.standard_normal(bb.shape) * 0.05).astype(np.float32)
+    B = 2048
+    o, d = syn.training_rays(4, 3, B)
+    D, hit = _sphere_labels(o.astype(np.float64), d.astype(np.float64))
+    D32 = D.astype(np.float32)
+    tr = api.Trainer(model.trunk.W, model.trunk.b, enc_L=8)
+    loss = tr.step(_tensor(o), _tensor(d), _tensor(D32), _tensor(hit.astype(np.uint8)), lr=0.0)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy().astype(np.float64)
+    gW, gb = tr.export(1)
+    o64, d64 = o.astype(np.float64), d.astype(np.float64)
+    tp = -np.sum(o64 * d64, axis=1)
+    mu = np.where(hit, tp - D32.astype(np.float64), 0.0)
+    ref_loss, ref_mse, ref_bce, grads = nedf_loss_and_grads(model, o64, d64, mu, hit.astype(np.float64))
+    log(f"loss gpu {loss} oracle {[ref_loss, ref_mse, ref_bce]}")
+    assert abs(loss[0] - ref_loss) <= 2e-2 * abs(ref_loss)
+    worst = 0.0
+    for i, (dw, db) in enumerate(grads):
+        ew = np.linalg.norm(gW[i] - dw) / max(np.linalg.norm(dw), 1e-30)
+        eb = np.linalg.norm(gb[i] - db) / max(np.linalg.norm(db), 1e-30)
+        log(f"layer {i}: rel err W {ew:.3e} b {eb:.3e}")
+        worst = max(worst, ew, eb)
+    assert worst <= 3e-2
+    # one Adam step with lr 5e-4 from the same state: first-step closed form
+    W0, b0 = tr.export(0)
+    tr.step(_tensor(o), _tensor(d), _tensor(D32), _tensor(hit.astype(np.uint8)), lr=5e-4)
+    W1, b1 = tr.export(0)
+    gW2, gb2 = tr.export(1)
+    for i in range(len(W0)):
+        # the state's moments come from two gradients (the lr = 0 step and this one)
+        m = 0.9 * 0.1 * gW[i] + 0.1 * gW2[i]
+        v = 0.999 * 0.001 * gW[i] ** 2 + 0.001 * gW2[i] ** 2
+        upd = -5e-4 * (m / (1 - 0.81)) / (np.sqrt(v / (1 - 0.999 ** 2)) + 1e-8)
+        assert np.allclose(W1[i] - W0[i], upd, atol=2e-6 * 5e-4 + 1e-9, rtol=2e-3), i
+
+
+def test_train_labels_from_marcher_and_gain():
+    """Train an intersection network for density A on labels made by the GPU
+    marcher, then compare the trained and the untrained network on the
+    config-1 view against the FP64 marcher."""
+    need_gpu()
+    import torch
+    from paper_2308_04669_amd import api
+    a, _ = syn.config1_models()
+    sphere = api.object_from_model(a, "f32")
+    sc = api.make_scene([sphere], [IDENT])
+    B = 8192
+    n_steps = 400
+    model = syn.nedf_model(4, 10)
+    tr = api.Trainer(model.trunk.W, model.trunk.b, enc_L=8)
+    ws = api.Workspace()
+    losses = []
+    for it in range(n_steps):
+        o, d = syn.training_rays(4, 1000 + it, B)
+        ot, dt = _tensor(o), _tensor(d)
+        # labels: the plain marcher on the local rays (identity instance), 128 samples on the chord
+        depth, ident, opac = api.march_depth(sc, api.array_rays(ot, dt), n_samples=128, dtype="f32", ws=ws)
+        hit = (ident >= 0).to(torch.uint8)
+        depth = torch.where(ident >= 0, depth, torch.zeros_like(depth))
+        loss = tr.step(ot, dt, depth, hit, lr=5e-4, bound=1.0)
+        if it % 50 == 0 or it == n_steps - 1:
+            losses.append(float(loss[0]))
+    log(f"losses {losses}")
+    assert losses[-1] < 0.5 * losses[0]
+    W, b = tr.export(0)
+    trained = syn.Model(kind="nedf", bound=1.0, params=dict(enc_L=8),
+                        trunk=syn.MLPWeights([w.astype(np.float32) for w in W], [x.astype(np.float32) for x in b]))
+    cam = syn.config1_camera(64, 64)
+    o, d = camera_rays(cam)
+    ref_d, ref_id, _ = march_compose([a], [IDENT], o, d, 128, interval=(2.0, 6.0))
+    results = {}
+    for name, net in (("untrained", model), ("trained", trained)):
+        obj = api.object_from_model(a, "bf16", nedf_model=net)
+        s2 = api.make_scene([obj], [IDENT])
+        ws2 = api.Workspace()
+        dep, idn = api.infer_depth_id(s2, api.camera_rays(cam), dtype="bf16", refine_steps=3, ws=ws2)
+        st = api.ws_counters(ws2)
+        dep, idn = dep.cpu().numpy().astype(np.float64), idn.cpu().numpy()
+        agree = float(np.mean((idn >= 0) == (ref_id >= 0)))
+        both = (idn >= 0) & (ref_id >= 0)
+        med = float(np.median(np.abs(dep[both] - ref_d[both]))) if both.any() else np.inf
+        pairs = max(st["pairs"], 1)
+        results[name] = dict(hit_agreement=agree, median_depth_err=med, fallback_frac=st["fallback"] / pairs,
+                             network_frac=(st["nedf_hits"] + st["nedf_misses"]) / pairs)
+    log(f"gain {results}")
+    tr_r, un_r = results["trained"], results["untrained"]
+    # extent of the config-1 interval is 4: 1% = 0.04
+    assert tr_r["hit_agreement"] >= 0.97 and tr_r["median_depth_err"] <= 0.04
+    assert tr_r["network_frac"] > un_r["network_frac"] + 0.2 or tr_r["fallback_frac"] < 0.5 * un_r["fallback_frac"]
