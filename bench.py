@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--f32-steps", type=int, default=2)
     p.add_argument("--cpu-pixels", type=int, default=6000)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="after the timed region, copy a tensor of this size (device to device) so that "
+                        "hardware byte counters can be scaled against a copy of known size")
     return p.parse_args()
 
 
@@ -150,6 +153,12 @@ def main():
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
     }
     line.update(extra)
+    if args.copy_mib > 0:
+        x = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = args.copy_mib << 20
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_pixels, args.samples, args.size)
     print(json.dumps(line), flush=True)

@@ -156,7 +156,8 @@ typedef struct nedf_march_opts {
 
 /* Options of the NeDF path (Eq. 1, 2, 7 with marcher fallback and refinement). */
 typedef struct nedf_infer_opts {
-  int32_t dtype;            /* precision of the intersection networks and of fallback/refinement fields */
+  int32_t dtype;            /* precision of fallback/refinement density fields; the intersection
+                               networks run in their blob's dtype (this dtype or NEDF_FP8) */
   float p_lo, p_hi;         /* hit probability band sent to the marcher (inclusive), default 0.2 / 0.8 */
   int32_t refine_steps;     /* secant updates on the winning pixel (0 = off), default 3 */
   float refine_h;           /* seed offset in world units, default 0.05 */
@@ -354,6 +355,24 @@ int32_t nedf_train_step(const nedf_mlp_shape* shape, void* state, const float* o
  * (which = 1) of a state into DEVICE arrays W[i] [out][in] / b[i]. */
 int32_t nedf_train_export(const nedf_mlp_shape* shape, const void* state, int32_t which, float* const* W,
                           float* const* b, nedf_stream_t stream);
+
+/* ------------------------------------------------------------- FP8 */
+
+/* Device workspace bytes of nedf_fp8_calibrate for a batch of B rays. */
+size_t nedf_fp8_calibrate_workspace_size(const nedf_mlp_shape* shape, int32_t B);
+
+/*
+ * Per-layer E4M3 scales of a network (width 256, n_out 2): a bfloat16 forward
+ * pass over B calibration rays (o_l, d_l device float32 [B][3], B a multiple
+ * of 64) records the largest |activation| entering every hidden layer; the
+ * weight scale is the largest |weight| of that layer.  scales (device float32
+ * [2 n_hidden]) receives {w_scale, a_scale} = amax / 448 per hidden layer,
+ * the layout nedf_pack_mlp expects for NEDF_FP8 (after a copy to the host).
+ * W[i] / b[i] are DEVICE float32 layers as for nedf_train_init.
+ */
+int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, const float* const* b,
+                           const float* o_l, const float* d_l, int32_t B, float* scales, void* ws,
+                           size_t ws_bytes, nedf_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -23,14 +23,14 @@ forward pass itself is pinned on hand-set weights).
 from .geometry import (camera_rays, to_local, pluecker, encode, sphere_chord,
                        inverse_transform)
 from .rounding import round_bf16, round_e4m3
-from .fields import mlp_forward, density, nerf_eval, nedf_eval, sdf, surface_value
+from .fields import mlp_forward, density, nerf_eval, nedf_eval, sdf, surface_value, fp8_calibrate
 from .render import (march, march_compose, nedf_pair, nedf_compose, secant_refine,
                      shade_deferred, shadow_factor, composite)
 from .train import nedf_loss_and_grads, adam_step
 
 __all__ = [
     "camera_rays", "to_local", "pluecker", "encode", "sphere_chord", "inverse_transform",
-    "round_bf16", "round_e4m3", "mlp_forward", "density", "nerf_eval", "nedf_eval", "sdf",
+    "round_bf16", "round_e4m3", "fp8_calibrate", "mlp_forward", "density", "nerf_eval", "nedf_eval", "sdf",
     "march", "march_compose", "nedf_pair", "nedf_compose", "secant_refine",
     "shade_deferred", "shadow_factor", "composite", "nedf_loss_and_grads", "adam_step",
 ]

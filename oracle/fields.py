@@ -167,3 +167,19 @@ def nedf_eval(model, o_l, d_l, gemm=None, scales=None):
     pl, _ = pluecker(np.asarray(o_l, F64), np.asarray(d_l, F64))
     out = mlp_forward(encode(pl, model.params["enc_L"]), model.trunk, gemm=gemm, scales=scales)
     return out[..., 0], out[..., 1]
+
+
+def fp8_calibrate(model, o_l, d_l):
+    """Per-hidden-layer E4M3 scales of an intersection network from a
+    calibration batch: w_scale = max|W| / 448 and a_scale = max|layer input|
+    / 448 over the batch (float64 forward; 448 is the largest finite E4M3
+    value).  Returns an array [n_hidden, 2] of (w_scale, a_scale)."""
+    pl, _ = pluecker(np.asarray(o_l, F64), np.asarray(d_l, F64))
+    h = encode(pl, model.params["enc_L"])
+    n = len(model.trunk.W)
+    out = []
+    for i in range(n - 1):
+        W = np.asarray(model.trunk.W[i], F64)
+        out.append((np.abs(W).max() / 448.0, np.abs(h).max() / 448.0))
+        h = np.maximum(h @ W.T + np.asarray(model.trunk.b[i], F64), 0.0)
+    return np.array(out)

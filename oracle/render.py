@@ -88,7 +88,7 @@ def march_compose(models, insts, o, d, n_samples, interval=None, hit_thr=0.5, ge
 
 
 def nedf_pair(nedf_model, dens_model, inst, o, d, p_lo=0.2, p_hi=0.8, n_samples=128,
-              hit_thr=0.5, gemm=None, fallback=True, net_fn=None):
+              hit_thr=0.5, gemm=None, fallback=True, net_fn=None, net_scales=None):
     """NeDF depth of one instance for world rays (Eq. 1, 2, 7), with the
     plain marcher as fallback for uncertain rays.
 
@@ -101,7 +101,8 @@ def nedf_pair(nedf_model, dens_model, inst, o, d, p_lo=0.2, p_hi=0.8, n_samples=
     marcher decides.  ``fallback=False`` classifies by p >= 0.5 instead.
 
     ``net_fn(o_l, d_l) -> (mu_hat, z)`` replaces the network (used to plug
-    in analytic stand-ins).  Returns (hit, D, p, path) with path 0 = network,
+    in analytic stand-ins); ``net_scales`` evaluates the network with E4M3
+    inputs at those per-layer (w_scale, a_scale) pairs.  Returns (hit, D, p, path) with path 0 = network,
     1 = marcher, 2 = no network evaluation needed (miss)."""
     o_l, d_l = to_local(inst, o, d)
     l = nedf_model.bound
@@ -117,7 +118,7 @@ def nedf_pair(nedf_model, dens_model, inst, o, d, p_lo=0.2, p_hi=0.8, n_samples=
     idx = np.nonzero(run)[0]
     if idx.size:
         if net_fn is None:
-            mu_hat, z = nedf_eval(nedf_model, o_l[idx], d_l[idx], gemm=gemm)
+            mu_hat, z = nedf_eval(nedf_model, o_l[idx], d_l[idx], gemm=gemm, scales=net_scales)
         else:
             mu_hat, z = net_fn(o_l[idx], d_l[idx])
         pi = sigmoid(z)

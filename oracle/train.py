@@ -17,26 +17,34 @@ import numpy as np
 
 from .geometry import encode, pluecker
 from .fields import softplus, sigmoid
+from .rounding import round_bf16
 
 F64 = np.float64
 
 
-def nedf_loss_and_grads(model, o_l, d_l, mu_label, hit_label, w_hit=0.1):
+def nedf_loss_and_grads(model, o_l, d_l, mu_label, hit_label, w_hit=0.1, gemm=None):
     """Returns (loss, mse_term, bce_term, grads) with grads a list of
-    (dW [out,in], db [out]) per layer, all float64."""
+    (dW [out,in], db [out]) per layer, all float64.
+
+    ``gemm="bf16"`` emulates a bfloat16 matrix-core implementation: the
+    encoded input, the hidden weights, every hidden activation and every
+    back-propagated hidden-layer gradient are rounded to bfloat16 where they
+    enter a matrix product (float64 accumulation); the head stays float64."""
+    rnd = round_bf16 if gemm == "bf16" else (lambda a: a)
     pl, _ = pluecker(np.asarray(o_l, F64), np.asarray(d_l, F64))
-    x = encode(pl, model.params["enc_L"])
+    x = rnd(encode(pl, model.params["enc_L"]))
     Ws = [np.asarray(w, F64) for w in model.trunk.W]
     bs = [np.asarray(b, F64) for b in model.trunk.b]
     n = len(Ws)
+    Wm = [rnd(w) if i < n - 1 else w for i, w in enumerate(Ws)]   # matrix-core copies
     B = x.shape[0]
     acts = [x]
     pre = []
     h = x
     for i in range(n):
-        z = h @ Ws[i].T + bs[i]
+        z = h @ Wm[i].T + bs[i]
         pre.append(z)
-        h = np.maximum(z, 0.0) if i < n - 1 else z
+        h = rnd(np.maximum(z, 0.0)) if i < n - 1 else z
         acts.append(h)
     out = acts[-1]
     mu_hat, z = out[:, 0], out[:, 1]
@@ -51,9 +59,9 @@ def nedf_loss_and_grads(model, o_l, d_l, mu_label, hit_label, w_hit=0.1):
     grads = [None] * n
     for i in range(n - 1, -1, -1):
         if i < n - 1:
-            g = g * (pre[i] > 0)
+            g = rnd(g * (acts[i + 1] > 0))
         grads[i] = (g.T @ acts[i], g.sum(axis=0))
-        g = g @ Ws[i]
+        g = g @ Wm[i]
     return loss, mse, bce, grads
 
 

@@ -104,6 +104,10 @@ SIGNATURES = [
                                     C.c_size_t, C.c_void_p]),
     ("nedf_train_export", C.c_int32, [C.POINTER(MlpShape), C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_void_p), C.c_void_p]),
+    ("nedf_fp8_calibrate_workspace_size", C.c_size_t, [C.POINTER(MlpShape), C.c_int32]),
+    ("nedf_fp8_calibrate", C.c_int32, [C.POINTER(MlpShape), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                       C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                       C.c_void_p]),
     ("nedf_march_depth", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(MarchOpts), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
 ]

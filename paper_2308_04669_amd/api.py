@@ -99,7 +99,8 @@ class ObjectSpec:
         return o
 
 
-def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None) -> ObjectSpec:
+def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None, nedf_dtype: str | None = None,
+                      nedf_scales=None) -> ObjectSpec:
     """Build an ObjectSpec from a model description with the attributes
     ``kind``, ``bound``, ``params``, ``trunk`` (W, b lists) and ``rgb``."""
     p = model.params
@@ -110,7 +111,7 @@ def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None) 
         else:
             spec = ObjectSpec("slab", model.bound, (p["sigma0"], p["z0"], p["z1"]) + colour)
         if nedf_model is not None:
-            spec.nedf = _pack_nedf(nedf_model, dtype, device)
+            spec.nedf = _pack_nedf(nedf_model, nedf_dtype or dtype, device, nedf_scales)
         return spec
     if model.kind in ("mlp", "nerf"):
         tr = model.trunk
@@ -131,15 +132,36 @@ def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None) 
             param = ()
         spec = ObjectSpec("mlp", model.bound, param, mode, dens)
         if nedf_model is not None:
-            spec.nedf = _pack_nedf(nedf_model, dtype, device)
+            spec.nedf = _pack_nedf(nedf_model, nedf_dtype or dtype, device, nedf_scales)
         return spec
     raise ValueError(model.kind)
 
 
-def _pack_nedf(nedf_model, dtype, device) -> PackedMLP:
+def _pack_nedf(nedf_model, dtype, device, fp8_scales=None) -> PackedMLP:
     t = nedf_model.trunk
     nshape = mlp_shape("pluecker", nedf_model.params["enc_L"], t.W[0].shape[0], len(t.W) - 1, 2)
-    return pack_mlp(t.W, t.b, nshape, dtype, device)
+    return pack_mlp(t.W, t.b, nshape, dtype, device, fp8_scales=fp8_scales)
+
+
+def fp8_calibrate(W, b, o_l: torch.Tensor, d_l: torch.Tensor, enc_L: int = 8, in_kind: str = "pluecker"):
+    """Per-hidden-layer E4M3 scales {w_scale, a_scale} from a GPU calibration
+    pass over the rays (o_l, d_l) (float32 [B, 3], B a multiple of 64)."""
+    lib = A.load()
+    dev = o_l.device
+    shape = mlp_shape(in_kind, enc_L, W[0].shape[0], len(W) - 1, W[-1].shape[0])
+    s = A.MlpShape(**{k: int(v) for k, v in shape.items()})
+    B = int(o_l.shape[0])
+    Wt = [torch.from_numpy(np.ascontiguousarray(w, np.float32)).to(dev) for w in W]
+    bt = [torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(dev) for x in b]
+    Wp = (C.c_void_p * len(Wt))(*[t.data_ptr() for t in Wt])
+    bp = (C.c_void_p * len(bt))(*[t.data_ptr() for t in bt])
+    n = lib.nedf_fp8_calibrate_workspace_size(C.byref(s), B)
+    ws = torch.empty(int(n), dtype=torch.uint8, device=dev)
+    scales = torch.zeros(2 * (len(W) - 1), dtype=torch.float32, device=dev)
+    A.check(lib.nedf_fp8_calibrate(C.byref(s), Wp, bp, o_l.data_ptr(), d_l.data_ptr(), B, scales.data_ptr(),
+                                   ws.data_ptr(), int(n), _stream()), "nedf_fp8_calibrate")
+    torch.cuda.current_stream().synchronize()
+    return scales.cpu().numpy().astype(np.float64)
 
 
 @dataclass

@@ -165,6 +165,7 @@ int32_t hip_fail(hipError_t e, const char* where) {
 // network shapes of the kernels that will run.
 struct Prepared {
   KArgs k;
+  int32_t nedf_dtype = -1;            // precision of the intersection networks
   uint32_t analytic = 0, mlp = 0, nedf = 0, sphere = 0, sdf_mlp = 0, nerf = 0;
   int32_t W = 0, H = 0, L = 0;        // density network shape (0 if none)
   nedf_mlp_shape dshape{};
@@ -225,8 +226,12 @@ int32_t prepare_scene(const nedf_scene* sc, int32_t dtype, Prepared& P) {
       const nedf_mlp_shape& s = o.nedf.shape;
       if (!aligned16(o.nedf.blob)) return fail(NEDF_ERR_ALIGN, "intersection network blob must be 16-byte aligned");
       if (s.in_kind != NEDF_IN_PLUECKER || s.n_out != 2) return fail(NEDF_ERR_SHAPE, "intersection network must take Pluecker coordinates and output (mu, logit)");
-      if (o.nedf.dtype != dtype) return fail(NEDF_ERR_DTYPE, "intersection network dtype differs from the call's dtype");
-      if (!nedf_net_supported(dtype, s.width, s.n_hidden, s.enc_L))
+      if (o.nedf.dtype != dtype && o.nedf.dtype != NEDF_FP8)
+        return fail(NEDF_ERR_DTYPE, "intersection network dtype must be the call's dtype or FP8");
+      if (P.nedf_dtype >= 0 && o.nedf.dtype != P.nedf_dtype)
+        return fail(NEDF_ERR_UNSUPPORTED, "all intersection networks of one call must share a dtype");
+      P.nedf_dtype = o.nedf.dtype;
+      if (!nedf_net_supported(o.nedf.dtype, s.width, s.n_hidden, s.enc_L))
         return fail(NEDF_ERR_UNSUPPORTED, "intersection network shape not instantiated (width 256, 8 hidden, L8)");
       P.nedf |= 1u << i;
     }
@@ -312,7 +317,7 @@ void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream
   // analytic objects without a network are marched directly
   const uint32_t direct = P.analytic & ~P.nedf;
   if (direct) stage_march(k, s, false, direct, dtype, 0, 0, 0);
-  if (P.nedf) stage_nedf(k, s, dtype);
+  if (P.nedf) stage_nedf(k, s, P.nedf_dtype);
   // uncertain pairs: marcher on list B
   stage_march(k, s, true, P.analytic, dtype, (P.mlp & P.nedf) ? P.W : 0, P.H, P.L);
   stage_finalize(k, s);
@@ -677,5 +682,25 @@ extern "C" int32_t nedf_train_export(const nedf_mlp_shape* shape, const void* st
   hipError_t e = launch_train_export(*shape, static_cast<const uint8_t*>(state), W, b, which == 1,
                                      static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "nedf_train_export");
+  return NEDF_OK;
+}
+
+extern "C" size_t nedf_fp8_calibrate_workspace_size(const nedf_mlp_shape* shape, int32_t B) {
+  if (check_train_shape(shape) || B <= 0) return 0;
+  return fp8_calibrate_ws_bytes(*shape, B);
+}
+
+extern "C" int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, const float* const* b,
+                                      const float* o_l, const float* d_l, int32_t B, float* scales, void* ws,
+                                      size_t ws_bytes, nedf_stream_t stream) {
+  int32_t st = check_train_shape(shape);
+  if (st) return st;
+  if (!W || !b || !o_l || !d_l || !scales || !ws) return fail(NEDF_ERR_NULL, "nedf_fp8_calibrate: NULL argument");
+  if (B <= 0 || B % 64 != 0) return fail(NEDF_ERR_SHAPE, "calibration batch must be a positive multiple of 64");
+  if (!aligned16(ws) || !aligned16(o_l) || !aligned16(d_l)) return fail(NEDF_ERR_ALIGN, "nedf_fp8_calibrate: misaligned pointer");
+  if (ws_bytes < fp8_calibrate_ws_bytes(*shape, B)) return fail(NEDF_ERR_WORKSPACE, "workspace smaller than nedf_fp8_calibrate_workspace_size()");
+  hipError_t e = launch_fp8_calibrate(*shape, W, b, o_l, d_l, B, scales, static_cast<uint8_t*>(ws),
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nedf_fp8_calibrate");
   return NEDF_OK;
 }

@@ -164,18 +164,21 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
   constexpr int SPC = 32 * NB;  // samples per wave per chunk
   static_assert(NB == 1, "the scan assumes one 32-sample block per wave");
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = a.L;
   const int N = a.n_samples;
   const int n_chunks = (N + SPC - 1) / SPC;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= PL->total_items) break;
+  const int total = PL->total_items;
+  // one item of lookahead: the next item is claimed during the current
+  // item's last pass so that its weights stream in behind this one's
+  if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+  __syncthreads();
+  int item = s_item;
+  int slot = 0;
+  bool primed = false;
+  while (item < total) {
     const int obj = item_object(PL, a.n_obj, item);
     const int local = (item - PL->item_start[obj]) * eng::WAVES + wave;
     const bool valid = local < PL->cnt[obj];
@@ -200,7 +203,16 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
     const float delta = (tb - ta) / float(N);
     const float pa[3] = {fmaf(ta, dl[0], ol[0]), fmaf(ta, dl[1], ol[1]), fmaf(ta, dl[2], ol[2])};
     float carry = 0.f, carry_c = 0.f, sw = 0.f, sw_c = 0.f, swt = 0.f, swt_c = 0.f;
+    int next = total;
     for (int c = 0; c < n_chunks; ++c) {
+      const bool last = c + 1 == n_chunks;
+      if (last) {
+        __syncthreads();  // every wave has read s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+        __syncthreads();
+        next = s_item;
+      }
+      const uint8_t* next_blob = !last ? blob : (next < total ? a.obj[item_object(PL, a.n_obj, next)].blob : nullptr);
       typename T::frag Benc[NB][KS0];
       const int si = c * SPC + (lane & 31);
       const float tr = (float(si) + 0.5f) * delta;
@@ -208,7 +220,9 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
       eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
       float partial[NB][1] = {{0.f}};
       typename T::frag Blast[NB][KSH];
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr);
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr, &slot,
+                                                          next_blob, primed);
+      primed = next_blob != nullptr;
       const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
       float v = mlp_sigma(od, u, p[0], p[1], p[2]) * delta;
       if (lane >= 32 || si >= N || !seg) v = 0.f;
@@ -236,6 +250,7 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
       if (A >= a.hit_thr && A > 0.0f) emit_key(a, pr.x, pr.y, g.s * ((swt + swt_c) / A));
       atomicMax(&a.opac[pr.x], __float_as_uint(fmaxf(A, 0.0f)));
     }
+    item = next;
   }
 }
 
@@ -250,23 +265,30 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
   constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
   PairList* FB = &a.C->B;
-  for (;;) {
+  const int total = PL->total_items;
+  if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
+  __syncthreads();
+  int item = s_item;
+  int slot = 0;
+  bool primed = false;
+  while (item < total) {
+    // claim the next item now so that its weights stream in behind this pass
+    __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
     __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= PL->total_items) break;
+    const int next = s_item;
     const int obj = item_object(PL, a.n_obj, item);
     const int local = (item - PL->item_start[obj]) * (32 * eng::WAVES) + wave * 32 + (lane & 31);
     const bool valid = local < PL->cnt[obj];
     const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.nedf_blob;
+    const uint8_t* next_blob = next < total ? a.obj[item_object(PL, a.n_obj, next)].nedf_blob : nullptr;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
     const float* hbias = reinterpret_cast<const float*>(blob + hb->off_head_b);
     const W2L g = load_w2l(a.w2l, int(pr.y));
@@ -279,10 +301,13 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
     const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
     const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
     typename T::frag Benc[NB][KS0];
-    eng::encode_input<DT, 6, L, KS0>(pl, half, Benc[0]);
+    const float in_scale = DT == 2 ? reinterpret_cast<const float*>(blob + hb->off_scales)[0] : 1.0f;
+    eng::encode_input<DT, 6, L, KS0>(pl, half, Benc[0], in_scale);
     float partial[NB][2] = {{0.f, 0.f}};
     typename T::frag Blast[NB][KSH];
-    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr);
+    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr, &slot,
+                                                        next_blob, primed);
+    primed = next_blob != nullptr;
     const float mu_hat = partial[0][0] + __shfl_xor(partial[0][0], 32) + hbias[0];
     const float z = partial[0][1] + __shfl_xor(partial[0][1], 32) + hbias[1];
     const float p = sigmoidf_(z);
@@ -306,6 +331,7 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
       atomicAdd(&a.C->stats[1], __popcll(m));
       atomicAdd(&a.C->stats[2], __popcll(mv) - __popcll(mh) - __popcll(m));
     }
+    item = next;
   }
 }
 
@@ -357,7 +383,7 @@ bool march_mlp_supported(int dtype, int width, int n_hidden, int L) {
 }
 
 bool nedf_net_supported(int dtype, int width, int n_hidden, int L) {
-  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16 && dtype != NEDF_FP8) return false;
   return width == 256 && n_hidden == 8 && L == 8;
 }
 
@@ -420,7 +446,8 @@ void stage_march(const KArgs& k0, hipStream_t s, bool list_b, uint32_t analytic_
 void stage_nedf(const KArgs& k0, hipStream_t s, int dtype) {
   KArgs k = k0;
   prof_mark("infer.nedf", s, true);
-  if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s);
+  if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s);
+  else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s);
   else launch_nedf_net<0>(k, s);
   prof_mark("infer.nedf", s, false);
 }

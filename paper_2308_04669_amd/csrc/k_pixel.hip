@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
@@ -155,6 +155,11 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
     float o[3], d[3], ol[3], dl[3];
     make_ray(a.rays, pr.x, o, d);
     to_local(g, o, d, ol, dl);
+    // the item's field evaluations run back to back on one blob: each pass
+    // but the last prefetches the next pass's first chunks
+    const int n_eval = 2 + (a.refine_steps > 1 ? a.refine_steps - 1 : 0);
+    int eval_i = 0, slot = 0;
+    bool primed = false;
     auto f = [&](float t) {
       const float tl = t * g.inv_s;
       float p[3] = {fmaf(tl, dl[0], ol[0]), fmaf(tl, dl[1], ol[1]), fmaf(tl, dl[2], ol[2])};
@@ -162,7 +167,10 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
       eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
       float partial[NB][1] = {{0.f}};
       typename T::frag Blast[NB][KSH];
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr);
+      const uint8_t* nb_ = ++eval_i < n_eval ? blob : nullptr;
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr, &slot,
+                                                          nb_, primed);
+      primed = nb_ != nullptr;
       const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
       return mlp_surface(od, u, p[0], p[1], p[2]);
     };
@@ -210,7 +218,7 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
   constexpr int KSR = KSH + KSD;
   constexpr int CBR = eng::chunk_bytes<DT>(KSR, 3);
   constexpr int CHUNK = eng::cmax(eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1)), CBR);
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const int K = a.shade_K;  // 1, 2, 4, 8, 16 or 32

@@ -51,10 +51,38 @@ __global__ void k_train_encode(const float* o_l, const float* d_l, const float* 
     }
     row[f] = bf16_bits(v);
   }
+  if (!depth) return;  // calibration: no labels
   const float tperp = -(o[0] * d[0] + o[1] * d[1] + o[2] * d[2]);
   const bool h = hit[s] != 0;
   alpha[s] = h ? 1.0f : 0.0f;
   mu[s] = h ? (tperp - depth[s]) / bound : 0.0f;
+}
+
+// amax of |x| over n bfloat16 values (non-negative float bits order as
+// unsigned integers).
+__global__ void k_amax16(const uint16_t* x, size_t n, uint32_t* out) {
+  float m = 0.f;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    m = fmaxf(m, fabsf(bf16_val(x[i])));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_amax32(const float* x, size_t n, uint32_t* out) {
+  float m = 0.f;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    m = fmaxf(m, fabsf(x[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// Scales {w_scale, a_scale} = amax / 448 per hidden layer (E4M3 largest finite).
+__global__ void k_fp8_scales(const uint32_t* amax_w, const uint32_t* amax_a, int n_hidden, float* scales) {
+  const int i = threadIdx.x;
+  if (i >= n_hidden) return;
+  const float w = __uint_as_float(amax_w[i]), a = __uint_as_float(amax_a[i]);
+  scales[2 * i] = w > 0.f ? w / 448.0f : 1.0f;
+  scales[2 * i + 1] = a > 0.f ? a / 448.0f : 1.0f;
 }
 
 // ---- GEMM ---------------------------------------------------------------------
@@ -390,6 +418,52 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, reinterpret_cast<int64_t*>(st));
   prof_mark("train.step", s, false);
   return hipGetLastError();
+}
+
+// Per-layer E4M3 scales of a network from a calibration batch: the bfloat16
+// forward pass of the training path records amax of every hidden layer's
+// input; weight scales from the float32 weights.  ws holds a temporary
+// training state followed by the forward workspace.
+hipError_t launch_fp8_calibrate(const nedf_mlp_shape& sh, const float* const* W, const float* const* b,
+                                const float* o_l, const float* d_l, int B, float* scales, uint8_t* ws,
+                                hipStream_t s) {
+  const nedf_train_layout tl = nedf_train_layout_of(sh);
+  uint8_t* st = ws;
+  uint8_t* fw = ws + nedf_tl_align(tl.total);
+  uint32_t* amax = reinterpret_cast<uint32_t*>(fw + train_ws_bytes(sh, B));
+  const int W_ = sh.width, NH = sh.n_hidden;
+  hipError_t e = launch_train_init(sh, W, b, st, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(amax), size_t(2 * NEDF_MAX_LAYERS));
+  const int K0p = tl.L[0].Kpad;
+  uint16_t* Hin = reinterpret_cast<uint16_t*>(fw);
+  uint16_t* Hs = reinterpret_cast<uint16_t*>(fw + nedf_tl_align(size_t(B) * K0p * 2));
+  float* mu = nullptr;
+  hipLaunchKernelGGL(k_train_encode, dim3(blocks(B)), dim3(256), 0, s, o_l, d_l, static_cast<const float*>(nullptr),
+                     static_cast<const uint8_t*>(nullptr), B, sh.in_kind, sh.enc_L, K0p, 1.0f, Hin, mu, mu);
+  hipLaunchKernelGGL(k_amax16, dim3(256), dim3(256), 0, s, Hin, size_t(B) * K0p, amax + NEDF_MAX_LAYERS);
+  for (int l = 0; l < NH; ++l) {
+    GemmArgs g{};
+    g.A = l == 0 ? Hin : Hs + size_t(l - 1) * B * W_;
+    g.lda = l == 0 ? K0p : W_;
+    g.B = reinterpret_cast<const uint16_t*>(st + tl.L[l].W16);
+    g.ldb = tl.L[l].Kpad;
+    g.M = B; g.N = W_; g.K = tl.L[l].Kpad;
+    g.k_per_split = g.K;
+    g.bias = reinterpret_cast<const float*>(st + tl.L[l].b);
+    g.out16 = Hs + size_t(l) * B * W_;
+    g.ldo = W_;
+    gemm<0, 1, 0>(g, 1, s);
+    if (l + 1 < NH) hipLaunchKernelGGL(k_amax16, dim3(256), dim3(256), 0, s, g.out16, size_t(B) * W_, amax + NEDF_MAX_LAYERS + l + 1);
+    hipLaunchKernelGGL(k_amax32, dim3(64), dim3(256), 0, s, reinterpret_cast<const float*>(st + tl.L[l].W),
+                       size_t(tl.L[l].N) * tl.L[l].K, amax + l);
+  }
+  hipLaunchKernelGGL(k_fp8_scales, dim3(1), dim3(64), 0, s, amax, amax + NEDF_MAX_LAYERS, NH, scales);
+  return hipGetLastError();
+}
+
+size_t fp8_calibrate_ws_bytes(const nedf_mlp_shape& sh, int B) {
+  return nedf_tl_align(nedf_train_layout_of(sh).total) + train_ws_bytes(sh, B) + 2 * NEDF_MAX_LAYERS * 4 + 256;
 }
 
 hipError_t launch_train_export(const nedf_mlp_shape& sh, const uint8_t* st, float* const* W, float* const* b,

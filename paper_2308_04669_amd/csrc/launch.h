@@ -84,6 +84,10 @@ hipError_t launch_train_init(const nedf_mlp_shape& sh, const float* const* W, co
 hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float* o_l, const float* d_l,
                              const float* depth, const uint8_t* hit, int B, float lr, float b1, float b2, float eps,
                              float w_hit, float bound, float* loss, uint8_t* ws, hipStream_t s);
+hipError_t launch_fp8_calibrate(const nedf_mlp_shape& sh, const float* const* W, const float* const* b,
+                                const float* o_l, const float* d_l, int B, float* scales, uint8_t* ws,
+                                hipStream_t s);
+size_t fp8_calibrate_ws_bytes(const nedf_mlp_shape& sh, int B);
 hipError_t launch_train_export(const nedf_mlp_shape& sh, const uint8_t* st, float* const* W, float* const* b,
                                bool grads, hipStream_t s);
 

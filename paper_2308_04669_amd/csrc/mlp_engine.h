@@ -12,6 +12,10 @@
 
 namespace eng {
 
+// Four 32-bit lanes as a native vector (so inline asm can bind it to a
+// 128-bit VGPR tuple).
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int WAVES = 4;
 constexpr int THREADS = 64 * WAVES;
 
@@ -26,7 +30,7 @@ template <> struct Tr<1> {  // bfloat16 inputs, float32 accumulate
   __device__ static __forceinline__ f32x16_t mma(frag a, frag b, f32x16_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
-  __device__ static __forceinline__ frag pick(const uint4& w, int) { return __builtin_bit_cast(frag, w); }
+  __device__ static __forceinline__ frag pick(const u32x4& w, int) { return __builtin_bit_cast(frag, w); }
 };
 
 template <> struct Tr<0> {  // float32
@@ -38,10 +42,64 @@ template <> struct Tr<0> {  // float32
   __device__ static __forceinline__ f32x16_t mma(frag a, frag b, f32x16_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
-  __device__ static __forceinline__ frag pick(const uint4& w, int i) {
+  __device__ static __forceinline__ frag pick(const u32x4& w, int i) {
     return __uint_as_float(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w);
   }
 };
+
+template <> struct Tr<2> {  // OCP E4M3 inputs with per-layer scales, float32 accumulate
+  typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8_t;
+  using frag = i32x8_t;              // 32 fp8 values per lane
+  static constexpr int KPS = 64;
+  static constexpr int FRAG = 2048;  // two 1 KB halves (lane words 0..15 and 16..31)
+  static constexpr int KPR = 1;      // unused for FP8 (two reads per K-step)
+  static constexpr int NB = 1;
+  __device__ static __forceinline__ f32x16_t mma(frag a, frag b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+  }
+  __device__ static __forceinline__ frag pick2(const u32x4& lo, const u32x4& hi) {
+    frag f;
+    f[0] = int(lo.x); f[1] = int(lo.y); f[2] = int(lo.z); f[3] = int(lo.w);
+    f[4] = int(hi.x); f[5] = int(hi.y); f[6] = int(hi.z); f[7] = int(hi.w);
+    return f;
+  }
+};
+
+// Matrix ops of one group of G consecutive 16-byte LDS reads (read r0..r0+G-1
+// of the chunk) against the B operand.
+template <int DT, int NB, int KS_IN, int G>
+__device__ __forceinline__ void mma_group(const u32x4 (&w)[G], int r0, int R,
+                                          const typename Tr<DT>::frag (&Bin)[NB][KS_IN], f32x16_t (&acc)[NB]) {
+  using T = Tr<DT>;
+  if constexpr (DT == 2) {
+#pragma unroll
+    for (int r = 0; r + 1 < G; r += 2) {
+      if (r0 + r + 1 < R) {
+        const int ks = (r0 + r) / 2;
+        const typename T::frag a = T::pick2(w[r], w[r + 1]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = T::mma(a, Bin[nb][ks], acc[nb]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      if (r0 + r < R) {
+#pragma unroll
+        for (int i = 0; i < T::KPR; ++i) {
+          const int ks = (r0 + r) * T::KPR + i;
+          const typename T::frag a = T::pick(w[r], i);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = T::mma(a, Bin[nb][ks], acc[nb]);
+        }
+      }
+    }
+  }
+}
+
+// Matrix ops per group (for scheduling hints).
+template <int DT, int NB, int G>
+constexpr int mma_per_group() { return DT == 2 ? (G / 2) * NB : G * Tr<DT>::KPR * NB; }
 
 // Bytes of one chunk: K-steps of fragments, bias, head rows.
 template <int DT>
@@ -52,37 +110,100 @@ constexpr int chunk_bytes(int ks, int heads) {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // ---- chunk staging ---------------------------------------------------------
-// Chunks go global -> LDS directly (global_load_lds_dwordx4): each wave moves
-// 1 KB pieces, 16 bytes per lane, no staging registers.  The caller waits
-// for the loads (vmcnt) and barriers before the buffer is read.
+// Chunks go global -> LDS directly (global_load_lds_dwordx4): 1 KB pieces,
+// 16 bytes per lane.  Every wave issues the same number of copy
+// instructions per chunk (waves without a piece of their own repeat the last
+// piece, which writes identical bytes), so the number of a wave's
+// outstanding copies is a compile-time constant and the wait for a chunk can
+// leave the younger chunk's copies in flight.
+constexpr int dma_instr(int bytes) { return ((bytes + 1023) / 1024 + WAVES - 1) / WAVES; }
+
 template <int BYTES>
 __device__ __forceinline__ void dma_chunk(const uint8_t* src, uint8_t* dst) {
   constexpr int P = (BYTES + 1023) / 1024;
+  constexpr int NI = dma_instr(BYTES);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < (P + WAVES - 1) / WAVES; ++i) {
-    const int piece = wave + i * WAVES;
-    if (piece < P) {
-      const int off = piece * 1024 + lane * 16;
-      if (BYTES % 1024 == 0 || off < BYTES)
-        __builtin_amdgcn_global_load_lds(src + off, dst + piece * 1024, 16, 0, 0);
-    }
+  for (int i = 0; i < NI; ++i) {
+    int piece = wave + i * WAVES;
+    piece = piece < P ? piece : P - 1;
+    const int off = piece * 1024 + lane * 16;
+    if (BYTES % 1024 == 0 || off < BYTES)
+      __builtin_amdgcn_global_load_lds(src + off, dst + piece * 1024, 16, 0, 0);
   }
 }
 
-__device__ __forceinline__ void dma_wait_barrier() {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+// Wait until at most N vector-memory operations of this wave are pending
+// (lgkm and exp counters left at their maxima), then barrier.
+template <int N>
+__device__ __forceinline__ void dma_wait_barrier_n() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // A plain __syncthreads() would add a release fence, which waits for every
+  // outstanding global->LDS copy (vmcnt 0) including the younger prefetch.
+  // The memory clobber keeps all memory operations on their side of the
+  // barrier; the LDS reads of this wave are already complete (their explicit
+  // lgkmcnt waits precede this point in program order).
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+__device__ __forceinline__ void dma_wait_barrier() { dma_wait_barrier_n<0>(); }
+
+constexpr int NBUF = 3;  // LDS chunk buffers (prefetch distance 2)
+
+// LDS reads of a chunk.  The compiler waits for every outstanding
+// global->LDS copy (vmcnt 0) before any LDS read it can see, because it cannot
+// tell that the copy targets another buffer; these reads are therefore issued
+// as inline ds_read_b128 and completed with explicit lgkmcnt waits that are
+// tied to the destination registers (LDS operations complete in order, so
+// "at most N outstanding" guarantees every read issued before the last N).
+typedef __attribute__((address_space(3))) uint8_t lds_byte_t;
+
+__device__ __forceinline__ uint32_t lds_offset(const uint8_t* p) {
+  return uint32_t(reinterpret_cast<uintptr_t>((const lds_byte_t*)p));
+}
+
+__device__ __forceinline__ u32x4 lds_read16(uint32_t addr) {
+  u32x4 v;
+  asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(addr));
+  return v;
+}
+
+template <int N>
+__device__ __forceinline__ void lds_wait4(u32x4& a, u32x4& b, u32x4& c, u32x4& d) {
+  asm volatile("s_waitcnt lgkmcnt(%4)" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N));
+}
+// Same with the count given as a value that unrolling turns into a constant.
+__device__ __forceinline__ void lds_wait4_n(int n, u32x4& a, u32x4& b, u32x4& c, u32x4& d) {
+  switch (n) {
+    case 0: lds_wait4<0>(a, b, c, d); break;
+    case 1: lds_wait4<1>(a, b, c, d); break;
+    case 2: lds_wait4<2>(a, b, c, d); break;
+    case 3: lds_wait4<3>(a, b, c, d); break;
+    default: lds_wait4<4>(a, b, c, d); break;
+  }
 }
 
 // ---- epilogues ---------------------------------------------------------------
 // ReLU of output block fb, written as the next layer's B operand.
 template <int DT, int NB, int KSO>
 __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
-                                           typename Tr<DT>::frag (&Bout)[NB][KSO]) {
+                                           typename Tr<DT>::frag (&Bout)[NB][KSO], float2 qs) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    if constexpr (DT == 1) {
+    if constexpr (DT == 2) {
+      // real = acc * qs.x; ReLU; quantise real / a_next = acc * (qs.x * qs.y)
+      // to E4M3 (saturating at +-448); block fb fills half of K-step fb / 2
+      const float m = qs.x * qs.y;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = fminf(fmaxf(acc[nb][4 * q + j] * m, 0.0f), 448.0f);
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+        Bout[nb][fb / 2][(fb % 2) * 4 + q] = w;
+      }
+    } else if constexpr (DT == 1) {
       // round to bfloat16, then ReLU on the packed 16-bit patterns (a signed
       // 16-bit max with 0 clears exactly the negative values)
 #pragma unroll
@@ -113,7 +234,7 @@ __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
 // the head rows of this block read from the chunk in LDS.
 template <int NB, int NOUT>
 __device__ __forceinline__ void epi_head(const f32x16_t (&acc)[NB], const uint8_t* heads, int half,
-                                         float (&partial)[NB][NOUT]) {
+                                         float (&partial)[NB][NOUT], float to_real = 1.0f) {
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const float4* w4 = reinterpret_cast<const float4*>(heads + 128 * o + 64 * half);
@@ -122,10 +243,10 @@ __device__ __forceinline__ void epi_head(const f32x16_t (&acc)[NB], const uint8_
       const float4 t = w4[q];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        partial[nb][o] = fmaf(t.x, fmaxf(acc[nb][4 * q + 0], 0.0f), partial[nb][o]);
-        partial[nb][o] = fmaf(t.y, fmaxf(acc[nb][4 * q + 1], 0.0f), partial[nb][o]);
-        partial[nb][o] = fmaf(t.z, fmaxf(acc[nb][4 * q + 2], 0.0f), partial[nb][o]);
-        partial[nb][o] = fmaf(t.w, fmaxf(acc[nb][4 * q + 3], 0.0f), partial[nb][o]);
+        partial[nb][o] = fmaf(t.x, fmaxf(acc[nb][4 * q + 0] * to_real, 0.0f), partial[nb][o]);
+        partial[nb][o] = fmaf(t.y, fmaxf(acc[nb][4 * q + 1] * to_real, 0.0f), partial[nb][o]);
+        partial[nb][o] = fmaf(t.z, fmaxf(acc[nb][4 * q + 2] * to_real, 0.0f), partial[nb][o]);
+        partial[nb][o] = fmaf(t.w, fmaxf(acc[nb][4 * q + 3] * to_real, 0.0f), partial[nb][o]);
       }
     }
   }
@@ -153,90 +274,95 @@ template <int DT, int NB, int KS_IN, int FB, int CB_THIS, int CB_NEXT, int KSO, 
 __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_IN],
                                       typename Tr<DT>::frag (&Bout)[NB][KSO], const uint8_t* w_this,
                                       const uint8_t* w_next, uint8_t* lds, int& cur,
-                                      float (&partial)[NB][NOUT]) {
+                                      float (&partial)[NB][NOUT], float2 qscale = make_float2(1.f, 1.f)) {
   using T = Tr<DT>;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
-  constexpr int R = KS_IN / T::KPR;             // 16-byte LDS reads per chunk
-  static_assert(KS_IN % T::KPR == 0, "K-steps must fill whole LDS reads");
+  constexpr int R = KS_IN * T::FRAG / 1024;     // 16-byte-per-lane LDS reads per chunk
+  static_assert((KS_IN * T::FRAG) % 1024 == 0, "K-steps must fill whole LDS reads");
   // hidden-layer epilogues are deferred by one block so that their vector
   // work overlaps the next block's matrix ops
   constexpr bool DEFER = (MODE == 0);
   f32x16_t prev[NB];
 #pragma unroll
   for (int fb = 0; fb < FB; ++fb) {
-    uint8_t* nbuf = lds + (cur ^ 1) * CHUNK;
-    if (fb + 1 < FB) {
-      dma_chunk<CB_THIS>(w_this + size_t(fb + 1) * CB_THIS, nbuf);
+    // chunk fb is in buffer `cur`, chunk fb + 1 in flight into cur + 1;
+    // start chunk fb + 2 (this layer, or the following one at w_next)
+    const int nslot = cur + 2 >= NBUF ? cur + 2 - NBUF : cur + 2;
+    uint8_t* nbuf = lds + nslot * CHUNK;
+    bool issued = false;
+    if (fb + 2 < FB) {
+      dma_chunk<CB_THIS>(w_this + size_t(fb + 2) * CB_THIS, nbuf);
+      issued = true;
     } else if (w_next != nullptr) {
-      if constexpr (CB_NEXT > 0) dma_chunk<CB_NEXT>(w_next, nbuf);
+      if constexpr (CB_NEXT > 0) {
+        dma_chunk<CB_NEXT>(w_next + size_t(fb + 2 - FB) * CB_NEXT, nbuf);
+        issued = true;
+      }
     }
     const uint8_t* chunk = lds + cur * CHUNK;
-    const uint4* words = reinterpret_cast<const uint4*>(chunk) + lane;
+    const uint32_t cbase = lds_offset(chunk) + uint32_t(lane) * 16u;
+    const uint32_t bbase = lds_offset(chunk) + uint32_t(KS_IN * T::FRAG) + uint32_t(half) * 64u;
+    // Reads: bias (4 x 16 B), then groups of G fragment reads; group g+1 is
+    // issued before the matrix ops of group g.
+    constexpr int G = 4;
+    constexpr int NG = (R + G - 1) / G;
+    // reads in group g (the last group may be partial)
+    constexpr auto nrd = [](int g) constexpr { return g < 0 || g * G >= R ? 0 : (R - g * G < G ? R - g * G : G); };
+    u32x4 bw[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bw[q] = lds_read16(bbase + 16u * q);
+    u32x4 wbuf[2][G];
+#pragma unroll
+    for (int r = 0; r < G; ++r)
+      if (r < R) wbuf[0][r] = lds_read16(cbase + uint32_t(r) * 1024u);
     f32x16_t acc[NB];
+#pragma unroll
+    for (int r = 0; r < G; ++r)
+      if (G + r < R) wbuf[1][r] = lds_read16(cbase + uint32_t(G + r) * 1024u);
+    lds_wait4<nrd(0) + nrd(1)>(bw[0], bw[1], bw[2], bw[3]);
     {
-      const f32x16_t b0 = bias_acc(chunk + KS_IN * T::FRAG, half);
+      f32x16_t b0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        b0[4 * q + 0] = __uint_as_float(bw[q].x); b0[4 * q + 1] = __uint_as_float(bw[q].y);
+        b0[4 * q + 2] = __uint_as_float(bw[q].z); b0[4 * q + 3] = __uint_as_float(bw[q].w);
+      }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
     }
-    // Software pipeline over the chunk's 16-byte LDS reads: the reads of
-    // group g+1 are issued before the matrix ops of group g; scheduling
-    // barriers keep the compiler from sinking them, so LDS latency is
-    // covered by a group of matrix ops.
-    constexpr int G = 4;
-    constexpr int NG = (R + G - 1) / G;
-    uint4 wbuf[2][G];
-#pragma unroll
-    for (int r = 0; r < G; ++r)
-      if (r < R) wbuf[0][r] = words[r * 64];
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
-      if (gi + 1 < NG) {
+      u32x4 (&cw)[G] = wbuf[gi & 1];
+      lds_wait4_n(nrd(gi + 1), cw[0], cw[1], cw[2], cw[3]);
+      mma_group<DT, NB, KS_IN, G>(cw, gi * G, R, Bin, acc);
+      if constexpr (DEFER) {
+        if (fb > 0 && gi == 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
+      }
+      // reads of group gi + 2 reuse this group's registers
+      if (gi + 2 < NG) {
 #pragma unroll
         for (int r = 0; r < G; ++r)
-          if ((gi + 1) * G + r < R) wbuf[(gi + 1) & 1][r] = words[((gi + 1) * G + r) * 64];
+          if ((gi + 2) * G + r < R) cw[r] = lds_read16(cbase + uint32_t((gi + 2) * G + r) * 1024u);
       }
-#pragma unroll
-      for (int r = 0; r < G; ++r) {
-        if (gi * G + r < R) {
-#pragma unroll
-          for (int i = 0; i < T::KPR; ++i) {
-            const int ks = (gi * G + r) * T::KPR + i;
-            const typename T::frag a = T::pick(wbuf[gi & 1][r], i);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = T::mma(a, Bin[nb][ks], acc[nb]);
-          }
-        }
-      }
-      if constexpr (DEFER) {
-        if (fb > 0 && gi == 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout);
-      }
-      // order inside the region: next group's LDS reads, then matrix ops
-      // interleaved with the deferred epilogue's vector ops
-      if (gi + 1 < NG) __builtin_amdgcn_sched_group_barrier(0x100, G, 0);
-      if (DEFER && fb > 0 && gi == 0) {
-#pragma unroll
-        for (int m = 0; m < G * T::KPR * NB; ++m) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
-        }
-      } else {
-        __builtin_amdgcn_sched_group_barrier(0x008, G * T::KPR * NB, 0);
-      }
-      __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (DEFER) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
     } else {
-      if constexpr (MODE == 2) epi_hidden<DT, NB, KSO>(fb, acc, Bout);
-      epi_head<NB, NOUT>(acc, chunk + KS_IN * T::FRAG + 128, half, partial);
+      if constexpr (MODE == 2) epi_hidden<DT, NB, KSO>(fb, acc, Bout, qscale);
+      epi_head<NB, NOUT>(acc, chunk + KS_IN * T::FRAG + 128, half, partial, qscale.x);
     }
-    dma_wait_barrier();
-    cur ^= 1;
+    // chunk fb + 1 must have landed; chunk fb + 2's copies may stay in flight
+    if (issued) {
+      if (fb + 2 < FB) dma_wait_barrier_n<dma_instr(CB_THIS)>();
+      else dma_wait_barrier_n<dma_instr(CB_NEXT > 0 ? CB_NEXT : 1024)>();
+    } else {
+      dma_wait_barrier();
+    }
+    cur = cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1;
   }
-  if constexpr (DEFER) epi_hidden<DT, NB, KSO>(FB - 1, prev, Bout);
+  if constexpr (DEFER) epi_hidden<DT, NB, KSO>(FB - 1, prev, Bout, qscale);
 }
 
 // ---- whole trunk ------------------------------------------------------------
@@ -244,13 +370,17 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
 // products accumulate into `partial` (each lane half over its own features;
 // the caller adds the halves).  With KEEP_LAST the last hidden activation is
 // also left in Blast as a B operand (input of the colour layer, whose first
-// chunk, CB_AFTER bytes at w_after, is prefetched).
+// two chunks, CB_AFTER bytes each from w_after, are prefetched).  Otherwise,
+// when next_blob is given (a blob of the same shape), the last layer
+// prefetches that network's first two chunks so that the next pass can start
+// with primed = true.  *cur_io is the LDS buffer of the pass's first chunk.
 template <int DT, int WIDTH, int KS0, int NHID, int NOUT, int CHUNK, bool KEEP_LAST, int CB_AFTER>
 __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t* blob,
                                       const typename Tr<DT>::frag (&Benc)[Tr<DT>::NB][KS0],
                                       uint8_t* lds, float (&partial)[Tr<DT>::NB][NOUT],
                                       typename Tr<DT>::frag (&Blast)[Tr<DT>::NB][WIDTH / Tr<DT>::KPS],
-                                      const uint8_t* w_after, int* cur_io = nullptr) {
+                                      const uint8_t* w_after, int* cur_io = nullptr,
+                                      const uint8_t* next_blob = nullptr, bool primed = false) {
   using T = Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int FB = WIDTH / 32;
@@ -263,33 +393,44 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
   typename T::frag X[NB][KSH], Y[NB][KSH];
   int cur = cur_io ? *cur_io : 0;
   const uint64_t* off = hb->off_layer;
-  dma_chunk<CB0>(blob + off[0], lds + cur * CHUNK);
-  dma_wait_barrier();
+  // FP8: per-layer (to-real multiplier, inverse scale of the next input)
+  const float* qsc = reinterpret_cast<const float*>(blob + hb->off_scales);
+  auto QS = [&](int L) {
+    return DT == 2 ? make_float2(qsc[1 + 2 * L], qsc[2 + 2 * L]) : make_float2(1.f, 1.f);
+  };
+  if (!primed) {
+    dma_chunk<CB0>(blob + off[0], lds + cur * CHUNK);
+    dma_chunk<CB0>(blob + off[0] + CB0, lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * CHUNK);
+    dma_wait_barrier_n<dma_instr(CB0)>();
+  }
+  // chunks after the last hidden layer: the colour layer, or the next pass
+  constexpr int CB_TAIL = KEEP_LAST ? CB_AFTER : CB0;
+  const uint8_t* w_tail = KEEP_LAST ? w_after : (next_blob ? next_blob + off[0] : nullptr);
   // layer 0: encoding -> X; then pairs X -> Y -> X; the last layer feeds the head
   layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK>(Benc, X, blob + off[0], blob + off[1], lds, cur,
-                                                       partial);
+                                                       partial, QS(0));
   constexpr int PAIRS = (NHID - 2) / 2;
   for (int p = 0; p < PAIRS; ++p) {
     const int L = 1 + 2 * p;
     layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(X, Y, blob + off[L], blob + off[L + 1], lds, cur,
-                                                         partial);
+                                                         partial, QS(L));
     if ((NHID - 2) % 2 == 0 && p == PAIRS - 1) {
       layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(Y, X, blob + off[L + 1], blob + off[L + 2], lds,
-                                                           cur, partial);
+                                                           cur, partial, QS(L + 1));
     } else {
       layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(Y, X, blob + off[L + 1], blob + off[L + 2], lds,
-                                                           cur, partial);
+                                                           cur, partial, QS(L + 1));
     }
   }
   constexpr int LAST_MODE = KEEP_LAST ? 2 : 1;
   if constexpr ((NHID - 2) % 2 == 1) {
     layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(X, Y, blob + off[NHID - 2], blob + off[NHID - 1],
-                                                         lds, cur, partial);
-    layer<DT, NB, KSH, FB, CBL, CB_AFTER, KSH, NOUT, LAST_MODE, CHUNK>(Y, Blast, blob + off[NHID - 1], w_after,
-                                                                      lds, cur, partial);
+                                                         lds, cur, partial, QS(NHID - 2));
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK>(Y, Blast, blob + off[NHID - 1], w_tail,
+                                                                     lds, cur, partial, QS(NHID - 1));
   } else {
-    layer<DT, NB, KSH, FB, CBL, CB_AFTER, KSH, NOUT, LAST_MODE, CHUNK>(X, Blast, blob + off[NHID - 1], w_after,
-                                                                      lds, cur, partial);
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK>(X, Blast, blob + off[NHID - 1], w_tail,
+                                                                     lds, cur, partial, QS(NHID - 1));
   }
   if (cur_io) *cur_io = cur;
 }
@@ -311,8 +452,24 @@ __device__ __forceinline__ float enc_slot(const float (&p)[N], int a, int half) 
 
 template <int DT, int N, int L, int KS0>
 __device__ __forceinline__ void encode_input(const float (&p)[N], int half,
-                                             typename Tr<DT>::frag (&B)[KS0]) {
-  if constexpr (DT == 1) {
+                                             typename Tr<DT>::frag (&B)[KS0], float inv_scale = 1.0f) {
+  if constexpr (DT == 2) {
+    // 32 slots per K-step and lane half, quantised to E4M3 with the
+    // input's activation scale
+#pragma unroll
+    for (int ks = 0; ks < KS0; ++ks) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          v[j] = fminf(fmaxf(enc_slot<N, L>(p, 32 * ks + 4 * q + j, half) * inv_scale, -448.0f), 448.0f);
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+        B[ks][q] = w;
+      }
+    }
+  } else if constexpr (DT == 1) {
 #pragma unroll
     for (int ks = 0; ks < KS0; ++ks) {
       bf16x8_t v;
@@ -329,7 +486,7 @@ __device__ __forceinline__ void encode_input(const float (&p)[N], int half,
 // K-steps of an encoded input with n components and L levels.
 template <int DT>
 constexpr int ks_for_slots(int slots) {
-  return DT == 1 ? (slots + 7) / 8 : (slots + 3) / 4 * 4;
+  return DT == 2 ? (slots + 31) / 32 : DT == 1 ? (slots + 7) / 8 : (slots + 3) / 4 * 4;
 }
 
 }  // namespace eng

@@ -1,6 +1,7 @@
 // Host-side packing of float32 network weights into the blob layout read by
 // the matrix-core kernels (see blob_layout.h for the register layout).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -12,6 +13,34 @@
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// float -> OCP E4M3FN code: nearest finite value, ties to the even code,
+// saturating at +-448 (codes 0x00..0x7E for the magnitude).
+uint8_t e4m3_rne(float f) {
+  static double val[127];
+  static bool init = false;
+  if (!init) {
+    for (int c = 0; c < 127; ++c) {
+      const int e = c >> 3, m = c & 7;
+      val[c] = e == 0 ? std::ldexp(m / 8.0, -6) : std::ldexp(1.0 + m / 8.0, e - 7);
+    }
+    init = true;
+  }
+  const double a = std::fabs(double(f));
+  int best = 0;
+  if (a >= 448.0) {
+    best = 126;
+  } else {
+    int lo = 0;
+    while (lo + 1 < 127 && val[lo + 1] <= a) ++lo;
+    best = lo;
+    if (lo + 1 < 127) {
+      const double dl = a - val[lo], dh = val[lo + 1] - a;
+      if (dh < dl || (dh == dl && ((lo + 1) & 1) == 0)) best = lo + 1;
+    }
+  }
+  return uint8_t(best | (std::signbit(f) && best ? 0x80 : 0));
+}
 
 uint16_t bf16_rne(float f) {
   uint32_t u;
@@ -33,7 +62,7 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
   Plan p;
   std::memset(&p.h, 0, sizeof(p.h));
   if (!s) { p.why = "shape is NULL"; return p; }
-  if (dtype != NEDF_F32 && dtype != NEDF_BF16) { p.why = "dtype not supported by the packer"; return p; }
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16 && dtype != NEDF_FP8) { p.why = "dtype not supported by the packer"; return p; }
   if (s->in_kind != NEDF_IN_XYZ && s->in_kind != NEDF_IN_PLUECKER) { p.why = "bad in_kind"; return p; }
   if (s->width != 64 && s->width != 256) { p.why = "width must be 64 or 256"; return p; }
   if (s->n_hidden < 2 || s->n_hidden > NEDF_MAX_LAYERS) { p.why = "n_hidden must be 2..16"; return p; }
@@ -44,6 +73,8 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
   if (s->rgb_width && s->in_kind != NEDF_IN_XYZ) { p.why = "colour branch needs an xyz input"; return p; }
   nedf_blob_header& h = p.h;
   const bool bf = dtype == NEDF_BF16;
+  const bool f8 = dtype == NEDF_FP8;
+  if (f8 && s->rgb_width) { p.why = "FP8 packing covers networks without a colour branch"; return p; }
   const int n = in_components(s->in_kind);
   h.magic = NEDF_BLOB_MAGIC;
   h.version = NEDF_BLOB_VERSION;
@@ -59,13 +90,13 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
   h.n_dir = s->rgb_width ? uint32_t(3 * (1 + 2 * s->dir_L)) : 0u;
   const int slots = nedf_enc_slots(n, s->enc_L);
   auto round4 = [](int x) { return (x + 3) / 4 * 4; };
-  h.ks_in = bf ? uint32_t((slots + 7) / 8) : uint32_t(round4(slots));
-  h.ks_hidden = bf ? uint32_t(s->width / 16) : uint32_t(s->width / 2);
+  h.ks_in = f8 ? uint32_t((slots + 31) / 32) : bf ? uint32_t((slots + 7) / 8) : uint32_t(round4(slots));
+  h.ks_hidden = f8 ? uint32_t(s->width / 64) : bf ? uint32_t(s->width / 16) : uint32_t(s->width / 2);
   if (s->rgb_width) {
     const int dslots = nedf_enc_slots(3, s->dir_L);
     h.ks_rgb = h.ks_hidden + (bf ? uint32_t((dslots + 7) / 8) : uint32_t(round4(dslots)));
   }
-  h.frag_bytes = bf ? 1024u : 256u;
+  h.frag_bytes = f8 ? 2048u : bf ? 1024u : 256u;
   const size_t fbn = size_t(s->width / 32);
   size_t off = align256(sizeof(nedf_blob_header));
   for (int i = 0; i < s->n_hidden; ++i) {
@@ -86,20 +117,32 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
     off = align256(off + 16);
   }
   h.off_scales = off;
-  off = align256(off + NEDF_MAX_LAYERS * 2 * 4);
+  off = align256(off + (1 + 2 * NEDF_MAX_LAYERS) * 4);
   h.total_bytes = off;
   p.ok = true;
   return p;
 }
+
+int n_comp(const nedf_blob_header& h) { return h.in_kind == NEDF_IN_PLUECKER ? 6 : 3; }
 
 // Actual input feature (or -1) of logical K index k.
 //   part: 0 = encoded network input, 1 = previous hidden layer,
 //         2 = colour layer (hidden features, then the direction encoding)
 int logical_to_feature(const nedf_blob_header& h, int part, int k) {
   const bool bf = h.dtype == NEDF_BF16;
+  const bool f8 = h.dtype == NEDF_FP8;
   int ks, hh, j;
-  if (bf) { ks = k / 16; hh = (k % 16) / 8; j = k % 8; }
+  if (f8) { ks = k / 64; hh = (k % 64) / 32; j = k % 32; }
+  else if (bf) { ks = k / 16; hh = (k % 16) / 8; j = k % 8; }
   else { ks = k / 2; hh = k % 2; j = 0; }
+  if (f8) {
+    if (part == 0) {
+      const int a = 32 * ks + j;
+      if (a >= nedf_enc_slots(n_comp(h), int(h.enc_L))) return -1;
+      return nedf_enc_feature(n_comp(h), int(h.enc_L), a, hh);
+    }
+    return nedf_acc_feature(2 * ks + j / 16, hh, j % 16);
+  }
   const int n = h.in_kind == NEDF_IN_PLUECKER ? 6 : 3;
   if (part == 0) {
     const int a = bf ? 8 * ks + j : ks;
@@ -120,8 +163,26 @@ int logical_to_feature(const nedf_blob_header& h, int part, int k) {
 
 // Write the fragments of one Linear layer W [rows][cols] (row-major).
 void pack_fragments(const nedf_blob_header& h, int part, const float* W, int rows, int cols,
-                    int ks_count, size_t chunk_bytes, uint8_t* dst) {
+                    int ks_count, size_t chunk_bytes, uint8_t* dst, float w_scale = 1.0f) {
   const bool bf = h.dtype == NEDF_BF16;
+  if (h.dtype == NEDF_FP8) {
+    // FP8: lane l of K-step ks holds 32 bytes k = 64 ks + 32 (l / 32) + j;
+    // bytes 0..15 in the first 1 KB half of the fragment, 16..31 in the second
+    for (int fb = 0; fb < rows / 32; ++fb)
+      for (int ks = 0; ks < ks_count; ++ks) {
+        uint8_t* frag = dst + size_t(fb) * chunk_bytes + size_t(ks) * 2048;
+        for (int l = 0; l < 64; ++l) {
+          const int row = 32 * fb + (l % 32);
+          for (int jj = 0; jj < 32; ++jj) {
+            const int k = 64 * ks + 32 * (l / 32) + jj;
+            const int f = logical_to_feature(h, part, k);
+            const float v = (f >= 0 && f < cols) ? W[size_t(row) * cols + f] / w_scale : 0.0f;
+            frag[(jj / 16) * 1024 + l * 16 + (jj % 16)] = e4m3_rne(v);
+          }
+        }
+      }
+    return;
+  }
   const int fbn = rows / 32;
   for (int fb = 0; fb < fbn; ++fb)
     for (int ks = 0; ks < ks_count; ++ks) {
@@ -147,12 +208,14 @@ void pack_fragments(const nedf_blob_header& h, int part, const float* W, int row
     }
 }
 
-// Bias of every output block, placed after the block's fragments.
-void pack_bias(const float* b, int rows, int ks_count, int frag_bytes, size_t chunk_bytes, uint8_t* dst) {
+// Bias of every output block, placed after the block's fragments (divided by
+// the layer's to-real multiplier for FP8, whose accumulators are in scaled units).
+void pack_bias(const float* b, int rows, int ks_count, int frag_bytes, size_t chunk_bytes, uint8_t* dst,
+               float to_real = 1.0f) {
   for (int fb = 0; fb < rows / 32; ++fb) {
     float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes);
     for (int hh = 0; hh < 2; ++hh)
-      for (int r = 0; r < 16; ++r) out[hh * 16 + r] = b[nedf_acc_feature(fb, hh, r)];
+      for (int r = 0; r < 16; ++r) out[hh * 16 + r] = b[nedf_acc_feature(fb, hh, r)] / to_real;
   }
 }
 
@@ -183,9 +246,8 @@ extern "C" size_t nedf_mlp_packed_bytes(const nedf_mlp_shape* shape, int32_t dty
 extern "C" int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, const float* const* W,
                                  const float* const* b, const float* fp8_scales, void* out,
                                  size_t out_bytes) {
-  (void)fp8_scales;
   if (!shape || !W || !b || !out) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: NULL argument");
-  if (dtype == NEDF_FP8) return nedf::fail(NEDF_ERR_UNSUPPORTED, "nedf_pack_mlp: FP8 packing not available");
+  if (dtype == NEDF_FP8 && !fp8_scales) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: FP8 needs per-layer scales");
   Plan p = plan_blob(shape, dtype);
   if (!p.ok) return nedf::fail(dtype == NEDF_F32 || dtype == NEDF_BF16 ? NEDF_ERR_SHAPE : NEDF_ERR_DTYPE,
                                "nedf_pack_mlp: " + p.why);
@@ -199,12 +261,25 @@ extern "C" int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, con
   std::memcpy(base, &h, sizeof(h));
   const int Wd = shape->width;
   const int fragb = int(h.frag_bytes);
+  const bool f8 = dtype == NEDF_FP8;
+  float* sc = reinterpret_cast<float*>(base + h.off_scales);
+  if (f8) {
+    // scales: [0] 1 / a_0, then per layer {a_L w_L (to real), 1 / a_{L+1}}
+    for (int i = 0; i < shape->n_hidden; ++i)
+      if (!(fp8_scales[2 * i] > 0.0f) || !(fp8_scales[2 * i + 1] > 0.0f))
+        return nedf::fail(NEDF_ERR_SHAPE, "nedf_pack_mlp: FP8 scales must be positive");
+    sc[0] = 1.0f / fp8_scales[1];
+    for (int i = 0; i < shape->n_hidden; ++i) {
+      sc[1 + 2 * i] = fp8_scales[2 * i] * fp8_scales[2 * i + 1];
+      sc[2 + 2 * i] = i + 1 < shape->n_hidden ? 1.0f / fp8_scales[2 * (i + 1) + 1] : 1.0f;
+    }
+  }
   for (int i = 0; i < shape->n_hidden; ++i) {
     const int cols = i == 0 ? int(h.n_in) : Wd;
     const int ks = int(i == 0 ? h.ks_in : h.ks_hidden);
     uint8_t* dst = base + h.off_layer[i];
-    pack_fragments(h, i == 0 ? 0 : 1, W[i], Wd, cols, ks, h.chunk_bytes[i], dst);
-    pack_bias(b[i], Wd, ks, fragb, h.chunk_bytes[i], dst);
+    pack_fragments(h, i == 0 ? 0 : 1, W[i], Wd, cols, ks, h.chunk_bytes[i], dst, f8 ? fp8_scales[2 * i] : 1.0f);
+    pack_bias(b[i], Wd, ks, fragb, h.chunk_bytes[i], dst, f8 ? sc[1 + 2 * i] : 1.0f);
     if (i == shape->n_hidden - 1)
       pack_head(W[shape->n_hidden], shape->n_out, Wd, ks, fragb, h.chunk_bytes[i], dst);
   }

@@ -55,3 +55,23 @@ def test_paper_architecture_reading_matches_storage():
     m = syn.nerf_model(2, 0)
     n = sum(w.size + b.size for w, b in zip(m.trunk.W + m.rgb.W, m.trunk.b + m.rgb.b))
     assert n == 513924
+
+
+def test_fp8_calibration_amax_definition():
+    """The calibration scales are the largest magnitudes / 448: scaling a
+    batch so that its amax is known fixes them exactly."""
+    from oracle import fp8_calibrate, round_e4m3
+    g = np.random.default_rng(5)
+    t = syn.normal_mlp(syn.rng(0, 63), [6 * 3, 8, 8, 2], hidden_gain=2.0)
+    m = syn.Model(kind="nedf", bound=1.0, trunk=t, params=dict(enc_L=1))
+    o = g.standard_normal((50, 3)) * 3
+    d = g.standard_normal((50, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    sc = fp8_calibrate(m, o, d)
+    assert sc.shape == (2, 2)
+    assert np.isclose(sc[0, 0], np.abs(t.W[0]).max() / 448) and np.isclose(sc[1, 0], np.abs(t.W[1]).max() / 448)
+    # the first layer's input amax is the largest |encoded feature|: sin/cos <= 1, |d| = 1, |o x d| <= |o|
+    pl = np.concatenate([d, np.cross(o, d)], axis=1)
+    assert np.abs(d).max() <= sc[0, 1] * 448 <= max(1.0, np.abs(pl).max()) + 1e-12
+    # the scaled maxima quantise to the top code
+    assert round_e4m3(np.abs(t.W[0]).max() / sc[0, 0]) == 448.0

@@ -82,7 +82,7 @@ def test_nedf_compose_ties_lower_index():
     import oracle.render as R
     orig = R.nedf_eval
     try:
-        R.nedf_eval = lambda m, ol, dl, gemm=None: net(ol, dl)
+        R.nedf_eval = lambda m, ol, dl, gemm=None, scales=None: net(ol, dl)
         depth, ident = nedf_compose([model], [None], insts, o, d, fallback=False)
     finally:
         R.nedf_eval = orig

@@ -144,3 +144,88 @@ def test_wide_blob_dataflow_bf16():
     got = emulate(blob, h, pts)
     ref = mlp_forward(encode(pts, 10), t, gemm="bf16")
     assert np.allclose(got, ref, atol=1e-6, rtol=1e-5), np.abs(got - ref).max()
+
+
+def e4m3_decode(codes):
+    codes = np.asarray(codes, np.int64)
+    s = np.where(codes & 0x80, -1.0, 1.0)
+    e = (codes >> 3) & 15
+    m = codes & 7
+    v = np.where(e == 0, np.ldexp(m / 8.0, -6), np.ldexp(1.0 + m / 8.0, e - 7))
+    return s * v
+
+
+def emulate_fp8(blob, h, pts6, L):
+    """Replay of the FP8 dataflow (K-steps of 64, 32 bytes per lane, per-layer
+    scales folded into bias and epilogue) for 32 Pluecker inputs."""
+    from oracle import round_e4m3
+    sc = np.frombuffer(blob[h["off_scales"]:][:4 * 33].tobytes(), np.float32).astype(np.float64)
+    W = h["width"]
+
+    def frag(base, fb, ks, chunk):
+        off = base + fb * chunk + ks * 2048
+        A = np.zeros((32, 64))
+        for l in range(64):
+            for jj in range(32):
+                byte = blob[off + (jj // 16) * 1024 + l * 16 + (jj % 16)]
+                A[l % 32, 32 * (l // 32) + jj] = e4m3_decode(byte)
+        return A
+
+    B = []
+    for ks in range(h["ks_in"]):
+        Bm = np.zeros((64, 32))
+        for half in range(2):
+            for j in range(32):
+                Bm[32 * half + j] = round_e4m3(enc_slot(pts6, 32 * ks + j, half, L) * sc[0])
+        B.append(Bm)
+    out = np.zeros((32, h["n_out"]))
+    for layer in range(h["n_hidden"]):
+        ks_n = h["ks_in"] if layer == 0 else h["ks_hidden"]
+        chunk = h["chunk_bytes"][layer]
+        base = h["off_layer"][layer]
+        to_real, inv_next = sc[1 + 2 * layer], sc[2 + 2 * layer]
+        newB = [np.zeros((64, 32)) for _ in range(W // 64)]
+        for fb in range(W // 32):
+            bias = np.frombuffer(blob[base + fb * chunk + ks_n * 2048:][:128].tobytes(), np.float32)
+            C = np.zeros((32, 32))
+            for ks in range(ks_n):
+                C += frag(base, fb, ks, chunk) @ B[ks]
+            for l in range(64):
+                half = l // 32
+                for r in range(16):
+                    row = 8 * (r // 4) + 4 * half + (r % 4)
+                    real = max((C[row, l % 32] + bias[half * 16 + r]) * to_real, 0.0)
+                    j = (fb % 2) * 16 + r
+                    newB[fb // 2][32 * half + j, l % 32] = round_e4m3(real * inv_next)
+                    if layer == h["n_hidden"] - 1:
+                        for o in range(h["n_out"]):
+                            hw = np.frombuffer(blob[base + fb * chunk + ks_n * 2048 + 128 * (1 + o):][:128].tobytes(),
+                                               np.float32)
+                            out[l % 32, o] += hw[half * 16 + r] * real
+        B = newB
+    hb = np.frombuffer(blob[h["off_head_b"]:][:8].tobytes(), np.float32)
+    return out + hb[:h["n_out"]]
+
+
+def test_fp8_blob_dataflow():
+    g = syn.rng(0, 62)
+    t = syn.normal_mlp(g, [102, 256, 256, 2], hidden_gain=2.0)
+    for bb in t.b:
+        bb[:] = (g.standard_normal(bb.shape) * 0.05).astype(np.float32)
+    pts6 = np.concatenate([g.standard_normal((32, 3)), g.uniform(-0.8, 0.8, (32, 3))], axis=1)
+    pts6[:, :3] /= np.linalg.norm(pts6[:, :3], axis=1, keepdims=True)
+    # scales {w_scale, a_scale} per hidden layer from the float64 forward
+    x = encode(pts6, 8)
+    acts = [x]
+    hcur = x
+    for i in range(2):
+        hcur = np.maximum(hcur @ t.W[i].astype(np.float64).T + t.b[i], 0)
+        acts.append(hcur)
+    scales = np.array([[np.abs(t.W[i]).max() / 448, np.abs(acts[i]).max() / 448] for i in range(2)])
+    shape = api.mlp_shape("pluecker", 8, 256, 2, 2)
+    blob = api.pack_host(t.W, t.b, shape, "fp8", fp8_scales=scales.reshape(-1))
+    h = header(blob)
+    assert h["dtype"] == 2 and h["ks_in"] == 2 and h["ks_hidden"] == 4
+    got = emulate_fp8(blob, h, pts6, 8)
+    ref = mlp_forward(x, t, scales=[tuple(s) for s in scales])
+    assert np.allclose(got, ref, atol=1e-4, rtol=1e-4), np.abs(got - ref).max()
