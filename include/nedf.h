@@ -236,7 +236,8 @@ int32_t nedf_check_status(const void* ws, nedf_stream_t stream);
 /*
  * Stage timing.  nedf_profile_enable(1) clears the record list and makes every
  * later call bracket its kernel launches with HIP events on its stream, under
- * stage names ("march.cull", "march.mlp", ...); nedf_profile_enable(0) stops
+ * stage names ("depth.cull", "march.mlp", ...; a stage run inside another is
+ * named "outer/inner", e.g. "shadow/infer.nedf"); nedf_profile_enable(0) stops
  * recording.  nedf_profile_read synchronises on the recorded events and
  * returns, per stage in first-seen order, the summed elapsed milliseconds and
  * the number of brackets: names is a host buffer of max_stages x 64 chars.

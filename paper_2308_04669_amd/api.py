@@ -305,7 +305,7 @@ def infer_depth_id(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_lo: flo
 
 def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, K: int = 8,
                    h: float = 0.05, clear_rgb=(0.0, 0.0, 0.0), dtype: str = "bf16", ws: Workspace | None = None,
-                   out: torch.Tensor | None = None) -> torch.Tensor:
+                   out: torch.Tensor | None = None, pair_capacity: int = 0) -> torch.Tensor:
     """Deferred shading of every pixel with a valid ID; returns rgb [n, 3]."""
     lib = A.load()
     n = n_rays(rays)
@@ -315,7 +315,9 @@ def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: to
     opts = A.ShadeOpts(K=K, h=h, dtype=A.DTYPES[dtype])
     for i in range(3):
         opts.clear_rgb[i] = float(clear_rgb[i])
-    nbytes = lib.nedf_workspace_size(A.OPS["shade"], C.byref(sc), C.byref(rays), 0)
+    # one (pixel, instance) pair per pixel at most
+    cap = int(pair_capacity) if pair_capacity > 0 else n
+    nbytes = lib.nedf_workspace_size(A.OPS["shade"], C.byref(sc), C.byref(rays), cap)
     ws = ws or Workspace(dev)
     buf = ws.get(nbytes)
     A.check(lib.nedf_shade_deferred(C.byref(sc), C.byref(rays), _ptr(depth), _ptr(ident), C.byref(opts),
@@ -326,7 +328,7 @@ def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: to
 def shadow(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, lights, eps: float,
            beta: float = 0.5, method: str = "nedf", dtype: str = "bf16", n_samples: int = 128,
            p_lo: float = 0.2, p_hi: float = 0.8, rgb_inout: torch.Tensor | None = None,
-           ws: Workspace | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+           ws: Workspace | None = None, out: torch.Tensor | None = None, pair_capacity: int = 0) -> torch.Tensor:
     """Shadow step of Alg. 2 for point lights; returns the multiplier [n]
     and multiplies ``rgb_inout`` by it when given."""
     lib = A.load()
@@ -337,7 +339,7 @@ def shadow(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tens
     sc = scene.struct()
     io = infer_opts(dtype, p_lo, p_hi, 0, 0.05, n_samples)
     opts = A.ShadowOpts(eps=eps, beta=beta, method=0 if method == "nedf" else 1, infer=io)
-    nbytes = lib.nedf_workspace_size(A.OPS["shadow"], C.byref(sc), C.byref(rays), 0)
+    nbytes = lib.nedf_workspace_size(A.OPS["shadow"], C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
     buf = ws.get(nbytes)
     A.check(lib.nedf_shadow(C.byref(sc), C.byref(rays), _ptr(depth), _ptr(ident), L.ctypes.data, L.shape[0],

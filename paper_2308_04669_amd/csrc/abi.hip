@@ -39,14 +39,14 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 namespace {
 struct ProfRec {
-  const char* name;
+  std::string name;  // "outer/inner" for stages nested in another stage
   hipEvent_t a, b;
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
-std::map<const void*, size_t> g_prof_open;  // stream -> index of the open record
+std::map<const void*, std::vector<size_t>> g_prof_open;  // stream -> stack of open records
 
 hipEvent_t prof_event() {
   if (!g_prof_pool.empty()) {
@@ -66,17 +66,18 @@ void prof_mark(const char* name, void* stream, bool begin) {
   if (!g_prof_on) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<size_t>& open = g_prof_open[stream];
   if (begin) {
-    ProfRec r{name, prof_event(), prof_event()};
+    ProfRec r{open.empty() ? std::string(name) : g_prof_recs[open.back()].name + "/" + name, prof_event(),
+              prof_event()};
     if (!r.a || !r.b) return;
-    hipEventRecord(r.a, s);
-    g_prof_open[stream] = g_prof_recs.size();
+    (void)hipEventRecord(r.a, s);
+    open.push_back(g_prof_recs.size());
     g_prof_recs.push_back(r);
   } else {
-    auto it = g_prof_open.find(stream);
-    if (it == g_prof_open.end()) return;
-    hipEventRecord(g_prof_recs[it->second].b, s);
-    g_prof_open.erase(it);
+    if (open.empty()) return;
+    (void)hipEventRecord(g_prof_recs[open.back()].b, s);
+    open.pop_back();
   }
 }
 

@@ -11,6 +11,25 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 #define NEDF_WS_STATUS 0          // int32 status word at workspace offset 0
 #define NEDF_KEY_EMPTY 0x7F800000FFFFFFFFull  // (+inf bits << 32) | 0xFFFFFFFF
 
+// Loads of wave-uniform values through the scalar cache.  The address is made
+// provably uniform (readfirstlane) and read through the constant address
+// space, so the load is counted with the LDS/scalar operations and waiting
+// for it never waits for outstanding vector-memory (global->LDS) copies.
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+  return reinterpret_cast<const void*>((uint64_t(hi) << 32) | lo);
+}
+__device__ __forceinline__ uint64_t uniform_load_u64(const void* p) {
+  typedef __attribute__((address_space(4))) const uint64_t cu64;
+  return *(cu64*)uniform_ptr(p);
+}
+__device__ __forceinline__ float uniform_load_f32(const void* p) {
+  typedef __attribute__((address_space(4))) const float cf32;
+  return *(cf32*)uniform_ptr(p);
+}
+
 // World->local record (see nedf_compose_transforms): o_l = R^T o / s + c.
 struct W2L {
   float rt[9];

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
   constexpr int SPC = 32 * NB;  // samples per wave per chunk
   static_assert(NB == 1, "the scan assumes one 32-sample block per wave");
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = a.L;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.blob;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
-    const float head_b = reinterpret_cast<const float*>(blob + hb->off_head_b)[0];
+    const float head_b = uniform_load_f32(blob + uniform_load_u64(&hb->off_head_b));
     const W2L g = load_w2l(a.w2l, int(pr.y));
     float o[3], d[3], ol[3], dl[3];
     make_ray(a.rays, pr.x, o, d);
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
   constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
@@ -290,7 +290,8 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
     const uint8_t* blob = od.nedf_blob;
     const uint8_t* next_blob = next < total ? a.obj[item_object(PL, a.n_obj, next)].nedf_blob : nullptr;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
-    const float* hbias = reinterpret_cast<const float*>(blob + hb->off_head_b);
+    const float* hbias_p = reinterpret_cast<const float*>(blob + uniform_load_u64(&hb->off_head_b));
+    const float hbias[2] = {uniform_load_f32(hbias_p), uniform_load_f32(hbias_p + 1)};
     const W2L g = load_w2l(a.w2l, int(pr.y));
     float o[3], d[3], ol[3], dl[3];
     make_ray(a.rays, pr.x, o, d);
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
     const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
     const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
     typename T::frag Benc[NB][KS0];
-    const float in_scale = DT == 2 ? reinterpret_cast<const float*>(blob + hb->off_scales)[0] : 1.0f;
+    const float in_scale = DT == 2 ? uniform_load_f32(blob + uniform_load_u64(&hb->off_scales)) : 1.0f;
     eng::encode_input<DT, 6, L, KS0>(pl, half, Benc[0], in_scale);
     float partial[NB][2] = {{0.f, 0.f}};
     typename T::frag Blast[NB][KSH];

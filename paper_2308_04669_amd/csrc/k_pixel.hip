@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.blob;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
-    const float head_b = reinterpret_cast<const float*>(blob + hb->off_head_b)[0];
+    const float head_b = uniform_load_f32(blob + uniform_load_u64(&hb->off_head_b));
     const W2L g = load_w2l(a.w2l, int(pr.y));
     float o[3], d[3], ol[3], dl[3];
     make_ray(a.rays, pr.x, o, d);
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
   constexpr int KSR = KSH + KSD;
   constexpr int CBR = eng::chunk_bytes<DT>(KSR, 3);
   constexpr int CHUNK = eng::cmax(eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1)), CBR);
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * CHUNK];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const int K = a.shade_K;  // 1, 2, 4, 8, 16 or 32
@@ -238,8 +238,9 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.blob;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
-    const float head_b = reinterpret_cast<const float*>(blob + hb->off_head_b)[0];
-    const float* rgb_b = reinterpret_cast<const float*>(blob + hb->off_rgbh_b);
+    const float head_b = uniform_load_f32(blob + uniform_load_u64(&hb->off_head_b));
+    const float* rgb_bp = reinterpret_cast<const float*>(blob + uniform_load_u64(&hb->off_rgbh_b));
+    const float rgb_b[3] = {uniform_load_f32(rgb_bp), uniform_load_f32(rgb_bp + 1), uniform_load_f32(rgb_bp + 2)};
     const W2L g = load_w2l(a.w2l, int(pr.y));
     float o[3], d[3], ol[3], dl[3];
     make_ray(a.rays, pr.x, o, d);
@@ -254,8 +255,8 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
     float partial[NB][1] = {{0.f}};
     typename T::frag Blast[NB][KSH];
     int cur = 0;
-    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR>(hb, blob, Benc, lds, partial, Blast,
-                                                         blob + hb->off_rgb, &cur);
+    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR, RGBW / 32>(hb, blob, Benc, lds, partial, Blast,
+                                                         blob + uniform_load_u64(&hb->off_rgb), &cur);
     const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
     const float sig = mlp_sigma(od, u, p[0], p[1], p[2]);
     // colour layer input: [h_last, gamma_dirL(d_l)]
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
     }
     float prgb[NB][3] = {{0.f, 0.f, 0.f}};
     typename T::frag dummy[NB][1];
-    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK>(Bc, dummy, blob + hb->off_rgb, nullptr, lds, cur,
+    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK>(Bc, dummy, blob + uniform_load_u64(&hb->off_rgb), nullptr, lds, cur,
                                                               prgb);
     float c[3];
 #pragma unroll

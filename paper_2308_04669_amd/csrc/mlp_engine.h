@@ -3,11 +3,15 @@
 // A workgroup of 4 waves evaluates one network for 4 x 32 x NB samples.  Each
 // wave keeps its samples' activations in registers as matrix-core B operands
 // for the whole network (see blob_layout.h); the workgroup streams the
-// weights through LDS one output block ("chunk": 32 output features x all K,
-// plus that block's bias and head rows) at a time, double-buffered: while the
-// waves multiply chunk i from one LDS buffer, chunk i+1 is copied from global
-// memory (L2) straight into the other buffer; one barrier per chunk.
+// weights through LDS.  A "chunk" is one output block (32 output features x
+// all K, plus that block's bias and head rows); SB consecutive chunks form a
+// superchunk, the unit of one global->LDS copy and one barrier.  Three LDS
+// slots form a ring: while the waves multiply superchunk i, superchunks i+1
+// and i+2 are being copied from global memory (L2) straight into the other
+// two slots.
 #pragma once
+#include <utility>
+
 #include "device_common.h"
 
 namespace eng {
@@ -162,25 +166,17 @@ __device__ __forceinline__ uint32_t lds_offset(const uint8_t* p) {
   return uint32_t(reinterpret_cast<uintptr_t>((const lds_byte_t*)p));
 }
 
+template <int OFF>
 __device__ __forceinline__ u32x4 lds_read16(uint32_t addr) {
+  static_assert(OFF >= 0 && OFF < 65536 && OFF % 16 == 0, "ds_read_b128 offset");
   u32x4 v;
-  asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(addr));
+  asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "n"(OFF));
   return v;
 }
 
 template <int N>
 __device__ __forceinline__ void lds_wait4(u32x4& a, u32x4& b, u32x4& c, u32x4& d) {
   asm volatile("s_waitcnt lgkmcnt(%4)" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N));
-}
-// Same with the count given as a value that unrolling turns into a constant.
-__device__ __forceinline__ void lds_wait4_n(int n, u32x4& a, u32x4& b, u32x4& c, u32x4& d) {
-  switch (n) {
-    case 0: lds_wait4<0>(a, b, c, d); break;
-    case 1: lds_wait4<1>(a, b, c, d); break;
-    case 2: lds_wait4<2>(a, b, c, d); break;
-    case 3: lds_wait4<3>(a, b, c, d); break;
-    default: lds_wait4<4>(a, b, c, d); break;
-  }
 }
 
 // ---- epilogues ---------------------------------------------------------------
@@ -230,47 +226,41 @@ __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
   }
 }
 
-// Narrow heads: partial[nb][o] += sum_r w[o][h][r] * relu(acc[nb][r]), with
-// the head rows of this block read from the chunk in LDS.
-template <int NB, int NOUT>
-__device__ __forceinline__ void epi_head(const f32x16_t (&acc)[NB], const uint8_t* heads, int half,
-                                         float (&partial)[NB][NOUT], float to_real = 1.0f) {
-#pragma unroll
-  for (int o = 0; o < NOUT; ++o) {
-    const float4* w4 = reinterpret_cast<const float4*>(heads + 128 * o + 64 * half);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 t = w4[q];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        partial[nb][o] = fmaf(t.x, fmaxf(acc[nb][4 * q + 0] * to_real, 0.0f), partial[nb][o]);
-        partial[nb][o] = fmaf(t.y, fmaxf(acc[nb][4 * q + 1] * to_real, 0.0f), partial[nb][o]);
-        partial[nb][o] = fmaf(t.z, fmaxf(acc[nb][4 * q + 2] * to_real, 0.0f), partial[nb][o]);
-        partial[nb][o] = fmaf(t.w, fmaxf(acc[nb][4 * q + 3] * to_real, 0.0f), partial[nb][o]);
-      }
-    }
-  }
-}
-
-__device__ __forceinline__ f32x16_t bias_acc(const uint8_t* bias, int half) {
-  const float4* b4 = reinterpret_cast<const float4*>(bias + 64 * half);
-  f32x16_t a;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float4 t = b4[q];
-    a[4 * q + 0] = t.x; a[4 * q + 1] = t.y; a[4 * q + 2] = t.z; a[4 * q + 3] = t.w;
-  }
-  return a;
-}
-
 // ---- one layer -----------------------------------------------------------
+// Output blocks are streamed in "superchunks" of SB consecutive chunks (one
+// barrier per superchunk; the chunks of a layer are contiguous in the blob).
+template <int DT> constexpr int sb_max() { return DT == 0 ? 1 : DT == 1 ? 2 : 4; }
+template <int DT> constexpr int sb_for(int fb) {
+  int s = sb_max<DT>();
+  while (s > 1 && (fb % s != 0 || fb / s < 2)) s /= 2;  // at least two per layer
+  return s;
+}
+// LDS bytes of one ring slot for chunks of at most `chunk` bytes.
+template <int DT> constexpr int slot_bytes(int chunk) { return chunk * sb_max<DT>(); }
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1.
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // Multiplies the FB chunks of a layer (KS_IN K-steps each, CB_THIS bytes)
-// against Bin.  Chunk 0 must be in LDS buffer `cur` on entry; the next chunk
-// (next block, or the first chunk of the following layer at w_next, CB_NEXT
-// bytes) is prefetched during each block.
+// against Bin.  Superchunk 0 must be in LDS slot `cur` on entry and
+// superchunk 1 in flight into the next slot; superchunk sc + 2 (of this
+// layer, or of the following one at w_next: FB_NEXT chunks of CB_NEXT bytes)
+// is started while superchunk sc is multiplied.
+//
+// Within a superchunk the LDS reads form one fixed sequence of read groups,
+// per block: bias (4 reads), fragment groups of up to G reads, and for the
+// head modes one group per head row; D groups are kept in flight ahead of the
+// group being consumed.
 // MODE 0: hidden epilogue into Bout.  MODE 1: head epilogue.  MODE 2: both.
 template <int DT, int NB, int KS_IN, int FB, int CB_THIS, int CB_NEXT, int KSO, int NOUT, int MODE,
-          int CHUNK>
+          int CHUNK, int FB_NEXT = FB>
 __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_IN],
                                       typename Tr<DT>::frag (&Bout)[NB][KSO], const uint8_t* w_this,
                                       const uint8_t* w_next, uint8_t* lds, int& cur,
@@ -278,85 +268,136 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   using T = Tr<DT>;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
-  constexpr int R = KS_IN * T::FRAG / 1024;     // 16-byte-per-lane LDS reads per chunk
+  constexpr int SLOT = slot_bytes<DT>(CHUNK);
+  constexpr int SB = sb_for<DT>(FB);
+  constexpr int NSC = FB / SB;
+  constexpr int SB_N = sb_for<DT>(FB_NEXT);
+  constexpr int SCB = SB * CB_THIS;
+  constexpr int SCB_N = SB_N * CB_NEXT;
+  static_assert(FB % SB == 0 && NSC >= 2, "layer must span at least two superchunks");
+  static_assert(SCB <= SLOT && SCB_N <= SLOT, "LDS slot too small");
+  static_assert(SCB < 65536, "LDS read offsets are 16-bit");
+  constexpr int R = KS_IN * T::FRAG / 1024;  // 16-byte-per-lane LDS reads per chunk
   static_assert((KS_IN * T::FRAG) % 1024 == 0, "K-steps must fill whole LDS reads");
+  constexpr int G = 4;
+  constexpr int NG = (R + G - 1) / G;
+  constexpr int NH = MODE >= 1 ? NOUT : 0;
+  constexpr int PER = 1 + NG + NH;  // read groups per block
+  constexpr int E = SB * PER;       // read groups per superchunk
+  constexpr int D = 3;              // groups issued ahead of consumption
+  constexpr int BIAS = KS_IN * T::FRAG;
   // hidden-layer epilogues are deferred by one block so that their vector
   // work overlaps the next block's matrix ops
   constexpr bool DEFER = (MODE == 0);
   f32x16_t prev[NB];
 #pragma unroll
-  for (int fb = 0; fb < FB; ++fb) {
-    // chunk fb is in buffer `cur`, chunk fb + 1 in flight into cur + 1;
-    // start chunk fb + 2 (this layer, or the following one at w_next)
+  for (int sc = 0; sc < NSC; ++sc) {
+    // start superchunk sc + 2 (this layer, or the following one at w_next)
     const int nslot = cur + 2 >= NBUF ? cur + 2 - NBUF : cur + 2;
-    uint8_t* nbuf = lds + nslot * CHUNK;
+    uint8_t* nbuf = lds + nslot * SLOT;
     bool issued = false;
-    if (fb + 2 < FB) {
-      dma_chunk<CB_THIS>(w_this + size_t(fb + 2) * CB_THIS, nbuf);
+    if (sc + 2 < NSC) {
+      dma_chunk<SCB>(w_this + size_t(sc + 2) * SCB, nbuf);
       issued = true;
     } else if (w_next != nullptr) {
       if constexpr (CB_NEXT > 0) {
-        dma_chunk<CB_NEXT>(w_next + size_t(fb + 2 - FB) * CB_NEXT, nbuf);
+        dma_chunk<SCB_N>(w_next + size_t(sc + 2 - NSC) * SCB_N, nbuf);
         issued = true;
       }
     }
-    const uint8_t* chunk = lds + cur * CHUNK;
-    const uint32_t cbase = lds_offset(chunk) + uint32_t(lane) * 16u;
-    const uint32_t bbase = lds_offset(chunk) + uint32_t(KS_IN * T::FRAG) + uint32_t(half) * 64u;
-    // Reads: bias (4 x 16 B), then groups of G fragment reads; group g+1 is
-    // issued before the matrix ops of group g.
-    constexpr int G = 4;
-    constexpr int NG = (R + G - 1) / G;
-    // reads in group g (the last group may be partial)
-    constexpr auto nrd = [](int g) constexpr { return g < 0 || g * G >= R ? 0 : (R - g * G < G ? R - g * G : G); };
-    u32x4 bw[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) bw[q] = lds_read16(bbase + 16u * q);
-    u32x4 wbuf[2][G];
-#pragma unroll
-    for (int r = 0; r < G; ++r)
-      if (r < R) wbuf[0][r] = lds_read16(cbase + uint32_t(r) * 1024u);
+    const uint32_t base = lds_offset(lds + cur * SLOT);
+    const uint32_t fbase = base + uint32_t(lane) * 16u;  // fragment reads
+    const uint32_t bbase = base + uint32_t(half) * 64u;  // bias and head rows
+    u32x4 ring[D][G];
     f32x16_t acc[NB];
-#pragma unroll
-    for (int r = 0; r < G; ++r)
-      if (G + r < R) wbuf[1][r] = lds_read16(cbase + uint32_t(G + r) * 1024u);
-    lds_wait4<nrd(0) + nrd(1)>(bw[0], bw[1], bw[2], bw[3]);
-    {
-      f32x16_t b0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        b0[4 * q + 0] = __uint_as_float(bw[q].x); b0[4 * q + 1] = __uint_as_float(bw[q].y);
-        b0[4 * q + 2] = __uint_as_float(bw[q].z); b0[4 * q + 3] = __uint_as_float(bw[q].w);
+    // number of reads of group e
+    constexpr auto cnt = [](int e) constexpr {
+      if (e >= E) return 0;
+      const int j = e % PER;
+      if (j == 0 || j > NG) return 4;
+      const int g = j - 1;
+      return R - g * G < G ? R - g * G : G;
+    };
+    auto issue = [&](auto ec) __attribute__((always_inline)) {
+      constexpr int e = decltype(ec)::value;
+      if constexpr (e < E) {
+        constexpr int k = e / PER, j = e % PER;
+        u32x4(&dst)[G] = ring[e % D];
+        if constexpr (j == 0) {
+          static_for<4>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            dst[q] = lds_read16<k * CB_THIS + BIAS + 16 * q>(bbase);
+          });
+        } else if constexpr (j <= NG) {
+          constexpr int g = j - 1;
+          static_for<cnt(e)>([&](auto rc) __attribute__((always_inline)) {
+            constexpr int r = decltype(rc)::value;
+            dst[r] = lds_read16<k * CB_THIS + (g * G + r) * 1024>(fbase);
+          });
+        } else {
+          constexpr int o = j - 1 - NG;
+          static_for<4>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            dst[q] = lds_read16<k * CB_THIS + BIAS + 128 + 128 * o + 16 * q>(bbase);
+          });
+        }
       }
+    };
+    static_for<D>(issue);
+    static_for<E>([&](auto ec) __attribute__((always_inline)) {
+      constexpr int e = decltype(ec)::value;
+      constexpr int k = e / PER, j = e % PER;
+      const int fb = sc * SB + k;
+      u32x4(&cw)[G] = ring[e % D];
+      // groups e + 1 .. e + D - 1 may stay in flight
+      constexpr int after = cnt(e + 1) + cnt(e + 2);
+      static_assert(D == 3, "wait count assumes three groups in flight");
+      lds_wait4<after>(cw[0], cw[1], cw[2], cw[3]);
+      if constexpr (j == 0) {
+        f32x16_t b0;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
-    }
+        for (int q = 0; q < 4; ++q) {
+          b0[4 * q + 0] = __uint_as_float(cw[q].x); b0[4 * q + 1] = __uint_as_float(cw[q].y);
+          b0[4 * q + 2] = __uint_as_float(cw[q].z); b0[4 * q + 3] = __uint_as_float(cw[q].w);
+        }
 #pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-      u32x4 (&cw)[G] = wbuf[gi & 1];
-      lds_wait4_n(nrd(gi + 1), cw[0], cw[1], cw[2], cw[3]);
-      mma_group<DT, NB, KS_IN, G>(cw, gi * G, R, Bin, acc);
-      if constexpr (DEFER) {
-        if (fb > 0 && gi == 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
+      } else if constexpr (j <= NG) {
+        mma_group<DT, NB, KS_IN, G>(cw, (j - 1) * G, R, Bin, acc);
+        if constexpr (DEFER && j == 1) {
+          if (fb > 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
+        }
+        if constexpr (j == NG) {
+          if constexpr (DEFER) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
+          } else if constexpr (MODE == 2) {
+            epi_hidden<DT, NB, KSO>(fb, acc, Bout, qscale);
+          }
+        }
+      } else {
+        // head row o: partial[nb][o] += w . relu(real(acc))
+        constexpr int o = j - 1 - NG;
+        const float tr = qscale.x;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            float s = partial[nb][o];
+            s = fmaf(__uint_as_float(cw[q].x), fmaxf(acc[nb][4 * q + 0] * tr, 0.0f), s);
+            s = fmaf(__uint_as_float(cw[q].y), fmaxf(acc[nb][4 * q + 1] * tr, 0.0f), s);
+            s = fmaf(__uint_as_float(cw[q].z), fmaxf(acc[nb][4 * q + 2] * tr, 0.0f), s);
+            s = fmaf(__uint_as_float(cw[q].w), fmaxf(acc[nb][4 * q + 3] * tr, 0.0f), s);
+            partial[nb][o] = s;
+          }
+        }
       }
-      // reads of group gi + 2 reuse this group's registers
-      if (gi + 2 < NG) {
-#pragma unroll
-        for (int r = 0; r < G; ++r)
-          if ((gi + 2) * G + r < R) cw[r] = lds_read16(cbase + uint32_t((gi + 2) * G + r) * 1024u);
-      }
-    }
-    if constexpr (DEFER) {
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
-    } else {
-      if constexpr (MODE == 2) epi_hidden<DT, NB, KSO>(fb, acc, Bout, qscale);
-      epi_head<NB, NOUT>(acc, chunk + KS_IN * T::FRAG + 128, half, partial, qscale.x);
-    }
-    // chunk fb + 1 must have landed; chunk fb + 2's copies may stay in flight
+      issue(std::integral_constant<int, e + D>{});
+    });
+    // superchunk sc + 1 must have landed; sc + 2's copies may stay in flight
     if (issued) {
-      if (fb + 2 < FB) dma_wait_barrier_n<dma_instr(CB_THIS)>();
-      else dma_wait_barrier_n<dma_instr(CB_NEXT > 0 ? CB_NEXT : 1024)>();
+      if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB)>();
+      else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024)>();
     } else {
       dma_wait_barrier();
     }
@@ -369,12 +410,15 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
 // Hidden layers 0..NHID-1 of the blob on the encoded input Benc; the head dot
 // products accumulate into `partial` (each lane half over its own features;
 // the caller adds the halves).  With KEEP_LAST the last hidden activation is
-// also left in Blast as a B operand (input of the colour layer, whose first
-// two chunks, CB_AFTER bytes each from w_after, are prefetched).  Otherwise,
+// also left in Blast as a B operand (input of the colour layer of FB_AFTER
+// chunks of CB_AFTER bytes at w_after, whose first two superchunks are
+// prefetched).  Otherwise,
 // when next_blob is given (a blob of the same shape), the last layer
-// prefetches that network's first two chunks so that the next pass can start
-// with primed = true.  *cur_io is the LDS buffer of the pass's first chunk.
-template <int DT, int WIDTH, int KS0, int NHID, int NOUT, int CHUNK, bool KEEP_LAST, int CB_AFTER>
+// prefetches that network's first two superchunks so that the next pass can
+// start with primed = true.  *cur_io is the LDS slot of the pass's first
+// superchunk.  The caller's LDS array holds NBUF slots of slot_bytes(CHUNK).
+template <int DT, int WIDTH, int KS0, int NHID, int NOUT, int CHUNK, bool KEEP_LAST, int CB_AFTER,
+          int FB_AFTER = WIDTH / 32>
 __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t* blob,
                                       const typename Tr<DT>::frag (&Benc)[Tr<DT>::NB][KS0],
                                       uint8_t* lds, float (&partial)[Tr<DT>::NB][NOUT],
@@ -392,44 +436,49 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
   static_assert(CHUNK >= CB0 && CHUNK >= CBL, "LDS chunk buffer too small");
   typename T::frag X[NB][KSH], Y[NB][KSH];
   int cur = cur_io ? *cur_io : 0;
-  const uint64_t* off = hb->off_layer;
+  // header fields are read through the scalar cache (see uniform_load_u64)
+  auto off = [&](int L) { return uniform_load_u64(&hb->off_layer[L]); };
   // FP8: per-layer (to-real multiplier, inverse scale of the next input)
-  const float* qsc = reinterpret_cast<const float*>(blob + hb->off_scales);
+  const float* qsc = reinterpret_cast<const float*>(blob + (DT == 2 ? uniform_load_u64(&hb->off_scales) : 0));
   auto QS = [&](int L) {
-    return DT == 2 ? make_float2(qsc[1 + 2 * L], qsc[2 + 2 * L]) : make_float2(1.f, 1.f);
+    return DT == 2 ? make_float2(uniform_load_f32(qsc + 1 + 2 * L), uniform_load_f32(qsc + 2 + 2 * L))
+                   : make_float2(1.f, 1.f);
   };
+  constexpr int SLOT = slot_bytes<DT>(CHUNK);
+  constexpr int SC0 = sb_for<DT>(FB) * CB0;  // first-layer superchunk bytes
   if (!primed) {
-    dma_chunk<CB0>(blob + off[0], lds + cur * CHUNK);
-    dma_chunk<CB0>(blob + off[0] + CB0, lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * CHUNK);
-    dma_wait_barrier_n<dma_instr(CB0)>();
+    dma_chunk<SC0>(blob + off(0), lds + cur * SLOT);
+    dma_chunk<SC0>(blob + off(0) + SC0, lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * SLOT);
+    dma_wait_barrier_n<dma_instr(SC0)>();
   }
   // chunks after the last hidden layer: the colour layer, or the next pass
   constexpr int CB_TAIL = KEEP_LAST ? CB_AFTER : CB0;
-  const uint8_t* w_tail = KEEP_LAST ? w_after : (next_blob ? next_blob + off[0] : nullptr);
+  constexpr int FB_TAIL = KEEP_LAST ? FB_AFTER : FB;
+  const uint8_t* w_tail = KEEP_LAST ? w_after : (next_blob ? next_blob + off(0) : nullptr);
   // layer 0: encoding -> X; then pairs X -> Y -> X; the last layer feeds the head
-  layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK>(Benc, X, blob + off[0], blob + off[1], lds, cur,
+  layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK>(Benc, X, blob + off(0), blob + off(1), lds, cur,
                                                        partial, QS(0));
   constexpr int PAIRS = (NHID - 2) / 2;
   for (int p = 0; p < PAIRS; ++p) {
     const int L = 1 + 2 * p;
-    layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(X, Y, blob + off[L], blob + off[L + 1], lds, cur,
+    layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(X, Y, blob + off(L), blob + off(L + 1), lds, cur,
                                                          partial, QS(L));
     if ((NHID - 2) % 2 == 0 && p == PAIRS - 1) {
-      layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(Y, X, blob + off[L + 1], blob + off[L + 2], lds,
+      layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
                                                            cur, partial, QS(L + 1));
     } else {
-      layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(Y, X, blob + off[L + 1], blob + off[L + 2], lds,
+      layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
                                                            cur, partial, QS(L + 1));
     }
   }
   constexpr int LAST_MODE = KEEP_LAST ? 2 : 1;
   if constexpr ((NHID - 2) % 2 == 1) {
-    layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(X, Y, blob + off[NHID - 2], blob + off[NHID - 1],
+    layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(X, Y, blob + off(NHID - 2), blob + off(NHID - 1),
                                                          lds, cur, partial, QS(NHID - 2));
-    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK>(Y, Blast, blob + off[NHID - 1], w_tail,
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL>(Y, Blast, blob + off(NHID - 1), w_tail,
                                                                      lds, cur, partial, QS(NHID - 1));
   } else {
-    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK>(X, Blast, blob + off[NHID - 1], w_tail,
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL>(X, Blast, blob + off(NHID - 1), w_tail,
                                                                      lds, cur, partial, QS(NHID - 1));
   }
   if (cur_io) *cur_io = cur;

@@ -224,3 +224,55 @@ def sdf_scene(config: int, n_inst: int, n_models: int = 4, width: int = 64, heig
     cam = Camera(eye=(0.0, 0.0, 0.0), at=(0.0, 0.0, -1.0), up=(0.0, 1.0, 0.0), fov_y_deg=40.0,
                  width=width, height=height)
     return models, insts, cam
+
+
+def _outside_all(p, insts, bounds) -> bool:
+    return all(np.linalg.norm(p - i.T) > i.s * bounds[i.model] for i in insts)
+
+
+def batched_scene(config: int, n_inst: int, width: int, height: int, n_models: int = 4,
+                  coverage=(0.01, 0.20), z_range=(6.0, 30.0), fov_y_deg: float = 40.0,
+                  lights=((20.0, 30.0, 10.0), (-25.0, 20.0, 5.0))):
+    """Many instances of a few SDF-biased NeRF objects with uneven screen
+    coverage.  Camera at the origin looking down -z.  Instance k uses model
+    k mod n_models, a uniform rotation, a target screen coverage
+    c ~ U[coverage] (fraction of the image), a depth z ~ U[z_range] and a
+    screen position uniform over the image; its bounding-sphere radius is
+    R = z sqrt(c W H / pi) / f_px, so s = R / l.  A light inside a bounding
+    sphere is moved by seeded unit steps until it is outside every one.
+    Returns models, instances, camera, lights."""
+    models = [nerf_model(config, 100 + k, sigma_mode="sdf", sdf_shape=k % 4) for k in range(n_models)]
+    bounds = [m.bound for m in models]
+    g = rng(config, 901)
+    f_px = 0.5 * height / np.tan(np.radians(0.5 * fov_y_deg))
+    insts = []
+    for k in range(n_inst):
+        c = g.uniform(*coverage)
+        z = g.uniform(*z_range)
+        u, v = g.uniform(0.0, width), g.uniform(0.0, height)
+        T = np.array([(u - 0.5 * width) / f_px * z, (0.5 * height - v) / f_px * z, -z])
+        R_world = z * np.sqrt(c * width * height / np.pi) / f_px
+        m = k % n_models
+        insts.append(Instance(model=m, R=shoemake_rotation(g), T=T, s=float(R_world / bounds[m])))
+    cam = Camera(eye=(0.0, 0.0, 0.0), at=(0.0, 0.0, -1.0), up=(0.0, 1.0, 0.0), fov_y_deg=fov_y_deg,
+                 width=width, height=height)
+    gl = rng(config, 902)
+    out_lights = []
+    for L in lights:
+        p = np.array(L, dtype=np.float64)
+        while not _outside_all(p, insts, bounds):
+            w = gl.standard_normal(3)
+            p = p + w / np.linalg.norm(w)
+        out_lights.append(p)
+    return models, insts, cam, out_lights
+
+
+def config4_scene(width: int = 1920, height: int = 1080, n_inst: int = 1000):
+    """The batched-composition scene: 1,000 instances of 4 models at 1080p,
+    two point lights."""
+    return batched_scene(4, n_inst, width, height)
+
+
+def config5_scene(width: int = 3840, height: int = 2160, n_inst: int = 64):
+    """The precision-stress scene: 64 instances (16 per model) at 2160p."""
+    return batched_scene(5, n_inst, width, height)
