@@ -191,6 +191,18 @@ def frame_bench(args):
             api.shadow(sc, rays, depth, ident, lights, eps, beta=0.5, method="nedf", dtype=args.dtype,
                        n_samples=args.fallback_samples, rgb_inout=rgb, ws=ws, out=fac)
 
+    # superchunk sizes of the matrix-core kernels from the library's autotuner:
+    # the intersection network on this frame, the marcher on a pixel subset
+    g = np.random.default_rng(4669 + 1000 * config + 78)
+    tpix = np.sort(g.choice(n, size=min(4096, n), replace=False))
+    to_, td_ = subset_rays(cam, tpix % W, tpix // W)
+    trays = api.array_rays(torch.from_numpy(to_).cuda(), torch.from_numpy(td_).cuda())
+    tune = {"nedf": api.autotune("nedf", args.dtype, sc, rays,
+                                 api.infer_opts(args.dtype, refine_steps=3, n_samples=args.fallback_samples),
+                                 reps=1, ws=ws),
+            "march": api.autotune("march", args.dtype, sc, trays,
+                                  api.march_opts(args.fallback_samples, dtype=args.dtype), reps=1)}
+    log(f"autotune {tune}")
     for _ in range(args.warmup):
         frame()
     torch.cuda.synchronize()
@@ -280,6 +292,7 @@ def frame_bench(args):
                      "frac": achieved / peak, "traffic": None, "kernel": kname, "avg_launch_ms": k_ms,
                      "flop_per_launch": k_flops},
         "stages_ms_per_step": per,
+        "autotune": tune,
         "training": train,
         "setup_train_s": setup_train_s,
     }

@@ -375,6 +375,43 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
                            const float* o_l, const float* d_l, int32_t B, float* scales, void* ws,
                            size_t ws_bytes, nedf_stream_t stream);
 
+/*
+ * Autotuning.  Not a step of the paper's method: a tuning aid for the grouped
+ * launches that evaluate every (ray, instance) pair of Alg. 1 per object.
+ * The tunable tile of the matrix-core kernels is the number of
+ * 32-row weight chunks streamed into LDS per copy and barrier ("superchunk");
+ * it is kept per kernel and dtype in a process-wide table guarded by a mutex
+ * (the library's only global state besides the profiler).
+ *
+ * nedf_tune_candidates writes the values instantiated for (kernel, dtype) into
+ * out (up to 4) and their number into n.  nedf_tune_get/nedf_tune_set read and
+ * write the table (set rejects values that are not candidates with
+ * NEDF_ERR_UNSUPPORTED).  nedf_autotune runs the stage of `kernel` on the
+ * caller's inputs once per candidate (`reps` timed runs each, after one
+ * warm-up), keeps the fastest in the table and describes the trial in
+ * *report (host).  `opts` is a nedf_march_opts* for NEDF_TUNE_MARCH (plain
+ * marcher, nedf_march_depth) and a nedf_infer_opts* for NEDF_TUNE_NEDF
+ * (nedf_infer_depth_id, tuning the intersection-network kernel of `dtype`);
+ * depth and id are caller-owned device outputs of n_rays elements; ws as for
+ * those calls.  Synchronises `stream`.
+ */
+typedef enum { NEDF_TUNE_MARCH = 0, NEDF_TUNE_NEDF = 1 } nedf_tune_kernel;
+
+typedef struct {
+  int32_t kernel, dtype;
+  int32_t n_candidates;
+  int32_t candidate[4];
+  float ms[4];
+  int32_t chosen;
+} nedf_tune_report;
+
+int32_t nedf_tune_candidates(int32_t kernel, int32_t dtype, int32_t* out, int32_t* n);
+int32_t nedf_tune_get(int32_t kernel, int32_t dtype, int32_t* value);
+int32_t nedf_tune_set(int32_t kernel, int32_t dtype, int32_t value);
+int32_t nedf_autotune(int32_t kernel, int32_t dtype, const nedf_scene* scene, const nedf_rays* rays,
+                      const void* opts, float* depth, int32_t* id, void* ws, size_t ws_bytes, int32_t reps,
+                      nedf_stream_t stream, nedf_tune_report* report);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@ FIELDS = {"sphere": 0, "slab": 1, "mlp": 2}
 SIGMA_MODES = {"softplus": 0, "softplus_masked": 1, "sdf": 2}
 IN_KINDS = {"xyz": 0, "pluecker": 1}
 OPS = {"march": 0, "infer": 1, "shade": 2, "shadow": 3}
+TUNE_KERNELS = {"march": 0, "nedf": 1}
 
 
 class MlpShape(C.Structure):
@@ -73,6 +74,11 @@ class TrainOpts(C.Structure):
                 ("w_hit", C.c_float), ("bound", C.c_float)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("dtype", C.c_int32), ("n_candidates", C.c_int32),
+                ("candidate", C.c_int32 * 4), ("ms", C.c_float * 4), ("chosen", C.c_int32)]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = [
     ("nedf_version", C.c_char_p, []),
@@ -110,6 +116,12 @@ SIGNATURES = [
                                        C.c_void_p]),
     ("nedf_march_depth", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(MarchOpts), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nedf_tune_candidates", C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("nedf_tune_get", C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    ("nedf_tune_set", C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
+    ("nedf_autotune", C.c_int32, [C.c_int32, C.c_int32, C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
+                                  C.POINTER(TuneReport)]),
 ]
 
 _lib = None

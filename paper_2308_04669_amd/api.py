@@ -434,3 +434,54 @@ class Trainer:
                 "nedf_train_export")
         torch.cuda.current_stream().synchronize()
         return [t.cpu().numpy().astype(np.float64) for t in Wt], [t.cpu().numpy().astype(np.float64) for t in bt]
+
+
+# ---------------------------------------------------------------- tuning
+def tune_candidates(kernel: str, dtype: str) -> list:
+    lib = A.load()
+    out, n = (C.c_int32 * 4)(), C.c_int32(0)
+    A.check(lib.nedf_tune_candidates(A.TUNE_KERNELS[kernel], A.DTYPES[dtype], out, C.byref(n)),
+            "nedf_tune_candidates")
+    return [int(out[i]) for i in range(n.value)]
+
+
+def tune_get(kernel: str, dtype: str) -> int:
+    lib = A.load()
+    v = C.c_int32(0)
+    A.check(lib.nedf_tune_get(A.TUNE_KERNELS[kernel], A.DTYPES[dtype], C.byref(v)), "nedf_tune_get")
+    return int(v.value)
+
+
+def tune_set(kernel: str, dtype: str, value: int) -> None:
+    lib = A.load()
+    A.check(lib.nedf_tune_set(A.TUNE_KERNELS[kernel], A.DTYPES[dtype], int(value)), "nedf_tune_set")
+
+
+def autotune(kernel: str, dtype: str, scene: SceneGPU, rays: A.Rays, opts, reps: int = 2,
+             ws: Workspace | None = None, pair_capacity: int = 0) -> dict:
+    """Run nedf_autotune for ``kernel`` ("march" with march options, "nedf"
+    with infer options) and ``dtype`` on these inputs; returns the trial
+    report (candidates, ms per run, chosen value)."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    depth = torch.empty(n, dtype=torch.float32, device=dev)
+    ident = torch.empty(n, dtype=torch.int32, device=dev)
+    sc = scene.struct()
+    op = A.OPS["march"] if kernel == "march" else A.OPS["infer"]
+    nbytes = lib.nedf_workspace_size(op, C.byref(sc), C.byref(rays), int(pair_capacity))
+    ws = ws or Workspace(dev)
+    buf = ws.get(nbytes)
+    rep = A.TuneReport()
+    A.check(lib.nedf_autotune(A.TUNE_KERNELS[kernel], A.DTYPES[dtype], C.byref(sc), C.byref(rays), C.byref(opts),
+                              _ptr(depth), _ptr(ident), buf.data_ptr(), int(nbytes), int(reps), _stream(),
+                              C.byref(rep)), "nedf_autotune")
+    k = rep.n_candidates
+    return {"kernel": kernel, "dtype": dtype, "candidates": [int(rep.candidate[i]) for i in range(k)],
+            "ms": [float(rep.ms[i]) for i in range(k)], "chosen": int(rep.chosen)}
+
+
+def march_opts(n_samples: int = 128, clip_to_bound: bool = True, t_near: float = 0.0, t_far: float = 0.0,
+               hit_threshold: float = 0.5, dtype: str = "f32") -> A.MarchOpts:
+    return A.MarchOpts(n_samples=n_samples, clip_to_bound=int(clip_to_bound), t_near=t_near, t_far=t_far,
+                       hit_threshold=hit_threshold, dtype=A.DTYPES[dtype])

@@ -705,3 +705,112 @@ extern "C" int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* 
   if (e != hipSuccess) return hip_fail(e, "nedf_fp8_calibrate");
   return NEDF_OK;
 }
+
+
+// ---- tuning table and autotuner ---------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+// [kernel][dtype]: chunks per superchunk
+int g_tune[2][3] = {{1, 2, 4}, {1, 2, 4}};
+
+int tune_candidates(int kernel, int dtype, int32_t* out) {
+  if (kernel < 0 || kernel > 1 || dtype < 0 || dtype > 2) return 0;
+  if (dtype == NEDF_F32) { out[0] = 1; return 1; }
+  if (dtype == NEDF_BF16) { out[0] = 1; out[1] = 2; return 2; }
+  if (kernel == NEDF_TUNE_NEDF) { out[0] = 1; out[1] = 2; out[2] = 4; return 3; }
+  return 0;  // no FP8 marcher
+}
+}  // namespace
+
+namespace nedf {
+int tune_value(int kernel, int dtype) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (kernel < 0 || kernel > 1 || dtype < 0 || dtype > 2) return 1;
+  return g_tune[kernel][dtype];
+}
+}  // namespace nedf
+
+extern "C" int32_t nedf_tune_candidates(int32_t kernel, int32_t dtype, int32_t* out, int32_t* n) {
+  if (!out || !n) return fail(NEDF_ERR_NULL, "nedf_tune_candidates: NULL argument");
+  *n = tune_candidates(kernel, dtype, out);
+  if (*n == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_tune_get(int32_t kernel, int32_t dtype, int32_t* value) {
+  if (!value) return fail(NEDF_ERR_NULL, "nedf_tune_get: NULL argument");
+  int32_t c[4];
+  if (tune_candidates(kernel, dtype, c) == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
+  *value = tune_value(kernel, dtype);
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_tune_set(int32_t kernel, int32_t dtype, int32_t value) {
+  int32_t c[4];
+  const int n = tune_candidates(kernel, dtype, c);
+  if (n == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
+  bool ok = false;
+  for (int i = 0; i < n; ++i) ok |= c[i] == value;
+  if (!ok) return fail(NEDF_ERR_UNSUPPORTED, "value is not an instantiated candidate");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[kernel][dtype] = value;
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_autotune(int32_t kernel, int32_t dtype, const nedf_scene* scene, const nedf_rays* rays,
+                                 const void* opts, float* depth, int32_t* id, void* ws, size_t ws_bytes,
+                                 int32_t reps, nedf_stream_t stream, nedf_tune_report* report) {
+  if (!scene || !rays || !opts || !report) return fail(NEDF_ERR_NULL, "nedf_autotune: NULL argument");
+  if (reps < 1 || reps > 100) return fail(NEDF_ERR_SHAPE, "reps must be 1..100");
+  int32_t cand[4];
+  const int n = tune_candidates(kernel, dtype, cand);
+  if (n == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto run = [&]() -> int32_t {
+    if (kernel == NEDF_TUNE_MARCH)
+      return nedf_march_depth(scene, rays, static_cast<const nedf_march_opts*>(opts), depth, id, nullptr, ws,
+                              ws_bytes, stream);
+    return nedf_infer_depth_id(scene, rays, static_cast<const nedf_infer_opts*>(opts), depth, id, ws, ws_bytes,
+                               stream);
+  };
+  const int32_t saved = tune_value(kernel, dtype);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(NEDF_ERR_HIP, "nedf_autotune: event creation failed");
+  }
+  int32_t st = NEDF_OK;
+  int best = -1;
+  std::memset(report, 0, sizeof(*report));
+  report->kernel = kernel;
+  report->dtype = dtype;
+  report->n_candidates = n;
+  for (int i = 0; i < n && st == NEDF_OK; ++i) {
+    report->candidate[i] = cand[i];
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[kernel][dtype] = cand[i];
+    }
+    st = run();  // warm-up
+    if (st) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == NEDF_OK; ++r) st = run();
+    (void)hipEventRecord(e1, s);
+    if (st) break;
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(NEDF_ERR_HIP, "nedf_autotune: event sync failed"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    report->ms[i] = ms / float(reps);
+    if (best < 0 || report->ms[i] < report->ms[best]) best = i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (st != NEDF_OK || best < 0) {
+    g_tune[kernel][dtype] = saved;
+    return st ? st : fail(NEDF_ERR_HIP, "nedf_autotune: no candidate ran");
+  }
+  g_tune[kernel][dtype] = cand[best];
+  report->chosen = cand[best];
+  return NEDF_OK;
+}

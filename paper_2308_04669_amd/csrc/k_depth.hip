@@ -29,34 +29,155 @@ __device__ __forceinline__ bool pair_test(const KArgs& a, const float o[3], cons
   return sphere_chord(ol, dl, a.obj[obj].bound, ta, tb);
 }
 
-// Pass 0 counts pairs per object in list A; pass 1 writes them.  One thread
-// per ray, wave-aggregated atomics per (wave, instance).
-template <int PASS>
-__global__ void k_cull(KArgs a) {
-  const int64_t ray = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const bool live = ray < a.n_rays;
+// Culling and binning (Alg. 1, "models in the view frustum"): list A gets
+// one (ray, instance) pair for every ray that meets an instance's bounding
+// sphere ahead of its origin.  A workgroup takes 256 rays: a 16 x 16 pixel
+// tile for camera rays, 256 consecutive rays for ray arrays.  For a tile it
+// first keeps only the instances whose bounding sphere can meet the tile's
+// frustum (a conservative test; the exact per-ray test decides), in index
+// order.  Pass 0 counts pairs per object, pass 1 reserves one range per
+// object for the workgroup and writes the pairs; counts are aggregated per
+// wave and per workgroup in LDS, so global atomics are one per (workgroup,
+// object).
+constexpr int CULL_TILE = 16;
+constexpr int CULL_BATCH = 1024;  // candidate instances held in LDS at a time
+
+struct TileFrustum {
+  float eye[3], rh[3], uh[3], fw[3];  // camera basis (unit vectors)
+  float nx0, nx1, ny0, ny1;           // tile bounds as x/z and y/z slopes
+};
+
+__device__ __forceinline__ bool tile_meets_sphere(const TileFrustum& f, const float c[3], float r) {
+  const float q[3] = {c[0] - f.eye[0], c[1] - f.eye[1], c[2] - f.eye[2]};
+  const float X = q[0] * f.rh[0] + q[1] * f.rh[1] + q[2] * f.rh[2];
+  const float Y = q[0] * f.uh[0] + q[1] * f.uh[1] + q[2] * f.uh[2];
+  const float Z = q[0] * f.fw[0] + q[1] * f.fw[1] + q[2] * f.fw[2];
+  // margin for float rounding of the instance record and of the basis
+  const float rr = r + 1e-4f * (fabsf(X) + fabsf(Y) + fabsf(Z) + r) + 1e-6f;
+  if (Z < -rr) return false;
+  if (X - f.nx0 * Z < -rr * sqrtf(1.0f + f.nx0 * f.nx0)) return false;
+  if (f.nx1 * Z - X < -rr * sqrtf(1.0f + f.nx1 * f.nx1)) return false;
+  if (Y - f.ny0 * Z < -rr * sqrtf(1.0f + f.ny0 * f.ny0)) return false;
+  if (f.ny1 * Z - Y < -rr * sqrtf(1.0f + f.ny1 * f.ny1)) return false;
+  return true;
+}
+
+// World-space bounding sphere of instance k: centre -s R c, radius s l.
+__device__ __forceinline__ void instance_sphere(const KArgs& a, int k, int obj, float c[3], float& r) {
+  const W2L g = load_w2l(a.w2l, k);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    c[i] = -g.s * (g.rt[i] * g.c[0] + g.rt[3 + i] * g.c[1] + g.rt[6 + i] * g.c[2]);
+  r = g.s * a.obj[obj].bound;
+}
+
+template <int PASS, bool CAMERA>
+__global__ __launch_bounds__(256) void k_cull(KArgs a) {
+  __shared__ int s_cand[CULL_BATCH];
+  __shared__ int s_wsum[4];
+  __shared__ int s_cnt[NEDF_MAX_OBJECTS], s_base[NEDF_MAX_OBJECTS];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int64_t ray;
+  bool live;
+  TileFrustum f;
+  if constexpr (CAMERA) {
+    const int W = a.rays.width, H = a.rays.height;
+    const int px = blockIdx.x * CULL_TILE + (t % CULL_TILE), py = blockIdx.y * CULL_TILE + (t / CULL_TILE);
+    live = px < W && py < H;
+    ray = int64_t(py) * W + px;
+    // pixel-centre extremes of the tile as slopes in the camera basis
+    const float ax = sqrtf(a.rays.right[0] * a.rays.right[0] + a.rays.right[1] * a.rays.right[1] +
+                           a.rays.right[2] * a.rays.right[2]);
+    const float ay = sqrtf(a.rays.up[0] * a.rays.up[0] + a.rays.up[1] * a.rays.up[1] + a.rays.up[2] * a.rays.up[2]);
+    for (int i = 0; i < 3; ++i) {
+      f.eye[i] = a.rays.eye[i];
+      f.rh[i] = a.rays.right[i] / ax;
+      f.uh[i] = a.rays.up[i] / ay;
+      f.fw[i] = a.rays.fwd[i];
+    }
+    const int i0 = blockIdx.x * CULL_TILE, i1 = min(W, i0 + CULL_TILE) - 1;
+    const int j0 = blockIdx.y * CULL_TILE, j1 = min(H, j0 + CULL_TILE) - 1;
+    f.nx0 = ax * (2.0f * (float(i0) + 0.5f) / float(W) - 1.0f);
+    f.nx1 = ax * (2.0f * (float(i1) + 0.5f) / float(W) - 1.0f);
+    f.ny1 = ay * (1.0f - 2.0f * (float(j0) + 0.5f) / float(H));
+    f.ny0 = ay * (1.0f - 2.0f * (float(j1) + 0.5f) / float(H));
+  } else {
+    ray = int64_t(blockIdx.x) * blockDim.x + t;
+    live = ray < a.n_rays;
+  }
   float o[3] = {0, 0, 0}, d[3] = {0, 0, 1};
   if (live) make_ray(a.rays, ray, o, d);
-  const int lane = threadIdx.x & 63;
   PairList* L = &a.C->A;
-  for (int k = 0; k < a.n_inst; ++k) {
-    const int obj = a.inst_object[k];
-    const bool pass = live && obj >= 0 && obj < a.n_obj && pair_test(a, o, d, k, obj);
-    const uint64_t m = __ballot(pass);
-    if (m == 0) continue;
-    const int cnt = __popcll(m);
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    if (PASS == 0) {
-      if (lane == leader) atomicAdd(&L->cnt[obj], cnt);
-    } else {
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&L->fill[obj], cnt);
-      base = __shfl(base, leader);
-      if (pass) {
-        const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-        if (pos < L->cnt[obj]) a.pairs[L->off[obj] + pos] = make_uint2(uint32_t(ray), uint32_t(k));
+  if (t < NEDF_MAX_OBJECTS) s_cnt[t] = 0;
+  __syncthreads();
+  // traversal 0 counts; in pass 1 traversal 1 writes
+  for (int trav = 0; trav <= PASS; ++trav) {
+    for (int base = 0; base < a.n_inst; base += CULL_BATCH) {
+      const int nb = min(CULL_BATCH, a.n_inst - base);
+      int nc = 0;
+      if constexpr (CAMERA) {
+        // ordered compaction of the instances whose sphere meets the tile
+        __syncthreads();
+        for (int c0 = 0; c0 < nb; c0 += 256) {
+          const int k = base + c0 + t;
+          bool keep = false;
+          if (c0 + t < nb) {
+            const int obj = a.inst_object[k];
+            if (obj >= 0 && obj < a.n_obj) {
+              if (!a.clip) {
+                keep = true;
+              } else {
+                float c[3], r;
+                instance_sphere(a, k, obj, c, r);
+                keep = tile_meets_sphere(f, c, r);
+              }
+            }
+          }
+          const uint64_t m = __ballot(keep);
+          if (lane == 0) s_wsum[wave] = __popcll(m);
+          __syncthreads();
+          int off = nc;
+          for (int w = 0; w < wave; ++w) off += s_wsum[w];
+          const int tot = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+          if (keep) s_cand[off + __popcll(m & ((1ull << lane) - 1ull))] = k;
+          nc += tot;
+          __syncthreads();
+        }
+      } else {
+        nc = nb;
+      }
+      for (int ci = 0; ci < nc; ++ci) {
+        const int k = CAMERA ? s_cand[ci] : base + ci;
+        const int obj = a.inst_object[k];
+        const bool pass = live && obj >= 0 && obj < a.n_obj && pair_test(a, o, d, k, obj);
+        const uint64_t m = __ballot(pass);
+        if (m == 0) continue;
+        const int cnt = __popcll(m);
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        if (trav == 0) {
+          if (lane == leader) atomicAdd(&s_cnt[obj], cnt);
+        } else {
+          int off = 0;
+          if (lane == leader) off = atomicAdd(&s_cnt[obj], cnt);
+          off = __shfl(off, leader);
+          if (pass) {
+            const int pos = s_base[obj] + off + __popcll(m & ((1ull << lane) - 1ull));
+            if (pos < L->cnt[obj]) a.pairs[L->off[obj] + pos] = make_uint2(uint32_t(ray), uint32_t(k));
+          }
+        }
       }
     }
+    __syncthreads();
+    if (t < a.n_obj) {
+      const int c = s_cnt[t];
+      if (PASS == 0) {
+        if (c) atomicAdd(&L->cnt[t], c);
+      } else if (trav == 0) {
+        s_base[t] = c ? atomicAdd(&L->fill[t], c) : 0;
+        s_cnt[t] = 0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -155,7 +276,7 @@ __global__ void k_march_analytic(KArgs a, uint32_t mask) {
 // one object from list a.L; each wave marches its pair in chunks of 32
 // samples through the register-resident density network, then scans the
 // chunk's optical depths across the wave.
-template <int DT, int WIDTH, int NHID, int L>
+template <int DT, int WIDTH, int NHID, int L, int SBX>
 __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
@@ -164,7 +285,7 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
   constexpr int SPC = 32 * NB;  // samples per wave per chunk
   static_assert(NB == 1, "the scan assumes one 32-sample block per wave");
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = a.L;
@@ -220,7 +341,8 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
       eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
       float partial[NB][1] = {{0.f}};
       typename T::frag Blast[NB][KSH];
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr, &slot,
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
+                                                                           nullptr, &slot,
                                                           next_blob, primed);
       primed = next_blob != nullptr;
       const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
@@ -258,14 +380,14 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
 // object; each lane pair evaluates the intersection network on its pair's
 // line coordinates.  Confident hits go to the key buffer, uncertain pairs
 // (and origins inside the bounding sphere) to list B for the marcher.
-template <int DT, int WIDTH, int NHID, int L>
+template <int DT, int WIDTH, int NHID, int L, int SBX>
 __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
@@ -306,7 +428,8 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
     eng::encode_input<DT, 6, L, KS0>(pl, half, Benc[0], in_scale);
     float partial[NB][2] = {{0.f, 0.f}};
     typename T::frag Blast[NB][KSH];
-    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr, &slot,
+    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
+                                                                         nullptr, &slot,
                                                         next_blob, primed);
     primed = next_blob != nullptr;
     const float mu_hat = partial[0][0] + __shfl_xor(partial[0][0], 32) + hbias[0];
@@ -361,14 +484,34 @@ int cu_count() {
   return ncu;
 }
 
+// The superchunk size of the 256-wide BF16/FP8 kernels comes from the tuning
+// table (nedf_autotune); other shapes use the default.
 template <int DT, int WIDTH, int NHID, int L>
 void launch_march_mlp(const KArgs& k, hipStream_t s) {
-  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L>), dim3(cu_count()), dim3(eng::THREADS), 0, s, k);
+  const dim3 g(cu_count()), b(eng::THREADS);
+  if constexpr (DT == 1 && WIDTH == 256) {
+    if (tune_value(NEDF_TUNE_MARCH, DT) == 1) {
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1>), g, b, 0, s, k);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>()>), g, b, 0, s, k);
 }
 
 template <int DT>
 void launch_nedf_net(const KArgs& k, hipStream_t s) {
-  hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8>), dim3(cu_count()), dim3(eng::THREADS), 0, s, k);
+  const dim3 g(cu_count()), b(eng::THREADS);
+  const int sb = tune_value(NEDF_TUNE_NEDF, DT);
+  if constexpr (DT == 2) {
+    if (sb == 1) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1>), g, b, 0, s, k);
+    else if (sb == 2) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2>), g, b, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4>), g, b, 0, s, k);
+  } else if constexpr (DT == 1) {
+    if (sb == 1) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1>), g, b, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2>), g, b, 0, s, k);
+  } else {
+    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1>), g, b, 0, s, k);
+  }
 }
 
 unsigned grid_for(int64_t n) {
@@ -406,9 +549,16 @@ void stage_init_cull(const KArgs& k0, hipStream_t s, uint32_t item_mask, int ite
   const unsigned g = grid_for(k.n_rays);
   prof_mark("depth.cull", s, true);
   hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, s, k);
-  hipLaunchKernelGGL(k_cull<0>, dim3(g), dim3(256), 0, s, k);
-  hipLaunchKernelGGL(k_scan_A, dim3(1), dim3(64), 0, s, k);
-  hipLaunchKernelGGL(k_cull<1>, dim3(g), dim3(256), 0, s, k);
+  if (k.rays.kind == 0) {
+    const dim3 tg((k.rays.width + CULL_TILE - 1) / CULL_TILE, (k.rays.height + CULL_TILE - 1) / CULL_TILE);
+    hipLaunchKernelGGL((k_cull<0, true>), tg, dim3(256), 0, s, k);
+    hipLaunchKernelGGL(k_scan_A, dim3(1), dim3(64), 0, s, k);
+    hipLaunchKernelGGL((k_cull<1, true>), tg, dim3(256), 0, s, k);
+  } else {
+    hipLaunchKernelGGL((k_cull<0, false>), dim3(g), dim3(256), 0, s, k);
+    hipLaunchKernelGGL(k_scan_A, dim3(1), dim3(64), 0, s, k);
+    hipLaunchKernelGGL((k_cull<1, false>), dim3(g), dim3(256), 0, s, k);
+  }
   prof_mark("depth.cull", s, false);
 }
 

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, eng::sb_default<DT>())];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
   constexpr int KSR = KSH + KSD;
   constexpr int CBR = eng::chunk_bytes<DT>(KSR, 3);
   constexpr int CHUNK = eng::cmax(eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1)), CBR);
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes<DT>(CHUNK)];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, eng::sb_default<DT>())];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const int K = a.shade_K;  // 1, 2, 4, 8, 16 or 32

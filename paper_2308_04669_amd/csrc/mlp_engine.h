@@ -226,17 +226,41 @@ __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
   }
 }
 
+// Forces the B-operand words written by epi_hidden(fb) to be computed before
+// this point in the instruction stream (an empty volatile asm that reads them).
+template <int DT, int NB, int KSO>
+__device__ __forceinline__ void pin_block(int fb, typename Tr<DT>::frag (&Bout)[NB][KSO]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    if constexpr (DT == 2) {
+      asm volatile("" ::"v"(Bout[nb][fb / 2][(fb % 2) * 4 + 0]), "v"(Bout[nb][fb / 2][(fb % 2) * 4 + 1]),
+                   "v"(Bout[nb][fb / 2][(fb % 2) * 4 + 2]), "v"(Bout[nb][fb / 2][(fb % 2) * 4 + 3]));
+    } else if constexpr (DT == 1) {
+      asm volatile("" ::"v"(Bout[nb][2 * fb]), "v"(Bout[nb][2 * fb + 1]));
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; r += 4)
+        asm volatile("" ::"v"(Bout[nb][16 * fb + r]), "v"(Bout[nb][16 * fb + r + 1]), "v"(Bout[nb][16 * fb + r + 2]),
+                     "v"(Bout[nb][16 * fb + r + 3]));
+    }
+  }
+}
+
 // ---- one layer -----------------------------------------------------------
 // Output blocks are streamed in "superchunks" of SB consecutive chunks (one
 // barrier per superchunk; the chunks of a layer are contiguous in the blob).
-template <int DT> constexpr int sb_max() { return DT == 0 ? 1 : DT == 1 ? 2 : 4; }
-template <int DT> constexpr int sb_for(int fb) {
-  int s = sb_max<DT>();
-  while (s > 1 && (fb % s != 0 || fb / s < 2)) s /= 2;  // at least two per layer
+// Default chunks per superchunk by dtype (the autotuner may pick another
+// instantiated value).
+template <int DT> constexpr int sb_default() { return DT == 0 ? 1 : DT == 1 ? 2 : 4; }
+// Chunks per superchunk of a layer with fb chunks when sbx are requested:
+// the largest power of two <= sbx dividing fb with at least two superchunks.
+constexpr int sb_for(int fb, int sbx) {
+  int s = sbx;
+  while (s > 1 && (fb % s != 0 || fb / s < 2)) s /= 2;
   return s;
 }
 // LDS bytes of one ring slot for chunks of at most `chunk` bytes.
-template <int DT> constexpr int slot_bytes(int chunk) { return chunk * sb_max<DT>(); }
+constexpr int slot_bytes(int chunk, int sbx) { return chunk * sbx; }
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1.
 template <class F, int... I>
@@ -260,7 +284,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // group being consumed.
 // MODE 0: hidden epilogue into Bout.  MODE 1: head epilogue.  MODE 2: both.
 template <int DT, int NB, int KS_IN, int FB, int CB_THIS, int CB_NEXT, int KSO, int NOUT, int MODE,
-          int CHUNK, int FB_NEXT = FB>
+          int CHUNK, int FB_NEXT = FB, int SBX = sb_default<DT>()>
 __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_IN],
                                       typename Tr<DT>::frag (&Bout)[NB][KSO], const uint8_t* w_this,
                                       const uint8_t* w_next, uint8_t* lds, int& cur,
@@ -268,10 +292,10 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   using T = Tr<DT>;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
-  constexpr int SLOT = slot_bytes<DT>(CHUNK);
-  constexpr int SB = sb_for<DT>(FB);
+  constexpr int SLOT = slot_bytes(CHUNK, SBX);
+  constexpr int SB = sb_for(FB, SBX);
   constexpr int NSC = FB / SB;
-  constexpr int SB_N = sb_for<DT>(FB_NEXT);
+  constexpr int SB_N = sb_for(FB_NEXT, SBX);
   constexpr int SCB = SB * CB_THIS;
   constexpr int SCB_N = SB_N * CB_NEXT;
   static_assert(FB % SB == 0 && NSC >= 2, "layer must span at least two superchunks");
@@ -369,6 +393,10 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
         }
         if constexpr (j == NG) {
           if constexpr (DEFER) {
+            // the previous block's epilogue must be finished by the end of
+            // this block (otherwise the compiler sinks every epilogue of the
+            // layer to its end, holding all accumulators live)
+            if (fb > 0) pin_block<DT, NB, KSO>(fb - 1, Bout);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
           } else if constexpr (MODE == 2) {
@@ -416,9 +444,10 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
 // when next_blob is given (a blob of the same shape), the last layer
 // prefetches that network's first two superchunks so that the next pass can
 // start with primed = true.  *cur_io is the LDS slot of the pass's first
-// superchunk.  The caller's LDS array holds NBUF slots of slot_bytes(CHUNK).
+// superchunk.  The caller's LDS array holds NBUF slots of slot_bytes(CHUNK,
+// SBX) bytes.
 template <int DT, int WIDTH, int KS0, int NHID, int NOUT, int CHUNK, bool KEEP_LAST, int CB_AFTER,
-          int FB_AFTER = WIDTH / 32>
+          int FB_AFTER = WIDTH / 32, int SBX = sb_default<DT>()>
 __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t* blob,
                                       const typename Tr<DT>::frag (&Benc)[Tr<DT>::NB][KS0],
                                       uint8_t* lds, float (&partial)[Tr<DT>::NB][NOUT],
@@ -444,8 +473,8 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
     return DT == 2 ? make_float2(uniform_load_f32(qsc + 1 + 2 * L), uniform_load_f32(qsc + 2 + 2 * L))
                    : make_float2(1.f, 1.f);
   };
-  constexpr int SLOT = slot_bytes<DT>(CHUNK);
-  constexpr int SC0 = sb_for<DT>(FB) * CB0;  // first-layer superchunk bytes
+  constexpr int SLOT = slot_bytes(CHUNK, SBX);
+  constexpr int SC0 = sb_for(FB, SBX) * CB0;  // first-layer superchunk bytes
   if (!primed) {
     dma_chunk<SC0>(blob + off(0), lds + cur * SLOT);
     dma_chunk<SC0>(blob + off(0) + SC0, lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * SLOT);
@@ -456,29 +485,29 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
   constexpr int FB_TAIL = KEEP_LAST ? FB_AFTER : FB;
   const uint8_t* w_tail = KEEP_LAST ? w_after : (next_blob ? next_blob + off(0) : nullptr);
   // layer 0: encoding -> X; then pairs X -> Y -> X; the last layer feeds the head
-  layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK>(Benc, X, blob + off(0), blob + off(1), lds, cur,
+  layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK, FB, SBX>(Benc, X, blob + off(0), blob + off(1), lds, cur,
                                                        partial, QS(0));
   constexpr int PAIRS = (NHID - 2) / 2;
   for (int p = 0; p < PAIRS; ++p) {
     const int L = 1 + 2 * p;
-    layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(X, Y, blob + off(L), blob + off(L + 1), lds, cur,
+    layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK, FB, SBX>(X, Y, blob + off(L), blob + off(L + 1), lds, cur,
                                                          partial, QS(L));
     if ((NHID - 2) % 2 == 0 && p == PAIRS - 1) {
-      layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
+      layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK, FB, SBX>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
                                                            cur, partial, QS(L + 1));
     } else {
-      layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
+      layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK, FB, SBX>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
                                                            cur, partial, QS(L + 1));
     }
   }
   constexpr int LAST_MODE = KEEP_LAST ? 2 : 1;
   if constexpr ((NHID - 2) % 2 == 1) {
-    layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK>(X, Y, blob + off(NHID - 2), blob + off(NHID - 1),
+    layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK, FB, SBX>(X, Y, blob + off(NHID - 2), blob + off(NHID - 1),
                                                          lds, cur, partial, QS(NHID - 2));
-    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL>(Y, Blast, blob + off(NHID - 1), w_tail,
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL, SBX>(Y, Blast, blob + off(NHID - 1), w_tail,
                                                                      lds, cur, partial, QS(NHID - 1));
   } else {
-    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL>(X, Blast, blob + off(NHID - 1), w_tail,
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL, SBX>(X, Blast, blob + off(NHID - 1), w_tail,
                                                                      lds, cur, partial, QS(NHID - 1));
   }
   if (cur_io) *cur_io = cur;

@@ -84,3 +84,27 @@ def test_host_validation_before_launch():
     obj[0].field = 0
     assert lib.nedf_workspace_size(0, C.byref(sc), C.byref(r), 0) >= 16 * 8 + 256
     assert b"must" in lib.nedf_last_error() or lib.nedf_last_error()
+
+
+def test_tuning_table_host_logic():
+    """Tuning table: candidates per (kernel, dtype), get/set with rejection of
+    values that are not instantiated (host-only calls)."""
+    from paper_2308_04669_amd import _abi as A
+    from paper_2308_04669_amd import api
+    assert api.tune_candidates("march", "f32") == [1]
+    assert api.tune_candidates("march", "bf16") == [1, 2]
+    assert api.tune_candidates("nedf", "fp8") == [1, 2, 4]
+    with pytest.raises(A.NedfError):
+        api.tune_candidates("march", "fp8")
+    old = api.tune_get("nedf", "bf16")
+    assert old in (1, 2)
+    api.tune_set("nedf", "bf16", 1)
+    assert api.tune_get("nedf", "bf16") == 1
+    with pytest.raises(A.NedfError) as e:
+        api.tune_set("nedf", "bf16", 3)
+    assert e.value.status == 8
+    api.tune_set("nedf", "bf16", old)
+    lib = A.load()
+    rep = A.TuneReport()
+    # NULL arguments and a bad repetition count are rejected before any launch
+    assert lib.nedf_autotune(1, 1, None, None, None, None, None, None, 0, 1, None, C.byref(rep)) == 1
