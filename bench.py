@@ -540,7 +540,7 @@ def main():
         line["copy_calibration_bytes"] = args.copy_mib << 20
     if not args.no_cpu_baseline:
         if args.workload == "frame":
-            line["cpu_baseline"] = frame_cpu_baseline(ctx, args.cpu_pixels or 200)
+            line["cpu_baseline"] = frame_cpu_baseline(ctx, args.cpu_pixels or 2000)
         else:
             line["cpu_baseline"] = marcher_cpu_baseline(args.cpu_pixels or 6000, args.samples, args.size)
     print(json.dumps(line), flush=True)

@@ -248,12 +248,14 @@ int32_t nedf_profile_read(int32_t max_stages, char* names, double* total_ms, int
 
 /*
  * Counters of the last call that used `ws` (synchronises `stream`), host
- * int64 out[5]: [0] (ray, instance) pairs after culling (or binned pixels of
+ * int64 out[6]: [0] (ray, instance) pairs after culling (or binned pixels of
  * the last per-pixel stage), [1] work items of that list, [2] pairs decided
  * by the intersection network, [3] pairs sent to the marcher, [4] pairs the
- * network classified as misses.
+ * network classified as misses, [5] marcher pairs left after the depth test
+ * against the network's hits (a pair entering its bounding sphere beyond the
+ * pixel's nearest hit cannot change the result and is not marched).
  */
-int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out5);
+int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out6);
 
 /* ------------------------------------------------------------- hot path */
 

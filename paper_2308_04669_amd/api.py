@@ -357,10 +357,10 @@ def ws_counters(ws: Workspace) -> dict:
     """Counters of the last call on ``ws``: pairs, items, and the NeDF
     routing statistics (network-decided hits, marcher fallbacks, misses)."""
     lib = A.load()
-    out = (C.c_int64 * 5)()
+    out = (C.c_int64 * 6)()
     A.check(lib.nedf_ws_counters(ws.buf.data_ptr(), _stream(), out), "nedf_ws_counters")
     return dict(pairs=int(out[0]), items=int(out[1]), nedf_hits=int(out[2]), fallback=int(out[3]),
-                nedf_misses=int(out[4]))
+                nedf_misses=int(out[4]), fallback_marched=int(out[5]))
 
 
 def profile_enable(on: bool = True) -> None:

@@ -390,18 +390,19 @@ extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {
   return st;
 }
 
-extern "C" int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out5) {
-  if (!ws || !out5) return fail(NEDF_ERR_NULL, "nedf_ws_counters: NULL argument");
+extern "C" int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out6) {
+  if (!ws || !out6) return fail(NEDF_ERR_NULL, "nedf_ws_counters: NULL argument");
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
   WsCounters c;
   e = hipMemcpy(&c, static_cast<const uint8_t*>(ws) + 256, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
-  out5[0] = c.A.total_pairs;
-  out5[1] = c.A.total_items;
-  out5[2] = c.stats[0];
-  out5[3] = c.stats[1];
-  out5[4] = c.stats[2];
+  out6[0] = c.A.total_pairs;
+  out6[1] = c.A.total_items;
+  out6[2] = c.stats[0];
+  out6[3] = c.stats[1];
+  out6[4] = c.stats[2];
+  out6[5] = c.stats[3];
   return NEDF_OK;
 }
 

@@ -231,6 +231,62 @@ __global__ void k_scan_items(KArgs a, PairList* L) {
   L->work_counter = 0;
 }
 
+// Depth test of the fallback list (exact): a pair whose ray enters the
+// instance's bounding sphere beyond the pixel's current nearest hit cannot
+// win the min-reduce, since every marcher sample lies inside the chord and
+// the marched depth is a weighted mean of sample depths.  Kept pairs are
+// compacted into list A's pair array (free after the network stage) at list
+// B's segment offsets; list B's counts are replaced by the kept counts.
+__global__ void k_zero_fill(KArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x < NEDF_MAX_OBJECTS) a.C->B.fill[threadIdx.x] = 0;
+}
+
+__global__ void k_fallback_depth_test(KArgs a, uint2* out) {
+  PairList* B = &a.C->B;
+  const int lane = threadIdx.x & 63;
+  for (int m = 0; m < a.n_obj; ++m) {
+    const int cnt = B->cnt[m], off = B->off[m];
+    const float bound = a.obj[m].bound;
+    // uniform trip count per wave so that the ballot below sees whole waves
+    const int stride = gridDim.x * blockDim.x;
+    for (int q0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); q0 < cnt; q0 += stride) {
+      const int q = q0 + lane;
+      bool keep = false;
+      uint2 pr = make_uint2(0u, 0u);
+      if (q < cnt) {
+        pr = a.pairs[off + q];
+        const W2L g = load_w2l(a.w2l, int(pr.y));
+        float o[3], d[3], ol[3], dl[3], ta = 0.f, tb = 0.f;
+        make_ray(a.rays, pr.x, o, d);
+        to_local(g, o, d, ol, dl);
+        const bool seg = a.clip ? sphere_chord(ol, dl, bound, ta, tb) : true;
+        const float t_in = a.clip ? g.s * ta : a.t_near;
+        const float best = __uint_as_float(uint32_t(a.keys[pr.x] >> 32));
+        keep = seg && !(best < t_in);
+      }
+      const uint64_t mk = __ballot(keep);
+      if (mk) {
+        const int leader = __ffsll((unsigned long long)mk) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&B->fill[m], __popcll(mk));
+        base = __shfl(base, leader);
+        if (keep) out[off + base + __popcll(mk & ((1ull << lane) - 1ull))] = pr;
+      }
+    }
+  }
+}
+
+__global__ void k_fallback_commit(KArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  PairList* B = &a.C->B;
+  int kept = 0;
+  for (int m = 0; m < a.n_obj; ++m) {
+    B->cnt[m] = B->fill[m];
+    kept += B->fill[m];
+  }
+  a.C->stats[3] = kept;
+}
+
 // One thread per pair of an analytic object in `mask`; sequential
 // compensated scan.
 __global__ void k_march_analytic(KArgs a, uint32_t mask) {
@@ -568,7 +624,15 @@ void stage_march(const KArgs& k0, hipStream_t s, bool list_b, uint32_t analytic_
   (void)Lenc;
   KArgs k = k0;
   k.L = list_b ? &k.C->B : &k.C->A;
-  k.pairs = list_b ? k.pairsB : k.pairs;
+  if (list_b) {
+    // depth-test the fallback pairs against the network's hits, compacting
+    // them into list A's array, which the marcher then reads
+    k.pairs = k.pairsB;
+    hipLaunchKernelGGL(k_zero_fill, dim3(1), dim3(64), 0, s, k);
+    hipLaunchKernelGGL(k_fallback_depth_test, dim3(2048), dim3(256), 0, s, k, k0.pairs);
+    hipLaunchKernelGGL(k_fallback_commit, dim3(1), dim3(64), 0, s, k);
+    k.pairs = k0.pairs;
+  }
   if (list_b) {
     k.item_mask = 0;
     for (int m = 0; m < k.n_obj; ++m)

@@ -314,9 +314,103 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   // work overlaps the next block's matrix ops
   constexpr bool DEFER = (MODE == 0);
   f32x16_t prev[NB];
+  // number of reads of group e
+  constexpr auto cnt = [](int e) constexpr {
+    if (e >= E) return 0;
+    const int j = e % PER;
+    if (j == 0 || j > NG) return 4;
+    const int g = j - 1;
+    return R - g * G < G ? R - g * G : G;
+  };
+  u32x4 ring[D][G];
+  // issue the reads of group e of the superchunk at LDS byte address `base`
+  auto issue = [&](auto ec, uint32_t base) __attribute__((always_inline)) {
+    constexpr int e = decltype(ec)::value;
+    if constexpr (e < E) {
+      constexpr int k = e / PER, j = e % PER;
+      u32x4(&dst)[G] = ring[e % D];
+      const uint32_t fbase = base + uint32_t(lane) * 16u;  // fragment reads
+      const uint32_t bbase = base + uint32_t(half) * 64u;  // bias and head rows
+      if constexpr (j == 0) {
+        static_for<4>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          dst[q] = lds_read16<k * CB_THIS + BIAS + 16 * q>(bbase);
+        });
+      } else if constexpr (j <= NG) {
+        constexpr int g = j - 1;
+        static_for<cnt(e)>([&](auto rc) __attribute__((always_inline)) {
+          constexpr int r = decltype(rc)::value;
+          dst[r] = lds_read16<k * CB_THIS + (g * G + r) * 1024>(fbase);
+        });
+      } else {
+        constexpr int o = j - 1 - NG;
+        static_for<4>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          dst[q] = lds_read16<k * CB_THIS + BIAS + 128 + 128 * o + 16 * q>(bbase);
+        });
+      }
+    }
+  };
+  f32x16_t acc[NB];
+  // consume group e (already in registers cw) of superchunk sc
+  auto consume = [&](auto ec, int sc, const u32x4(&cw)[G]) __attribute__((always_inline)) {
+    constexpr int e = decltype(ec)::value;
+    constexpr int k = e / PER, j = e % PER;
+    const int fb = sc * SB + k;
+    if constexpr (j == 0) {
+      f32x16_t b0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        b0[4 * q + 0] = __uint_as_float(cw[q].x); b0[4 * q + 1] = __uint_as_float(cw[q].y);
+        b0[4 * q + 2] = __uint_as_float(cw[q].z); b0[4 * q + 3] = __uint_as_float(cw[q].w);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
+    } else if constexpr (j <= NG) {
+      mma_group<DT, NB, KS_IN, G>(cw, (j - 1) * G, R, Bin, acc);
+      if constexpr (DEFER && j == 1) {
+        if (fb > 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
+      }
+      if constexpr (j == NG) {
+        if constexpr (DEFER) {
+          // the previous block's epilogue must be finished by the end of
+          // this block (otherwise the compiler sinks every epilogue of the
+          // layer to its end, holding all accumulators live)
+          if (fb > 0) pin_block<DT, NB, KSO>(fb - 1, Bout);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
+        } else if constexpr (MODE == 2) {
+          epi_hidden<DT, NB, KSO>(fb, acc, Bout, qscale);
+        }
+      }
+    } else {
+      // head row o: partial[nb][o] += w . relu(real(acc))
+      constexpr int o = j - 1 - NG;
+      const float tr = qscale.x;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          float s = partial[nb][o];
+          s = fmaf(__uint_as_float(cw[q].x), fmaxf(acc[nb][4 * q + 0] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[q].y), fmaxf(acc[nb][4 * q + 1] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[q].z), fmaxf(acc[nb][4 * q + 2] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[q].w), fmaxf(acc[nb][4 * q + 3] * tr, 0.0f), s);
+          partial[nb][o] = s;
+        }
+      }
+    }
+  };
+  // the first D groups of superchunk 0
+  {
+    const uint32_t base0 = lds_offset(lds + cur * SLOT);
+    static_for<D>([&](auto ec) __attribute__((always_inline)) { issue(ec, base0); });
+  }
 #pragma unroll
   for (int sc = 0; sc < NSC; ++sc) {
-    // start superchunk sc + 2 (this layer, or the following one at w_next)
+    // superchunk sc is in slot `cur` (its first D groups already issued),
+    // sc + 1 in flight into cur + 1; start sc + 2 (this layer, or the
+    // following one at w_next) into the slot sc - 1 used
     const int nslot = cur + 2 >= NBUF ? cur + 2 - NBUF : cur + 2;
     uint8_t* nbuf = lds + nslot * SLOT;
     bool issued = false;
@@ -330,104 +424,47 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
       }
     }
     const uint32_t base = lds_offset(lds + cur * SLOT);
-    const uint32_t fbase = base + uint32_t(lane) * 16u;  // fragment reads
-    const uint32_t bbase = base + uint32_t(half) * 64u;  // bias and head rows
-    u32x4 ring[D][G];
-    f32x16_t acc[NB];
-    // number of reads of group e
-    constexpr auto cnt = [](int e) constexpr {
-      if (e >= E) return 0;
-      const int j = e % PER;
-      if (j == 0 || j > NG) return 4;
-      const int g = j - 1;
-      return R - g * G < G ? R - g * G : G;
-    };
-    auto issue = [&](auto ec) __attribute__((always_inline)) {
-      constexpr int e = decltype(ec)::value;
-      if constexpr (e < E) {
-        constexpr int k = e / PER, j = e % PER;
-        u32x4(&dst)[G] = ring[e % D];
-        if constexpr (j == 0) {
-          static_for<4>([&](auto qc) __attribute__((always_inline)) {
-            constexpr int q = decltype(qc)::value;
-            dst[q] = lds_read16<k * CB_THIS + BIAS + 16 * q>(bbase);
-          });
-        } else if constexpr (j <= NG) {
-          constexpr int g = j - 1;
-          static_for<cnt(e)>([&](auto rc) __attribute__((always_inline)) {
-            constexpr int r = decltype(rc)::value;
-            dst[r] = lds_read16<k * CB_THIS + (g * G + r) * 1024>(fbase);
-          });
-        } else {
-          constexpr int o = j - 1 - NG;
-          static_for<4>([&](auto qc) __attribute__((always_inline)) {
-            constexpr int q = decltype(qc)::value;
-            dst[q] = lds_read16<k * CB_THIS + BIAS + 128 + 128 * o + 16 * q>(bbase);
-          });
-        }
-      }
-    };
-    static_for<D>(issue);
     static_for<E>([&](auto ec) __attribute__((always_inline)) {
       constexpr int e = decltype(ec)::value;
-      constexpr int k = e / PER, j = e % PER;
-      const int fb = sc * SB + k;
       u32x4(&cw)[G] = ring[e % D];
       // groups e + 1 .. e + D - 1 may stay in flight
       constexpr int after = cnt(e + 1) + cnt(e + 2);
       static_assert(D == 3, "wait count assumes three groups in flight");
       lds_wait4<after>(cw[0], cw[1], cw[2], cw[3]);
-      if constexpr (j == 0) {
-        f32x16_t b0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          b0[4 * q + 0] = __uint_as_float(cw[q].x); b0[4 * q + 1] = __uint_as_float(cw[q].y);
-          b0[4 * q + 2] = __uint_as_float(cw[q].z); b0[4 * q + 3] = __uint_as_float(cw[q].w);
+      if constexpr (e + 1 < E) {
+        consume(ec, sc, cw);
+        issue(std::integral_constant<int, e + D>{}, base);
+      } else if (sc + 1 < NSC) {
+        // last group of a superchunk that is not the layer's last: every
+        // read of this superchunk has completed, so pass the barrier first,
+        // start the next superchunk's reads, and only then run this
+        // group's matrix ops, which cover the reads' latency
+        u32x4 tail[G] = {cw[0], cw[1], cw[2], cw[3]};
+        // superchunk sc + 1 must have landed; sc + 2's copies may stay in flight
+        if (issued) {
+          if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB)>();
+          else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024)>();
+        } else {
+          dma_wait_barrier();
         }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
-      } else if constexpr (j <= NG) {
-        mma_group<DT, NB, KS_IN, G>(cw, (j - 1) * G, R, Bin, acc);
-        if constexpr (DEFER && j == 1) {
-          if (fb > 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
-        }
-        if constexpr (j == NG) {
-          if constexpr (DEFER) {
-            // the previous block's epilogue must be finished by the end of
-            // this block (otherwise the compiler sinks every epilogue of the
-            // layer to its end, holding all accumulators live)
-            if (fb > 0) pin_block<DT, NB, KSO>(fb - 1, Bout);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
-          } else if constexpr (MODE == 2) {
-            epi_hidden<DT, NB, KSO>(fb, acc, Bout, qscale);
-          }
-        }
+        const uint32_t nbase = lds_offset(lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * SLOT);
+        static_for<D>([&](auto gc) __attribute__((always_inline)) { issue(gc, nbase); });
+        // the matrix ops below may not move above the reads just issued
+        asm volatile("" : "+v"(tail[0]), "+v"(tail[1]), "+v"(tail[2]), "+v"(tail[3]));
+        consume(ec, sc, tail);
       } else {
-        // head row o: partial[nb][o] += w . relu(real(acc))
-        constexpr int o = j - 1 - NG;
-        const float tr = qscale.x;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            float s = partial[nb][o];
-            s = fmaf(__uint_as_float(cw[q].x), fmaxf(acc[nb][4 * q + 0] * tr, 0.0f), s);
-            s = fmaf(__uint_as_float(cw[q].y), fmaxf(acc[nb][4 * q + 1] * tr, 0.0f), s);
-            s = fmaf(__uint_as_float(cw[q].z), fmaxf(acc[nb][4 * q + 2] * tr, 0.0f), s);
-            s = fmaf(__uint_as_float(cw[q].w), fmaxf(acc[nb][4 * q + 3] * tr, 0.0f), s);
-            partial[nb][o] = s;
-          }
-        }
+        consume(ec, sc, cw);
       }
-      issue(std::integral_constant<int, e + D>{});
     });
-    // superchunk sc + 1 must have landed; sc + 2's copies may stay in flight
-    if (issued) {
-      if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB)>();
-      else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024)>();
-    } else {
-      dma_wait_barrier();
+    if (sc + 1 == NSC) {
+      // the layer's last superchunk: the next layer's first superchunk must
+      // have landed; its second may stay in flight
+      if (issued) {
+        if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB)>();
+        else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024)>();
+      } else {
+        dma_wait_barrier();
+      }
     }
     cur = cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1;
   }
