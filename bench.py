@@ -465,6 +465,10 @@ def marcher_bench(args):
         assert api.check_status(ws) == 0
         return ms, stages, pairs
 
+    # launch shape of the marcher from the library's autotuner, on this frame
+    tsc = api.make_scene([api.object_from_model(m, args.dtype) for m in models], insts)
+    tune = api.autotune("march", args.dtype, tsc, rays, api.march_opts(args.samples, dtype=args.dtype), reps=1)
+    log(f"autotune {tune}")
     ms, stages, pairs = run(args.dtype, args.steps, args.warmup)
     mlp_ms, mlp_cnt = stages.get("march.mlp", (0.0, 1))
     avg_mlp = mlp_ms / max(mlp_cnt, 1)
@@ -492,6 +496,7 @@ def marcher_bench(args):
                      "kernel": "march.mlp", "avg_launch_ms": avg_mlp,
                      "flop_per_launch": flops},
         "stages_ms_per_step": stage_table(stages),
+        "autotune": tune,
     }
     if args.dtype != "f32" and args.f32_steps > 0:
         ms32, st32, _ = run("f32", args.f32_steps, 1)

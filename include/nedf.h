@@ -380,13 +380,15 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
 /*
  * Autotuning.  Not a step of the paper's method: a tuning aid for the grouped
  * launches that evaluate every (ray, instance) pair of Alg. 1 per object.
- * The tunable tile of the matrix-core kernels is the number of
- * 32-row weight chunks streamed into LDS per copy and barrier ("superchunk");
- * it is kept per kernel and dtype in a process-wide table guarded by a mutex
- * (the library's only global state besides the profiler).
+ * The tunable launch shape of the matrix-core kernels is encoded as
+ * 10 * occupancy + superchunk: the number of persistent workgroups per CU
+ * (1 or 2) and the number of 32-row weight chunks streamed into LDS per copy
+ * and barrier (1, 2 or 4).  It is kept per kernel and dtype in a process-wide
+ * table guarded by a mutex (the library's only global state besides the
+ * profiler).
  *
  * nedf_tune_candidates writes the values instantiated for (kernel, dtype) into
- * out (up to 4) and their number into n.  nedf_tune_get/nedf_tune_set read and
+ * out (up to NEDF_TUNE_MAX) and their number into n.  nedf_tune_get/nedf_tune_set read and
  * write the table (set rejects values that are not candidates with
  * NEDF_ERR_UNSUPPORTED).  nedf_autotune runs the stage of `kernel` on the
  * caller's inputs once per candidate (`reps` timed runs each, after one
@@ -398,12 +400,13 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
  * those calls.  Synchronises `stream`.
  */
 typedef enum { NEDF_TUNE_MARCH = 0, NEDF_TUNE_NEDF = 1 } nedf_tune_kernel;
+#define NEDF_TUNE_MAX 8
 
 typedef struct {
   int32_t kernel, dtype;
   int32_t n_candidates;
-  int32_t candidate[4];
-  float ms[4];
+  int32_t candidate[NEDF_TUNE_MAX];
+  float ms[NEDF_TUNE_MAX];
   int32_t chosen;
 } nedf_tune_report;
 

@@ -74,9 +74,12 @@ class TrainOpts(C.Structure):
                 ("w_hit", C.c_float), ("bound", C.c_float)]
 
 
+TUNE_MAX = 8
+
+
 class TuneReport(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("dtype", C.c_int32), ("n_candidates", C.c_int32),
-                ("candidate", C.c_int32 * 4), ("ms", C.c_float * 4), ("chosen", C.c_int32)]
+                ("candidate", C.c_int32 * TUNE_MAX), ("ms", C.c_float * TUNE_MAX), ("chosen", C.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point

@@ -439,7 +439,7 @@ class Trainer:
 # ---------------------------------------------------------------- tuning
 def tune_candidates(kernel: str, dtype: str) -> list:
     lib = A.load()
-    out, n = (C.c_int32 * 4)(), C.c_int32(0)
+    out, n = (C.c_int32 * A.TUNE_MAX)(), C.c_int32(0)
     A.check(lib.nedf_tune_candidates(A.TUNE_KERNELS[kernel], A.DTYPES[dtype], out, C.byref(n)),
             "nedf_tune_candidates")
     return [int(out[i]) for i in range(n.value)]

@@ -711,14 +711,17 @@ extern "C" int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* 
 // ---- tuning table and autotuner ---------------------------------------------
 namespace {
 std::mutex g_tune_mu;
-// [kernel][dtype]: chunks per superchunk
-int g_tune[2][3] = {{1, 2, 4}, {1, 2, 4}};
+// [kernel][dtype]: 10 * workgroups per CU + chunks per superchunk
+int g_tune[2][3] = {{11, 12, 14}, {11, 12, 14}};
 
 int tune_candidates(int kernel, int dtype, int32_t* out) {
   if (kernel < 0 || kernel > 1 || dtype < 0 || dtype > 2) return 0;
-  if (dtype == NEDF_F32) { out[0] = 1; return 1; }
-  if (dtype == NEDF_BF16) { out[0] = 1; out[1] = 2; return 2; }
-  if (kernel == NEDF_TUNE_NEDF) { out[0] = 1; out[1] = 2; out[2] = 4; return 3; }
+  if (dtype == NEDF_F32) { out[0] = 11; return 1; }
+  if (dtype == NEDF_BF16) { out[0] = 11; out[1] = 12; out[2] = 21; return 3; }
+  if (kernel == NEDF_TUNE_NEDF) {
+    out[0] = 11; out[1] = 12; out[2] = 14; out[3] = 21; out[4] = 22;
+    return 5;
+  }
   return 0;  // no FP8 marcher
 }
 }  // namespace
@@ -740,14 +743,14 @@ extern "C" int32_t nedf_tune_candidates(int32_t kernel, int32_t dtype, int32_t* 
 
 extern "C" int32_t nedf_tune_get(int32_t kernel, int32_t dtype, int32_t* value) {
   if (!value) return fail(NEDF_ERR_NULL, "nedf_tune_get: NULL argument");
-  int32_t c[4];
+  int32_t c[NEDF_TUNE_MAX];
   if (tune_candidates(kernel, dtype, c) == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
   *value = tune_value(kernel, dtype);
   return NEDF_OK;
 }
 
 extern "C" int32_t nedf_tune_set(int32_t kernel, int32_t dtype, int32_t value) {
-  int32_t c[4];
+  int32_t c[NEDF_TUNE_MAX];
   const int n = tune_candidates(kernel, dtype, c);
   if (n == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
   bool ok = false;
@@ -763,7 +766,7 @@ extern "C" int32_t nedf_autotune(int32_t kernel, int32_t dtype, const nedf_scene
                                  int32_t reps, nedf_stream_t stream, nedf_tune_report* report) {
   if (!scene || !rays || !opts || !report) return fail(NEDF_ERR_NULL, "nedf_autotune: NULL argument");
   if (reps < 1 || reps > 100) return fail(NEDF_ERR_SHAPE, "reps must be 1..100");
-  int32_t cand[4];
+  int32_t cand[NEDF_TUNE_MAX];
   const int n = tune_candidates(kernel, dtype, cand);
   if (n == 0) return fail(NEDF_ERR_UNSUPPORTED, "no tunable kernel for this (kernel, dtype)");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -332,8 +332,8 @@ __global__ void k_march_analytic(KArgs a, uint32_t mask) {
 // one object from list a.L; each wave marches its pair in chunks of 32
 // samples through the register-resident density network, then scans the
 // chunk's optical depths across the wave.
-template <int DT, int WIDTH, int NHID, int L, int SBX>
-__global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
@@ -436,16 +436,19 @@ __global__ __launch_bounds__(256, 1) void k_march_mlp(KArgs a) {
 // object; each lane pair evaluates the intersection network on its pair's
 // line coordinates.  Confident hits go to the key buffer, uncertain pairs
 // (and origins inside the bounding sphere) to list B for the marcher.
-template <int DT, int WIDTH, int NHID, int L, int SBX>
-__global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
   __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
+  // per-lane pair state parked across the network (keeps registers free)
+  __shared__ __attribute__((aligned(16))) uint8_t s_stash[16 * eng::THREADS];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
+  const uint32_t stash = eng::lds_offset(s_stash) + 16u * threadIdx.x;
   PairList* PL = &a.C->A;
   PairList* FB = &a.C->B;
   const int total = PL->total_items;
@@ -454,6 +457,8 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
   int item = s_item;
   int slot = 0;
   bool primed = false;
+  // routing counts, per wave, flushed once at the end
+  int n_hit = 0, n_fb = 0, n_miss = 0;
   while (item < total) {
     // claim the next item now so that its weights stream in behind this pass
     __syncthreads();
@@ -481,21 +486,33 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
     const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
     typename T::frag Benc[NB][KS0];
     const float in_scale = DT == 2 ? uniform_load_f32(blob + uniform_load_u64(&hb->off_scales)) : 1.0f;
-    eng::encode_input<DT, 6, L, KS0>(pl, half, Benc[0], in_scale);
+    // lane-half-dependent encoding constants are recomputed per pass rather
+    // than hoisted out of the loop (where they would stay live, and spill,
+    // across the network)
+    int half_v = half;
+    asm volatile("" : "+v"(half_v));
+    eng::encode_input<DT, 6, L, KS0>(pl, half_v, Benc[0], in_scale);
+    // ray and instance ids (< 2^31, flags in bit 31), t_perp and s
+    eng::lds_write16(stash, eng::u32x4{pr.x | (valid ? 0x80000000u : 0u), pr.y | (inside ? 0x80000000u : 0u),
+                                       __float_as_uint(tperp), __float_as_uint(g.s)});
     float partial[NB][2] = {{0.f, 0.f}};
     typename T::frag Blast[NB][KSH];
     eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
                                                                          nullptr, &slot,
                                                         next_blob, primed);
     primed = next_blob != nullptr;
+    eng::u32x4 st = eng::lds_read16<0>(stash), d1 = st, d2 = st, d3 = st;
+    eng::lds_wait4<0>(st, d1, d2, d3);
+    const uint2 prs = make_uint2(st.x & 0x7FFFFFFFu, st.y & 0x7FFFFFFFu);
+    const bool valid_s = (st.x >> 31) != 0, inside_s = (st.y >> 31) != 0;
     const float mu_hat = partial[0][0] + __shfl_xor(partial[0][0], 32) + hbias[0];
     const float z = partial[0][1] + __shfl_xor(partial[0][1], 32) + hbias[1];
     const float p = sigmoidf_(z);
-    const float D = g.s * (tperp - l * fminf(fmaxf(mu_hat, -1.0f), 1.0f));
-    const bool mine = valid && half == 0;
-    const bool to_fb = mine && (inside || (p >= a.p_lo && p <= a.p_hi));
+    const float D = __uint_as_float(st.w) * (__uint_as_float(st.z) - l * fminf(fmaxf(mu_hat, -1.0f), 1.0f));
+    const bool mine = valid_s && half == 0;
+    const bool to_fb = mine && (inside_s || (p >= a.p_lo && p <= a.p_hi));
     const bool hit = mine && !to_fb && p > a.p_hi && D > 0.0f;
-    if (hit) emit_key(a, pr.x, pr.y, D);
+    if (hit) emit_key(a, prs.x, prs.y, D);
     // wave-aggregated push into the object's segment of list B
     const uint64_t m = __ballot(to_fb);
     if (m) {
@@ -503,15 +520,18 @@ __global__ __launch_bounds__(256, 1) void k_nedf(KArgs a) {
       int base = 0;
       if (lane == leader) base = atomicAdd(&FB->cnt[obj], __popcll(m));
       base = __shfl(base, leader);
-      if (to_fb) a.pairsB[FB->off[obj] + base + __popcll(m & ((1ull << lane) - 1ull))] = pr;
+      if (to_fb) a.pairsB[FB->off[obj] + base + __popcll(m & ((1ull << lane) - 1ull))] = prs;
     }
     const uint64_t mh = __ballot(hit), mv = __ballot(mine);
-    if (lane == 0) {
-      atomicAdd(&a.C->stats[0], __popcll(mh));
-      atomicAdd(&a.C->stats[1], __popcll(m));
-      atomicAdd(&a.C->stats[2], __popcll(mv) - __popcll(mh) - __popcll(m));
-    }
+    n_hit += __popcll(mh);
+    n_fb += __popcll(m);
+    n_miss += __popcll(mv) - __popcll(mh) - __popcll(m);
     item = next;
+  }
+  if (lane == 0 && (n_hit | n_fb | n_miss)) {
+    atomicAdd(&a.C->stats[0], n_hit);
+    atomicAdd(&a.C->stats[1], n_fb);
+    atomicAdd(&a.C->stats[2], n_miss);
   }
 }
 
@@ -540,33 +560,43 @@ int cu_count() {
   return ncu;
 }
 
-// The superchunk size of the 256-wide BF16/FP8 kernels comes from the tuning
-// table (nedf_autotune); other shapes use the default.
+// Launch shape of the 256-wide BF16/FP8 kernels from the tuning table: value
+// 10 * occupancy + superchunk (workgroups per CU, chunks per copy); other
+// shapes use one workgroup per CU and the default superchunk.  The grid is
+// persistent: one workgroup per CU and occupancy level.
 template <int DT, int WIDTH, int NHID, int L>
 void launch_march_mlp(const KArgs& k, hipStream_t s) {
-  const dim3 g(cu_count()), b(eng::THREADS);
+  const dim3 b(eng::THREADS);
   if constexpr (DT == 1 && WIDTH == 256) {
-    if (tune_value(NEDF_TUNE_MARCH, DT) == 1) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1>), g, b, 0, s, k);
+    const int v = tune_value(NEDF_TUNE_MARCH, DT);
+    if (v == 11) {
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1>), dim3(cu_count()), b, 0, s, k);
+      return;
+    }
+    if (v == 21) {
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 2>), dim3(2 * cu_count()), b, 0, s, k);
       return;
     }
   }
-  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>()>), g, b, 0, s, k);
+  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>(), 1>), dim3(cu_count()), b, 0, s, k);
 }
 
 template <int DT>
 void launch_nedf_net(const KArgs& k, hipStream_t s) {
-  const dim3 g(cu_count()), b(eng::THREADS);
-  const int sb = tune_value(NEDF_TUNE_NEDF, DT);
+  const dim3 b(eng::THREADS), g1(cu_count()), g2(2 * cu_count());
+  const int v = tune_value(NEDF_TUNE_NEDF, DT);
   if constexpr (DT == 2) {
-    if (sb == 1) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1>), g, b, 0, s, k);
-    else if (sb == 2) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2>), g, b, 0, s, k);
-    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4>), g, b, 0, s, k);
+    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1>), g1, b, 0, s, k);
+    else if (v == 12) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1>), g1, b, 0, s, k);
+    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2>), g2, b, 0, s, k);
+    else if (v == 22) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 2>), g2, b, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1>), g1, b, 0, s, k);
   } else if constexpr (DT == 1) {
-    if (sb == 1) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1>), g, b, 0, s, k);
-    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2>), g, b, 0, s, k);
+    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1>), g1, b, 0, s, k);
+    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2>), g2, b, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1>), g1, b, 0, s, k);
   } else {
-    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1>), g, b, 0, s, k);
+    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1>), g1, b, 0, s, k);
   }
 }
 

@@ -174,6 +174,12 @@ __device__ __forceinline__ u32x4 lds_read16(uint32_t addr) {
   return v;
 }
 
+// A 16-byte LDS write issued the same way (no wait is implied by the
+// compiler; reads of the same address by the same wave return it in order).
+__device__ __forceinline__ void lds_write16(uint32_t addr, u32x4 v) {
+  asm volatile("ds_write_b128 %0, %1" ::"v"(addr), "v"(v));
+}
+
 template <int N>
 __device__ __forceinline__ void lds_wait4(u32x4& a, u32x4& b, u32x4& c, u32x4& d) {
   asm volatile("s_waitcnt lgkmcnt(%4)" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N));
@@ -314,64 +320,104 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   // work overlaps the next block's matrix ops
   constexpr bool DEFER = (MODE == 0);
   f32x16_t prev[NB];
+  // Read groups of a superchunk in consumption order: the bias of its first
+  // block, then per block k its fragment groups, with the bias of block k + 1
+  // placed before block k's last fragment group (so that initialising the
+  // next accumulator overlaps block k's last matrix ops), then block k's head
+  // rows.  kind 0 bias, 1 fragment group (idx g), 2 head row (idx o).
+  struct Grp {
+    int kind, k, idx;
+  };
+  constexpr auto grp = [](int e) constexpr {
+    int n = 0;
+    for (int k = 0; k < SB; ++k) {
+      if (k == 0) {
+        if (n == e) return Grp{0, 0, 0};
+        ++n;
+      }
+      for (int g = 0; g < NG; ++g) {
+        if (g == NG - 1 && k + 1 < SB) {
+          if (n == e) return Grp{0, k + 1, 0};
+          ++n;
+        }
+        if (n == e) return Grp{1, k, g};
+        ++n;
+      }
+      for (int o = 0; o < NH; ++o) {
+        if (n == e) return Grp{2, k, o};
+        ++n;
+      }
+    }
+    return Grp{-1, 0, 0};
+  };
   // number of reads of group e
-  constexpr auto cnt = [](int e) constexpr {
+  constexpr auto cnt = [grp](int e) constexpr {
     if (e >= E) return 0;
-    const int j = e % PER;
-    if (j == 0 || j > NG) return 4;
-    const int g = j - 1;
-    return R - g * G < G ? R - g * G : G;
+    const Grp q = grp(e);
+    if (q.kind != 1) return 4;
+    return R - q.idx * G < G ? R - q.idx * G : G;
   };
   u32x4 ring[D][G];
   // issue the reads of group e of the superchunk at LDS byte address `base`
   auto issue = [&](auto ec, uint32_t base) __attribute__((always_inline)) {
     constexpr int e = decltype(ec)::value;
     if constexpr (e < E) {
-      constexpr int k = e / PER, j = e % PER;
+      constexpr Grp q = grp(e);
+      constexpr int k = q.k;
       u32x4(&dst)[G] = ring[e % D];
       const uint32_t fbase = base + uint32_t(lane) * 16u;  // fragment reads
       const uint32_t bbase = base + uint32_t(half) * 64u;  // bias and head rows
-      if constexpr (j == 0) {
+      if constexpr (q.kind == 0) {
         static_for<4>([&](auto qc) __attribute__((always_inline)) {
-          constexpr int q = decltype(qc)::value;
-          dst[q] = lds_read16<k * CB_THIS + BIAS + 16 * q>(bbase);
+          constexpr int i = decltype(qc)::value;
+          dst[i] = lds_read16<k * CB_THIS + BIAS + 16 * i>(bbase);
         });
-      } else if constexpr (j <= NG) {
-        constexpr int g = j - 1;
+      } else if constexpr (q.kind == 1) {
+        constexpr int g = q.idx;
         static_for<cnt(e)>([&](auto rc) __attribute__((always_inline)) {
           constexpr int r = decltype(rc)::value;
           dst[r] = lds_read16<k * CB_THIS + (g * G + r) * 1024>(fbase);
         });
       } else {
-        constexpr int o = j - 1 - NG;
+        constexpr int o = q.idx;
         static_for<4>([&](auto qc) __attribute__((always_inline)) {
-          constexpr int q = decltype(qc)::value;
-          dst[q] = lds_read16<k * CB_THIS + BIAS + 128 + 128 * o + 16 * q>(bbase);
+          constexpr int i = decltype(qc)::value;
+          dst[i] = lds_read16<k * CB_THIS + BIAS + 128 + 128 * o + 16 * i>(bbase);
         });
       }
     }
   };
-  f32x16_t acc[NB];
+  // accumulators alternate between consecutive blocks of a superchunk
+  f32x16_t acc2[2][NB];
   // consume group e (already in registers cw) of superchunk sc
   auto consume = [&](auto ec, int sc, const u32x4(&cw)[G]) __attribute__((always_inline)) {
     constexpr int e = decltype(ec)::value;
-    constexpr int k = e / PER, j = e % PER;
+    constexpr Grp q = grp(e);
+    constexpr int k = q.k;
+    f32x16_t(&acc)[NB] = acc2[k & 1];
     const int fb = sc * SB + k;
-    if constexpr (j == 0) {
+    if constexpr (q.kind == 0) {
       f32x16_t b0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        b0[4 * q + 0] = __uint_as_float(cw[q].x); b0[4 * q + 1] = __uint_as_float(cw[q].y);
-        b0[4 * q + 2] = __uint_as_float(cw[q].z); b0[4 * q + 3] = __uint_as_float(cw[q].w);
+      for (int i = 0; i < 4; ++i) {
+        b0[4 * i + 0] = __uint_as_float(cw[i].x); b0[4 * i + 1] = __uint_as_float(cw[i].y);
+        b0[4 * i + 2] = __uint_as_float(cw[i].z); b0[4 * i + 3] = __uint_as_float(cw[i].w);
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
-    } else if constexpr (j <= NG) {
-      mma_group<DT, NB, KS_IN, G>(cw, (j - 1) * G, R, Bin, acc);
-      if constexpr (DEFER && j == 1) {
+    } else if constexpr (q.kind == 1) {
+      constexpr int g = q.idx;
+      mma_group<DT, NB, KS_IN, G>(cw, g * G, R, Bin, acc);
+      if constexpr (DEFER && g == 0) {
         if (fb > 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
       }
-      if constexpr (j == NG) {
+      // interleave vector work (epilogues, accumulator set-up) with the
+      // matrix ops instead of letting it pile up between two of them
+      static_for<mma_per_group<DT, NB, G>()>([&](auto) __attribute__((always_inline)) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix op
+        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);  // up to five VALU ops
+      });
+      if constexpr (g == NG - 1) {
         if constexpr (DEFER) {
           // the previous block's epilogue must be finished by the end of
           // this block (otherwise the compiler sinks every epilogue of the
@@ -385,20 +431,23 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
       }
     } else {
       // head row o: partial[nb][o] += w . relu(real(acc))
-      constexpr int o = j - 1 - NG;
+      constexpr int o = q.idx;
       const float tr = qscale.x;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           float s = partial[nb][o];
-          s = fmaf(__uint_as_float(cw[q].x), fmaxf(acc[nb][4 * q + 0] * tr, 0.0f), s);
-          s = fmaf(__uint_as_float(cw[q].y), fmaxf(acc[nb][4 * q + 1] * tr, 0.0f), s);
-          s = fmaf(__uint_as_float(cw[q].z), fmaxf(acc[nb][4 * q + 2] * tr, 0.0f), s);
-          s = fmaf(__uint_as_float(cw[q].w), fmaxf(acc[nb][4 * q + 3] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[i].x), fmaxf(acc[nb][4 * i + 0] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[i].y), fmaxf(acc[nb][4 * i + 1] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[i].z), fmaxf(acc[nb][4 * i + 2] * tr, 0.0f), s);
+          s = fmaf(__uint_as_float(cw[i].w), fmaxf(acc[nb][4 * i + 3] * tr, 0.0f), s);
           partial[nb][o] = s;
         }
       }
+      // computed here, not sunk past the layer with the head rows held live
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) asm volatile("" : "+v"(partial[nb][o]));
     }
   };
   // the first D groups of superchunk 0

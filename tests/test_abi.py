@@ -91,15 +91,15 @@ def test_tuning_table_host_logic():
     values that are not instantiated (host-only calls)."""
     from paper_2308_04669_amd import _abi as A
     from paper_2308_04669_amd import api
-    assert api.tune_candidates("march", "f32") == [1]
-    assert api.tune_candidates("march", "bf16") == [1, 2]
-    assert api.tune_candidates("nedf", "fp8") == [1, 2, 4]
+    assert api.tune_candidates("march", "f32") == [11]
+    assert api.tune_candidates("march", "bf16") == [11, 12, 21]
+    assert api.tune_candidates("nedf", "fp8") == [11, 12, 14, 21, 22]
     with pytest.raises(A.NedfError):
         api.tune_candidates("march", "fp8")
     old = api.tune_get("nedf", "bf16")
-    assert old in (1, 2)
-    api.tune_set("nedf", "bf16", 1)
-    assert api.tune_get("nedf", "bf16") == 1
+    assert old in (11, 12, 21)
+    api.tune_set("nedf", "bf16", 21)
+    assert api.tune_get("nedf", "bf16") == 21
     with pytest.raises(A.NedfError) as e:
         api.tune_set("nedf", "bf16", 3)
     assert e.value.status == 8
