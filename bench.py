@@ -202,6 +202,9 @@ def frame_bench(args):
                                  reps=1, ws=ws),
             "march": api.autotune("march", args.dtype, sc, trays,
                                   api.march_opts(args.fallback_samples, dtype=args.dtype), reps=1)}
+    tune["slabs"] = api.autotune("slabs", args.dtype, sc, rays,
+                                 api.infer_opts(args.dtype, refine_steps=3, n_samples=args.fallback_samples),
+                                 reps=1, ws=ws)
     log(f"autotune {tune}")
     for _ in range(args.warmup):
         frame()
@@ -252,14 +255,18 @@ def frame_bench(args):
                "median_depth_err": med, "median_depth_err_frac_extent": med / extent, "extent": extent,
                "reference": "library FP32 marcher, 192 samples per pair"}
 
-    # dominant kernel of the timed frames
+    # dominant kernel of the timed frames, per launch: the network runs once
+    # per depth slab, so a launch's algorithmic work is the frame's evaluated
+    # pairs over the launches per frame
     ev = st["nedf_hits"] + st["fallback"] + st["nedf_misses"]
+    net_ms, net_n = stages.get("infer.nedf/net", (0.0, 1))
+    launches = max(net_n // max(args.steps, 1), 1)
     cand = {
-        "infer.nedf": (per.get("infer.nedf", 0.0), 2.0 * MAC_NEDF * ev, args.dtype),
-        "fallback.mlp": (per.get("fallback.mlp", 0.0), 2.0 * MAC_PER_SAMPLE * args.fallback_samples * st["fallback"],
-                         args.dtype),
+        "infer.nedf/net": (net_ms / max(net_n, 1), 2.0 * MAC_NEDF * ev / launches, args.dtype),
+        "fallback.mlp": (per.get("fallback.mlp", 0.0), 2.0 * MAC_PER_SAMPLE * args.fallback_samples *
+                         st.get("fallback_marched", st["fallback"]), args.dtype),
     }
-    kname = max(cand, key=lambda k: cand[k][0])
+    kname = max(cand, key=lambda k: cand[k][0] * (launches if k == "infer.nedf/net" else 1))
     k_ms, k_flops, k_dt = cand[kname]
     achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
     peak = PEAK_TFLOPS[k_dt]
@@ -282,7 +289,8 @@ def frame_bench(args):
                                f"({args.fallback_samples} samples) + 3-step refine, "
                                + ("depth+ID only" if args.no_shading else
                                   "K=8 deferred shading, 2 point lights with shadow rays"),
-                   "pairs_per_frame": int(ev), "nedf_hits": int(st["nedf_hits"]),
+                   "pairs_per_frame": int(st["culled_pairs"]), "network_pairs_evaluated": int(ev),
+                   "nedf_hits": int(st["nedf_hits"]), "fallback_pairs_marched": int(st["fallback_marched"]),
                    "fallback_pairs": int(st["fallback"]), "fallback_frac": st["fallback"] / max(ev, 1)},
         "depth_id": {"rays_per_s": n / (depth_ms * 1e-3) if depth_ms > 0 else None, "ms": depth_ms,
                      "vs_fp32_marcher": (n / (depth_ms * 1e-3)) / marcher_rps if depth_ms > 0 else None},
@@ -290,7 +298,7 @@ def frame_bench(args):
         "quality": quality,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None, "kernel": kname, "avg_launch_ms": k_ms,
-                     "flop_per_launch": k_flops},
+                     "flop_per_launch": k_flops, "launches_per_frame": launches if kname.endswith("net") else 1},
         "stages_ms_per_step": per,
         "autotune": tune,
         "training": train,
@@ -375,6 +383,9 @@ def precision_bench(args):
         scn = api.make_scene(objs, insts)
         depth = torch.empty(n, dtype=torch.float32, device="cuda")
         ident = torch.empty(n, dtype=torch.int32, device="cuda")
+        io = api.infer_opts(dens_dt, refine_steps=refine, n_samples=args.fallback_samples)
+        api.autotune("nedf", nedf_dt, scn, rays, io, reps=1, ws=ws)
+        api.autotune("slabs", nedf_dt, scn, rays, io, reps=1, ws=ws)
 
         def step():
             scn.inst_w2l = api.compose_transforms(scn.inst_G)

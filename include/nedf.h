@@ -247,15 +247,16 @@ int32_t nedf_profile_read(int32_t max_stages, char* names, double* total_ms, int
                           int32_t* n_stages);
 
 /*
- * Counters of the last call that used `ws` (synchronises `stream`), host
- * int64 out[6]: [0] (ray, instance) pairs after culling (or binned pixels of
+ * Counters of the last call that used `ws` (synchronises `stream`):
+ * [0] (ray, instance) pairs after culling (or binned pixels of
  * the last per-pixel stage), [1] work items of that list, [2] pairs decided
  * by the intersection network, [3] pairs sent to the marcher, [4] pairs the
  * network classified as misses, [5] marcher pairs left after the depth test
  * against the network's hits (a pair entering its bounding sphere beyond the
- * pixel's nearest hit cannot change the result and is not marched).
+ * pixel's nearest hit cannot change the result and is not marched), [6]
+ * (ray, instance) pairs after the last culling.  Host int64 out[7].
  */
-int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out6);
+int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out7);
 
 /* ------------------------------------------------------------- hot path */
 
@@ -383,7 +384,11 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
  * The tunable launch shape of the matrix-core kernels is encoded as
  * 10 * occupancy + superchunk: the number of persistent workgroups per CU
  * (1 or 2) and the number of 32-row weight chunks streamed into LDS per copy
- * and barrier (1, 2 or 4).  It is kept per kernel and dtype in a process-wide
+ * and barrier (1, 2 or 4).  NEDF_TUNE_SLABS is the number of depth slabs in
+ * which nedf_infer_depth_id runs the intersection network front to back
+ * (1, 2, 4 or 8; an exact pruning: a pair whose smallest possible depth lies
+ * beyond the pixel's nearest hit is skipped).  It is kept per kernel and
+ * dtype in a process-wide
  * table guarded by a mutex (the library's only global state besides the
  * profiler).
  *
@@ -394,12 +399,13 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
  * caller's inputs once per candidate (`reps` timed runs each, after one
  * warm-up), keeps the fastest in the table and describes the trial in
  * *report (host).  `opts` is a nedf_march_opts* for NEDF_TUNE_MARCH (plain
- * marcher, nedf_march_depth) and a nedf_infer_opts* for NEDF_TUNE_NEDF
- * (nedf_infer_depth_id, tuning the intersection-network kernel of `dtype`);
+ * marcher, nedf_march_depth) and a nedf_infer_opts* for NEDF_TUNE_NEDF and
+ * NEDF_TUNE_SLABS (nedf_infer_depth_id, tuning the intersection-network
+ * kernel of `dtype`);
  * depth and id are caller-owned device outputs of n_rays elements; ws as for
  * those calls.  Synchronises `stream`.
  */
-typedef enum { NEDF_TUNE_MARCH = 0, NEDF_TUNE_NEDF = 1 } nedf_tune_kernel;
+typedef enum { NEDF_TUNE_MARCH = 0, NEDF_TUNE_NEDF = 1, NEDF_TUNE_SLABS = 2 } nedf_tune_kernel;
 #define NEDF_TUNE_MAX 8
 
 typedef struct {

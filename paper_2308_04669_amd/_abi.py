@@ -18,7 +18,7 @@ FIELDS = {"sphere": 0, "slab": 1, "mlp": 2}
 SIGMA_MODES = {"softplus": 0, "softplus_masked": 1, "sdf": 2}
 IN_KINDS = {"xyz": 0, "pluecker": 1}
 OPS = {"march": 0, "infer": 1, "shade": 2, "shadow": 3}
-TUNE_KERNELS = {"march": 0, "nedf": 1}
+TUNE_KERNELS = {"march": 0, "nedf": 1, "slabs": 2}
 
 
 class MlpShape(C.Structure):

@@ -357,10 +357,10 @@ def ws_counters(ws: Workspace) -> dict:
     """Counters of the last call on ``ws``: pairs, items, and the NeDF
     routing statistics (network-decided hits, marcher fallbacks, misses)."""
     lib = A.load()
-    out = (C.c_int64 * 6)()
+    out = (C.c_int64 * 7)()
     A.check(lib.nedf_ws_counters(ws.buf.data_ptr(), _stream(), out), "nedf_ws_counters")
     return dict(pairs=int(out[0]), items=int(out[1]), nedf_hits=int(out[2]), fallback=int(out[3]),
-                nedf_misses=int(out[4]), fallback_marched=int(out[5]))
+                nedf_misses=int(out[4]), fallback_marched=int(out[5]), culled_pairs=int(out[6]))
 
 
 def profile_enable(on: bool = True) -> None:
@@ -468,7 +468,7 @@ def autotune(kernel: str, dtype: str, scene: SceneGPU, rays: A.Rays, opts, reps:
     depth = torch.empty(n, dtype=torch.float32, device=dev)
     ident = torch.empty(n, dtype=torch.int32, device=dev)
     sc = scene.struct()
-    op = A.OPS["march"] if kernel == "march" else A.OPS["infer"]
+    op = A.OPS["march"] if kernel == "march" else A.OPS["infer"]  # "nedf" and "slabs" tune the infer call
     nbytes = lib.nedf_workspace_size(op, C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
     buf = ws.get(nbytes)

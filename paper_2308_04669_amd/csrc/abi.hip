@@ -104,11 +104,12 @@ WsLayout ws_layout(int64_t n_rays, size_t extra_bytes, size_t ws_bytes) {
   l.opac = align256(l.keys + size_t(n_rays) * 8);
   l.extra = align256(l.opac + size_t(n_rays) * 4);
   l.pairs = align256(l.extra + extra_bytes);
-  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / 16) : 0;
+  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / 24) : 0;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   l.capacity = cap;
   l.pairsB = l.pairs + size_t(cap) * 8;
-  l.end = l.pairsB + size_t(cap) * 8;
+  l.pairsS = l.pairsB + size_t(cap) * 8;
+  l.end = l.pairsS + size_t(cap) * 8;
   return l;
 }
 
@@ -253,6 +254,7 @@ int32_t prepare_ws(Prepared& P, const RaySrcHost& rs, size_t extra, void* ws, si
   k.opac = reinterpret_cast<uint32_t*>(w + lay.opac);
   k.pairs = reinterpret_cast<uint2*>(w + lay.pairs);
   k.pairsB = reinterpret_cast<uint2*>(w + lay.pairsB);
+  k.pairsS = reinterpret_cast<uint2*>(w + lay.pairsS);
   k.capacity = lay.capacity;
   return NEDF_OK;
 }
@@ -318,7 +320,7 @@ void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream
   // analytic objects without a network are marched directly
   const uint32_t direct = P.analytic & ~P.nedf;
   if (direct) stage_march(k, s, false, direct, dtype, 0, 0, 0);
-  if (P.nedf) stage_nedf(k, s, P.nedf_dtype);
+  if (P.nedf) stage_nedf(k, s, P.nedf_dtype, P.nedf, tune_value(NEDF_TUNE_SLABS, P.nedf_dtype));
   // uncertain pairs: marcher on list B
   stage_march(k, s, true, P.analytic, dtype, (P.mlp & P.nedf) ? P.W : 0, P.H, P.L);
   stage_finalize(k, s);
@@ -376,7 +378,7 @@ extern "C" size_t nedf_workspace_size(int32_t op, const nedf_scene* scene, const
   if (cap < 1) cap = 1;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   const size_t extra = op == NEDF_OP_SHADOW ? size_t(n) * SHADOW_EXTRA_PER_RAY : 0;
-  return ws_fixed_bytes(n, extra) + size_t(cap) * 16;
+  return ws_fixed_bytes(n, extra) + size_t(cap) * 24;
 }
 
 extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {
@@ -390,19 +392,20 @@ extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {
   return st;
 }
 
-extern "C" int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out6) {
-  if (!ws || !out6) return fail(NEDF_ERR_NULL, "nedf_ws_counters: NULL argument");
+extern "C" int32_t nedf_ws_counters(const void* ws, nedf_stream_t stream, int64_t* out7) {
+  if (!ws || !out7) return fail(NEDF_ERR_NULL, "nedf_ws_counters: NULL argument");
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
   WsCounters c;
   e = hipMemcpy(&c, static_cast<const uint8_t*>(ws) + 256, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "nedf_ws_counters");
-  out6[0] = c.A.total_pairs;
-  out6[1] = c.A.total_items;
-  out6[2] = c.stats[0];
-  out6[3] = c.stats[1];
-  out6[4] = c.stats[2];
-  out6[5] = c.stats[3];
+  out7[0] = c.A.total_pairs;
+  out7[1] = c.A.total_items;
+  out7[2] = c.stats[0];
+  out7[3] = c.stats[1];
+  out7[4] = c.stats[2];
+  out7[5] = c.stats[3];
+  out7[6] = c.stats[4];
   return NEDF_OK;
 }
 
@@ -558,7 +561,13 @@ extern "C" int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, c
       apply_march_opts(Ps.k, opts->infer.march);
       nedf_infer_opts io = opts->infer;
       io.refine_steps = 0;  // the occlusion test needs no refined depth
+      // only whether a hit lies closer than |L - x| - eps matters: pairs that
+      // cannot change that are skipped (the depth buffer of the shadow rays is
+      // then exact below that distance only)
+      Ps.k.ray_tmax = dist;
+      Ps.k.tmax_eps = opts->eps;
       run_infer(Ps, dtype, io, s);
+      Ps.k.ray_tmax = nullptr;
     } else {
       apply_march_opts(Ps.k, opts->infer.march);
       Ps.k.clip = 1;
@@ -711,11 +720,16 @@ extern "C" int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* 
 // ---- tuning table and autotuner ---------------------------------------------
 namespace {
 std::mutex g_tune_mu;
-// [kernel][dtype]: 10 * workgroups per CU + chunks per superchunk
-int g_tune[2][3] = {{11, 12, 14}, {11, 12, 14}};
+// [kernel][dtype]: 10 * workgroups per CU + chunks per superchunk; for
+// NEDF_TUNE_SLABS the number of depth slabs of the network stage
+int g_tune[3][3] = {{11, 12, 14}, {11, 12, 14}, {4, 4, 4}};
 
 int tune_candidates(int kernel, int dtype, int32_t* out) {
-  if (kernel < 0 || kernel > 1 || dtype < 0 || dtype > 2) return 0;
+  if (kernel < 0 || kernel > 2 || dtype < 0 || dtype > 2) return 0;
+  if (kernel == NEDF_TUNE_SLABS) {
+    out[0] = 1; out[1] = 2; out[2] = 4; out[3] = 8;
+    return 4;
+  }
   if (dtype == NEDF_F32) { out[0] = 11; return 1; }
   if (dtype == NEDF_BF16) { out[0] = 11; out[1] = 12; out[2] = 21; return 3; }
   if (kernel == NEDF_TUNE_NEDF) {
@@ -729,7 +743,7 @@ int tune_candidates(int kernel, int dtype, int32_t* out) {
 namespace nedf {
 int tune_value(int kernel, int dtype) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (kernel < 0 || kernel > 1 || dtype < 0 || dtype > 2) return 1;
+  if (kernel < 0 || kernel > 2 || dtype < 0 || dtype > 2) return 1;
   return g_tune[kernel][dtype];
 }
 }  // namespace nedf

@@ -17,7 +17,8 @@ __global__ void k_init(KArgs a) {
     a.opac[i] = 0u;
   }
   if (i == 0) *a.status = 0;
-  if (i < int64_t(sizeof(WsCounters) / 4)) reinterpret_cast<int32_t*>(a.C)[i] = 0;
+  if (i < int64_t(sizeof(WsCounters) / 4))
+    reinterpret_cast<int32_t*>(a.C)[i] = i == int64_t(offsetof(WsCounters, dmin_bits) / 4) ? 0x7F800000 : 0;
 }
 
 __device__ __forceinline__ bool pair_test(const KArgs& a, const float o[3], const float d[3], int inst,
@@ -211,6 +212,7 @@ __global__ void k_scan_A(KArgs a) {
   L->total_items = items;
   L->total_pairs = int32_t(off);
   L->work_counter = 0;
+  a.C->stats[4] = int32_t(off);  // pairs after culling (kept when later stages rebin list A)
   if (over) set_status(a.status, NEDF_ERR_CAPACITY);
 }
 
@@ -229,6 +231,98 @@ __global__ void k_scan_items(KArgs a, PairList* L) {
   L->total_items = items;
   L->total_pairs = total;
   L->work_counter = 0;
+}
+
+// Front-to-back network stage.  A pair can report no depth below
+// s (t_perp - l): the network's depth is s (t_perp - l clamp(mu_hat, -1, 1))
+// and the marcher's lies inside the chord, which starts at or after it.  The
+// pairs are split into depth slabs of that bound and the network runs slab by
+// slab, nearest first; a pair whose bound lies beyond the pixel's nearest hit
+// so far cannot win the min-reduce and is skipped.  The result is the same as
+// evaluating every pair.
+__device__ __forceinline__ float pair_depth_bound(const KArgs& a, uint2 pr, float bound) {
+  const W2L g = load_w2l(a.w2l, int(pr.y));
+  float o[3], d[3], ol[3], dl[3];
+  make_ray(a.rays, pr.x, o, d);
+  to_local(g, o, d, ol, dl);
+  const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
+  return fmaxf(g.s * (tperp - bound), 0.0f);
+}
+
+// Range of the depth bounds over list A (objects with a network).
+__global__ __launch_bounds__(256) void k_depth_range(KArgs a, uint32_t mask) {
+  const PairList* A = &a.C->A;
+  float lo = INFINITY, hi = 0.0f;
+  for (int m = 0; m < a.n_obj; ++m) {
+    if (!((mask >> m) & 1u)) continue;
+    const int cnt = A->cnt[m], off = A->off[m];
+    const float bound = a.obj[m].bound;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+      const float dm = pair_depth_bound(a, a.pairs[off + q], bound);
+      lo = fminf(lo, dm);
+      hi = fmaxf(hi, dm);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off));
+    hi = fmaxf(hi, __shfl_xor(hi, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&a.C->dmin_bits, __float_as_uint(lo));
+    atomicMax(&a.C->dmax_bits, __float_as_uint(hi));
+  }
+}
+
+__device__ __forceinline__ int depth_slab(const KArgs& a, float dm, int n_slabs) {
+  const float lo = __uint_as_float(a.C->dmin_bits), hi = __uint_as_float(a.C->dmax_bits);
+  if (n_slabs <= 1 || !(hi > lo)) return 0;
+  const int k = int((dm - lo) * (float(n_slabs) / (hi - lo)));
+  return k < 0 ? 0 : (k >= n_slabs ? n_slabs - 1 : k);
+}
+
+__global__ void k_slab_begin(KArgs a) {
+  if (blockIdx.x != 0) return;
+  PairList* S = &a.C->S;
+  const PairList* A = &a.C->A;
+  for (int m = threadIdx.x; m < NEDF_MAX_OBJECTS; m += blockDim.x) {
+    S->cnt[m] = 0;
+    S->off[m] = A->off[m];
+  }
+}
+
+// List S = the pairs of list A in depth slab `slab` (objects in mask) whose
+// bound does not lie beyond the pixel's current nearest hit.
+__global__ __launch_bounds__(256) void k_slab_filter(KArgs a, uint32_t mask, int slab, int n_slabs) {
+  const PairList* A = &a.C->A;
+  PairList* S = &a.C->S;
+  const int lane = threadIdx.x & 63;
+  for (int m = 0; m < a.n_obj; ++m) {
+    if (!((mask >> m) & 1u)) continue;
+    const int cnt = A->cnt[m], off = A->off[m];
+    const float bound = a.obj[m].bound;
+    const int stride = gridDim.x * blockDim.x;
+    for (int q0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); q0 < cnt; q0 += stride) {
+      const int q = q0 + lane;
+      bool keep = false;
+      uint2 pr = make_uint2(0u, 0u);
+      if (q < cnt) {
+        pr = a.pairs[off + q];
+        const float dm = pair_depth_bound(a, pr, bound);
+        if (depth_slab(a, dm, n_slabs) == slab) {
+          // margin against last-bit differences between kernels
+          keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
+        }
+      }
+      const uint64_t mk = __ballot(keep);
+      if (mk) {
+        const int leader = __ffsll((unsigned long long)mk) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&S->cnt[m], __popcll(mk));
+        base = __shfl(base, leader);
+        if (keep) a.pairsS[off + base + __popcll(mk & ((1ull << lane) - 1ull))] = pr;
+      }
+    }
+  }
 }
 
 // Depth test of the fallback list (exact): a pair whose ray enters the
@@ -261,8 +355,7 @@ __global__ void k_fallback_depth_test(KArgs a, uint2* out) {
         to_local(g, o, d, ol, dl);
         const bool seg = a.clip ? sphere_chord(ol, dl, bound, ta, tb) : true;
         const float t_in = a.clip ? g.s * ta : a.t_near;
-        const float best = __uint_as_float(uint32_t(a.keys[pr.x] >> 32));
-        keep = seg && !(best < t_in);
+        keep = seg && !(depth_limit(a, pr.x) < t_in);
       }
       const uint64_t mk = __ballot(keep);
       if (mk) {
@@ -449,7 +542,7 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const uint32_t stash = eng::lds_offset(s_stash) + 16u * threadIdx.x;
-  PairList* PL = &a.C->A;
+  PairList* PL = a.L;  // the current depth slab
   PairList* FB = &a.C->B;
   const int total = PL->total_items;
   if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
@@ -688,12 +781,24 @@ void stage_march(const KArgs& k0, hipStream_t s, bool list_b, uint32_t analytic_
   }
 }
 
-void stage_nedf(const KArgs& k0, hipStream_t s, int dtype) {
+void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs) {
   KArgs k = k0;
   prof_mark("infer.nedf", s, true);
-  if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s);
-  else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s);
-  else launch_nedf_net<0>(k, s);
+  k.L = &k.C->S;
+  k.pairs = k.pairsS;
+  k.item_mask = nedf_mask;
+  k.item_pairs = 32 * eng::WAVES;
+  if (n_slabs > 1) hipLaunchKernelGGL(k_depth_range, dim3(1024), dim3(256), 0, s, k0, nedf_mask);
+  for (int slab = 0; slab < n_slabs; ++slab) {
+    hipLaunchKernelGGL(k_slab_begin, dim3(1), dim3(64), 0, s, k);
+    hipLaunchKernelGGL(k_slab_filter, dim3(2048), dim3(256), 0, s, k0, nedf_mask, slab, n_slabs);
+    hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(64), 0, s, k, k.L);
+    prof_mark("net", s, true);
+    if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s);
+    else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s);
+    else launch_nedf_net<0>(k, s);
+    prof_mark("net", s, false);
+  }
   prof_mark("infer.nedf", s, false);
 }
 

@@ -39,13 +39,16 @@ struct PairList {
 struct WsCounters {
   PairList A;       // primary pairs (culling result) / binned pixels
   PairList B;       // fallback pairs (NeDF uncertain rays)
-  int32_t stats[8]; // [0] pairs decided by the network, [1] sent to the marcher, [2] network misses
+  PairList S;       // pairs of the current depth slab of the network stage
+  int32_t stats[8]; // [0] pairs decided by the network, [1] sent to the marcher, [2] network misses,
+                    // [3] marcher pairs left after the depth test, [4] pairs after culling
+  uint32_t dmin_bits, dmax_bits;  // range of the pairs' lowest possible depths (float bits, >= 0)
 };
 
-// Workspace layout: status | counters | keys | opacity bits | pairs A | pairs B
-// | extra (shadow rays).  Capacity is per pair list.
+// Workspace layout: status | counters | keys | opacity bits | extra (shadow
+// rays) | pairs A | pairs B | pairs S.  Capacity is per pair list.
 struct WsLayout {
-  size_t counters, keys, opac, pairs, pairsB, extra, end;
+  size_t counters, keys, opac, pairs, pairsB, pairsS, extra, end;
   int64_t capacity;
 };
 
@@ -65,7 +68,9 @@ struct KArgs;
 void stage_init_cull(const KArgs& k, hipStream_t s, uint32_t item_mask, int item_pairs);
 void stage_march(const KArgs& k, hipStream_t s, bool list_b, uint32_t analytic_mask, int dtype, int W, int H,
                  int L);
-void stage_nedf(const KArgs& k, hipStream_t s, int dtype);
+// Intersection-network stage over list A, front to back in n_slabs depth
+// slabs (objects in nedf_mask).
+void stage_nedf(const KArgs& k, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs);
 void stage_finalize(const KArgs& k, hipStream_t s);
 void stage_bin_pixels(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mask, int per);
 void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mlp_mask, uint32_t sphere_mask,

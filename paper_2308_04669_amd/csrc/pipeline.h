@@ -25,6 +25,11 @@ struct KArgs {
   uint2* pairs;          // its pair array
   PairList* LB;          // second list (fallback)
   uint2* pairsB;
+  uint2* pairsS;         // depth-slab list of the network stage
+  // shadow-ray queries: only whether some hit lies closer than
+  // ray_tmax[ray] - tmax_eps matters (null for depth queries)
+  const float* ray_tmax;
+  float tmax_eps;
   int64_t capacity;
   uint64_t* keys;
   uint32_t* opac;
@@ -41,6 +46,16 @@ struct KArgs {
   float clear_rgb[3];
   float* rgb;
 };
+
+// Depth beyond which a pair of `ray` can no longer change the result: the
+// pixel's nearest hit so far; for shadow queries the occlusion distance, or
+// -inf once the ray is already known to be occluded.
+__device__ __forceinline__ float depth_limit(const KArgs& a, uint32_t ray) {
+  const float best = __uint_as_float(uint32_t(a.keys[ray] >> 32));
+  if (!a.ray_tmax) return best;
+  const float cut = a.ray_tmax[ray] - a.tmax_eps;
+  return best < cut ? -INFINITY : cut;
+}
 
 __device__ __forceinline__ void neu_add(float& s, float& c, float x) {
   const float t = s + x;

@@ -74,3 +74,32 @@ def test_march_superchunk_variants_identical_and_autotune():
         assert rep["chosen"] in rep["candidates"]
     finally:
         api.tune_set("march", "bf16", old)
+
+
+def test_depth_slabs_identical():
+    """The front-to-back depth slabs skip only pairs that cannot win: depth
+    and ID are bit-identical for 1, 2, 4 and 8 slabs, and more slabs evaluate
+    no more pairs."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, insts, cam, _ = syn.batched_scene(4, 200, 160, 90)
+    nedfs = [syn.nedf_model(4, 200 + k, head_scale=16.0) for k in range(len(models))]
+    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
+    rays = api.camera_rays(cam)
+    old = api.tune_get("slabs", "bf16")
+    outs, evald = {}, {}
+    try:
+        for v in api.tune_candidates("slabs", "bf16"):
+            api.tune_set("slabs", "bf16", v)
+            ws = api.Workspace()
+            dep, idn = api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=0, ws=ws)
+            st = api.ws_counters(ws)
+            evald[v] = st["nedf_hits"] + st["fallback"] + st["nedf_misses"]
+            outs[v] = (_np(dep), _np(idn))
+        log(f"[slabs] evaluated pairs {evald} of {st['pairs']}")
+        ref = outs[1]
+        for v, (dep, idn) in outs.items():
+            assert np.array_equal(idn, ref[1]) and np.array_equal(dep.view(np.uint32), ref[0].view(np.uint32))
+        assert evald[1] == st["pairs"] and evald[8] <= evald[1]
+    finally:
+        api.tune_set("slabs", "bf16", old)
