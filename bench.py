@@ -31,9 +31,11 @@ datasets).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -50,6 +52,42 @@ MAC_PER_SAMPLE = 63 * 256 + 7 * 256 * 256 + 256
 MAC_RGB = (256 + 27) * 128 + 128 * 3
 # intersection network per pair: 102 x 256 + 7 x 256x256 + 256 x 2
 MAC_NEDF = 102 * 256 + 7 * 256 * 256 + 256 * 2
+
+
+# HBM bytes per launch of a matrix-core kernel in the timed frames, from the
+# hardware byte counters of a profiled run of this benchmark (FETCH_SIZE and
+# WRITE_SIZE, each scaled by what it reads for a plain device copy of known
+# size).  Each record keeps a hash of the kernels' sources; the figure is
+# reported only while they are unchanged.
+NET_SOURCES = ["include/nedf.h"] + ["paper_2308_04669_amd/csrc/" + f for f in (
+    "k_depth.hip", "pipeline.h", "mlp_engine.h", "device_common.h", "launch.h", "runtime.h", "blob_layout.h")]
+TRAFFIC_RECORDS = {
+    "infer.nedf/net": os.path.join(ROOT, "profiles", "nedf_net_bf16_batched_1000inst_1920x1080.md"),
+    "fallback.mlp": os.path.join(ROOT, "profiles", "fallback_march_bf16_batched_1000inst_1920x1080.md"),
+}
+
+
+def sources_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(record: str, files):
+    """(bytes per launch, note) from a counter record, or (None, reason)."""
+    try:
+        with open(record) as fh:
+            kv = dict(re.findall(r"^- ([a-z_0-9]+): `([^`]*)`", fh.read(), re.M))
+    except OSError:
+        return None, "no counter record"
+    if kv.get("sources_sha256") != sources_hash(files):
+        return None, "kernel sources changed since the counters were taken"
+    try:
+        return float(kv["hbm_bytes_per_launch"]), os.path.relpath(record, ROOT)
+    except (KeyError, ValueError):
+        return None, "counter record without hbm_bytes_per_launch"
 
 
 def parse():
@@ -76,6 +114,8 @@ def parse():
     # oracle baseline and counters
     p.add_argument("--cpu-pixels", type=int, default=0, help="0: the workload's default sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--sources-hash", action="store_true",
+                   help="print the hash of the network kernel's sources (kept with its counter record) and exit")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed region, copy a tensor of this size (device to device) so that "
                         "hardware byte counters can be scaled against a copy of known size")
@@ -270,6 +310,7 @@ def frame_bench(args):
     k_ms, k_flops, k_dt = cand[kname]
     achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
     peak = PEAK_TFLOPS[k_dt]
+    traffic, traffic_src = recorded_traffic(TRAFFIC_RECORDS[kname], NET_SOURCES)
     line = {
         "metric": METRIC,
         "value": n / (ms * 1e-3),
@@ -297,7 +338,8 @@ def frame_bench(args):
         "fp32_marcher": {"rays_per_s": marcher_rps, "pixels": int(len(pix)), "samples_per_pair": 192},
         "quality": quality,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": kname, "avg_launch_ms": k_ms,
+                     "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "traffic_source": traffic_src, "kernel": kname, "avg_launch_ms": k_ms,
                      "flop_per_launch": k_flops, "launches_per_frame": launches if kname.endswith("net") else 1},
         "stages_ms_per_step": per,
         "autotune": tune,
@@ -535,6 +577,9 @@ def marcher_cpu_baseline(n_pixels: int, n_samples: int, size: int):
 
 def main():
     args = parse()
+    if args.sources_hash:
+        print(sources_hash(NET_SOURCES))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
               f"design note, not a build target", file=sys.stderr)

@@ -386,9 +386,9 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
  * (1 or 2) and the number of 32-row weight chunks streamed into LDS per copy
  * and barrier (1, 2 or 4).  NEDF_TUNE_SLABS is the number of depth slabs in
  * which nedf_infer_depth_id runs the intersection network front to back
- * (1, 2, 4 or 8; an exact pruning: a pair whose smallest possible depth lies
- * beyond the pixel's nearest hit is skipped).  It is kept per kernel and
- * dtype in a process-wide
+ * (1, 2, 4, 8, 16 or 32; an exact pruning: a pair whose smallest possible
+ * depth lies beyond the pixel's nearest hit is skipped).  It is kept per
+ * kernel and dtype in a process-wide
  * table guarded by a mutex (the library's only global state besides the
  * profiler).
  *

@@ -87,7 +87,7 @@ int32_t fail(int32_t code, const std::string& msg) {
 }
 
 
-// Workspace: status(256) | counters | keys n*8 | opacity n*4 | extra | pairs A | pairs B.
+// Workspace: status(256) | counters | keys n*8 | opacity n*4 | extra | pairs A | B | S | depth bounds.
 size_t ws_fixed_bytes(int64_t n_rays, size_t extra_bytes) {
   size_t off = 256;
   off = align256(off + sizeof(WsCounters));
@@ -104,12 +104,13 @@ WsLayout ws_layout(int64_t n_rays, size_t extra_bytes, size_t ws_bytes) {
   l.opac = align256(l.keys + size_t(n_rays) * 8);
   l.extra = align256(l.opac + size_t(n_rays) * 4);
   l.pairs = align256(l.extra + extra_bytes);
-  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / 24) : 0;
+  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / WS_BYTES_PER_PAIR) : 0;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   l.capacity = cap;
   l.pairsB = l.pairs + size_t(cap) * 8;
   l.pairsS = l.pairsB + size_t(cap) * 8;
-  l.end = l.pairsS + size_t(cap) * 8;
+  l.pairsD = l.pairsS + size_t(cap) * 8;
+  l.end = l.pairsD + size_t(cap) * 4;
   return l;
 }
 
@@ -255,6 +256,7 @@ int32_t prepare_ws(Prepared& P, const RaySrcHost& rs, size_t extra, void* ws, si
   k.pairs = reinterpret_cast<uint2*>(w + lay.pairs);
   k.pairsB = reinterpret_cast<uint2*>(w + lay.pairsB);
   k.pairsS = reinterpret_cast<uint2*>(w + lay.pairsS);
+  k.pair_dm = reinterpret_cast<float*>(w + lay.pairsD);
   k.capacity = lay.capacity;
   return NEDF_OK;
 }
@@ -378,7 +380,7 @@ extern "C" size_t nedf_workspace_size(int32_t op, const nedf_scene* scene, const
   if (cap < 1) cap = 1;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   const size_t extra = op == NEDF_OP_SHADOW ? size_t(n) * SHADOW_EXTRA_PER_RAY : 0;
-  return ws_fixed_bytes(n, extra) + size_t(cap) * 24;
+  return ws_fixed_bytes(n, extra) + size_t(cap) * WS_BYTES_PER_PAIR;
 }
 
 extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {
@@ -554,6 +556,8 @@ extern "C" int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, c
   Ps.k.depth = depth_l;
   Ps.k.id = nullptr;
   Ps.k.opacity = nullptr;
+  // one shadow ray per pixel: cull the array in image tiles
+  Ps.k.ray_grid_w = rs.kind == 0 ? rs.width : 0;
   prof_mark("shadow", s, true);
   for (int m = 0; m < n_lights; ++m) {
     stage_shadow_rays(Pp.k, s, id, lights + 3 * m, so, sd, dist);
@@ -722,13 +726,13 @@ namespace {
 std::mutex g_tune_mu;
 // [kernel][dtype]: 10 * workgroups per CU + chunks per superchunk; for
 // NEDF_TUNE_SLABS the number of depth slabs of the network stage
-int g_tune[3][3] = {{11, 12, 14}, {11, 12, 14}, {4, 4, 4}};
+int g_tune[3][3] = {{11, 12, 14}, {11, 12, 14}, {8, 8, 8}};
 
 int tune_candidates(int kernel, int dtype, int32_t* out) {
   if (kernel < 0 || kernel > 2 || dtype < 0 || dtype > 2) return 0;
   if (kernel == NEDF_TUNE_SLABS) {
-    out[0] = 1; out[1] = 2; out[2] = 4; out[3] = 8;
-    return 4;
+    for (int i = 0; i < 6; ++i) out[i] = 1 << i;
+    return 6;
   }
   if (dtype == NEDF_F32) { out[0] = 11; return 1; }
   if (dtype == NEDF_BF16) { out[0] = 11; out[1] = 12; out[2] = 21; return 3; }

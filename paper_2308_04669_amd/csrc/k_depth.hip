@@ -21,13 +21,20 @@ __global__ void k_init(KArgs a) {
     reinterpret_cast<int32_t*>(a.C)[i] = i == int64_t(offsetof(WsCounters, dmin_bits) / 4) ? 0x7F800000 : 0;
 }
 
+// Exact per-ray test; dm gets the lowest depth the pair can report,
+// s (t_perp - l) clamped at 0 (the network's depth is s (t_perp - l mu) with
+// mu clamped to [-1, 1], the marcher's lies inside the chord).
 __device__ __forceinline__ bool pair_test(const KArgs& a, const float o[3], const float d[3], int inst,
-                                          int obj) {
+                                          int obj, float& dm) {
+  dm = 0.0f;
   if (!a.clip) return true;
   const W2L g = load_w2l(a.w2l, inst);
   float ol[3], dl[3], ta, tb;
   to_local(g, o, d, ol, dl);
-  return sphere_chord(ol, dl, a.obj[obj].bound, ta, tb);
+  const float bound = a.obj[obj].bound;
+  const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
+  dm = fmaxf(g.s * (tperp - bound), 0.0f);
+  return sphere_chord(ol, dl, bound, ta, tb);
 }
 
 // Culling and binning (Alg. 1, "models in the view frustum"): list A gets
@@ -72,6 +79,26 @@ __device__ __forceinline__ void instance_sphere(const KArgs& a, int k, int obj, 
   r = g.s * a.obj[obj].bound;
 }
 
+// Ray bundle of an array-ray workgroup: origins within rho of O, directions
+// within angle theta of the unit axis (cos_theta).  A sphere (c, r) can be
+// met by one of its rays only if the forward cone from O with half-angle
+// theta meets the sphere grown by rho (shifting a ray's origin to O moves
+// each of its points by at most rho).
+struct RayBundle {
+  float O[3], ax[3];
+  float rho, theta;
+  bool any, prune;
+};
+
+__device__ __forceinline__ bool bundle_meets_sphere(const RayBundle& b, const float c[3], float r) {
+  const float v[3] = {c[0] - b.O[0], c[1] - b.O[1], c[2] - b.O[2]};
+  const float L = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const float R = r + b.rho + 1e-4f * (L + r) + 1e-6f;
+  if (L <= R) return true;
+  const float cphi = fminf(fmaxf((v[0] * b.ax[0] + v[1] * b.ax[1] + v[2] * b.ax[2]) / L, -1.0f), 1.0f);
+  return acosf(cphi) <= b.theta + asinf(R / L) + 1e-4f;
+}
+
 template <int PASS, bool CAMERA>
 __global__ __launch_bounds__(256) void k_cull(KArgs a) {
   __shared__ int s_cand[CULL_BATCH];
@@ -102,22 +129,76 @@ __global__ __launch_bounds__(256) void k_cull(KArgs a) {
     f.nx1 = ax * (2.0f * (float(i1) + 0.5f) / float(W) - 1.0f);
     f.ny1 = ay * (1.0f - 2.0f * (float(j0) + 0.5f) / float(H));
     f.ny0 = ay * (1.0f - 2.0f * (float(j1) + 0.5f) / float(H));
+  } else if (a.ray_grid_w > 0) {
+    // image-shaped ray array: 16 x 16 tiles give tight bundles
+    const int W = a.ray_grid_w;
+    const int px = blockIdx.x * CULL_TILE + (t % CULL_TILE), py = blockIdx.y * CULL_TILE + (t / CULL_TILE);
+    ray = int64_t(py) * W + px;
+    live = px < W && ray < a.n_rays;
   } else {
     ray = int64_t(blockIdx.x) * blockDim.x + t;
     live = ray < a.n_rays;
   }
   float o[3] = {0, 0, 0}, d[3] = {0, 0, 1};
   if (live) make_ray(a.rays, ray, o, d);
+  RayBundle bd;
+  if constexpr (!CAMERA) {
+    // bundle of the workgroup's rays with a finite direction
+    __shared__ float s_red[4][8];
+    const bool ok = live && isfinite(d[0]) && isfinite(d[1]) && isfinite(d[2]) && isfinite(o[0]) &&
+                    isfinite(o[1]) && isfinite(o[2]);
+    float acc[7] = {ok ? o[0] : 0.f, ok ? o[1] : 0.f, ok ? o[2] : 0.f, ok ? d[0] : 0.f, ok ? d[1] : 0.f,
+                    ok ? d[2] : 0.f, ok ? 1.f : 0.f};
+    for (int i = 0; i < 7; ++i)
+      for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off);
+    if (lane == 0)
+      for (int i = 0; i < 7; ++i) s_red[wave][i] = acc[i];
+    __syncthreads();
+    float tot[7];
+    for (int i = 0; i < 7; ++i) tot[i] = s_red[0][i] + s_red[1][i] + s_red[2][i] + s_red[3][i];
+    bd.any = tot[6] > 0.f;
+    const float n = fmaxf(tot[6], 1.f);
+    const float dl = sqrtf(tot[3] * tot[3] + tot[4] * tot[4] + tot[5] * tot[5]);
+    for (int i = 0; i < 3; ++i) {
+      bd.O[i] = tot[i] / n;
+      bd.ax[i] = dl > 0.f ? tot[3 + i] / dl : 0.f;
+    }
+    float rho = 0.f, ct = 1.f;
+    if (ok) {
+      const float e[3] = {o[0] - bd.O[0], o[1] - bd.O[1], o[2] - bd.O[2]};
+      rho = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+      ct = d[0] * bd.ax[0] + d[1] * bd.ax[1] + d[2] * bd.ax[2];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      rho = fmaxf(rho, __shfl_xor(rho, off));
+      ct = fminf(ct, __shfl_xor(ct, off));
+    }
+    __syncthreads();
+    if (lane == 0) {
+      s_red[wave][0] = rho;
+      s_red[wave][1] = ct;
+    }
+    __syncthreads();
+    bd.rho = fmaxf(fmaxf(s_red[0][0], s_red[1][0]), fmaxf(s_red[2][0], s_red[3][0]));
+    const float cmin = fminf(fminf(s_red[0][1], s_red[1][1]), fminf(s_red[2][1], s_red[3][1]));
+    bd.theta = acosf(fminf(fmaxf(cmin, -1.0f), 1.0f));
+    // prune only coherent bundles (a wide one would keep nearly everything)
+    bd.prune = bd.any && a.clip && cmin > 0.5f && dl > 0.f;
+  }
   PairList* L = &a.C->A;
   if (t < NEDF_MAX_OBJECTS) s_cnt[t] = 0;
+  float dlo = INFINITY, dhi = 0.0f;  // range of the pairs' depth bounds (pass 0)
   __syncthreads();
   // traversal 0 counts; in pass 1 traversal 1 writes
   for (int trav = 0; trav <= PASS; ++trav) {
     for (int base = 0; base < a.n_inst; base += CULL_BATCH) {
       const int nb = min(CULL_BATCH, a.n_inst - base);
       int nc = 0;
-      if constexpr (CAMERA) {
+      bool compact = CAMERA;
+      if constexpr (!CAMERA) compact = bd.prune || !bd.any;
+      if (compact) {
         // ordered compaction of the instances whose sphere meets the tile
+        // (camera rays) or the ray bundle (ray arrays)
         __syncthreads();
         for (int c0 = 0; c0 < nb; c0 += 256) {
           const int k = base + c0 + t;
@@ -125,12 +206,18 @@ __global__ __launch_bounds__(256) void k_cull(KArgs a) {
           if (c0 + t < nb) {
             const int obj = a.inst_object[k];
             if (obj >= 0 && obj < a.n_obj) {
-              if (!a.clip) {
-                keep = true;
-              } else {
+              if constexpr (CAMERA) {
+                if (!a.clip) {
+                  keep = true;
+                } else {
+                  float c[3], r;
+                  instance_sphere(a, k, obj, c, r);
+                  keep = tile_meets_sphere(f, c, r);
+                }
+              } else if (bd.any) {
                 float c[3], r;
                 instance_sphere(a, k, obj, c, r);
-                keep = tile_meets_sphere(f, c, r);
+                keep = bundle_meets_sphere(bd, c, r);
               }
             }
           }
@@ -148,22 +235,30 @@ __global__ __launch_bounds__(256) void k_cull(KArgs a) {
         nc = nb;
       }
       for (int ci = 0; ci < nc; ++ci) {
-        const int k = CAMERA ? s_cand[ci] : base + ci;
+        const int k = compact ? s_cand[ci] : base + ci;
         const int obj = a.inst_object[k];
-        const bool pass = live && obj >= 0 && obj < a.n_obj && pair_test(a, o, d, k, obj);
+        float dm = 0.0f;
+        const bool pass = live && obj >= 0 && obj < a.n_obj && pair_test(a, o, d, k, obj, dm);
         const uint64_t m = __ballot(pass);
         if (m == 0) continue;
         const int cnt = __popcll(m);
         const int leader = __ffsll((unsigned long long)m) - 1;
         if (trav == 0) {
           if (lane == leader) atomicAdd(&s_cnt[obj], cnt);
+          if (PASS == 0 && pass) {
+            dlo = fminf(dlo, dm);
+            dhi = fmaxf(dhi, dm);
+          }
         } else {
           int off = 0;
           if (lane == leader) off = atomicAdd(&s_cnt[obj], cnt);
           off = __shfl(off, leader);
           if (pass) {
             const int pos = s_base[obj] + off + __popcll(m & ((1ull << lane) - 1ull));
-            if (pos < L->cnt[obj]) a.pairs[L->off[obj] + pos] = make_uint2(uint32_t(ray), uint32_t(k));
+            if (pos < L->cnt[obj]) {
+              a.pairs[L->off[obj] + pos] = make_uint2(uint32_t(ray), uint32_t(k));
+              a.pair_dm[L->off[obj] + pos] = dm;
+            }
           }
         }
       }
@@ -179,6 +274,16 @@ __global__ __launch_bounds__(256) void k_cull(KArgs a) {
       }
     }
     __syncthreads();
+  }
+  if constexpr (PASS == 0) {
+    for (int off = 32; off > 0; off >>= 1) {
+      dlo = fminf(dlo, __shfl_xor(dlo, off));
+      dhi = fmaxf(dhi, __shfl_xor(dhi, off));
+    }
+    if (lane == 0 && dlo <= dhi) {
+      atomicMin(&a.C->dmin_bits, __float_as_uint(dlo));
+      atomicMax(&a.C->dmax_bits, __float_as_uint(dhi));
+    }
   }
 }
 
@@ -233,46 +338,14 @@ __global__ void k_scan_items(KArgs a, PairList* L) {
   L->work_counter = 0;
 }
 
-// Front-to-back network stage.  A pair can report no depth below
-// s (t_perp - l): the network's depth is s (t_perp - l clamp(mu_hat, -1, 1))
-// and the marcher's lies inside the chord, which starts at or after it.  The
-// pairs are split into depth slabs of that bound and the network runs slab by
-// slab, nearest first; a pair whose bound lies beyond the pixel's nearest hit
-// so far cannot win the min-reduce and is skipped.  The result is the same as
-// evaluating every pair.
-__device__ __forceinline__ float pair_depth_bound(const KArgs& a, uint2 pr, float bound) {
-  const W2L g = load_w2l(a.w2l, int(pr.y));
-  float o[3], d[3], ol[3], dl[3];
-  make_ray(a.rays, pr.x, o, d);
-  to_local(g, o, d, ol, dl);
-  const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
-  return fmaxf(g.s * (tperp - bound), 0.0f);
-}
-
-// Range of the depth bounds over list A (objects with a network).
-__global__ __launch_bounds__(256) void k_depth_range(KArgs a, uint32_t mask) {
-  const PairList* A = &a.C->A;
-  float lo = INFINITY, hi = 0.0f;
-  for (int m = 0; m < a.n_obj; ++m) {
-    if (!((mask >> m) & 1u)) continue;
-    const int cnt = A->cnt[m], off = A->off[m];
-    const float bound = a.obj[m].bound;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
-      const float dm = pair_depth_bound(a, a.pairs[off + q], bound);
-      lo = fminf(lo, dm);
-      hi = fmaxf(hi, dm);
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, off));
-    hi = fmaxf(hi, __shfl_xor(hi, off));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMin(&a.C->dmin_bits, __float_as_uint(lo));
-    atomicMax(&a.C->dmax_bits, __float_as_uint(hi));
-  }
-}
-
+// Front-to-back network stage.  A pair can report no depth below its bound
+// s (t_perp - l) (kept per pair by the culling pass, with the bounds' range):
+// the network's depth is s (t_perp - l clamp(mu_hat, -1, 1)) and the
+// marcher's lies inside the chord, which starts at or after it.  The pairs
+// are split into depth slabs of that bound and the network runs slab by slab,
+// nearest first; a pair whose bound lies beyond the pixel's nearest hit so far
+// cannot win the min-reduce and is skipped.  The result is the same as
+// evaluating every pair, whatever the slab boundaries.
 __device__ __forceinline__ int depth_slab(const KArgs& a, float dm, int n_slabs) {
   const float lo = __uint_as_float(a.C->dmin_bits), hi = __uint_as_float(a.C->dmax_bits);
   if (n_slabs <= 1 || !(hi > lo)) return 0;
@@ -299,16 +372,15 @@ __global__ __launch_bounds__(256) void k_slab_filter(KArgs a, uint32_t mask, int
   for (int m = 0; m < a.n_obj; ++m) {
     if (!((mask >> m) & 1u)) continue;
     const int cnt = A->cnt[m], off = A->off[m];
-    const float bound = a.obj[m].bound;
     const int stride = gridDim.x * blockDim.x;
     for (int q0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); q0 < cnt; q0 += stride) {
       const int q = q0 + lane;
       bool keep = false;
       uint2 pr = make_uint2(0u, 0u);
       if (q < cnt) {
-        pr = a.pairs[off + q];
-        const float dm = pair_depth_bound(a, pr, bound);
+        const float dm = a.pair_dm[off + q];
         if (depth_slab(a, dm, n_slabs) == slab) {
+          pr = a.pairs[off + q];
           // margin against last-bit differences between kernels
           keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
         }
@@ -734,9 +806,14 @@ void stage_init_cull(const KArgs& k0, hipStream_t s, uint32_t item_mask, int ite
     hipLaunchKernelGGL(k_scan_A, dim3(1), dim3(64), 0, s, k);
     hipLaunchKernelGGL((k_cull<1, true>), tg, dim3(256), 0, s, k);
   } else {
-    hipLaunchKernelGGL((k_cull<0, false>), dim3(g), dim3(256), 0, s, k);
+    dim3 ag(g);
+    if (k.ray_grid_w > 0) {
+      const int64_t h = (k.n_rays + k.ray_grid_w - 1) / k.ray_grid_w;
+      ag = dim3((k.ray_grid_w + CULL_TILE - 1) / CULL_TILE, unsigned((h + CULL_TILE - 1) / CULL_TILE));
+    }
+    hipLaunchKernelGGL((k_cull<0, false>), ag, dim3(256), 0, s, k);
     hipLaunchKernelGGL(k_scan_A, dim3(1), dim3(64), 0, s, k);
-    hipLaunchKernelGGL((k_cull<1, false>), dim3(g), dim3(256), 0, s, k);
+    hipLaunchKernelGGL((k_cull<1, false>), ag, dim3(256), 0, s, k);
   }
   prof_mark("depth.cull", s, false);
 }
@@ -788,7 +865,6 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
   k.pairs = k.pairsS;
   k.item_mask = nedf_mask;
   k.item_pairs = 32 * eng::WAVES;
-  if (n_slabs > 1) hipLaunchKernelGGL(k_depth_range, dim3(1024), dim3(256), 0, s, k0, nedf_mask);
   for (int slab = 0; slab < n_slabs; ++slab) {
     hipLaunchKernelGGL(k_slab_begin, dim3(1), dim3(64), 0, s, k);
     hipLaunchKernelGGL(k_slab_filter, dim3(2048), dim3(256), 0, s, k0, nedf_mask, slab, n_slabs);

@@ -46,9 +46,11 @@ struct WsCounters {
 };
 
 // Workspace layout: status | counters | keys | opacity bits | extra (shadow
-// rays) | pairs A | pairs B | pairs S.  Capacity is per pair list.
+// rays) | pairs A | pairs B | pairs S | depth bounds of list A.  Capacity is
+// per pair list.
+constexpr size_t WS_BYTES_PER_PAIR = 3 * 8 + 4;
 struct WsLayout {
-  size_t counters, keys, opac, pairs, pairsB, pairsS, extra, end;
+  size_t counters, keys, opac, pairs, pairsB, pairsS, pairsD, extra, end;
   int64_t capacity;
 };
 

@@ -26,10 +26,14 @@ struct KArgs {
   PairList* LB;          // second list (fallback)
   uint2* pairsB;
   uint2* pairsS;         // depth-slab list of the network stage
+  float* pair_dm;        // per pair of list A: lowest depth it can report (world units)
   // shadow-ray queries: only whether some hit lies closer than
   // ray_tmax[ray] - tmax_eps matters (null for depth queries)
   const float* ray_tmax;
   float tmax_eps;
+  // ray arrays laid out as an image of this width (shadow rays, one per
+  // pixel): culled in 16 x 16 tiles; 0 for unstructured arrays
+  int32_t ray_grid_w;
   int64_t capacity;
   uint64_t* keys;
   uint32_t* opac;

@@ -94,6 +94,7 @@ def test_tuning_table_host_logic():
     assert api.tune_candidates("march", "f32") == [11]
     assert api.tune_candidates("march", "bf16") == [11, 12, 21]
     assert api.tune_candidates("nedf", "fp8") == [11, 12, 14, 21, 22]
+    assert api.tune_candidates("slabs", "bf16") == [1, 2, 4, 8, 16, 32]
     with pytest.raises(A.NedfError):
         api.tune_candidates("march", "fp8")
     old = api.tune_get("nedf", "bf16")
