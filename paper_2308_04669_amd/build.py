@@ -1,13 +1,17 @@
 """Build the HIP C-ABI library ``libnedf.so`` in-tree for gfx950.
 
-Each translation unit under ``csrc/`` is compiled with hipcc into
-``_build/`` (in parallel), then linked into ``paper_2308_04669_amd/libnedf.so``.
-Run as ``python -m paper_2308_04669_amd.build``.
+The sources (``csrc/`` and ``include/``) are first copied into
+``_build/src/``, so that hipcc's host and device passes, which read a file
+separately, see the same text even if the tree changes during the build.
+Each translation unit is compiled into ``_build/`` (in parallel), then linked
+into ``paper_2308_04669_amd/libnedf.so``.  Run as
+``python -m paper_2308_04669_amd.build``.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import shutil
 import subprocess
 import sys
 
@@ -20,16 +24,27 @@ LIB = os.path.join(PKG, "libnedf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
+SNAP = os.path.join(BUILD, "src")
+SNAP_CSRC = os.path.join(SNAP, "csrc")
+SNAP_INCLUDE = os.path.join(SNAP, "include")
+
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function",
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{SNAP_INCLUDE}", f"-I{SNAP_CSRC}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-result"]
+
+
+def _snapshot():
+    if os.path.isdir(SNAP):
+        shutil.rmtree(SNAP)
+    shutil.copytree(CSRC, SNAP_CSRC)
+    shutil.copytree(INCLUDE, SNAP_INCLUDE)
 
 
 def _sources():
     out = []
-    for f in sorted(os.listdir(CSRC)):
+    for f in sorted(os.listdir(SNAP_CSRC)):
         if f.endswith(".hip") or f.endswith(".cpp"):
-            out.append(os.path.join(CSRC, f))
+            out.append(os.path.join(SNAP_CSRC, f))
     return out
 
 
@@ -50,6 +65,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    _snapshot()
     srcs = _sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))

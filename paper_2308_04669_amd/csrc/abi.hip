@@ -105,12 +105,14 @@ WsLayout ws_layout(int64_t n_rays, size_t extra_bytes, size_t ws_bytes) {
   l.extra = align256(l.opac + size_t(n_rays) * 4);
   l.pairs = align256(l.extra + extra_bytes);
   int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / WS_BYTES_PER_PAIR) : 0;
-  if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
+  if (cap > (int64_t(1) << 31) - 16) cap = (int64_t(1) << 31) - 16;
+  cap &= ~int64_t(15);
   l.capacity = cap;
   l.pairsB = l.pairs + size_t(cap) * 8;
   l.pairsS = l.pairsB + size_t(cap) * 8;
   l.pairsD = l.pairsS + size_t(cap) * 8;
-  l.end = l.pairsD + size_t(cap) * 4;
+  l.pairsSlab = l.pairsD + size_t(cap) * 4;
+  l.end = l.pairsSlab + size_t(cap);
   return l;
 }
 
@@ -257,6 +259,7 @@ int32_t prepare_ws(Prepared& P, const RaySrcHost& rs, size_t extra, void* ws, si
   k.pairsB = reinterpret_cast<uint2*>(w + lay.pairsB);
   k.pairsS = reinterpret_cast<uint2*>(w + lay.pairsS);
   k.pair_dm = reinterpret_cast<float*>(w + lay.pairsD);
+  k.pair_slab = w + lay.pairsSlab;
   k.capacity = lay.capacity;
   return NEDF_OK;
 }
@@ -378,7 +381,8 @@ extern "C" size_t nedf_workspace_size(int32_t op, const nedf_scene* scene, const
   }
   int64_t cap = pair_capacity > 0 ? pair_capacity : n * int64_t(scene->n_inst > 0 ? scene->n_inst : 1);
   if (cap < 1) cap = 1;
-  if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
+  cap = (cap + 15) & ~int64_t(15);  // the layout keeps a multiple of 16
+  if (cap > (int64_t(1) << 31) - 16) cap = (int64_t(1) << 31) - 16;
   const size_t extra = op == NEDF_OP_SHADOW ? size_t(n) * SHADOW_EXTRA_PER_RAY : 0;
   return ws_fixed_bytes(n, extra) + size_t(cap) * WS_BYTES_PER_PAIR;
 }
@@ -735,10 +739,13 @@ int tune_candidates(int kernel, int dtype, int32_t* out) {
     return 6;
   }
   if (dtype == NEDF_F32) { out[0] = 11; return 1; }
-  if (dtype == NEDF_BF16) { out[0] = 11; out[1] = 12; out[2] = 21; return 3; }
-  if (kernel == NEDF_TUNE_NEDF) {
-    out[0] = 11; out[1] = 12; out[2] = 14; out[3] = 21; out[4] = 22;
+  if (dtype == NEDF_BF16) {
+    out[0] = 11; out[1] = 12; out[2] = 21; out[3] = 111; out[4] = 112;
     return 5;
+  }
+  if (kernel == NEDF_TUNE_NEDF) {
+    out[0] = 11; out[1] = 12; out[2] = 14; out[3] = 21; out[4] = 22; out[5] = 111; out[6] = 112; out[7] = 114;
+    return 8;
   }
   return 0;  // no FP8 marcher
 }

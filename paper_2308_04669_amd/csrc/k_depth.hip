@@ -17,8 +17,10 @@ __global__ void k_init(KArgs a) {
     a.opac[i] = 0u;
   }
   if (i == 0) *a.status = 0;
-  if (i < int64_t(sizeof(WsCounters) / 4))
-    reinterpret_cast<int32_t*>(a.C)[i] = i == int64_t(offsetof(WsCounters, dmin_bits) / 4) ? 0x7F800000 : 0;
+  // every counter word, whatever the grid size
+  constexpr int64_t words = int64_t(sizeof(WsCounters) / 4);
+  for (int64_t w = i; w < words; w += int64_t(gridDim.x) * blockDim.x)
+    reinterpret_cast<int32_t*>(a.C)[w] = w == int64_t(offsetof(WsCounters, dmin_bits) / 4) ? 0x7F800000 : 0;
 }
 
 // Exact per-ray test; dm gets the lowest depth the pair can report,
@@ -363,14 +365,32 @@ __global__ void k_slab_begin(KArgs a) {
   }
 }
 
-// List S = the pairs of list A in depth slab `slab` (objects in mask) whose
-// bound does not lie beyond the pixel's current nearest hit.
-__global__ __launch_bounds__(256) void k_slab_filter(KArgs a, uint32_t mask, int slab, int n_slabs) {
+// Wave-aggregated append of the kept pairs to their objects' segments of
+// list S (lanes of one wave may belong to different objects).
+__device__ __forceinline__ void push_slab(const KArgs& a, PairList* S, int lane, bool keep, int m, uint2 pr) {
+  uint64_t todo = __ballot(keep);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int m0 = __shfl(m, leader);
+    const uint64_t mk = __ballot(keep && m == m0);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&S->cnt[m0], __popcll(mk));
+    base = __shfl(base, leader);
+    if (keep && m == m0) a.pairsS[S->off[m0] + base + __popcll(mk & ((1ull << lane) - 1ull))] = pr;
+    todo &= ~mk;
+  }
+}
+
+// List S = the pairs of list A in depth slab 0 (objects in mask) whose bound
+// does not lie beyond the pixel's current nearest hit.  Also records every
+// pair's slab in one byte (0xFF for objects outside the mask), so that the
+// later slabs read one byte per pair instead of the bound.
+__global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int n_slabs) {
   const PairList* A = &a.C->A;
   PairList* S = &a.C->S;
   const int lane = threadIdx.x & 63;
   for (int m = 0; m < a.n_obj; ++m) {
-    if (!((mask >> m) & 1u)) continue;
+    const bool in = (mask >> m) & 1u;
     const int cnt = A->cnt[m], off = A->off[m];
     const int stride = gridDim.x * blockDim.x;
     for (int q0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); q0 < cnt; q0 += stride) {
@@ -379,20 +399,45 @@ __global__ __launch_bounds__(256) void k_slab_filter(KArgs a, uint32_t mask, int
       uint2 pr = make_uint2(0u, 0u);
       if (q < cnt) {
         const float dm = a.pair_dm[off + q];
-        if (depth_slab(a, dm, n_slabs) == slab) {
+        const int sl = in ? depth_slab(a, dm, n_slabs) : 0xFF;
+        a.pair_slab[off + q] = uint8_t(sl);
+        if (sl == 0) {
           pr = a.pairs[off + q];
           // margin against last-bit differences between kernels
           keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
         }
       }
-      const uint64_t mk = __ballot(keep);
-      if (mk) {
-        const int leader = __ffsll((unsigned long long)mk) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&S->cnt[m], __popcll(mk));
-        base = __shfl(base, leader);
-        if (keep) a.pairsS[off + base + __popcll(mk & ((1ull << lane) - 1ull))] = pr;
+      if (in) push_slab(a, S, lane, keep, m, pr);
+    }
+  }
+}
+
+// List S for slab `slab` >= 1 from the recorded slab bytes: each lane scans
+// four consecutive pairs of list A (all objects) per step.
+__global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
+  const PairList* A = &a.C->A;
+  PairList* S = &a.C->S;
+  const int lane = threadIdx.x & 63;
+  const int total = A->off[a.n_obj];
+  const int words = (total + 3) / 4;
+  const uint32_t* sw = reinterpret_cast<const uint32_t*>(a.pair_slab);
+  const int stride = gridDim.x * blockDim.x;
+  for (int w0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); w0 < words; w0 += stride) {
+    const int w = w0 + lane;
+    const uint32_t b = w < words ? sw[w] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * w + j;
+      bool keep = false;
+      int m = 0;
+      uint2 pr = make_uint2(0u, 0u);
+      if (q < total && int((b >> (8 * j)) & 0xFFu) == slab) {
+        pr = a.pairs[q];
+        m = a.inst_object[pr.y];
+        const float dm = a.pair_dm[q];
+        keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
       }
+      push_slab(a, S, lane, keep, m, pr);
     }
   }
 }
@@ -494,18 +539,17 @@ __global__ void k_march_analytic(KArgs a, uint32_t mask) {
 }
 
 // Matrix-core marcher: a workgroup takes items of 4 pairs (one per wave) of
-// one object from list a.L; each wave marches its pair in chunks of 32
-// samples through the register-resident density network, then scans the
-// chunk's optical depths across the wave.
-template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC>
+// one object from list a.L; each wave marches its pair in chunks of 32 NB
+// samples through the register-resident density network (NB blocks of 32
+// share every weight read from LDS), then scans each block's optical depths
+// across the wave in sample order, so that the sums are the same for any NB.
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NB>
 __global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
   using T = eng::Tr<DT>;
-  constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
   constexpr int SPC = 32 * NB;  // samples per wave per chunk
-  static_assert(NB == 1, "the scan assumes one 32-sample block per wave");
   __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
@@ -556,37 +600,48 @@ __global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
       }
       const uint8_t* next_blob = !last ? blob : (next < total ? a.obj[item_object(PL, a.n_obj, next)].blob : nullptr);
       typename T::frag Benc[NB][KS0];
-      const int si = c * SPC + (lane & 31);
-      const float tr = (float(si) + 0.5f) * delta;
-      float p[3] = {fmaf(tr, dl[0], pa[0]), fmaf(tr, dl[1], pa[1]), fmaf(tr, dl[2], pa[2])};
-      eng::encode_input<DT, 3, L, KS0>(p, half, Benc[0]);
-      float partial[NB][1] = {{0.f}};
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float tr = (float(c * SPC + 32 * nb + (lane & 31)) + 0.5f) * delta;
+        float p[3] = {fmaf(tr, dl[0], pa[0]), fmaf(tr, dl[1], pa[1]), fmaf(tr, dl[2], pa[2])};
+        eng::encode_input<DT, 3, L, KS0>(p, half, Benc[nb]);
+      }
+      float partial[NB][1];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) partial[nb][0] = 0.f;
       typename T::frag Blast[NB][KSH];
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
-                                                                           nullptr, &slot,
-                                                          next_blob, primed);
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX, NB>(hb, blob, Benc, lds, partial,
+                                                                               Blast, nullptr, &slot, next_blob,
+                                                                               primed);
       primed = next_blob != nullptr;
-      const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
-      float v = mlp_sigma(od, u, p[0], p[1], p[2]) * delta;
-      if (lane >= 32 || si >= N || !seg) v = 0.f;
-      // inclusive scan of optical depth over the wave (sample order = lane order)
-      float incl = v;
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const float y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-      }
-      const float tau = (carry + carry_c) + (incl - v);
-      const float w = expf(-tau) * one_minus_exp_neg(v);
-      float ws = w, wts = w * (ta + tr);
+      for (int nb = 0; nb < NB; ++nb) {
+        const int si = c * SPC + 32 * nb + (lane & 31);
+        const float tr = (float(si) + 0.5f) * delta;
+        const float p[3] = {fmaf(tr, dl[0], pa[0]), fmaf(tr, dl[1], pa[1]), fmaf(tr, dl[2], pa[2])};
+        const float u = partial[nb][0] + __shfl_xor(partial[nb][0], 32) + head_b;
+        float v = mlp_sigma(od, u, p[0], p[1], p[2]) * delta;
+        if (lane >= 32 || si >= N || !seg) v = 0.f;
+        // inclusive scan of optical depth over the wave (sample order = lane order)
+        float incl = v;
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        ws += __shfl_xor(ws, off);
-        wts += __shfl_xor(wts, off);
+        for (int off = 1; off < 64; off <<= 1) {
+          const float y = __shfl_up(incl, off);
+          if (lane >= off) incl += y;
+        }
+        const float tau = (carry + carry_c) + (incl - v);
+        const float w = expf(-tau) * one_minus_exp_neg(v);
+        float ws = w, wts = w * (ta + tr);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          ws += __shfl_xor(ws, off);
+          wts += __shfl_xor(wts, off);
+        }
+        // a block wholly past the last sample adds exact zeros
+        neu_add(sw, sw_c, ws);
+        neu_add(swt, swt_c, wts);
+        neu_add(carry, carry_c, __shfl(incl, 63));
       }
-      neu_add(sw, sw_c, ws);
-      neu_add(swt, swt_c, wts);
-      neu_add(carry, carry_c, __shfl(incl, 63));
     }
     if (lane == 0 && valid && seg) {
       const float A = sw + sw_c;
@@ -597,20 +652,21 @@ __global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
   }
 }
 
-// NeDF stage: a workgroup takes items of 128 pairs (32 per wave) of one
-// object; each lane pair evaluates the intersection network on its pair's
-// line coordinates.  Confident hits go to the key buffer, uncertain pairs
-// (and origins inside the bounding sphere) to list B for the marcher.
-template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC>
+// NeDF stage: a workgroup takes items of 128 NB pairs (32 NB per wave) of
+// one object; each lane pair evaluates the intersection network on its pairs'
+// line coordinates (NB blocks of 32 pairs share every weight read from LDS).
+// Confident hits go to the key buffer, uncertain pairs (and origins inside
+// the bounding sphere) to list B for the marcher.
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NB>
 __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
   using T = eng::Tr<DT>;
-  constexpr int NB = T::NB;
+  constexpr int PPW = 32 * NB;  // pairs per wave and item
   constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
   __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   // per-lane pair state parked across the network (keeps registers free)
-  __shared__ __attribute__((aligned(16))) uint8_t s_stash[16 * eng::THREADS];
+  __shared__ __attribute__((aligned(16))) uint8_t s_stash[16 * NB * eng::THREADS];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const uint32_t stash = eng::lds_offset(s_stash) + 16u * threadIdx.x;
@@ -631,24 +687,14 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
     __syncthreads();
     const int next = s_item;
     const int obj = item_object(PL, a.n_obj, item);
-    const int local = (item - PL->item_start[obj]) * (32 * eng::WAVES) + wave * 32 + (lane & 31);
-    const bool valid = local < PL->cnt[obj];
-    const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+    const int first = (item - PL->item_start[obj]) * (PPW * eng::WAVES) + wave * PPW + (lane & 31);
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.nedf_blob;
     const uint8_t* next_blob = next < total ? a.obj[item_object(PL, a.n_obj, next)].nedf_blob : nullptr;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
     const float* hbias_p = reinterpret_cast<const float*>(blob + uniform_load_u64(&hb->off_head_b));
     const float hbias[2] = {uniform_load_f32(hbias_p), uniform_load_f32(hbias_p + 1)};
-    const W2L g = load_w2l(a.w2l, int(pr.y));
-    float o[3], d[3], ol[3], dl[3];
-    make_ray(a.rays, pr.x, o, d);
-    to_local(g, o, d, ol, dl);
     const float l = od.bound;
-    float pl[6] = {dl[0], dl[1], dl[2], ol[1] * dl[2] - ol[2] * dl[1], ol[2] * dl[0] - ol[0] * dl[2],
-                   ol[0] * dl[1] - ol[1] * dl[0]};
-    const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
-    const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
     typename T::frag Benc[NB][KS0];
     const float in_scale = DT == 2 ? uniform_load_f32(blob + uniform_load_u64(&hb->off_scales)) : 1.0f;
     // lane-half-dependent encoding constants are recomputed per pass rather
@@ -656,41 +702,60 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
     // across the network)
     int half_v = half;
     asm volatile("" : "+v"(half_v));
-    eng::encode_input<DT, 6, L, KS0>(pl, half_v, Benc[0], in_scale);
-    // ray and instance ids (< 2^31, flags in bit 31), t_perp and s
-    eng::lds_write16(stash, eng::u32x4{pr.x | (valid ? 0x80000000u : 0u), pr.y | (inside ? 0x80000000u : 0u),
-                                       __float_as_uint(tperp), __float_as_uint(g.s)});
-    float partial[NB][2] = {{0.f, 0.f}};
-    typename T::frag Blast[NB][KSH];
-    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
-                                                                         nullptr, &slot,
-                                                        next_blob, primed);
-    primed = next_blob != nullptr;
-    eng::u32x4 st = eng::lds_read16<0>(stash), d1 = st, d2 = st, d3 = st;
-    eng::lds_wait4<0>(st, d1, d2, d3);
-    const uint2 prs = make_uint2(st.x & 0x7FFFFFFFu, st.y & 0x7FFFFFFFu);
-    const bool valid_s = (st.x >> 31) != 0, inside_s = (st.y >> 31) != 0;
-    const float mu_hat = partial[0][0] + __shfl_xor(partial[0][0], 32) + hbias[0];
-    const float z = partial[0][1] + __shfl_xor(partial[0][1], 32) + hbias[1];
-    const float p = sigmoidf_(z);
-    const float D = __uint_as_float(st.w) * (__uint_as_float(st.z) - l * fminf(fmaxf(mu_hat, -1.0f), 1.0f));
-    const bool mine = valid_s && half == 0;
-    const bool to_fb = mine && (inside_s || (p >= a.p_lo && p <= a.p_hi));
-    const bool hit = mine && !to_fb && p > a.p_hi && D > 0.0f;
-    if (hit) emit_key(a, prs.x, prs.y, D);
-    // wave-aggregated push into the object's segment of list B
-    const uint64_t m = __ballot(to_fb);
-    if (m) {
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&FB->cnt[obj], __popcll(m));
-      base = __shfl(base, leader);
-      if (to_fb) a.pairsB[FB->off[obj] + base + __popcll(m & ((1ull << lane) - 1ull))] = prs;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int local = first + 32 * nb;
+      const bool valid = local < PL->cnt[obj];
+      const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+      const W2L g = load_w2l(a.w2l, int(pr.y));
+      float o[3], d[3], ol[3], dl[3];
+      make_ray(a.rays, pr.x, o, d);
+      to_local(g, o, d, ol, dl);
+      float pl[6] = {dl[0], dl[1], dl[2], ol[1] * dl[2] - ol[2] * dl[1], ol[2] * dl[0] - ol[0] * dl[2],
+                     ol[0] * dl[1] - ol[1] * dl[0]};
+      const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
+      const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
+      eng::encode_input<DT, 6, L, KS0>(pl, half_v, Benc[nb], in_scale);
+      // ray and instance ids (< 2^31, flags in bit 31), t_perp and s
+      eng::lds_write16(stash + uint32_t(nb) * (16u * eng::THREADS),
+                       eng::u32x4{pr.x | (valid ? 0x80000000u : 0u), pr.y | (inside ? 0x80000000u : 0u),
+                                  __float_as_uint(tperp), __float_as_uint(g.s)});
     }
-    const uint64_t mh = __ballot(hit), mv = __ballot(mine);
-    n_hit += __popcll(mh);
-    n_fb += __popcll(m);
-    n_miss += __popcll(mv) - __popcll(mh) - __popcll(m);
+    float partial[NB][2];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) partial[nb][0] = partial[nb][1] = 0.f;
+    typename T::frag Blast[NB][KSH];
+    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0, WIDTH / 32, SBX, NB>(hb, blob, Benc, lds, partial, Blast,
+                                                                             nullptr, &slot, next_blob, primed);
+    primed = next_blob != nullptr;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      eng::u32x4 st = eng::lds_read16<0>(stash + uint32_t(nb) * (16u * eng::THREADS)), d1 = st, d2 = st, d3 = st;
+      eng::lds_wait4<0>(st, d1, d2, d3);
+      const uint2 prs = make_uint2(st.x & 0x7FFFFFFFu, st.y & 0x7FFFFFFFu);
+      const bool valid_s = (st.x >> 31) != 0, inside_s = (st.y >> 31) != 0;
+      const float mu_hat = partial[nb][0] + __shfl_xor(partial[nb][0], 32) + hbias[0];
+      const float z = partial[nb][1] + __shfl_xor(partial[nb][1], 32) + hbias[1];
+      const float p = sigmoidf_(z);
+      const float D = __uint_as_float(st.w) * (__uint_as_float(st.z) - l * fminf(fmaxf(mu_hat, -1.0f), 1.0f));
+      const bool mine = valid_s && half == 0;
+      const bool to_fb = mine && (inside_s || (p >= a.p_lo && p <= a.p_hi));
+      const bool hit = mine && !to_fb && p > a.p_hi && D > 0.0f;
+      if (hit) emit_key(a, prs.x, prs.y, D);
+      // wave-aggregated push into the object's segment of list B
+      const uint64_t m = __ballot(to_fb);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&FB->cnt[obj], __popcll(m));
+        base = __shfl(base, leader);
+        if (to_fb) a.pairsB[FB->off[obj] + base + __popcll(m & ((1ull << lane) - 1ull))] = prs;
+      }
+      const uint64_t mh = __ballot(hit), mv = __ballot(mine);
+      n_hit += __popcll(mh);
+      n_fb += __popcll(m);
+      n_miss += __popcll(mv) - __popcll(mh) - __popcll(m);
+    }
     item = next;
   }
   if (lane == 0 && (n_hit | n_fb | n_miss)) {
@@ -726,42 +791,60 @@ int cu_count() {
 }
 
 // Launch shape of the 256-wide BF16/FP8 kernels from the tuning table: value
-// 10 * occupancy + superchunk (workgroups per CU, chunks per copy); other
-// shapes use one workgroup per CU and the default superchunk.  The grid is
-// persistent: one workgroup per CU and occupancy level.
+// 100 * (32-row blocks per wave - 1) + 10 * occupancy + superchunk (blocks
+// sharing each weight read, workgroups per CU, chunks per copy); other shapes
+// use one block, one workgroup per CU and the default superchunk.  The grid
+// is persistent: one workgroup per CU and occupancy level.
 template <int DT, int WIDTH, int NHID, int L>
 void launch_march_mlp(const KArgs& k, hipStream_t s) {
   const dim3 b(eng::THREADS);
   if constexpr (DT == 1 && WIDTH == 256) {
     const int v = tune_value(NEDF_TUNE_MARCH, DT);
     if (v == 11) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1>), dim3(cu_count()), b, 0, s, k);
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 1>), dim3(cu_count()), b, 0, s, k);
       return;
     }
     if (v == 21) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 2>), dim3(2 * cu_count()), b, 0, s, k);
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 2, 1>), dim3(2 * cu_count()), b, 0, s, k);
+      return;
+    }
+    if (v == 111) {
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 2>), dim3(cu_count()), b, 0, s, k);
+      return;
+    }
+    if (v == 112) {
+      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 2, 1, 2>), dim3(cu_count()), b, 0, s, k);
       return;
     }
   }
-  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>(), 1>), dim3(cu_count()), b, 0, s, k);
+  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>(), 1, 1>), dim3(cu_count()), b, 0, s,
+                     k);
 }
 
+// Tuning value of the network kernel: 100 * (row blocks per wave - 1) +
+// 10 * workgroups per CU + chunks per superchunk.
+int nedf_rows(int v) { return v >= 100 ? 2 : 1; }
+
 template <int DT>
-void launch_nedf_net(const KArgs& k, hipStream_t s) {
+void launch_nedf_net(const KArgs& k, hipStream_t s, int v) {
   const dim3 b(eng::THREADS), g1(cu_count()), g2(2 * cu_count());
-  const int v = tune_value(NEDF_TUNE_NEDF, DT);
   if constexpr (DT == 2) {
-    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1>), g1, b, 0, s, k);
-    else if (v == 12) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1>), g1, b, 0, s, k);
-    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2>), g2, b, 0, s, k);
-    else if (v == 22) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 2>), g2, b, 0, s, k);
-    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1>), g1, b, 0, s, k);
+    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1>), g1, b, 0, s, k);
+    else if (v == 12) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1>), g1, b, 0, s, k);
+    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2, 1>), g2, b, 0, s, k);
+    else if (v == 22) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 2, 1>), g2, b, 0, s, k);
+    else if (v == 111) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 2>), g1, b, 0, s, k);
+    else if (v == 112) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 2>), g1, b, 0, s, k);
+    else if (v == 114) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 2>), g1, b, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1>), g1, b, 0, s, k);
   } else if constexpr (DT == 1) {
-    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1>), g1, b, 0, s, k);
-    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2>), g2, b, 0, s, k);
-    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1>), g1, b, 0, s, k);
+    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1>), g1, b, 0, s, k);
+    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2, 1>), g2, b, 0, s, k);
+    else if (v == 111) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 2>), g1, b, 0, s, k);
+    else if (v == 112) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 2>), g1, b, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1>), g1, b, 0, s, k);
   } else {
-    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1>), g1, b, 0, s, k);
+    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1>), g1, b, 0, s, k);
   }
 }
 
@@ -864,15 +947,18 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
   k.L = &k.C->S;
   k.pairs = k.pairsS;
   k.item_mask = nedf_mask;
-  k.item_pairs = 32 * eng::WAVES;
+  // launch shape from the tuning table, fixed for all slabs of the stage
+  const int v = dtype == NEDF_F32 ? 11 : tune_value(NEDF_TUNE_NEDF, dtype);
+  k.item_pairs = 32 * eng::WAVES * nedf_rows(v);
   for (int slab = 0; slab < n_slabs; ++slab) {
     hipLaunchKernelGGL(k_slab_begin, dim3(1), dim3(64), 0, s, k);
-    hipLaunchKernelGGL(k_slab_filter, dim3(2048), dim3(256), 0, s, k0, nedf_mask, slab, n_slabs);
+    if (slab == 0) hipLaunchKernelGGL(k_slab_first, dim3(2048), dim3(256), 0, s, k0, nedf_mask, n_slabs);
+    else hipLaunchKernelGGL(k_slab_next, dim3(2048), dim3(256), 0, s, k0, slab);
     hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(64), 0, s, k, k.L);
     prof_mark("net", s, true);
-    if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s);
-    else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s);
-    else launch_nedf_net<0>(k, s);
+    if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s, v);
+    else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s, v);
+    else launch_nedf_net<0>(k, s, v);
     prof_mark("net", s, false);
   }
   prof_mark("infer.nedf", s, false);

@@ -126,14 +126,14 @@ __global__ void k_refine_analytic(KArgs a, uint32_t mask) {
 
 // Density-network refinement: items of 128 pixels (32 per wave) of one
 // SDF-mode object; each evaluation of f is one pass of the trunk.
-template <int DT, int WIDTH, int NHID, int L>
-__global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_refine_mlp(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1));
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, eng::sb_default<DT>())];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   PairList* PL = &a.C->A;
@@ -168,8 +168,8 @@ __global__ __launch_bounds__(256, 1) void k_refine_mlp(KArgs a) {
       float partial[NB][1] = {{0.f}};
       typename T::frag Blast[NB][KSH];
       const uint8_t* nb_ = ++eval_i < n_eval ? blob : nullptr;
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0>(hb, blob, Benc, lds, partial, Blast, nullptr, &slot,
-                                                          nb_, primed);
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
+                                                                           nullptr, &slot, nb_, primed);
       primed = nb_ != nullptr;
       const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
       return mlp_surface(od, u, p[0], p[1], p[2]);
@@ -208,8 +208,8 @@ __global__ void k_clear_rgb(KArgs a, const int32_t* ids) {
 // NeRF shading: a wave shades 32 / K pixels with K samples each; trunk with
 // the sigma head, then the colour layer on [h_last, gamma_dirL(d)], then
 // local compositing across each pixel's K lanes.
-template <int DT, int WIDTH, int NHID, int L, int DIRL, int RGBW>
-__global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int DIRL, int RGBW, int SBX, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_shade(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
   constexpr int KSR = KSH + KSD;
   constexpr int CBR = eng::chunk_bytes<DT>(KSR, 3);
   constexpr int CHUNK = eng::cmax(eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 1)), CBR);
-  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, eng::sb_default<DT>())];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const int K = a.shade_K;  // 1, 2, 4, 8, 16 or 32
@@ -255,8 +255,8 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
     float partial[NB][1] = {{0.f}};
     typename T::frag Blast[NB][KSH];
     int cur = 0;
-    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR, RGBW / 32>(hb, blob, Benc, lds, partial, Blast,
-                                                         blob + uniform_load_u64(&hb->off_rgb), &cur);
+    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR, RGBW / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
+                                                                         blob + uniform_load_u64(&hb->off_rgb), &cur);
     const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
     const float sig = mlp_sigma(od, u, p[0], p[1], p[2]);
     // colour layer input: [h_last, gamma_dirL(d_l)]
@@ -271,8 +271,8 @@ __global__ __launch_bounds__(256, 1) void k_shade(KArgs a) {
     }
     float prgb[NB][3] = {{0.f, 0.f, 0.f}};
     typename T::frag dummy[NB][1];
-    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK>(Bc, dummy, blob + uniform_load_u64(&hb->off_rgb), nullptr, lds, cur,
-                                                              prgb);
+    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK, RGBW / 32, SBX>(
+        Bc, dummy, blob + uniform_load_u64(&hb->off_rgb), nullptr, lds, cur, prgb);
     float c[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) c[ch] = sigmoidf_(prgb[0][ch] + __shfl_xor(prgb[0][ch], 32) + rgb_b[ch]);
@@ -389,9 +389,9 @@ void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ml
   if (mlp_mask) {
     stage_bin_pixels(k, s, ids, mlp_mask, 32 * eng::WAVES);
     if (dtype == NEDF_BF16)
-      hipLaunchKernelGGL((k_refine_mlp<1, 256, 8, 10>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_refine_mlp<1, 256, 8, 10, 1, 2>), dim3(2 * cu_count2()), dim3(eng::THREADS), 0, s, k);
     else
-      hipLaunchKernelGGL((k_refine_mlp<0, 256, 8, 10>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_refine_mlp<0, 256, 8, 10, eng::sb_default<0>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
   }
   prof_mark("infer.refine", s, false);
 }
@@ -402,9 +402,9 @@ void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ner
   if (nerf_mask) {
     stage_bin_pixels(k, s, ids, nerf_mask, (32 / k.shade_K) * eng::WAVES);
     if (dtype == NEDF_BF16)
-      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, eng::sb_default<1>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
     else
-      hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128, eng::sb_default<0>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
   }
   prof_mark("shade", s, false);
 }

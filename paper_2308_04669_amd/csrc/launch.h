@@ -46,11 +46,11 @@ struct WsCounters {
 };
 
 // Workspace layout: status | counters | keys | opacity bits | extra (shadow
-// rays) | pairs A | pairs B | pairs S | depth bounds of list A.  Capacity is
-// per pair list.
-constexpr size_t WS_BYTES_PER_PAIR = 3 * 8 + 4;
+// rays) | pairs A | pairs B | pairs S | depth bounds of list A | depth slabs
+// of list A.  Capacity is per pair list (a multiple of 16).
+constexpr size_t WS_BYTES_PER_PAIR = 3 * 8 + 4 + 1;
 struct WsLayout {
-  size_t counters, keys, opac, pairs, pairsB, pairsS, pairsD, extra, end;
+  size_t counters, keys, opac, pairs, pairsB, pairsS, pairsD, pairsSlab, extra, end;
   int64_t capacity;
 };
 

@@ -533,15 +533,14 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
 // superchunk.  The caller's LDS array holds NBUF slots of slot_bytes(CHUNK,
 // SBX) bytes.
 template <int DT, int WIDTH, int KS0, int NHID, int NOUT, int CHUNK, bool KEEP_LAST, int CB_AFTER,
-          int FB_AFTER = WIDTH / 32, int SBX = sb_default<DT>()>
+          int FB_AFTER = WIDTH / 32, int SBX = sb_default<DT>(), int NB = Tr<DT>::NB>
 __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t* blob,
-                                      const typename Tr<DT>::frag (&Benc)[Tr<DT>::NB][KS0],
-                                      uint8_t* lds, float (&partial)[Tr<DT>::NB][NOUT],
-                                      typename Tr<DT>::frag (&Blast)[Tr<DT>::NB][WIDTH / Tr<DT>::KPS],
+                                      const typename Tr<DT>::frag (&Benc)[NB][KS0],
+                                      uint8_t* lds, float (&partial)[NB][NOUT],
+                                      typename Tr<DT>::frag (&Blast)[NB][WIDTH / Tr<DT>::KPS],
                                       const uint8_t* w_after, int* cur_io = nullptr,
                                       const uint8_t* next_blob = nullptr, bool primed = false) {
   using T = Tr<DT>;
-  constexpr int NB = T::NB;
   constexpr int FB = WIDTH / 32;
   constexpr int KSH = WIDTH / T::KPS;
   constexpr int CB0 = chunk_bytes<DT>(KS0, 0);

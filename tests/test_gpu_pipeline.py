@@ -104,6 +104,27 @@ def test_infer_network_and_fallback(dtype):
     assert st["hits"] > 100
 
 
+def test_counters_reset_for_small_ray_counts():
+    """A call with fewer rays than one workgroup still resets every device
+    counter: the same call twice on one workspace reports the same routing."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene(size=12)
+    log("case: infer bf16 12x12 (144 rays) twice on one workspace")
+    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
+    ws = api.Workspace()
+    got = []
+    for _ in range(2):
+        depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype="bf16", refine_steps=0, n_samples=64,
+                                          ws=ws)
+        got.append((api.ws_counters(ws), _np(depth), _np(ident)))
+    log(f"routing {got[0][0]} / {got[1][0]}")
+    assert got[0][0] == got[1][0]
+    st = got[0][0]
+    assert 0 < st["nedf_hits"] + st["fallback"] + st["nedf_misses"] <= st["culled_pairs"]
+    assert np.array_equal(got[0][2], got[1][2]) and np.array_equal(got[0][1].view(np.uint32), got[1][1].view(np.uint32))
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_infer_secant_refinement(dtype):
     need_gpu()
