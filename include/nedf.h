@@ -160,7 +160,8 @@ typedef struct nedf_infer_opts {
                                networks run in their blob's dtype (this dtype or NEDF_FP8) */
   float p_lo, p_hi;         /* hit probability band sent to the marcher (inclusive), default 0.2 / 0.8 */
   int32_t refine_steps;     /* secant updates on the winning pixel (0 = off), default 3 */
-  float refine_h;           /* seed offset in world units, default 0.05 */
+  float refine_h;           /* seed offset in the object's own units (world offset refine_h * s for an
+                               instance of scale s), default 0.05 */
   nedf_march_opts march;    /* marcher used for fallback pairs (clip_to_bound must be 1) */
 } nedf_infer_opts;
 

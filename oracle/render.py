@@ -167,11 +167,13 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
     Reading: the iteration runs on f(t) = q(G^{-1}(o + t d)) in world t,
     where q is the field's surface function (``surface_value``: the logit of
     sigma / sigma_max, zero on the iso-surface sigma = sigma_max / 2, nearly
-    affine across a sharp surface).  Seeds t0 = D - h, t1 = D + h, used only
-    when f(t0) < 0 <= f(t1).  Each step t+ = t1 - f1 (t1 - t0) / (f1 - f0),
-    then (t0, t1) <- (t1, t+).  It stops when the denominator is 0 or an
-    iterate leaves [D - 2h, D + 2h]; the last accepted iterate (initially D)
-    is returned.  ``steps`` updates need steps + 1 field evaluations."""
+    affine across a sharp surface).  h is a distance in the object's own
+    (canonical) units, so the world offset is e = h s for an instance of
+    scale s.  Seeds t0 = D - e, t1 = D + e, used only when
+    f(t0) < 0 <= f(t1).  Each step t+ = t1 - f1 (t1 - t0) / (f1 - f0), then
+    (t0, t1) <- (t1, t+).  It stops when the denominator is 0 or an iterate
+    leaves [D - 2e, D + 2e]; the last accepted iterate (initially D) is
+    returned.  ``steps`` updates need steps + 1 field evaluations."""
     o = np.asarray(o, F64)
     d = np.asarray(d, F64)
     D_hat = np.asarray(D_hat, F64)
@@ -185,10 +187,11 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
     if n == 0:
         return out
     allr = np.arange(n)
-    t0, t1 = D_hat - h, D_hat + h
+    e = h * float(inst.s)
+    t0, t1 = D_hat - e, D_hat + e
     f0, f1 = f(t0, allr), f(t1, allr)
     active = (f0 < 0) & (f1 >= 0)
-    lo, hi = D_hat - 2 * h, D_hat + 2 * h
+    lo, hi = D_hat - 2 * e, D_hat + 2 * e
     for it in range(steps):
         den = f1 - f0
         ok = active & (den != 0)

@@ -111,7 +111,7 @@ __global__ void k_refine_analytic(KArgs a, uint32_t mask) {
         return (od.param[1] - sqrtf(x * x + y * y + z * z)) / od.param[2];
       };
       Secant s;
-      s.start(a.depth[pr.x], a.refine_h);
+      s.start(a.depth[pr.x], a.refine_h * g.s);
       s.f0 = f(s.t0);
       s.f1 = f(s.t1);
       s.active = s.f0 < 0.0f && s.f1 >= 0.0f;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256, OCC) void k_refine_mlp(KArgs a) {
       return mlp_surface(od, u, p[0], p[1], p[2]);
     };
     Secant s;
-    s.start(a.depth[pr.x], a.refine_h);
+    s.start(a.depth[pr.x], a.refine_h * g.s);
     s.f0 = f(s.t0);
     s.f1 = f(s.t1);
     s.active = s.f0 < 0.0f && s.f1 >= 0.0f;

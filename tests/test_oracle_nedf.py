@@ -113,6 +113,25 @@ def test_secant_linear_exact_and_sphere_convergence():
     assert np.array_equal(out2, t_in - 0.2)
 
 
+def test_secant_scale_covariance():
+    """h is in the object's units: refining on an instance scaled by s about
+    the origin, seen from s times farther, gives s times the unscaled depths
+    (and a guess off by 0.02 s is still inside the bracket)."""
+    a, _ = syn.config1_models()
+    cam = syn.config1_camera()
+    o, d = camera_rays(cam)
+    tp = -np.sum(o * d, axis=1)
+    b2 = np.sum(o * o, axis=1) - tp ** 2
+    sel = np.nonzero(b2 < 0.4 ** 2)[0]
+    t_in = tp[sel] - np.sqrt(0.25 - b2[sel])
+    ref = secant_refine(a, IDENT, o[sel], d[sel], t_in + 0.02)
+    for sc in (0.25, 3.0):
+        big = syn.Instance(0, np.eye(3), np.zeros(3), sc)
+        out = secant_refine(a, big, sc * o[sel], d[sel], sc * (t_in + 0.02))
+        assert np.allclose(out, sc * ref, rtol=1e-9, atol=1e-12)
+        assert np.max(np.abs(out - sc * t_in)) < 1e-4 * sc
+
+
 def _tiny_nerf(const_rgb=None, stream=0, sigma_mode="softplus"):
     m = syn.nerf_model(0, stream, width=16, depth=2, enc_L=2, dir_L=1, rgb_width=8,
                        sigma_mode=sigma_mode)
