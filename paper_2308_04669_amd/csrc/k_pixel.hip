@@ -402,7 +402,7 @@ void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ner
   if (nerf_mask) {
     stage_bin_pixels(k, s, ids, nerf_mask, (32 / k.shade_K) * eng::WAVES);
     if (dtype == NEDF_BF16)
-      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, eng::sb_default<1>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, 1, 2>), dim3(2 * cu_count2()), dim3(eng::THREADS), 0, s, k);
     else
       hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128, eng::sb_default<0>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
   }
