@@ -412,26 +412,59 @@ __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int 
   }
 }
 
-// List S for slab `slab` >= 1 from the recorded slab bytes: each lane scans
-// four consecutive pairs of list A (all objects) per step.
+// List S for slab `slab` >= 1 from the recorded slab bytes.  Each lane scans
+// sixteen consecutive pairs of list A (one 16-byte load); the wave compacts
+// the indices of matching pairs in LDS and then tests them 64 at a time, one
+// per lane, so that the reads of bound, pair and key are issued together.
 __global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
+  __shared__ int s_cand[eng::WAVES][1024];
   const PairList* A = &a.C->A;
   PairList* S = &a.C->S;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int total = A->off[a.n_obj];
-  const int words = (total + 3) / 4;
-  const uint32_t* sw = reinterpret_cast<const uint32_t*>(a.pair_slab);
+  const int vecs = (total + 15) / 16;
+  const uint4* sv = reinterpret_cast<const uint4*>(a.pair_slab);
+  const uint32_t pat = 0x01010101u * uint32_t(slab);
+  int* cand = s_cand[wave];
   const int stride = gridDim.x * blockDim.x;
-  for (int w0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); w0 < words; w0 += stride) {
-    const int w = w0 + lane;
-    const uint32_t b = w < words ? sw[w] : 0xFFFFFFFFu;
+  for (int v0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); v0 < vecs; v0 += stride) {
+    const int v = v0 + lane;
+    uint32_t hits = 0;  // bit j: pair 16 v + j is in this slab
+    if (v < vecs) {
+      const uint4 b = sv[v];
+      const uint32_t wd[4] = {b.x ^ pat, b.y ^ pat, b.z ^ pat, b.w ^ pat};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = 4 * w + j;
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (((wd[i] >> (8 * j)) & 0xFFu) == 0u) hits |= 1u << (4 * i + j);
+      // bytes past the last pair are ignored
+      const int rem = total - 16 * v;
+      if (rem < 16) hits &= (1u << rem) - 1u;
+    }
+    const int c = __popc(hits);
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    const int n_cand = __shfl(incl, 63);
+    if (n_cand == 0) continue;
+    int k = incl - c;
+    while (hits) {
+      const int j = __ffs(hits) - 1;
+      cand[k++] = 16 * v + j;
+      hits &= hits - 1u;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int c0 = 0; c0 < n_cand; c0 += 64) {
+      const bool mine = c0 + lane < n_cand;
       bool keep = false;
       int m = 0;
       uint2 pr = make_uint2(0u, 0u);
-      if (q < total && int((b >> (8 * j)) & 0xFFu) == slab) {
+      if (mine) {
+        const int q = cand[c0 + lane];
         pr = a.pairs[q];
         m = a.inst_object[pr.y];
         const float dm = a.pair_dm[q];
@@ -439,6 +472,7 @@ __global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
       }
       push_slab(a, S, lane, keep, m, pr);
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
