@@ -104,15 +104,17 @@ WsLayout ws_layout(int64_t n_rays, size_t extra_bytes, size_t ws_bytes) {
   l.opac = align256(l.keys + size_t(n_rays) * 8);
   l.extra = align256(l.opac + size_t(n_rays) * 4);
   l.pairs = align256(l.extra + extra_bytes);
-  int64_t cap = ws_bytes > l.pairs ? int64_t((ws_bytes - l.pairs) / WS_BYTES_PER_PAIR) : 0;
-  if (cap > (int64_t(1) << 31) - 16) cap = (int64_t(1) << 31) - 16;
-  cap &= ~int64_t(15);
+  // per pair WS_BYTES_PER_PAIR, plus 4 bytes per SLAB_BLOCK pairs, plus slack
+  const int64_t avail = ws_bytes > l.pairs + 1024 ? int64_t(ws_bytes - l.pairs - 1024) : 0;
+  int64_t cap = avail / int64_t(WS_BYTES_PER_PAIR * SLAB_BLOCK + 4) * SLAB_BLOCK;
+  if (cap > (int64_t(1) << 31) - SLAB_BLOCK) cap = (int64_t(1) << 31) - SLAB_BLOCK;
   l.capacity = cap;
   l.pairsB = l.pairs + size_t(cap) * 8;
   l.pairsS = l.pairsB + size_t(cap) * 8;
   l.pairsD = l.pairsS + size_t(cap) * 8;
   l.pairsSlab = l.pairsD + size_t(cap) * 4;
-  l.end = l.pairsSlab + size_t(cap);
+  l.slabMask = l.pairsSlab + size_t(cap);
+  l.end = l.slabMask + size_t(cap / SLAB_BLOCK) * 4;
   return l;
 }
 
@@ -260,6 +262,7 @@ int32_t prepare_ws(Prepared& P, const RaySrcHost& rs, size_t extra, void* ws, si
   k.pairsS = reinterpret_cast<uint2*>(w + lay.pairsS);
   k.pair_dm = reinterpret_cast<float*>(w + lay.pairsD);
   k.pair_slab = w + lay.pairsSlab;
+  k.slab_mask = reinterpret_cast<uint32_t*>(w + lay.slabMask);
   k.capacity = lay.capacity;
   return NEDF_OK;
 }
@@ -381,10 +384,10 @@ extern "C" size_t nedf_workspace_size(int32_t op, const nedf_scene* scene, const
   }
   int64_t cap = pair_capacity > 0 ? pair_capacity : n * int64_t(scene->n_inst > 0 ? scene->n_inst : 1);
   if (cap < 1) cap = 1;
-  cap = (cap + 15) & ~int64_t(15);  // the layout keeps a multiple of 16
-  if (cap > (int64_t(1) << 31) - 16) cap = (int64_t(1) << 31) - 16;
+  cap = (cap + SLAB_BLOCK - 1) / SLAB_BLOCK * SLAB_BLOCK;  // the layout keeps whole slab blocks
+  if (cap > (int64_t(1) << 31) - SLAB_BLOCK) cap = (int64_t(1) << 31) - SLAB_BLOCK;
   const size_t extra = op == NEDF_OP_SHADOW ? size_t(n) * SHADOW_EXTRA_PER_RAY : 0;
-  return ws_fixed_bytes(n, extra) + size_t(cap) * WS_BYTES_PER_PAIR;
+  return ws_fixed_bytes(n, extra) + size_t(cap) * WS_BYTES_PER_PAIR + size_t(cap / SLAB_BLOCK) * 4 + 1024;
 }
 
 extern "C" int32_t nedf_check_status(const void* ws, nedf_stream_t stream) {

@@ -381,57 +381,121 @@ __device__ __forceinline__ void push_slab(const KArgs& a, PairList* S, int lane,
   }
 }
 
-// List S = the pairs of list A in depth slab 0 (objects in mask) whose bound
-// does not lie beyond the pixel's current nearest hit.  Also records every
-// pair's slab in one byte (0xFF for objects outside the mask), so that the
-// later slabs read one byte per pair instead of the bound.
-__global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int n_slabs) {
-  const PairList* A = &a.C->A;
-  PairList* S = &a.C->S;
-  const int lane = threadIdx.x & 63;
-  for (int m = 0; m < a.n_obj; ++m) {
-    const bool in = (mask >> m) & 1u;
-    const int cnt = A->cnt[m], off = A->off[m];
-    const int stride = gridDim.x * blockDim.x;
-    for (int q0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); q0 < cnt; q0 += stride) {
-      const int q = q0 + lane;
-      bool keep = false;
-      uint2 pr = make_uint2(0u, 0u);
-      if (q < cnt) {
-        const float dm = a.pair_dm[off + q];
-        const int sl = in ? depth_slab(a, dm, n_slabs) : 0xFF;
-        a.pair_slab[off + q] = uint8_t(sl);
-        if (sl == 0) {
-          pr = a.pairs[off + q];
-          // margin against last-bit differences between kernels
-          keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
-        }
-      }
-      if (in) push_slab(a, S, lane, keep, m, pr);
-    }
-  }
+// Object of pair q of list A (segments in object order; a handful of objects).
+__device__ __forceinline__ int pair_object(const PairList* A, int n_obj, int q) {
+  int m = 0;
+  while (m + 1 < n_obj && q >= A->off[m + 1]) ++m;
+  return m;
 }
 
-// List S for slab `slab` >= 1 from the recorded slab bytes.  Each lane scans
-// sixteen consecutive pairs of list A (one 16-byte load); the wave compacts
-// the indices of matching pairs in LDS and then tests them 64 at a time, one
-// per lane, so that the reads of bound, pair and key are issued together.
-__global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
-  __shared__ int s_cand[eng::WAVES][1024];
+// Tests the pairs whose bits are set in `hits` (lane's pairs q0 + j) against
+// the pixels' current nearest hits and appends the survivors to list S.  The
+// wave first compacts the candidate indices in LDS (`cand`, 1024 entries) and
+// then takes them 64 at a time, one per lane, so that bound, pair and key
+// reads are issued together.
+__device__ __forceinline__ void slab_candidates(const KArgs& a, PairList* S, int* cand, int lane, int q0,
+                                                uint32_t hits) {
+  const int c = __popc(hits);
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  const int n_cand = __shfl(incl, 63);
+  if (n_cand == 0) return;
+  int k = incl - c;
+  while (hits) {
+    cand[k++] = q0 + __ffs(hits) - 1;
+    hits &= hits - 1u;
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int c0 = 0; c0 < n_cand; c0 += 64) {
+    bool keep = false;
+    int m = 0;
+    uint2 pr = make_uint2(0u, 0u);
+    if (c0 + lane < n_cand) {
+      const int q = cand[c0 + lane];
+      pr = a.pairs[q];
+      m = a.inst_object[pr.y];
+      const float dm = a.pair_dm[q];
+      // margin against last-bit differences between kernels
+      keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
+    }
+    push_slab(a, S, lane, keep, m, pr);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// List S = the pairs of list A in depth slab 0 (objects in mask) whose bound
+// does not lie beyond the pixel's current nearest hit.  Also records every
+// pair's slab in one byte (0xFF for objects outside the mask) and, per block
+// of SLAB_BLOCK pairs, the set of slabs present, so that the later slabs skip
+// blocks without their pairs and read one byte per pair in the others.  A
+// wave takes one block: sixteen consecutive pairs per lane.
+__global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int n_slabs) {
+  __shared__ int s_cand[eng::WAVES][SLAB_BLOCK];
   const PairList* A = &a.C->A;
   PairList* S = &a.C->S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int total = A->off[a.n_obj];
-  const int vecs = (total + 15) / 16;
+  const int nblk = (total + SLAB_BLOCK - 1) / SLAB_BLOCK;
+  const float4* dv = reinterpret_cast<const float4*>(a.pair_dm);
+  uint4* sv = reinterpret_cast<uint4*>(a.pair_slab);
+  const int wstride = gridDim.x * eng::WAVES;
+  for (int blk = blockIdx.x * eng::WAVES + wave; blk < nblk; blk += wstride) {
+    const int q0 = blk * SLAB_BLOCK + 16 * lane;
+    uint32_t bits = 0, hits = 0;
+    if (q0 < total) {
+      uint32_t bytes[4];
+      int mo = pair_object(A, a.n_obj, q0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float4 v = dv[q0 / 4 + i];
+        const float dm[4] = {v.x, v.y, v.z, v.w};
+        uint32_t by = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int q = q0 + 4 * i + j;
+          while (mo + 1 < a.n_obj && q >= A->off[mo + 1]) ++mo;
+          int sl = 0xFF;
+          if (q < total && ((mask >> mo) & 1u)) {
+            sl = depth_slab(a, dm[j], n_slabs);
+            bits |= 1u << sl;
+            if (sl == 0) hits |= 1u << (4 * i + j);
+          }
+          by |= uint32_t(sl) << (8 * j);
+        }
+        bytes[i] = by;
+      }
+      sv[q0 / 16] = make_uint4(bytes[0], bytes[1], bytes[2], bytes[3]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+    if (lane == 0) a.slab_mask[blk] = bits;
+    slab_candidates(a, S, s_cand[wave], lane, q0, hits);
+  }
+}
+
+// List S for slab `slab` >= 1: a wave takes one block of SLAB_BLOCK pairs,
+// skips it unless its slab set holds `slab`, else scans the slab bytes
+// (sixteen per lane, one 16-byte load) and tests the matching pairs.
+__global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
+  __shared__ int s_cand[eng::WAVES][SLAB_BLOCK];
+  const PairList* A = &a.C->A;
+  PairList* S = &a.C->S;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int total = A->off[a.n_obj];
+  const int nblk = (total + SLAB_BLOCK - 1) / SLAB_BLOCK;
   const uint4* sv = reinterpret_cast<const uint4*>(a.pair_slab);
   const uint32_t pat = 0x01010101u * uint32_t(slab);
-  int* cand = s_cand[wave];
-  const int stride = gridDim.x * blockDim.x;
-  for (int v0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); v0 < vecs; v0 += stride) {
-    const int v = v0 + lane;
-    uint32_t hits = 0;  // bit j: pair 16 v + j is in this slab
-    if (v < vecs) {
-      const uint4 b = sv[v];
+  const int wstride = gridDim.x * eng::WAVES;
+  for (int blk = blockIdx.x * eng::WAVES + wave; blk < nblk; blk += wstride) {
+    if (!((a.slab_mask[blk] >> slab) & 1u)) continue;
+    const int q0 = blk * SLAB_BLOCK + 16 * lane;
+    uint32_t hits = 0;  // bit j: pair q0 + j is in this slab
+    if (q0 < total) {
+      const uint4 b = sv[q0 / 16];
       const uint32_t wd[4] = {b.x ^ pat, b.y ^ pat, b.z ^ pat, b.w ^ pat};
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -439,40 +503,10 @@ __global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
         for (int j = 0; j < 4; ++j)
           if (((wd[i] >> (8 * j)) & 0xFFu) == 0u) hits |= 1u << (4 * i + j);
       // bytes past the last pair are ignored
-      const int rem = total - 16 * v;
+      const int rem = total - q0;
       if (rem < 16) hits &= (1u << rem) - 1u;
     }
-    const int c = __popc(hits);
-    int incl = c;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(incl, off);
-      if (lane >= off) incl += y;
-    }
-    const int n_cand = __shfl(incl, 63);
-    if (n_cand == 0) continue;
-    int k = incl - c;
-    while (hits) {
-      const int j = __ffs(hits) - 1;
-      cand[k++] = 16 * v + j;
-      hits &= hits - 1u;
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int c0 = 0; c0 < n_cand; c0 += 64) {
-      const bool mine = c0 + lane < n_cand;
-      bool keep = false;
-      int m = 0;
-      uint2 pr = make_uint2(0u, 0u);
-      if (mine) {
-        const int q = cand[c0 + lane];
-        pr = a.pairs[q];
-        m = a.inst_object[pr.y];
-        const float dm = a.pair_dm[q];
-        keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
-      }
-      push_slab(a, S, lane, keep, m, pr);
-    }
-    __builtin_amdgcn_wave_barrier();
+    slab_candidates(a, S, s_cand[wave], lane, q0, hits);
   }
 }
 

@@ -47,10 +47,12 @@ struct WsCounters {
 
 // Workspace layout: status | counters | keys | opacity bits | extra (shadow
 // rays) | pairs A | pairs B | pairs S | depth bounds of list A | depth slabs
-// of list A.  Capacity is per pair list (a multiple of 16).
+// of list A | per 1024 pairs of list A, the set of slabs present (one bit per
+// slab).  Capacity is per pair list (a multiple of SLAB_BLOCK).
 constexpr size_t WS_BYTES_PER_PAIR = 3 * 8 + 4 + 1;
+constexpr int SLAB_BLOCK = 1024;
 struct WsLayout {
-  size_t counters, keys, opac, pairs, pairsB, pairsS, pairsD, pairsSlab, extra, end;
+  size_t counters, keys, opac, pairs, pairsB, pairsS, pairsD, pairsSlab, slabMask, extra, end;
   int64_t capacity;
 };
 

@@ -28,6 +28,7 @@ struct KArgs {
   uint2* pairsS;         // depth-slab list of the network stage
   float* pair_dm;        // per pair of list A: lowest depth it can report (world units)
   uint8_t* pair_slab;    // per pair of list A: its depth slab (network stage)
+  uint32_t* slab_mask;   // per SLAB_BLOCK pairs of list A: bit s set if slab s occurs
   // shadow-ray queries: only whether some hit lies closer than
   // ray_tmax[ray] - tmax_eps matters (null for depth queries)
   const float* ray_tmax;

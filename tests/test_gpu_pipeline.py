@@ -125,6 +125,25 @@ def test_counters_reset_for_small_ray_counts():
     assert np.array_equal(got[0][2], got[1][2]) and np.array_equal(got[0][1].view(np.uint32), got[1][1].view(np.uint32))
 
 
+def test_pair_capacity_overflow_is_reported():
+    """A pair capacity below the culled pair count is reported through the
+    status word (NEDF_ERR_CAPACITY) after the call; the same scene with enough
+    capacity reports OK."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene(size=48)
+    log("case: infer bf16 48x48 with pair capacity 1024 (too small), then default")
+    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
+    ws = api.Workspace()
+    api.infer_depth_id(sc, api.camera_rays(cam), dtype="bf16", refine_steps=0, n_samples=64, ws=ws,
+                       pair_capacity=1024)
+    assert api.check_status(ws) == 6
+    ws2 = api.Workspace()
+    api.infer_depth_id(sc, api.camera_rays(cam), dtype="bf16", refine_steps=0, n_samples=64, ws=ws2)
+    assert api.check_status(ws2) == 0
+    assert api.ws_counters(ws2)["culled_pairs"] > 1024
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_infer_secant_refinement(dtype):
     need_gpu()
