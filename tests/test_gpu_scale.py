@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
-from oracle import camera_rays, nedf_pair
+from oracle import camera_rays, nedf_pair, shade_deferred
 from oracle.render import march_instance
 from tests.gpu_util import need_gpu, gpu_scene, log
 
@@ -42,6 +42,43 @@ def _candidates(models, nedfs, insts, o, d, n_samples):
         t_perp = -np.sum(o_l * d_l, axis=-1)
         t_in = inst.s * (t_perp - np.sqrt(np.maximum(l * l - m * m, 0.0)))
         out.append((k, hit, D, p, path, A, np.where(m < l, t_in, np.inf)))
+    return out
+
+
+def _candidates_sparse(models, nedfs, insts, o, d, n_samples, t_max=None):
+    """As _candidates, but each instance's oracle runs only on the rays that
+    meet its bounding sphere, and (given t_max per ray) enter it no farther
+    than t_max; the others get no hit, p = 0, t_in = inf."""
+    from oracle import to_local
+    n = o.shape[0]
+    out = []
+    for k, inst in enumerate(insts):
+        o_l, d_l = to_local(inst, o, d)
+        m = np.linalg.norm(np.cross(o_l, d_l), axis=-1)
+        l = models[inst.model].bound
+        meet = m < l
+        if t_max is not None:
+            tp = -np.sum(o_l * d_l, axis=-1)
+            t_enter = inst.s * (tp - np.sqrt(np.maximum(l * l - m * m, 0.0)))
+            meet &= t_enter <= t_max
+        sel = np.nonzero(meet)[0]
+        if sel.size == 0:
+            continue
+        hit = np.zeros(n, bool)
+        D = np.full(n, np.inf)
+        p = np.zeros(n)
+        path = np.full(n, -1)
+        A = np.full(n, np.nan)
+        h_, D_, p_, path_ = nedf_pair(nedfs[inst.model], models[inst.model], inst, o[sel], d[sel], p_lo=0.2,
+                                      p_hi=0.8, n_samples=n_samples, gemm="bf16")
+        hit[sel], D[sel], p[sel], path[sel] = h_, D_, p_, path_
+        fb = sel[path_ == 1]
+        if fb.size:
+            _, Af, _ = march_instance(models[inst.model], inst, o[fb], d[fb], n_samples, None, "bf16")
+            A[fb] = Af
+        t_perp = -np.sum(o_l * d_l, axis=-1)
+        t_in = np.where(meet, inst.s * (t_perp - np.sqrt(np.maximum(l * l - m * m, 0.0))), np.inf)
+        out.append((k, hit, D, p, path, A, t_in))
     return out
 
 
@@ -124,3 +161,81 @@ def test_tiled_culling_keeps_every_pair():
     assert n_c > 10 * i_c.size
     assert abs(n_c - n_a) <= max(10, 1e-4 * n_a)
     assert differ <= max(5, 1e-4 * i_c.size)
+
+
+def test_batched_scene_full_frame_shading_sampled_parity():
+    """K = 8 deferred shading of the 1080p, 1,000-instance frame in the launch
+    configuration the benchmark times (BF16, two workgroups per CU), checked
+    on seeded sampled pixels against the FP64 oracle (BF16-emulating GEMMs)
+    given the same depth and ID buffers."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, insts, cam, _ = syn.config4_scene()
+    nedfs = [syn.nedf_model(4, 200 + k, head_scale=16.0) for k in range(len(models))]
+    log("case: batched scene 1920x1080, 1000 instances, BF16 shading K=8 on the frame's depth/ID")
+    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
+    rays = api.camera_rays(cam)
+    depth, ident = api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, n_samples=128)
+    rgb = api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, clear_rgb=(0.1, 0.2, 0.3), dtype="bf16")
+    depth, ident, rgb = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(rgb).astype(np.float64)
+    pix = syn.pixel_subset(4, cam.n_rays, 64)
+    o, d = camera_rays(cam, pix)
+    ref = shade_deferred(models, insts, o, d, depth[pix], ident[pix], K=8, h=0.05, clear=(0.1, 0.2, 0.3),
+                         gemm="bf16")
+    got = rgb[pix]
+    hit = ident[pix] >= 0
+    err = np.abs(got - ref).max(axis=1)
+    log(f"[batched shade bf16] pixels={len(pix)} hits={int(hit.sum())} max_err={err.max():.3e}")
+    assert hit.sum() >= len(pix) // 2
+    assert np.all(got[~hit] == np.array([0.1, 0.2, 0.3], np.float32))
+    assert err.max() <= 2e-2
+
+
+def test_batched_scene_full_frame_shadow_sampled_parity():
+    """Shadow rays to the two lights of the 1080p, 1,000-instance frame (BF16
+    intersection networks with marcher fallback, occlusion-aware pruning),
+    checked on seeded sampled pixels against the FP64 oracle's composition
+    along each shadow ray.  Exempt: a decision within a BF16 band of a
+    threshold on an instance that could occlude, or an occluder depth within
+    a small band of the cut |L - x| - eps."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, insts, cam, lights = syn.config4_scene()
+    nedfs = [syn.nedf_model(4, 200 + k, head_scale=16.0) for k in range(len(models))]
+    extent = syn.scene_extent(insts, [m.bound for m in models])
+    eps = 0.01 * extent
+    log("case: batched scene 1920x1080, 1000 instances, BF16 shadow rays to 2 lights")
+    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
+    rays = api.camera_rays(cam)
+    depth, ident = api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, n_samples=128)
+    fac = api.shadow(sc, rays, depth, ident, lights, eps, beta=0.5, method="nedf", dtype="bf16", n_samples=128)
+    depth, ident, fac = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(fac).astype(np.float64)
+    pix = syn.pixel_subset(4, cam.n_rays, 32, stream=9)
+    pix = pix[ident[pix] >= 0]
+    o, d = camera_rays(cam, pix)
+    x = o + depth[pix, None] * d
+    ref = np.ones(len(pix))
+    exempt = np.zeros(len(pix), bool)
+    for L in np.asarray(lights, np.float64).reshape(-1, 3):
+        v = x - L
+        dist = np.linalg.norm(v, axis=1)
+        ds = v / dist[:, None]
+        os_ = np.broadcast_to(L, ds.shape).copy()
+        cut = dist - eps
+        # instances entered beyond the cut (plus the exemption band) cannot occlude
+        cands = _candidates_sparse(models, nedfs, insts, os_, ds, 128, t_max=cut + 5e-3 * max(i.s for i in insts))
+        best = np.full(len(pix), np.inf)
+        near = np.zeros(len(pix), bool)
+        for k, hit, D, p, path, A, t_in in cands:
+            best = np.minimum(best, np.where(hit, D, np.inf))
+            flip = (np.abs(p - 0.2) <= 2e-2) | (np.abs(p - 0.8) <= 2e-2) | (np.abs(A - 0.5) <= 2e-2)
+            near |= flip & (t_in <= cut + 5e-3 * insts[k].s)
+            near |= hit & (np.abs(D - cut) <= 5e-3 * insts[k].s)
+        occl = best < cut
+        ref = np.where(occl, ref * 0.5, ref)
+        exempt |= near
+    bad = (fac[pix] != ref) & ~exempt
+    log(f"[batched shadow bf16] pixels={len(pix)} shadowed={int((ref < 1).sum())} exempt={int(exempt.sum())} "
+        f"mismatch={int(bad.sum())}")
+    assert len(pix) >= 12 and bad.sum() == 0
+    assert exempt.sum() <= len(pix) // 3
