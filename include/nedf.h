@@ -383,10 +383,11 @@ int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* const* W, c
  * Autotuning.  Not a step of the paper's method: a tuning aid for the grouped
  * launches that evaluate every (ray, instance) pair of Alg. 1 per object.
  * The tunable launch shape of the matrix-core kernels is encoded as
- * 100 * (blocks - 1) + 10 * occupancy + superchunk: the number of 32-pair
- * blocks each wave carries through the network (1 or 2, intersection network
- * only; two blocks share every weight read from LDS), the number of
- * persistent workgroups per CU (1 or 2) and the number of 32-row weight
+ * 1000 * (waves / 4 - 1) + 100 * (blocks - 1) + 10 * occupancy + superchunk:
+ * the waves of a workgroup (4 or 8; eight waves share one copy of each weight
+ * chunk in LDS), the number of 32-row blocks each wave carries through the
+ * network (1 or 2; two blocks share every weight read from LDS), the number
+ * of persistent workgroups per CU (1 or 2) and the number of 32-row weight
  * chunks streamed into LDS per copy and barrier (1, 2 or 4).  NEDF_TUNE_SLABS is the number of depth slabs in
  * which nedf_infer_depth_id runs the intersection network front to back
  * (1, 2, 4, 8, 16 or 32; an exact pruning: a pair whose smallest possible

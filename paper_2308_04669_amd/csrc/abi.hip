@@ -311,7 +311,7 @@ void apply_march_opts(KArgs& k, const nedf_march_opts& o) {
 
 // Plain-marcher depth into k.depth / k.id / k.opacity.
 void run_march(const Prepared& P, int dtype, hipStream_t s) {
-  stage_init_cull(P.k, s, P.mlp, eng::WAVES);
+  stage_init_cull(P.k, s, P.mlp, march_waves(dtype, P.W));
   KArgs k = P.k;
   k.L = &k.C->A;
   stage_march(k, s, false, P.analytic, dtype, P.mlp ? P.W : 0, P.H, P.L);
@@ -733,7 +733,7 @@ namespace {
 std::mutex g_tune_mu;
 // [kernel][dtype]: 10 * workgroups per CU + chunks per superchunk; for
 // NEDF_TUNE_SLABS the number of depth slabs of the network stage
-int g_tune[3][3] = {{11, 12, 14}, {11, 12, 14}, {8, 8, 8}};
+int g_tune[3][3] = {{11, 1012, 14}, {11, 1012, 14}, {8, 8, 8}};
 
 int tune_candidates(int kernel, int dtype, int32_t* out) {
   if (kernel < 0 || kernel > 2 || dtype < 0 || dtype > 2) return 0;
@@ -743,11 +743,11 @@ int tune_candidates(int kernel, int dtype, int32_t* out) {
   }
   if (dtype == NEDF_F32) { out[0] = 11; return 1; }
   if (dtype == NEDF_BF16) {
-    out[0] = 11; out[1] = 12; out[2] = 21; out[3] = 111; out[4] = 112;
-    return 5;
+    out[0] = 11; out[1] = 12; out[2] = 21; out[3] = 111; out[4] = 112; out[5] = 1011; out[6] = 1012;
+    return 7;
   }
   if (kernel == NEDF_TUNE_NEDF) {
-    out[0] = 11; out[1] = 12; out[2] = 14; out[3] = 21; out[4] = 22; out[5] = 111; out[6] = 112; out[7] = 114;
+    out[0] = 11; out[1] = 12; out[2] = 14; out[3] = 21; out[4] = 22; out[5] = 1011; out[6] = 1012; out[7] = 1014;
     return 8;
   }
   return 0;  // no FP8 marcher

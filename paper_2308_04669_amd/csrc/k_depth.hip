@@ -434,7 +434,7 @@ __device__ __forceinline__ void slab_candidates(const KArgs& a, PairList* S, int
 // blocks without their pairs and read one byte per pair in the others.  A
 // wave takes one block: sixteen consecutive pairs per lane.
 __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int n_slabs) {
-  __shared__ int s_cand[eng::WAVES][SLAB_BLOCK];
+  __shared__ int s_cand[4][SLAB_BLOCK];
   const PairList* A = &a.C->A;
   PairList* S = &a.C->S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -442,8 +442,8 @@ __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int 
   const int nblk = (total + SLAB_BLOCK - 1) / SLAB_BLOCK;
   const float4* dv = reinterpret_cast<const float4*>(a.pair_dm);
   uint4* sv = reinterpret_cast<uint4*>(a.pair_slab);
-  const int wstride = gridDim.x * eng::WAVES;
-  for (int blk = blockIdx.x * eng::WAVES + wave; blk < nblk; blk += wstride) {
+  const int wstride = gridDim.x * 4;
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += wstride) {
     const int q0 = blk * SLAB_BLOCK + 16 * lane;
     uint32_t bits = 0, hits = 0;
     if (q0 < total) {
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int 
 // skips it unless its slab set holds `slab`, else scans the slab bytes
 // (sixteen per lane, one 16-byte load) and tests the matching pairs.
 __global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
-  __shared__ int s_cand[eng::WAVES][SLAB_BLOCK];
+  __shared__ int s_cand[4][SLAB_BLOCK];
   const PairList* A = &a.C->A;
   PairList* S = &a.C->S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -489,8 +489,8 @@ __global__ __launch_bounds__(256) void k_slab_next(KArgs a, int slab) {
   const int nblk = (total + SLAB_BLOCK - 1) / SLAB_BLOCK;
   const uint4* sv = reinterpret_cast<const uint4*>(a.pair_slab);
   const uint32_t pat = 0x01010101u * uint32_t(slab);
-  const int wstride = gridDim.x * eng::WAVES;
-  for (int blk = blockIdx.x * eng::WAVES + wave; blk < nblk; blk += wstride) {
+  const int wstride = gridDim.x * 4;
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += wstride) {
     if (!((a.slab_mask[blk] >> slab) & 1u)) continue;
     const int q0 = blk * SLAB_BLOCK + 16 * lane;
     uint32_t hits = 0;  // bit j: pair q0 + j is in this slab
@@ -611,8 +611,8 @@ __global__ void k_march_analytic(KArgs a, uint32_t mask) {
 // samples through the register-resident density network (NB blocks of 32
 // share every weight read from LDS), then scans each block's optical depths
 // across the wave in sample order, so that the sums are the same for any NB.
-template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NB>
-__global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NB, int NW>
+__global__ __launch_bounds__(64 * NW, OCC) void k_march_mlp(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
   constexpr int KSH = WIDTH / T::KPS;
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
   bool primed = false;
   while (item < total) {
     const int obj = item_object(PL, a.n_obj, item);
-    const int local = (item - PL->item_start[obj]) * eng::WAVES + wave;
+    const int local = (item - PL->item_start[obj]) * NW + wave;
     const bool valid = local < PL->cnt[obj];
     const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
     const ObjDesc& od = a.obj[obj];
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) partial[nb][0] = 0.f;
       typename T::frag Blast[NB][KSH];
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX, NB>(hb, blob, Benc, lds, partial,
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX, NB, NW>(hb, blob, Benc, lds, partial,
                                                                                Blast, nullptr, &slot, next_blob,
                                                                                primed);
       primed = next_blob != nullptr;
@@ -725,8 +725,8 @@ __global__ __launch_bounds__(256, OCC) void k_march_mlp(KArgs a) {
 // line coordinates (NB blocks of 32 pairs share every weight read from LDS).
 // Confident hits go to the key buffer, uncertain pairs (and origins inside
 // the bounding sphere) to list B for the marcher.
-template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NB>
-__global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NB, int NW>
+__global__ __launch_bounds__(64 * NW, OCC) void k_nedf(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int PPW = 32 * NB;  // pairs per wave and item
   constexpr int KS0 = eng::ks_for_slots<DT>(6 * L + 3);
@@ -734,7 +734,8 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
   constexpr int CHUNK = eng::cmax(eng::chunk_bytes<DT>(KS0, 0), eng::chunk_bytes<DT>(KSH, 2));
   __shared__ __attribute__((aligned(16))) uint8_t lds[eng::NBUF * eng::slot_bytes(CHUNK, SBX)];
   // per-lane pair state parked across the network (keeps registers free)
-  __shared__ __attribute__((aligned(16))) uint8_t s_stash[16 * NB * eng::THREADS];
+  constexpr int NT = 64 * NW;
+  __shared__ __attribute__((aligned(16))) uint8_t s_stash[16 * NB * NT];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const uint32_t stash = eng::lds_offset(s_stash) + 16u * threadIdx.x;
@@ -755,7 +756,7 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
     __syncthreads();
     const int next = s_item;
     const int obj = item_object(PL, a.n_obj, item);
-    const int first = (item - PL->item_start[obj]) * (PPW * eng::WAVES) + wave * PPW + (lane & 31);
+    const int first = (item - PL->item_start[obj]) * (PPW * NW) + wave * PPW + (lane & 31);
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.nedf_blob;
     const uint8_t* next_blob = next < total ? a.obj[item_object(PL, a.n_obj, next)].nedf_blob : nullptr;
@@ -785,7 +786,7 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
       const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
       eng::encode_input<DT, 6, L, KS0>(pl, half_v, Benc[nb], in_scale);
       // ray and instance ids (< 2^31, flags in bit 31), t_perp and s
-      eng::lds_write16(stash + uint32_t(nb) * (16u * eng::THREADS),
+      eng::lds_write16(stash + uint32_t(nb) * (16u * NT),
                        eng::u32x4{pr.x | (valid ? 0x80000000u : 0u), pr.y | (inside ? 0x80000000u : 0u),
                                   __float_as_uint(tperp), __float_as_uint(g.s)});
     }
@@ -793,12 +794,12 @@ __global__ __launch_bounds__(256, OCC) void k_nedf(KArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) partial[nb][0] = partial[nb][1] = 0.f;
     typename T::frag Blast[NB][KSH];
-    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0, WIDTH / 32, SBX, NB>(hb, blob, Benc, lds, partial, Blast,
+    eng::trunk<DT, WIDTH, KS0, NHID, 2, CHUNK, false, 0, WIDTH / 32, SBX, NB, NW>(hb, blob, Benc, lds, partial, Blast,
                                                                              nullptr, &slot, next_blob, primed);
     primed = next_blob != nullptr;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      eng::u32x4 st = eng::lds_read16<0>(stash + uint32_t(nb) * (16u * eng::THREADS)), d1 = st, d2 = st, d3 = st;
+      eng::u32x4 st = eng::lds_read16<0>(stash + uint32_t(nb) * (16u * NT)), d1 = st, d2 = st, d3 = st;
       eng::lds_wait4<0>(st, d1, d2, d3);
       const uint2 prs = make_uint2(st.x & 0x7FFFFFFFu, st.y & 0x7FFFFFFFu);
       const bool valid_s = (st.x >> 31) != 0, inside_s = (st.y >> 31) != 0;
@@ -863,56 +864,55 @@ int cu_count() {
 // sharing each weight read, workgroups per CU, chunks per copy); other shapes
 // use one block, one workgroup per CU and the default superchunk.  The grid
 // is persistent: one workgroup per CU and occupancy level.
+// Tuning value of the matrix-core kernels: 1000 * (workgroup waves / 4 - 1) +
+// 100 * (row blocks per wave - 1) + 10 * workgroups per CU + chunks per
+// superchunk.
+int tune_waves(int v) { return v >= 1000 ? 8 : 4; }
+int nedf_rows(int v) { return v % 1000 >= 100 ? 2 : 1; }
+
 template <int DT, int WIDTH, int NHID, int L>
 void launch_march_mlp(const KArgs& k, hipStream_t s) {
-  const dim3 b(eng::THREADS);
+  const dim3 b4(256), b8(512), g1(cu_count()), g2(2 * cu_count());
   if constexpr (DT == 1 && WIDTH == 256) {
-    const int v = tune_value(NEDF_TUNE_MARCH, DT);
-    if (v == 11) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 1>), dim3(cu_count()), b, 0, s, k);
-      return;
-    }
-    if (v == 21) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 2, 1>), dim3(2 * cu_count()), b, 0, s, k);
-      return;
-    }
-    if (v == 111) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 2>), dim3(cu_count()), b, 0, s, k);
-      return;
-    }
-    if (v == 112) {
-      hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 2, 1, 2>), dim3(cu_count()), b, 0, s, k);
-      return;
+    switch (tune_value(NEDF_TUNE_MARCH, DT)) {
+      case 11: hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 1, 4>), g1, b4, 0, s, k); return;
+      case 21: hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 2, 1, 4>), g2, b4, 0, s, k); return;
+      case 111: hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 2, 4>), g1, b4, 0, s, k); return;
+      case 112: hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 2, 1, 2, 4>), g1, b4, 0, s, k); return;
+      case 1011: hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 1, 1, 1, 8>), g1, b8, 0, s, k); return;
+      case 1012: hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, 2, 1, 1, 8>), g1, b8, 0, s, k); return;
+      default: break;
     }
   }
-  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>(), 1, 1>), dim3(cu_count()), b, 0, s,
-                     k);
+  hipLaunchKernelGGL((k_march_mlp<DT, WIDTH, NHID, L, eng::sb_default<DT>(), 1, 1, 4>), g1, b4, 0, s, k);
 }
-
-// Tuning value of the network kernel: 100 * (row blocks per wave - 1) +
-// 10 * workgroups per CU + chunks per superchunk.
-int nedf_rows(int v) { return v >= 100 ? 2 : 1; }
 
 template <int DT>
 void launch_nedf_net(const KArgs& k, hipStream_t s, int v) {
-  const dim3 b(eng::THREADS), g1(cu_count()), g2(2 * cu_count());
+  const dim3 b4(256), b8(512), g1(cu_count()), g2(2 * cu_count());
   if constexpr (DT == 2) {
-    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1>), g1, b, 0, s, k);
-    else if (v == 12) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1>), g1, b, 0, s, k);
-    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2, 1>), g2, b, 0, s, k);
-    else if (v == 22) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 2, 1>), g2, b, 0, s, k);
-    else if (v == 111) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 2>), g1, b, 0, s, k);
-    else if (v == 112) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 2>), g1, b, 0, s, k);
-    else if (v == 114) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 2>), g1, b, 0, s, k);
-    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1>), g1, b, 0, s, k);
+    switch (v) {
+      case 11: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 4>), g1, b4, 0, s, k); return;
+      case 12: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 4>), g1, b4, 0, s, k); return;
+      case 21: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2, 1, 4>), g2, b4, 0, s, k); return;
+      case 22: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 2, 1, 4>), g2, b4, 0, s, k); return;
+      case 1011: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 8>), g1, b8, 0, s, k); return;
+      case 1012: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 8>), g1, b8, 0, s, k); return;
+      case 1014: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1, 8>), g1, b8, 0, s, k); return;
+      default: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1, 4>), g1, b4, 0, s, k); return;
+    }
   } else if constexpr (DT == 1) {
-    if (v == 11) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1>), g1, b, 0, s, k);
-    else if (v == 21) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2, 1>), g2, b, 0, s, k);
-    else if (v == 111) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 2>), g1, b, 0, s, k);
-    else if (v == 112) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 2>), g1, b, 0, s, k);
-    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1>), g1, b, 0, s, k);
+    switch (v) {
+      case 11: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 4>), g1, b4, 0, s, k); return;
+      case 21: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 2, 1, 4>), g2, b4, 0, s, k); return;
+      case 111: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 2, 4>), g1, b4, 0, s, k); return;
+      case 112: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 2, 4>), g1, b4, 0, s, k); return;
+      case 1011: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 8>), g1, b8, 0, s, k); return;
+      case 1012: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 8>), g1, b8, 0, s, k); return;
+      default: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 4>), g1, b4, 0, s, k); return;
+    }
   } else {
-    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1>), g1, b, 0, s, k);
+    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 4>), g1, b4, 0, s, k);
   }
 }
 
@@ -922,6 +922,11 @@ unsigned grid_for(int64_t n) {
 }
 
 }  // namespace
+
+int march_waves(int dtype, int width) {
+  if (dtype != NEDF_BF16 || width != 256) return 4;
+  return tune_waves(tune_value(NEDF_TUNE_MARCH, dtype));
+}
 
 bool march_mlp_supported(int dtype, int width, int n_hidden, int L) {
   if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
@@ -988,7 +993,7 @@ void stage_march(const KArgs& k0, hipStream_t s, bool list_b, uint32_t analytic_
     k.item_mask = 0;
     for (int m = 0; m < k.n_obj; ++m)
       if (k.obj[m].field == NEDF_FIELD_MLP) k.item_mask |= 1u << m;
-    k.item_pairs = eng::WAVES;
+    k.item_pairs = march_waves(dtype, W);
     hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(64), 0, s, k, k.L);
   }
   if (analytic_mask) {
@@ -1017,7 +1022,7 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
   k.item_mask = nedf_mask;
   // launch shape from the tuning table, fixed for all slabs of the stage
   const int v = dtype == NEDF_F32 ? 11 : tune_value(NEDF_TUNE_NEDF, dtype);
-  k.item_pairs = 32 * eng::WAVES * nedf_rows(v);
+  k.item_pairs = 32 * tune_waves(v) * nedf_rows(v);
   for (int slab = 0; slab < n_slabs; ++slab) {
     hipLaunchKernelGGL(k_slab_begin, dim3(1), dim3(64), 0, s, k);
     if (slab == 0) hipLaunchKernelGGL(k_slab_first, dim3(2048), dim3(256), 0, s, k0, nedf_mask, n_slabs);

@@ -126,8 +126,8 @@ __global__ void k_refine_analytic(KArgs a, uint32_t mask) {
 
 // Density-network refinement: items of 128 pixels (32 per wave) of one
 // SDF-mode object; each evaluation of f is one pass of the trunk.
-template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_refine_mlp(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int SBX, int OCC, int NW>
+__global__ __launch_bounds__(64 * NW, OCC) void k_refine_mlp(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256, OCC) void k_refine_mlp(KArgs a) {
     __syncthreads();
     if (item >= PL->total_items) break;
     const int obj = item_object(PL, a.n_obj, item);
-    const int local = (item - PL->item_start[obj]) * (32 * eng::WAVES) + wave * 32 + (lane & 31);
+    const int local = (item - PL->item_start[obj]) * (32 * NW) + wave * 32 + (lane & 31);
     const bool valid = local < PL->cnt[obj];
     const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
     const ObjDesc& od = a.obj[obj];
@@ -168,8 +168,8 @@ __global__ __launch_bounds__(256, OCC) void k_refine_mlp(KArgs a) {
       float partial[NB][1] = {{0.f}};
       typename T::frag Blast[NB][KSH];
       const uint8_t* nb_ = ++eval_i < n_eval ? blob : nullptr;
-      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
-                                                                           nullptr, &slot, nb_, primed);
+      eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, false, 0, WIDTH / 32, SBX, NB, NW>(hb, blob, Benc, lds, partial,
+                                                                                   Blast, nullptr, &slot, nb_, primed);
       primed = nb_ != nullptr;
       const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
       return mlp_surface(od, u, p[0], p[1], p[2]);
@@ -208,8 +208,8 @@ __global__ void k_clear_rgb(KArgs a, const int32_t* ids) {
 // NeRF shading: a wave shades 32 / K pixels with K samples each; trunk with
 // the sigma head, then the colour layer on [h_last, gamma_dirL(d)], then
 // local compositing across each pixel's K lanes.
-template <int DT, int WIDTH, int NHID, int L, int DIRL, int RGBW, int SBX, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_shade(KArgs a) {
+template <int DT, int WIDTH, int NHID, int L, int DIRL, int RGBW, int SBX, int OCC, int NW>
+__global__ __launch_bounds__(64 * NW, OCC) void k_shade(KArgs a) {
   using T = eng::Tr<DT>;
   constexpr int NB = T::NB;
   constexpr int KS0 = eng::ks_for_slots<DT>(3 * L + 2);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256, OCC) void k_shade(KArgs a) {
     __syncthreads();
     if (item >= PL->total_items) break;
     const int obj = item_object(PL, a.n_obj, item);
-    const int local = (item - PL->item_start[obj]) * (ppw * eng::WAVES) + wave * ppw + q;
+    const int local = (item - PL->item_start[obj]) * (ppw * NW) + wave * ppw + q;
     const bool valid = local < PL->cnt[obj];
     const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
     const ObjDesc& od = a.obj[obj];
@@ -255,8 +255,8 @@ __global__ __launch_bounds__(256, OCC) void k_shade(KArgs a) {
     float partial[NB][1] = {{0.f}};
     typename T::frag Blast[NB][KSH];
     int cur = 0;
-    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR, RGBW / 32, SBX>(hb, blob, Benc, lds, partial, Blast,
-                                                                         blob + uniform_load_u64(&hb->off_rgb), &cur);
+    eng::trunk<DT, WIDTH, KS0, NHID, 1, CHUNK, true, CBR, RGBW / 32, SBX, NB, NW>(
+        hb, blob, Benc, lds, partial, Blast, blob + uniform_load_u64(&hb->off_rgb), &cur);
     const float u = partial[0][0] + __shfl_xor(partial[0][0], 32) + head_b;
     const float sig = mlp_sigma(od, u, p[0], p[1], p[2]);
     // colour layer input: [h_last, gamma_dirL(d_l)]
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256, OCC) void k_shade(KArgs a) {
     }
     float prgb[NB][3] = {{0.f, 0.f, 0.f}};
     typename T::frag dummy[NB][1];
-    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK, RGBW / 32, SBX>(
+    eng::layer<DT, NB, KSR, RGBW / 32, CBR, 0, 1, 3, 1, CHUNK, RGBW / 32, SBX, NW>(
         Bc, dummy, blob + uniform_load_u64(&hb->off_rgb), nullptr, lds, cur, prgb);
     float c[3];
 #pragma unroll
@@ -387,11 +387,14 @@ void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ml
     hipLaunchKernelGGL(k_refine_analytic, dim3(256), dim3(256), 0, s, k, sphere_mask);
   }
   if (mlp_mask) {
-    stage_bin_pixels(k, s, ids, mlp_mask, 32 * eng::WAVES);
+    // BF16: two workgroups of 4 waves per CU (measured faster here than one
+    // of 8 waves, which spills); FP32: one of 4 waves
+    stage_bin_pixels(k, s, ids, mlp_mask, 32 * 4);
     if (dtype == NEDF_BF16)
-      hipLaunchKernelGGL((k_refine_mlp<1, 256, 8, 10, 1, 2>), dim3(2 * cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_refine_mlp<1, 256, 8, 10, 1, 2, 4>), dim3(2 * cu_count2()), dim3(256), 0, s, k);
     else
-      hipLaunchKernelGGL((k_refine_mlp<0, 256, 8, 10, eng::sb_default<0>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_refine_mlp<0, 256, 8, 10, eng::sb_default<0>(), 1, 4>), dim3(cu_count2()), dim3(256), 0,
+                         s, k);
   }
   prof_mark("infer.refine", s, false);
 }
@@ -400,11 +403,14 @@ void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ner
   prof_mark("shade", s, true);
   hipLaunchKernelGGL(k_clear_rgb, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids);
   if (nerf_mask) {
-    stage_bin_pixels(k, s, ids, nerf_mask, (32 / k.shade_K) * eng::WAVES);
+    // BF16: one workgroup of 8 waves per CU sharing each weight copy; FP32: 4 waves
+    const int nw = dtype == NEDF_BF16 ? 8 : 4;
+    stage_bin_pixels(k, s, ids, nerf_mask, (32 / k.shade_K) * nw);
     if (dtype == NEDF_BF16)
-      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, 1, 2>), dim3(2 * cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, 2, 1, 8>), dim3(cu_count2()), dim3(512), 0, s, k);
     else
-      hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128, eng::sb_default<0>(), 1>), dim3(cu_count2()), dim3(eng::THREADS), 0, s, k);
+      hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128, eng::sb_default<0>(), 1, 4>), dim3(cu_count2()), dim3(256),
+                         0, s, k);
   }
   prof_mark("shade", s, false);
 }

@@ -62,6 +62,9 @@ size_t ws_fixed_bytes(int64_t n_rays, size_t extra_bytes);
 hipError_t launch_compose_transforms(const double* G, int32_t n, float* w2l, hipStream_t s);
 
 bool march_mlp_supported(int dtype, int width, int n_hidden, int L);
+// Waves per workgroup of the marcher launch the tuning table selects (the
+// pairs per work item of a list it marches).
+int march_waves(int dtype, int width);
 bool nedf_net_supported(int dtype, int width, int n_hidden, int L);
 bool shade_supported(int dtype, const nedf_mlp_shape& s);
 bool refine_supported(int dtype, const nedf_mlp_shape& s);

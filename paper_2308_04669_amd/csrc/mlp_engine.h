@@ -1,6 +1,7 @@
 // Register-resident MLP engine on gfx950 matrix cores.
 //
-// A workgroup of 4 waves evaluates one network for 4 x 32 x NB samples.  Each
+// A workgroup of NW waves (4 or 8) evaluates one network for NW x 32 x NB
+// samples.  Each
 // wave keeps its samples' activations in registers as matrix-core B operands
 // for the whole network (see blob_layout.h); the workgroup streams the
 // weights through LDS.  A "chunk" is one output block (32 output features x
@@ -120,16 +121,16 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // piece, which writes identical bytes), so the number of a wave's
 // outstanding copies is a compile-time constant and the wait for a chunk can
 // leave the younger chunk's copies in flight.
-constexpr int dma_instr(int bytes) { return ((bytes + 1023) / 1024 + WAVES - 1) / WAVES; }
+constexpr int dma_instr(int bytes, int nw = WAVES) { return ((bytes + 1023) / 1024 + nw - 1) / nw; }
 
-template <int BYTES>
+template <int BYTES, int NW = WAVES>
 __device__ __forceinline__ void dma_chunk(const uint8_t* src, uint8_t* dst) {
   constexpr int P = (BYTES + 1023) / 1024;
-  constexpr int NI = dma_instr(BYTES);
+  constexpr int NI = dma_instr(BYTES, NW);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    int piece = wave + i * WAVES;
+    int piece = wave + i * NW;
     piece = piece < P ? piece : P - 1;
     const int off = piece * 1024 + lane * 16;
     if (BYTES % 1024 == 0 || off < BYTES)
@@ -290,7 +291,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // group being consumed.
 // MODE 0: hidden epilogue into Bout.  MODE 1: head epilogue.  MODE 2: both.
 template <int DT, int NB, int KS_IN, int FB, int CB_THIS, int CB_NEXT, int KSO, int NOUT, int MODE,
-          int CHUNK, int FB_NEXT = FB, int SBX = sb_default<DT>()>
+          int CHUNK, int FB_NEXT = FB, int SBX = sb_default<DT>(), int NW = WAVES>
 __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_IN],
                                       typename Tr<DT>::frag (&Bout)[NB][KSO], const uint8_t* w_this,
                                       const uint8_t* w_next, uint8_t* lds, int& cur,
@@ -464,11 +465,11 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
     uint8_t* nbuf = lds + nslot * SLOT;
     bool issued = false;
     if (sc + 2 < NSC) {
-      dma_chunk<SCB>(w_this + size_t(sc + 2) * SCB, nbuf);
+      dma_chunk<SCB, NW>(w_this + size_t(sc + 2) * SCB, nbuf);
       issued = true;
     } else if (w_next != nullptr) {
       if constexpr (CB_NEXT > 0) {
-        dma_chunk<SCB_N>(w_next + size_t(sc + 2 - NSC) * SCB_N, nbuf);
+        dma_chunk<SCB_N, NW>(w_next + size_t(sc + 2 - NSC) * SCB_N, nbuf);
         issued = true;
       }
     }
@@ -491,8 +492,8 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
         u32x4 tail[G] = {cw[0], cw[1], cw[2], cw[3]};
         // superchunk sc + 1 must have landed; sc + 2's copies may stay in flight
         if (issued) {
-          if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB)>();
-          else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024)>();
+          if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB, NW)>();
+          else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024, NW)>();
         } else {
           dma_wait_barrier();
         }
@@ -509,8 +510,8 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
       // the layer's last superchunk: the next layer's first superchunk must
       // have landed; its second may stay in flight
       if (issued) {
-        if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB)>();
-        else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024)>();
+        if (sc + 2 < NSC) dma_wait_barrier_n<dma_instr(SCB, NW)>();
+        else dma_wait_barrier_n<dma_instr(SCB_N > 0 ? SCB_N : 1024, NW)>();
       } else {
         dma_wait_barrier();
       }
@@ -533,7 +534,7 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
 // superchunk.  The caller's LDS array holds NBUF slots of slot_bytes(CHUNK,
 // SBX) bytes.
 template <int DT, int WIDTH, int KS0, int NHID, int NOUT, int CHUNK, bool KEEP_LAST, int CB_AFTER,
-          int FB_AFTER = WIDTH / 32, int SBX = sb_default<DT>(), int NB = Tr<DT>::NB>
+          int FB_AFTER = WIDTH / 32, int SBX = sb_default<DT>(), int NB = Tr<DT>::NB, int NW = WAVES>
 __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t* blob,
                                       const typename Tr<DT>::frag (&Benc)[NB][KS0],
                                       uint8_t* lds, float (&partial)[NB][NOUT],
@@ -561,38 +562,38 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
   constexpr int SLOT = slot_bytes(CHUNK, SBX);
   constexpr int SC0 = sb_for(FB, SBX) * CB0;  // first-layer superchunk bytes
   if (!primed) {
-    dma_chunk<SC0>(blob + off(0), lds + cur * SLOT);
-    dma_chunk<SC0>(blob + off(0) + SC0, lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * SLOT);
-    dma_wait_barrier_n<dma_instr(SC0)>();
+    dma_chunk<SC0, NW>(blob + off(0), lds + cur * SLOT);
+    dma_chunk<SC0, NW>(blob + off(0) + SC0, lds + (cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1) * SLOT);
+    dma_wait_barrier_n<dma_instr(SC0, NW)>();
   }
   // chunks after the last hidden layer: the colour layer, or the next pass
   constexpr int CB_TAIL = KEEP_LAST ? CB_AFTER : CB0;
   constexpr int FB_TAIL = KEEP_LAST ? FB_AFTER : FB;
   const uint8_t* w_tail = KEEP_LAST ? w_after : (next_blob ? next_blob + off(0) : nullptr);
   // layer 0: encoding -> X; then pairs X -> Y -> X; the last layer feeds the head
-  layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK, FB, SBX>(Benc, X, blob + off(0), blob + off(1), lds, cur,
+  layer<DT, NB, KS0, FB, CB0, CBH, KSH, NOUT, 0, CHUNK, FB, SBX, NW>(Benc, X, blob + off(0), blob + off(1), lds, cur,
                                                        partial, QS(0));
   constexpr int PAIRS = (NHID - 2) / 2;
   for (int p = 0; p < PAIRS; ++p) {
     const int L = 1 + 2 * p;
-    layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK, FB, SBX>(X, Y, blob + off(L), blob + off(L + 1), lds, cur,
+    layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK, FB, SBX, NW>(X, Y, blob + off(L), blob + off(L + 1), lds, cur,
                                                          partial, QS(L));
     if ((NHID - 2) % 2 == 0 && p == PAIRS - 1) {
-      layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK, FB, SBX>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
+      layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK, FB, SBX, NW>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
                                                            cur, partial, QS(L + 1));
     } else {
-      layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK, FB, SBX>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
+      layer<DT, NB, KSH, FB, CBH, CBH, KSH, NOUT, 0, CHUNK, FB, SBX, NW>(Y, X, blob + off(L + 1), blob + off(L + 2), lds,
                                                            cur, partial, QS(L + 1));
     }
   }
   constexpr int LAST_MODE = KEEP_LAST ? 2 : 1;
   if constexpr ((NHID - 2) % 2 == 1) {
-    layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK, FB, SBX>(X, Y, blob + off(NHID - 2), blob + off(NHID - 1),
+    layer<DT, NB, KSH, FB, CBH, CBL, KSH, NOUT, 0, CHUNK, FB, SBX, NW>(X, Y, blob + off(NHID - 2), blob + off(NHID - 1),
                                                          lds, cur, partial, QS(NHID - 2));
-    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL, SBX>(Y, Blast, blob + off(NHID - 1), w_tail,
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL, SBX, NW>(Y, Blast, blob + off(NHID - 1), w_tail,
                                                                      lds, cur, partial, QS(NHID - 1));
   } else {
-    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL, SBX>(X, Blast, blob + off(NHID - 1), w_tail,
+    layer<DT, NB, KSH, FB, CBL, CB_TAIL, KSH, NOUT, LAST_MODE, CHUNK, FB_TAIL, SBX, NW>(X, Blast, blob + off(NHID - 1), w_tail,
                                                                      lds, cur, partial, QS(NHID - 1));
   }
   if (cur_io) *cur_io = cur;
