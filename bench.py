@@ -107,6 +107,7 @@ def parse():
     p.add_argument("--fallback-samples", type=int, default=128)
     p.add_argument("--marcher-pixels", type=int, default=2048)
     p.add_argument("--no-shading", action="store_true", help="depth+ID only in the timed frame")
+    p.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing beside the eager frames")
     # marcher workload
     p.add_argument("--samples", type=int, default=192)
     p.add_argument("--size", type=int, default=800)
@@ -269,6 +270,32 @@ def frame_bench(args):
     per = stage_table(stages)
     depth_ms = sum(v for k, v in per.items() if "/" not in k and k not in ("shade", "shadow"))
 
+    # the same frame captured once in a HIP graph and replayed (launch-side
+    # cost of the ~240 kernels per frame removed); reported beside `value`
+    graph = None
+    if not args.no_graph:
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(gs):
+            frame()
+        gs.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=gs):
+            frame()
+        with torch.cuda.stream(gs):
+            for _ in range(args.warmup):
+                g.replay()
+            gs.synchronize()
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            g0.record(gs)
+            for _ in range(args.steps):
+                g.replay()
+            g1.record(gs)
+        gs.synchronize()
+        gms = g0.elapsed_time(g1) / args.steps
+        graph = {"ms_per_step": gms, "rays_per_s": n / (gms * 1e-3), "replays": args.steps}
+        assert api.check_status(ws) == 0, "graph replay reported a device status error"
+
     # plain FP32 marcher on a seeded pixel subset of the same scene
     g = np.random.default_rng(4669 + 1000 * config + 77)
     pix = np.sort(g.choice(n, size=min(args.marcher_pixels, n), replace=False))
@@ -343,6 +370,7 @@ def frame_bench(args):
                      "flop_per_launch": k_flops, "launches_per_frame": launches if kname.endswith("net") else 1},
         "stages_ms_per_step": per,
         "autotune": tune,
+        "graph": graph,
         "training": train,
         "setup_train_s": setup_train_s,
     }
