@@ -348,12 +348,6 @@ __global__ void k_scan_items(KArgs a, PairList* L) {
 // nearest first; a pair whose bound lies beyond the pixel's nearest hit so far
 // cannot win the min-reduce and is skipped.  The result is the same as
 // evaluating every pair, whatever the slab boundaries.
-__device__ __forceinline__ int depth_slab(const KArgs& a, float dm, int n_slabs) {
-  const float lo = __uint_as_float(a.C->dmin_bits), hi = __uint_as_float(a.C->dmax_bits);
-  if (n_slabs <= 1 || !(hi > lo)) return 0;
-  const int k = int((dm - lo) * (float(n_slabs) / (hi - lo)));
-  return k < 0 ? 0 : (k >= n_slabs ? n_slabs - 1 : k);
-}
 
 __global__ void k_slab_begin(KArgs a) {
   if (blockIdx.x != 0) return;
@@ -379,13 +373,6 @@ __device__ __forceinline__ void push_slab(const KArgs& a, PairList* S, int lane,
     if (keep && m == m0) a.pairsS[S->off[m0] + base + __popcll(mk & ((1ull << lane) - 1ull))] = pr;
     todo &= ~mk;
   }
-}
-
-// Object of pair q of list A (segments in object order; a handful of objects).
-__device__ __forceinline__ int pair_object(const PairList* A, int n_obj, int q) {
-  int m = 0;
-  while (m + 1 < n_obj && q >= A->off[m + 1]) ++m;
-  return m;
 }
 
 // Tests the pairs whose bits are set in `hits` (lane's pairs q0 + j) against
@@ -435,10 +422,18 @@ __device__ __forceinline__ void slab_candidates(const KArgs& a, PairList* S, int
 // wave takes one block: sixteen consecutive pairs per lane.
 __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int n_slabs) {
   __shared__ int s_cand[4][SLAB_BLOCK];
+  __shared__ int s_off[NEDF_MAX_OBJECTS + 1];
   const PairList* A = &a.C->A;
   PairList* S = &a.C->S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int total = A->off[a.n_obj];
+  // segment offsets and the slab map, read once (the loop below stores to
+  // global memory, so the compiler could not keep them in registers)
+  if (threadIdx.x <= a.n_obj) s_off[threadIdx.x] = A->off[threadIdx.x];
+  const float lo = __uint_as_float(a.C->dmin_bits), hi = __uint_as_float(a.C->dmax_bits);
+  const bool single = n_slabs <= 1 || !(hi > lo);
+  const float inv_w = single ? 0.0f : float(n_slabs) / (hi - lo);
+  __syncthreads();
+  const int total = s_off[a.n_obj];
   const int nblk = (total + SLAB_BLOCK - 1) / SLAB_BLOCK;
   const float4* dv = reinterpret_cast<const float4*>(a.pair_dm);
   uint4* sv = reinterpret_cast<uint4*>(a.pair_slab);
@@ -448,7 +443,9 @@ __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int 
     uint32_t bits = 0, hits = 0;
     if (q0 < total) {
       uint32_t bytes[4];
-      int mo = pair_object(A, a.n_obj, q0);
+      int mo = 0;
+      while (mo + 1 < a.n_obj && q0 >= s_off[mo + 1]) ++mo;
+      int next_off = mo + 1 < a.n_obj ? s_off[mo + 1] : 0x7FFFFFFF;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float4 v = dv[q0 / 4 + i];
@@ -457,10 +454,18 @@ __global__ __launch_bounds__(256) void k_slab_first(KArgs a, uint32_t mask, int 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int q = q0 + 4 * i + j;
-          while (mo + 1 < a.n_obj && q >= A->off[mo + 1]) ++mo;
+          while (q >= next_off) {
+            ++mo;
+            next_off = mo + 1 < a.n_obj ? s_off[mo + 1] : 0x7FFFFFFF;
+          }
           int sl = 0xFF;
           if (q < total && ((mask >> mo) & 1u)) {
-            sl = depth_slab(a, dm[j], n_slabs);
+            if (single) {
+              sl = 0;
+            } else {
+              const int kk = int((dm[j] - lo) * inv_w);
+              sl = kk < 0 ? 0 : (kk >= n_slabs ? n_slabs - 1 : kk);
+            }
             bits |= 1u << sl;
             if (sl == 0) hits |= 1u << (4 * i + j);
           }
