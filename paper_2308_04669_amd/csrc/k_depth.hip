@@ -359,27 +359,48 @@ __global__ void k_slab_begin(KArgs a) {
   }
 }
 
-// Wave-aggregated append of the kept pairs to their objects' segments of
-// list S (lanes of one wave may belong to different objects).
-__device__ __forceinline__ void push_slab(const KArgs& a, PairList* S, int lane, bool keep, int m, uint2 pr) {
-  uint64_t todo = __ballot(keep);
-  while (todo) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const int m0 = __shfl(m, leader);
-    const uint64_t mk = __ballot(keep && m == m0);
+// Candidates a lane tests at once in the slab filters.
+constexpr int SLAB_U = 4;
+
+// Wave-aggregated append of the kept pairs (SLAB_U per lane) to their
+// objects' segments of list S: one atomic per object present reserves the
+// slots of all of them.  Called with the whole wave active.
+__device__ __forceinline__ void push_slab(const KArgs& a, PairList* S, int lane, const bool (&keep)[SLAB_U],
+                                          const int (&m)[SLAB_U], const uint2 (&pr)[SLAB_U]) {
+  uint64_t pend[SLAB_U];
+#pragma unroll
+  for (int u = 0; u < SLAB_U; ++u) pend[u] = __ballot(keep[u]);
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (;;) {
+    int m0 = -1;
+#pragma unroll
+    for (int u = 0; u < SLAB_U; ++u)
+      if (m0 < 0 && pend[u]) m0 = __builtin_amdgcn_readlane(m[u], __ffsll((unsigned long long)pend[u]) - 1);
+    if (m0 < 0) break;
+    bool mine[SLAB_U];
+    int pos[SLAB_U], tot = 0;
+#pragma unroll
+    for (int u = 0; u < SLAB_U; ++u) {
+      mine[u] = keep[u] && m[u] == m0;
+      const uint64_t mk = __ballot(mine[u]);
+      pos[u] = tot + __popcll(mk & below);
+      tot += __popcll(mk);
+      pend[u] &= ~mk;
+    }
     int base = 0;
-    if (lane == leader) base = atomicAdd(&S->cnt[m0], __popcll(mk));
-    base = __shfl(base, leader);
-    if (keep && m == m0) a.pairsS[S->off[m0] + base + __popcll(mk & ((1ull << lane) - 1ull))] = pr;
-    todo &= ~mk;
+    if (lane == 0) base = atomicAdd(&S->cnt[m0], tot);
+    const int run = S->off[m0] + __builtin_amdgcn_readfirstlane(base);
+    for (int u = 0; u < SLAB_U; ++u)
+      if (mine[u]) a.pairsS[run + pos[u]] = pr[u];
   }
 }
 
 // Tests the pairs whose bits are set in `hits` (lane's pairs q0 + j) against
 // the pixels' current nearest hits and appends the survivors to list S.  The
 // wave first compacts the candidate indices in LDS (`cand`, 1024 entries) and
-// then takes them 64 at a time, one per lane, so that bound, pair and key
-// reads are issued together.
+// then takes them 64 * SLAB_U at a time, SLAB_U per lane, so that the bound,
+// pair and key reads of all of them are in flight together.  Called with the
+// whole wave active.
 __device__ __forceinline__ void slab_candidates(const KArgs& a, PairList* S, int* cand, int lane, int q0,
                                                 uint32_t hits) {
   const int c = __popc(hits);
@@ -397,17 +418,29 @@ __device__ __forceinline__ void slab_candidates(const KArgs& a, PairList* S, int
     hits &= hits - 1u;
   }
   __builtin_amdgcn_wave_barrier();
-  for (int c0 = 0; c0 < n_cand; c0 += 64) {
-    bool keep = false;
-    int m = 0;
-    uint2 pr = make_uint2(0u, 0u);
-    if (c0 + lane < n_cand) {
-      const int q = cand[c0 + lane];
-      pr = a.pairs[q];
-      m = a.inst_object[pr.y];
-      const float dm = a.pair_dm[q];
+  for (int c0 = 0; c0 < n_cand; c0 += 64 * SLAB_U) {
+    bool keep[SLAB_U];
+    int q[SLAB_U], m[SLAB_U];
+    uint2 pr[SLAB_U];
+    float dm[SLAB_U];
+    // lanes past the last candidate read the round's first one and drop it
+    const int q_first = cand[c0];
+#pragma unroll
+    for (int u = 0; u < SLAB_U; ++u) {
+      const int idx = c0 + 64 * u + lane;
+      keep[u] = idx < n_cand;
+      q[u] = keep[u] ? cand[idx] : q_first;
+    }
+#pragma unroll
+    for (int u = 0; u < SLAB_U; ++u) {
+      pr[u] = a.pairs[q[u]];
+      dm[u] = a.pair_dm[q[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < SLAB_U; ++u) {
+      m[u] = a.inst_object[pr[u].y];
       // margin against last-bit differences between kernels
-      keep = !(depth_limit(a, pr.x) < dm - (1e-5f * dm + 1e-5f));
+      keep[u] = keep[u] && !(depth_limit(a, pr[u].x) < dm[u] - (1e-5f * dm[u] + 1e-5f));
     }
     push_slab(a, S, lane, keep, m, pr);
   }
