@@ -360,7 +360,7 @@ __global__ void k_slab_begin(KArgs a) {
 }
 
 // Candidates a lane tests at once in the slab filters.
-constexpr int SLAB_U = 4;
+constexpr int SLAB_U = 8;
 
 // Wave-aggregated append of the kept pairs (SLAB_U per lane) to their
 // objects' segments of list S: one atomic per object present reserves the
