@@ -39,33 +39,58 @@ __global__ void k_zero_list(PairList* L) {
 }
 
 // Bin pixels with a valid ID whose object is in `mask` into list A as
-// (pixel, instance) pairs; pass 0 counts, pass 1 writes.  Lanes of a wave
-// are grouped by object so each group issues one atomic.
+// (pixel, instance) pairs; pass 0 counts, pass 1 writes.  A workgroup takes a
+// contiguous range of pixels and aggregates its counts per object in LDS
+// (lanes of a wave grouped by object, one LDS atomic per group), so global
+// atomics are one per (workgroup, object): per-wave global atomics on the
+// few counters of list A serialise across the whole chip.
+constexpr unsigned BIN_BLOCKS = 1024;
+
 template <int PASS>
-__global__ void k_bin(KArgs a, const int32_t* ids, uint32_t mask) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  int inst = p < a.n_rays ? ids[p] : -1;
-  int obj = inst >= 0 && inst < a.n_inst ? a.inst_object[inst] : -1;
-  const bool want = obj >= 0 && obj < a.n_obj && ((mask >> obj) & 1u);
+__global__ __launch_bounds__(256) void k_bin(KArgs a, const int32_t* ids, uint32_t mask) {
+  __shared__ int s_cnt[NEDF_MAX_OBJECTS], s_base[NEDF_MAX_OBJECTS];
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t per = ((a.n_rays + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+  const int64_t p0 = int64_t(blockIdx.x) * per;
+  const int64_t p1 = p0 + per < a.n_rays ? p0 + per : a.n_rays;
   PairList* L = &a.C->A;
-  uint64_t pending = __ballot(want);
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int o = __shfl(obj, leader);
-    const uint64_t match = __ballot(want && obj == o);
-    if (PASS == 0) {
-      if (lane == leader) atomicAdd(&L->cnt[o], __popcll(match));
-    } else {
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&L->fill[o], __popcll(match));
-      base = __shfl(base, leader);
-      if (want && obj == o) {
-        const int pos = base + __popcll(match & ((1ull << lane) - 1ull));
-        if (pos < L->cnt[o]) a.pairs[L->off[o] + pos] = make_uint2(uint32_t(p), uint32_t(inst));
+  if (t < NEDF_MAX_OBJECTS) s_cnt[t] = 0;
+  __syncthreads();
+  // traversal 0 counts; in pass 1 traversal 1 writes
+  for (int trav = 0; trav <= PASS; ++trav) {
+    for (int64_t pb = p0; pb < p1; pb += 256) {
+      const int64_t p = pb + t;
+      const int inst = p < p1 ? ids[p] : -1;
+      const int obj = inst >= 0 && inst < a.n_inst ? a.inst_object[inst] : -1;
+      const bool want = obj >= 0 && obj < a.n_obj && ((mask >> obj) & 1u);
+      uint64_t pending = __ballot(want);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int o = __shfl(obj, leader);
+        const uint64_t match = __ballot(want && obj == o);
+        int off = 0;
+        if (lane == leader) off = atomicAdd(&s_cnt[o], __popcll(match));
+        if (trav == 1) {
+          off = __shfl(off, leader);
+          if (want && obj == o) {
+            const int pos = s_base[o] + off + __popcll(match & ((1ull << lane) - 1ull));
+            if (pos < L->cnt[o]) a.pairs[L->off[o] + pos] = make_uint2(uint32_t(p), uint32_t(inst));
+          }
+        }
+        pending &= ~match;
       }
     }
-    pending &= ~match;
+    __syncthreads();
+    if (t < a.n_obj) {
+      const int c = s_cnt[t];
+      if (PASS == 0) {
+        if (c) atomicAdd(&L->cnt[t], c);
+      } else if (trav == 0) {
+        s_base[t] = c ? atomicAdd(&L->fill[t], c) : 0;
+        s_cnt[t] = 0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -372,7 +397,7 @@ void stage_bin_pixels(const KArgs& k0, hipStream_t s, const int32_t* ids, uint32
   k.item_mask = mask;
   k.item_pairs = per;
   k.L = &k.C->A;
-  const unsigned g = grid_n(k.n_rays);
+  const unsigned g = grid_n(k.n_rays) < BIN_BLOCKS ? grid_n(k.n_rays) : BIN_BLOCKS;
   hipLaunchKernelGGL(k_zero_list, dim3(1), dim3(256), 0, s, &k.C->A);
   hipLaunchKernelGGL(k_bin<0>, dim3(g), dim3(256), 0, s, k, ids, mask);
   hipLaunchKernelGGL(k_scan_pixels, dim3(1), dim3(64), 0, s, k);
