@@ -278,13 +278,25 @@ __global__ __launch_bounds__(256) void k_cull(KArgs a) {
     __syncthreads();
   }
   if constexpr (PASS == 0) {
+    // range of the workgroup's bounds, then one atomic pair per workgroup
+    // (atomics on one word from every wave of the chip serialise)
+    __shared__ float s_rng[2][4];
     for (int off = 32; off > 0; off >>= 1) {
       dlo = fminf(dlo, __shfl_xor(dlo, off));
       dhi = fmaxf(dhi, __shfl_xor(dhi, off));
     }
-    if (lane == 0 && dlo <= dhi) {
-      atomicMin(&a.C->dmin_bits, __float_as_uint(dlo));
-      atomicMax(&a.C->dmax_bits, __float_as_uint(dhi));
+    if (lane == 0) {
+      s_rng[0][wave] = dlo;
+      s_rng[1][wave] = dhi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      dlo = fminf(fminf(s_rng[0][0], s_rng[0][1]), fminf(s_rng[0][2], s_rng[0][3]));
+      dhi = fmaxf(fmaxf(s_rng[1][0], s_rng[1][1]), fmaxf(s_rng[1][2], s_rng[1][3]));
+      if (dlo <= dhi) {
+        atomicMin(&a.C->dmin_bits, __float_as_uint(dlo));
+        atomicMax(&a.C->dmax_bits, __float_as_uint(dhi));
+      }
     }
   }
 }
