@@ -22,15 +22,17 @@ forward pass itself is pinned on hand-set weights).
 """
 from .geometry import (camera_rays, to_local, pluecker, encode, sphere_chord,
                        inverse_transform)
-from .rounding import round_bf16, round_e4m3
+from .rounding import round_bf16, round_e4m3, bf16_rounding_margin, e4m3_rounding_margin
 from .fields import mlp_forward, density, nerf_eval, nedf_eval, sdf, surface_value, fp8_calibrate
-from .render import (march, march_compose, nedf_pair, nedf_compose, secant_refine,
+from .render import (march, march_compose, nedf_pair, nedf_compose, secant_refine, depth_lower_bound,
+                     compose_pruned, march_compose_pruned, nedf_compose_pruned,
                      shade_deferred, shadow_factor, composite)
 from .train import nedf_loss_and_grads, adam_step
 
 __all__ = [
     "camera_rays", "to_local", "pluecker", "encode", "sphere_chord", "inverse_transform",
-    "round_bf16", "round_e4m3", "fp8_calibrate", "mlp_forward", "density", "nerf_eval", "nedf_eval", "sdf",
-    "march", "march_compose", "nedf_pair", "nedf_compose", "secant_refine",
+    "round_bf16", "round_e4m3", "bf16_rounding_margin", "e4m3_rounding_margin", "fp8_calibrate", "mlp_forward", "density", "nerf_eval", "nedf_eval", "sdf",
+    "march", "march_compose", "nedf_pair", "nedf_compose", "secant_refine", "depth_lower_bound",
+    "compose_pruned", "march_compose_pruned", "nedf_compose_pruned",
     "shade_deferred", "shadow_factor", "composite", "nedf_loss_and_grads", "adam_step",
 ]

@@ -274,3 +274,82 @@ def shadow_factor(depth_fn, o, d, depth, ident, lights, eps, beta=0.5):
 def composite(rgb, factor):
     """Final image: colour buffer times shadow buffer (Fig. 1 data flow)."""
     return np.asarray(rgb, F64) * np.asarray(factor, F64)[:, None]
+
+
+def depth_lower_bound(bound, inst, o, d):
+    """Lowest world depth any method can report for a (ray, instance) pair,
+    or +inf when the pair is no candidate: s (t_perp - l) when the ray's line
+    passes within the local bounding radius l and the sphere is not behind an
+    outside origin.  The intersection network reports s (t_perp - l clamp(mu_hat))
+    and the marcher a depth inside the chord, both at least this bound."""
+    o_l, d_l = to_local(inst, o, d)
+    _, t_perp = pluecker(o_l, d_l)
+    mnorm = np.linalg.norm(np.cross(o_l, d_l), axis=-1)
+    inside = np.linalg.norm(o_l, axis=-1) < bound
+    cand = (mnorm < bound) & ((t_perp > 0) | inside)
+    return np.where(cand, inst.s * (t_perp - bound), np.inf)
+
+
+def compose_pruned(pair_fn, lower_bounds):
+    """Alg. 1 step 1 with exact pruning (front to back).
+
+    ``lower_bounds`` is [n_inst, n]: for each instance and ray a lower bound
+    on any depth the pair can report (+inf: no candidate).  Each ray visits
+    its candidates in increasing bound order and stops once the next bound
+    exceeds the best depth so far; since no skipped pair could report a
+    depth below its bound, the result equals the full minimum over all
+    instances in increasing index with ties to the lower index.
+    ``pair_fn(k, idx) -> (hit [m], D [m])`` evaluates instance k on the rays
+    ``idx``.  Returns (depth, id, pairs evaluated)."""
+    lb = np.asarray(lower_bounds, F64)
+    n_inst, n = lb.shape
+    depth = np.full(n, np.inf)
+    ident = np.full(n, -1, np.int64)
+    order = np.argsort(lb, axis=0, kind="stable")
+    cols = np.arange(n)
+    evaluated = 0
+    for r in range(n_inst):
+        k_r = order[r]
+        b_r = lb[k_r, cols]
+        need = np.isfinite(b_r) & (b_r <= depth)
+        if not need.any():
+            break
+        for k in np.unique(k_r[need]):
+            idx = np.nonzero(need & (k_r == k))[0]
+            hit, D = pair_fn(int(k), idx)
+            evaluated += idx.size
+            cur, cid = depth[idx], ident[idx]
+            better = hit & ((D < cur) | ((D == cur) & (k < cid)))
+            depth[idx[better]] = D[better]
+            ident[idx[better]] = k
+    return depth, ident, evaluated
+
+
+def march_compose_pruned(models, insts, o, d, n_samples, hit_thr=0.5, gemm=None):
+    """``march_compose`` on the bounding chords with exact pruning: same
+    depth and id buffers, fewer marched pairs.  Returns (depth, id, pairs)."""
+    o = np.asarray(o, F64)
+    d = np.asarray(d, F64)
+    lb = np.array([depth_lower_bound(models[i.model].bound, i, o, d) for i in insts])
+
+    def pair(k, idx):
+        inst = insts[k]
+        valid, A, D = march_instance(models[inst.model], inst, o[idx], d[idx], n_samples, None, gemm)
+        return valid & (A >= hit_thr), D
+
+    return compose_pruned(pair, lb)
+
+
+def nedf_compose_pruned(nedf_models, dens_models, insts, o, d, **kw):
+    """``nedf_compose`` with exact pruning: same depth and id buffers.
+    Returns (depth, id, pairs)."""
+    o = np.asarray(o, F64)
+    d = np.asarray(d, F64)
+    lb = np.array([depth_lower_bound(nedf_models[i.model].bound, i, o, d) for i in insts])
+
+    def pair(k, idx):
+        inst = insts[k]
+        hit, D, _, _ = nedf_pair(nedf_models[inst.model], dens_models[inst.model], inst, o[idx], d[idx], **kw)
+        return hit, D
+
+    return compose_pruned(pair, lb)
