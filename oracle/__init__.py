@@ -21,7 +21,7 @@ which are "parity unpinned" beyond being the stated definition (the MLP
 forward pass itself is pinned on hand-set weights).
 """
 from .geometry import (camera_rays, to_local, pluecker, encode, sphere_chord,
-                       inverse_transform)
+                       inverse_transform, f32_record, RecordInstance)
 from .rounding import round_bf16, round_e4m3, bf16_rounding_margin, e4m3_rounding_margin
 from .fields import mlp_forward, density, nerf_eval, nedf_eval, sdf, surface_value, fp8_calibrate
 from .render import (march, march_compose, nedf_pair, nedf_compose, secant_refine, depth_lower_bound,
@@ -30,7 +30,8 @@ from .render import (march, march_compose, nedf_pair, nedf_compose, secant_refin
 from .train import nedf_loss_and_grads, adam_step
 
 __all__ = [
-    "camera_rays", "to_local", "pluecker", "encode", "sphere_chord", "inverse_transform",
+    "camera_rays", "to_local", "pluecker", "encode", "sphere_chord", "inverse_transform", "f32_record",
+    "RecordInstance",
     "round_bf16", "round_e4m3", "bf16_rounding_margin", "e4m3_rounding_margin", "fp8_calibrate", "mlp_forward", "density", "nerf_eval", "nedf_eval", "sdf",
     "march", "march_compose", "nedf_pair", "nedf_compose", "secant_refine", "depth_lower_bound",
     "compose_pruned", "march_compose_pruned", "nedf_compose_pruned",

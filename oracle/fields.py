@@ -39,11 +39,15 @@ def _rounder(gemm):
     raise ValueError(gemm)
 
 
-def mlp_forward(x, weights, gemm=None, scales=None, return_hidden=False):
+def mlp_forward(x, weights, gemm=None, scales=None, return_hidden=False, acc=None):
     """Hidden layers h_{i+1} = ReLU(W_i h_i + b_i), then a linear head.
 
     ``scales`` (E4M3 emulation): list of (w_scale, a_scale) per hidden layer;
     the layer computes (q(h/a) . q(W/w)^T) * a * w + b with q = round_e4m3.
+    ``acc="f32"`` sums each hidden layer's products in float32 (in the BLAS
+    routine's order) instead of float64: one of the summation orders a
+    single-precision accumulator may take, used only to measure how much a
+    result depends on that order, never as the expected value.
     Returns the head output, and optionally the last hidden activation."""
     h = np.asarray(x, F64)
     n = len(weights.W)
@@ -54,7 +58,13 @@ def mlp_forward(x, weights, gemm=None, scales=None, return_hidden=False):
         if i < n - 1:
             if scales is not None:
                 ws, as_ = scales[i]
-                z = (round_e4m3(h / as_) @ round_e4m3(W / ws).T) * (as_ * ws) + b
+                qa, qw = round_e4m3(h / as_), round_e4m3(W / ws)
+                if acc == "f32":
+                    z = (qa.astype(np.float32) @ qw.T.astype(np.float32)).astype(F64) * (as_ * ws) + b
+                else:
+                    z = (qa @ qw.T) * (as_ * ws) + b
+            elif acc == "f32":
+                z = (rnd(h).astype(np.float32) @ rnd(W).T.astype(np.float32)).astype(F64) + b
             else:
                 z = rnd(h) @ rnd(W).T + b
             h = np.maximum(z, 0.0)

@@ -1,17 +1,22 @@
 """Rays, rigid transforms, encodings (FP64).  Test infrastructure only."""
 from __future__ import annotations
 
+from dataclasses import dataclass
+
 import numpy as np
 
 F64 = np.float64
 
 
-def camera_rays(cam, pixels=None):
+def camera_rays(cam, pixels=None, basis="exact"):
     """Pinhole primary rays, one per pixel (Alg. 1, NeDF generation step: a
     ray cast through each pixel).  Reading: eye ``cam.eye`` looking at
     ``cam.at``, vertical field of view ``cam.fov_y_deg``, square pixels,
     pixel (i, j) = (column, row from the top) sampled at its centre, unit
-    directions.  Returns (o [n,3], d [n,3]) float64."""
+    directions.  ``basis="f32"`` takes the camera as stored in single
+    precision: eye, forward axis and the right/up axes pre-scaled by the
+    image-plane half extents, each rounded to float32 (nearest even), the
+    rays then formed exactly from them.  Returns (o [n,3], d [n,3]) float64."""
     W, H = cam.width, cam.height
     if pixels is None:
         pixels = np.arange(W * H, dtype=np.int64)
@@ -25,9 +30,18 @@ def camera_rays(cam, pixels=None):
     th = np.tan(np.deg2rad(cam.fov_y_deg) / 2.0)
     i = (pixels % W).astype(F64)
     j = (pixels // W).astype(F64)
-    u = (2.0 * (i + 0.5) / W - 1.0) * th * W / H
-    v = (1.0 - 2.0 * (j + 0.5) / H) * th
-    d = u[:, None] * right + v[:, None] * upv + fwd
+    if basis == "f32":
+        r32 = (right * (th * W / H)).astype(np.float32).astype(F64)
+        u32 = (upv * th).astype(np.float32).astype(F64)
+        f32 = fwd.astype(np.float32).astype(F64)
+        eye = eye.astype(np.float32).astype(F64)
+        u = (2.0 * i + 1.0 - W) / W
+        v = (H - 2.0 * j - 1.0) / H
+        d = u[:, None] * r32 + v[:, None] * u32 + f32
+    else:
+        u = (2.0 * (i + 0.5) / W - 1.0) * th * W / H
+        v = (1.0 - 2.0 * (j + 0.5) / H) * th
+        d = u[:, None] * right + v[:, None] * upv + fwd
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     o = np.broadcast_to(eye, d.shape).copy()
     return o, d
@@ -43,12 +57,44 @@ def inverse_transform(R, T, s):
     return M, c
 
 
+@dataclass(frozen=True)
+class RecordInstance:
+    """An instance seen through a single-precision world-to-local record:
+    the inverse map of Eq. 7, G^{-1}(v) = R^T v / s + c with c = -R^T T / s,
+    composed exactly and then rounded to float32 (nearest even) entry by
+    entry, as the method's transform-preparation step stores it.  Fields hold
+    those float32 values as float64; ``s`` is the rounded scale that turns a
+    local depth into a world depth."""
+    model: int
+    R: np.ndarray       # float32-rounded rotation R (3x3), so R^T is its transpose
+    inv_s: float        # float32-rounded 1 / s
+    c: np.ndarray       # float32-rounded -R^T T / s
+    s: float            # float32-rounded s
+
+
+def _f32(x):
+    return np.asarray(x, F64).astype(np.float32).astype(F64)
+
+
+def f32_record(inst):
+    """The single-precision record of an instance (see ``RecordInstance``)."""
+    R = np.asarray(inst.R, F64)
+    s = float(inst.s)
+    c = -(R.T @ np.asarray(inst.T, F64)) / s
+    return RecordInstance(model=inst.model, R=_f32(R), inv_s=float(_f32(1.0 / s)), c=_f32(c), s=float(_f32(s)))
+
+
 def to_local(inst, o, d):
     """Map world rays to the instance's canonical space (Eq. 7: rays, not
     points, are transformed).  o_l = G^{-1}(o), d_l = R^T d (still unit);
-    a world distance t along the ray is t / s along the local ray."""
+    a world distance t along the ray is t / s along the local ray.  For a
+    ``RecordInstance`` the record's rounded entries are used, with exact
+    (float64) arithmetic: o_l = (R^T o) inv_s + c."""
     R = np.asarray(inst.R, F64)
-    o_l = (np.asarray(o, F64) - np.asarray(inst.T, F64)) @ R / inst.s
+    if isinstance(inst, RecordInstance):
+        o_l = (np.asarray(o, F64) @ R) * inst.inv_s + inst.c
+    else:
+        o_l = (np.asarray(o, F64) - np.asarray(inst.T, F64)) @ R / inst.s
     d_l = np.asarray(d, F64) @ R
     return o_l, d_l
 

@@ -160,7 +160,7 @@ def nedf_compose(nedf_models, dens_models, insts, o, d, **kw):
     return depth, ident
 
 
-def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
+def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None, margins=False):
     """Secant refinement of a hit depth on the density field near the
     predicted depth.
 
@@ -173,7 +173,12 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
     f(t0) < 0 <= f(t1).  Each step t+ = t1 - f1 (t1 - t0) / (f1 - f0), then
     (t0, t1) <- (t1, t+).  It stops when the denominator is 0 or an iterate
     leaves [D - 2e, D + 2e]; the last accepted iterate (initially D) is
-    returned.  ``steps`` updates need steps + 1 field evaluations."""
+    returned.  ``steps`` updates need steps + 1 field evaluations.
+
+    ``margins=True`` also returns, per ray, how close its decisions came to
+    going the other way: the smaller |f| of the two seeds (the bracket test)
+    and the smallest distance of an iterate to the guard interval's ends
+    (+inf where no iterate was tested)."""
     o = np.asarray(o, F64)
     d = np.asarray(d, F64)
     D_hat = np.asarray(D_hat, F64)
@@ -184,12 +189,15 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
         return surface_value(dens_model, o_l, gemm=gemm)
 
     out = D_hat.copy()
+    fmin = np.full(n, np.inf)
+    gmin = np.full(n, np.inf)
     if n == 0:
-        return out
+        return (out, fmin, gmin) if margins else out
     allr = np.arange(n)
     e = h * float(inst.s)
     t0, t1 = D_hat - e, D_hat + e
     f0, f1 = f(t0, allr), f(t1, allr)
+    fmin = np.minimum(np.abs(f0), np.abs(f1))
     active = (f0 < 0) & (f1 >= 0)
     lo, hi = D_hat - 2 * e, D_hat + 2 * e
     for it in range(steps):
@@ -197,6 +205,7 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
         ok = active & (den != 0)
         with np.errstate(invalid="ignore", divide="ignore"):
             tn = t1 - f1 * (t1 - t0) / np.where(den != 0, den, 1.0)
+        gmin = np.where(ok, np.minimum(gmin, np.minimum(np.abs(tn - lo), np.abs(hi - tn))), gmin)
         ok &= (tn >= lo) & (tn <= hi)
         out = np.where(ok, tn, out)
         active = ok
@@ -206,7 +215,7 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None):
             fn[ia] = f(tn, ia)
             t0, f0 = np.where(active, t1, t0), np.where(active, f1, f0)
             t1, f1 = np.where(active, tn, t1), np.where(active, fn, f1)
-    return out
+    return (out, fmin, gmin) if margins else out
 
 
 def shade_deferred(models, insts, o, d, depth, ident, K=8, h=0.05, clear=(0.0, 0.0, 0.0),

@@ -46,21 +46,106 @@ struct RaySrc {
   const float* d;
 };
 
-__device__ __forceinline__ void make_ray(const RaySrc& rs, int64_t ray, float o[3], float d[3]) {
+// ---- compensated single-precision arithmetic --------------------------------
+// Error-free transformations: a + b = s + e exactly (Knuth's two-sum) and
+// a * b = p + e exactly (one fused multiply-add).  Contraction is off so that
+// every operation stays as written.
+struct f2 {
+  float hi, lo;
+};
+__device__ __forceinline__ f2 two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+// |a| >= |b| (or a == 0): a + b = s + e exactly
+__device__ __forceinline__ f2 fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ f2 two_prod(float a, float b) {
+#pragma clang fp contract(off)
+  const float p = a * b;
+  return {p, fmaf(a, b, -p)};
+}
+// a0 v0 + a1 v1 + a2 v2 (+ a . vlo, first order) as hi + lo: the products
+// exact, their sum with its rounding errors kept (error about 2^-44 of the
+// sum of |terms|).
+__device__ __forceinline__ f2 dot3_c(float a0, float a1, float a2, const float v[3], const float vlo[3]) {
+#pragma clang fp contract(off)
+  const f2 p0 = two_prod(a0, v[0]), p1 = two_prod(a1, v[1]), p2 = two_prod(a2, v[2]);
+  const f2 s = two_sum(p0.hi, p1.hi);
+  const f2 t = two_sum(s.hi, p2.hi);
+  const float lo = ((p0.lo + p1.lo) + p2.lo) + (s.lo + t.lo) + ((a0 * vlo[0] + a1 * vlo[1]) + a2 * vlo[2]);
+  return fast_two_sum(t.hi, lo);
+}
+// a1 b2 - a2 b1 for hi + lo operands, first order in the lo parts.
+__device__ __forceinline__ f2 cross_c(f2 a1, f2 b2, f2 a2, f2 b1) {
+#pragma clang fp contract(off)
+  const f2 p = two_prod(a1.hi, b2.hi), q = two_prod(a2.hi, b1.hi);
+  const f2 s = two_sum(p.hi, -q.hi);
+  const float lo = s.lo + (p.lo - q.lo) + ((a1.hi * b2.lo + a1.lo * b2.hi) - (a2.hi * b1.lo + a2.lo * b1.hi));
+  return fast_two_sum(s.hi, lo);
+}
+
+// Ray number `ray`: single-precision origin o and direction d, and the
+// direction's residual dlo (d + dlo is the direction to about 2^-44; zero for
+// ray arrays, which are exact as given).  A camera ray (Alg. 1: one ray
+// through each pixel centre) is formed from the stored single-precision
+// basis in compensated arithmetic: the pixel's image-plane coordinates
+// u = (2i + 1 - W) / W and v = (H - 2j - 1) / H as hi + lo, the unnormalised
+// direction fwd + u right + v up as hi + lo, and its reciprocal length by a
+// single-precision square root refined with one Newton step on the residual,
+// so that d is the faithfully rounded unit direction.
+__device__ __forceinline__ void make_ray(const RaySrc& rs, int64_t ray, float o[3], float d[3], float dlo[3]) {
+#pragma clang fp contract(off)
   if (rs.kind == 0) {
     const int i = int(ray % rs.width), j = int(ray / rs.width);
-    const float u = 2.0f * (float(i) + 0.5f) / float(rs.width) - 1.0f;
-    const float v = 1.0f - 2.0f * (float(j) + 0.5f) / float(rs.height);
-    float x = fmaf(u, rs.right[0], fmaf(v, rs.up[0], rs.fwd[0]));
-    float y = fmaf(u, rs.right[1], fmaf(v, rs.up[1], rs.fwd[1]));
-    float z = fmaf(u, rs.right[2], fmaf(v, rs.up[2], rs.fwd[2]));
-    const float inv = 1.0f / sqrtf(x * x + y * y + z * z);
-    d[0] = x * inv; d[1] = y * inv; d[2] = z * inv;
+    const float W = float(rs.width), H = float(rs.height);
+    const float nu = float(2 * i + 1 - rs.width), nv = float(rs.height - 2 * j - 1);  // exact integers
+    const float uh = nu / W, vh = nv / H;
+    const float ul = fmaf(-uh, W, nu) / W, vl = fmaf(-vh, H, nv) / H;  // exact remainders, divided
+    f2 x[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const f2 p1 = two_prod(uh, rs.right[c]), p2 = two_prod(vh, rs.up[c]);
+      const f2 s1 = two_sum(rs.fwd[c], p1.hi);
+      const f2 s2 = two_sum(s1.hi, p2.hi);
+      const float lo = (s1.lo + s2.lo) + (p1.lo + p2.lo) + (ul * rs.right[c] + vl * rs.up[c]);
+      x[c] = fast_two_sum(s2.hi, lo);
+    }
+    // |x|^2 as hi + lo
+    const f2 q0 = two_prod(x[0].hi, x[0].hi), q1 = two_prod(x[1].hi, x[1].hi), q2 = two_prod(x[2].hi, x[2].hi);
+    const f2 a = two_sum(q0.hi, q1.hi);
+    const f2 b = two_sum(a.hi, q2.hi);
+    const float n2lo = ((q0.lo + q1.lo) + q2.lo) + (a.lo + b.lo) +
+                       2.0f * ((x[0].hi * x[0].lo + x[1].hi * x[1].lo) + x[2].hi * x[2].lo);
+    const f2 n2 = fast_two_sum(b.hi, n2lo);
+    // r ~ 1/|x|; e = 1 - |x|^2 r^2 evaluated to the residual; 1/|x| = r (1 + e/2)
+    const float r = 1.0f / sqrtf(n2.hi);
+    const f2 rr = two_prod(r, r);
+    const float t = fmaf(n2.hi, rr.hi, -1.0f);  // exact product, one rounding, |t| small
+    const float e = -((t + n2.hi * rr.lo) + n2.lo * rr.hi);
+    const float rlo = 0.5f * r * e;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const f2 p = two_prod(x[c].hi, r);
+      const f2 dd = fast_two_sum(p.hi, p.lo + (x[c].hi * rlo + x[c].lo * r));
+      d[c] = dd.hi;
+      dlo[c] = dd.lo;
+    }
     o[0] = rs.eye[0]; o[1] = rs.eye[1]; o[2] = rs.eye[2];
   } else {
     o[0] = rs.o[3 * ray + 0]; o[1] = rs.o[3 * ray + 1]; o[2] = rs.o[3 * ray + 2];
     d[0] = rs.d[3 * ray + 0]; d[1] = rs.d[3 * ray + 1]; d[2] = rs.d[3 * ray + 2];
+    dlo[0] = dlo[1] = dlo[2] = 0.0f;
   }
+}
+__device__ __forceinline__ void make_ray(const RaySrc& rs, int64_t ray, float o[3], float d[3]) {
+  float dlo[3];
+  make_ray(rs, ray, o, d, dlo);
 }
 
 __device__ __forceinline__ void to_local(const W2L& g, const float o[3], const float d[3], float ol[3],
@@ -84,6 +169,68 @@ __device__ __forceinline__ W2L load_w2l(const float* w2l, int inst) {
   return g;
 }
 
+// The local ray's line (Eq. 1-2) from the single-precision record and a
+// world ray (d + dlo), in compensated arithmetic: direction d_l = R^T d,
+// moment o_l x d_l and t_perp = -o_l . d_l.  |o_l| can be tens of bounding
+// radii while the moment of a candidate line is below one, so plain single
+// precision would lose that ratio of digits to cancellation, and the
+// encoding multiplies coordinate errors by up to 2^(L-1) pi.  Here each line
+// coordinate comes as hi + lo (pl, pllo), its exact value in the record's and
+// the ray's numbers to about 2^-44 relative to |o_l|; ol gets the rounded
+// local origin.
+__device__ __forceinline__ void local_line(const W2L& g, const float o[3], const float d[3], const float dlo[3],
+                                           float pl[6], float pllo[6], float& tperp, float ol_out[3]) {
+#pragma clang fp contract(off)
+  const float zero[3] = {0.0f, 0.0f, 0.0f};
+  f2 ol[3], dl[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float a0 = g.rt[3 * r + 0], a1 = g.rt[3 * r + 1], a2 = g.rt[3 * r + 2];
+    const f2 a = dot3_c(a0, a1, a2, o, zero);
+    const f2 q = two_prod(a.hi, g.inv_s);
+    const float qlo = fmaf(a.lo, g.inv_s, q.lo);
+    const f2 t = two_sum(q.hi, g.c[r]);
+    ol[r] = fast_two_sum(t.hi, t.lo + qlo);
+    dl[r] = dot3_c(a0, a1, a2, d, dlo);
+    ol_out[r] = ol[r].hi;
+    pl[r] = dl[r].hi;
+    pllo[r] = dl[r].lo;
+  }
+  const f2 m0 = cross_c(ol[1], dl[2], ol[2], dl[1]);
+  const f2 m1 = cross_c(ol[2], dl[0], ol[0], dl[2]);
+  const f2 m2 = cross_c(ol[0], dl[1], ol[1], dl[0]);
+  pl[3] = m0.hi; pllo[3] = m0.lo;
+  pl[4] = m1.hi; pllo[4] = m1.lo;
+  pl[5] = m2.hi; pllo[5] = m2.lo;
+  const f2 p0 = two_prod(ol[0].hi, dl[0].hi), p1 = two_prod(ol[1].hi, dl[1].hi), p2 = two_prod(ol[2].hi, dl[2].hi);
+  const f2 s = two_sum(p0.hi, p1.hi);
+  const f2 t = two_sum(s.hi, p2.hi);
+  const float lo = ((p0.lo + p1.lo) + p2.lo) + (s.lo + t.lo) +
+                   ((ol[0].hi * dl[0].lo + ol[0].lo * dl[0].hi) + (ol[1].hi * dl[1].lo + ol[1].lo * dl[1].hi) +
+                    (ol[2].hi * dl[2].lo + ol[2].lo * dl[2].hi));
+  tperp = -(t.hi + lo);
+}
+
+// Line coordinates of a ray given in local space (o, d single precision,
+// exact as given): the moment o x d with the same compensated cross product,
+// as hi + lo.
+__device__ __forceinline__ void line_of_local(const float o[3], const float d[3], float pl[6], float pllo[6],
+                                              float& tperp) {
+#pragma clang fp contract(off)
+  const float zero[3] = {0.0f, 0.0f, 0.0f};
+  const f2 O[3] = {{o[0], 0.f}, {o[1], 0.f}, {o[2], 0.f}}, D[3] = {{d[0], 0.f}, {d[1], 0.f}, {d[2], 0.f}};
+  const f2 m0 = cross_c(O[1], D[2], O[2], D[1]);
+  const f2 m1 = cross_c(O[2], D[0], O[0], D[2]);
+  const f2 m2 = cross_c(O[0], D[1], O[1], D[0]);
+  pl[0] = d[0]; pl[1] = d[1]; pl[2] = d[2];
+  pllo[0] = pllo[1] = pllo[2] = 0.0f;
+  pl[3] = m0.hi; pllo[3] = m0.lo;
+  pl[4] = m1.hi; pllo[4] = m1.lo;
+  pl[5] = m2.hi; pllo[5] = m2.lo;
+  const f2 t = dot3_c(o[0], o[1], o[2], d, zero);
+  tperp = -(t.hi + t.lo);
+}
+
 // Chord [a, b] of a unit-direction ray inside |x| <= radius, clipped to t >= 0.
 __device__ __forceinline__ bool sphere_chord(const float ol[3], const float dl[3], float radius,
                                              float& a, float& b) {
@@ -97,12 +244,19 @@ __device__ __forceinline__ bool sphere_chord(const float ol[3], const float dl[3
   return b > a;
 }
 
-// sin(pi * y) through the hardware sine (argument in revolutions) after an
-// exact reduction of y to [-1, 1].
-__device__ __forceinline__ float sinpi_hw(float y) {
-  const float r = y - 2.0f * rintf(0.5f * y);  // exact for |y| < 2^23
-  return __builtin_amdgcn_sinf(0.5f * r);
+// sin(pi y) (h = 0) or cos(pi y) (h = 1) through the hardware sine
+// (argument in revolutions) for y given as y + ylo (|ylo| tiny against one):
+// y is first reduced exactly to r in [-1, 1] (y - 2 rint(y / 2) is exact for
+// |y| < 2^23); the residual and the cosine's quarter-period shift join after
+// the reduction, where the argument 0.5 r + (0.5 ylo + 0.25 h) rounds by at
+// most 1.5 2^-25 revolutions, not before it, where it would round at the
+// precision of y (2^-17 at y ~ 100).  One instruction serves both lane
+// halves (sine and cosine lanes).
+__device__ __forceinline__ float sinpi_hw(float y, float ylo, int h) {
+  const float r = y - 2.0f * rintf(0.5f * y);
+  return __builtin_amdgcn_sinf(fmaf(0.5f, r, fmaf(0.5f, ylo, 0.25f * float(h))));
 }
+__device__ __forceinline__ float sinpi_hw(float y, int h = 0) { return sinpi_hw(y, 0.0f, h); }
 
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
 

@@ -34,8 +34,15 @@ __device__ __forceinline__ bool pair_test(const KArgs& a, const float o[3], cons
   float ol[3], dl[3], ta, tb;
   to_local(g, o, d, ol, dl);
   const float bound = a.obj[obj].bound;
+  // single-precision t_perp differs from the intersection network's
+  // compensated one by a few units in the last place of the terms that form
+  // o_l (R^T o / s and c, each at most |o|_1 / s and |c|_1 in size); the
+  // bound is lowered by 2^-20 times their sum plus one, well beyond that, so
+  // that it never exceeds a depth the network can report
   const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
-  dm = fmaxf(g.s * (tperp - bound), 0.0f);
+  const float slack = 9.5367431640625e-7f * ((fabsf(o[0]) + fabsf(o[1]) + fabsf(o[2])) * g.inv_s +
+                                             fabsf(g.c[0]) + fabsf(g.c[1]) + fabsf(g.c[2]) + 1.0f);
+  dm = fmaxf(g.s * (tperp - bound - slack), 0.0f);
   return sphere_chord(ol, dl, bound, ta, tb);
 }
 
@@ -827,14 +834,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_nedf(KArgs a) {
       const bool valid = local < PL->cnt[obj];
       const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
       const W2L g = load_w2l(a.w2l, int(pr.y));
-      float o[3], d[3], ol[3], dl[3];
-      make_ray(a.rays, pr.x, o, d);
-      to_local(g, o, d, ol, dl);
-      float pl[6] = {dl[0], dl[1], dl[2], ol[1] * dl[2] - ol[2] * dl[1], ol[2] * dl[0] - ol[0] * dl[2],
-                     ol[0] * dl[1] - ol[1] * dl[0]};
-      const float tperp = -(ol[0] * dl[0] + ol[1] * dl[1] + ol[2] * dl[2]);
+      float o[3], d[3], dlo[3], ol[3], pl[6], pllo[6], tperp;
+      make_ray(a.rays, pr.x, o, d, dlo);
+      local_line(g, o, d, dlo, pl, pllo, tperp, ol);
       const bool inside = ol[0] * ol[0] + ol[1] * ol[1] + ol[2] * ol[2] < l * l;
-      eng::encode_input<DT, 6, L, KS0>(pl, half_v, Benc[nb], in_scale);
+      eng::encode_input<DT, 6, L, KS0>(pl, pllo, half_v, Benc[nb], in_scale);
       // ray and instance ids (< 2^31, flags in bit 31), t_perp and s
       eng::lds_write16(stash + uint32_t(nb) * (16u * NT),
                        eng::u32x4{pr.x | (valid ? 0x80000000u : 0u), pr.y | (inside ? 0x80000000u : 0u),

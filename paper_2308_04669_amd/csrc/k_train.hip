@@ -28,14 +28,12 @@ __global__ void k_train_encode(const float* o_l, const float* d_l, const float* 
   if (s >= B) return;
   const float o[3] = {o_l[3 * s], o_l[3 * s + 1], o_l[3 * s + 2]};
   const float d[3] = {d_l[3 * s], d_l[3 * s + 1], d_l[3 * s + 2]};
-  float p[6];
+  float p[6], plo[6] = {0, 0, 0, 0, 0, 0};
   int n;
   if (in_kind == NEDF_IN_PLUECKER) {
     n = 6;
-    p[0] = d[0]; p[1] = d[1]; p[2] = d[2];
-    p[3] = o[1] * d[2] - o[2] * d[1];
-    p[4] = o[2] * d[0] - o[0] * d[2];
-    p[5] = o[0] * d[1] - o[1] * d[0];
+    float tp;
+    line_of_local(o, d, p, plo, tp);
   } else {
     n = 3;
     p[0] = o[0]; p[1] = o[1]; p[2] = o[2];
@@ -47,12 +45,13 @@ __global__ void k_train_encode(const float* o_l, const float* d_l, const float* 
       v = p[f];
     } else if (f < n * (1 + 2 * L)) {
       const int q = f - n, level = q / (2 * n), w = q % (2 * n), c = w % n;
-      v = sinpi_hw(fmaf(float(1 << level), p[c], w >= n ? 0.5f : 0.0f));
+      v = sinpi_hw(float(1 << level) * p[c], float(1 << level) * plo[c], w >= n ? 1 : 0);
     }
     row[f] = bf16_bits(v);
   }
   if (!depth) return;  // calibration: no labels
-  const float tperp = -(o[0] * d[0] + o[1] * d[1] + o[2] * d[2]);
+  float pl[6], pllo[6], tperp;
+  line_of_local(o, d, pl, pllo, tperp);
   const bool h = hit[s] != 0;
   alpha[s] = h ? 1.0f : 0.0f;
   mu[s] = h ? (tperp - depth[s]) / bound : 0.0f;

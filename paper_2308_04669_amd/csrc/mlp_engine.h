@@ -602,11 +602,15 @@ __device__ __forceinline__ void trunk(const nedf_blob_header* hb, const uint8_t*
 // ---- first-layer encoding ----------------------------------------------------
 // Slot a holds sin(pi (2^level p_comp + h / 2)) for a < n L (h = 0 gives
 // sin, h = 1 cos), then the identity components two per slot, then zeros.
+// plo carries residuals of the components (p + plo their values to beyond
+// single precision; zero for inputs exact as given): the scaled residual
+// joins the sine's argument after the exact period reduction, so a
+// top-level feature is not off by 2^level times p's rounding.
 template <int N, int L>
-__device__ __forceinline__ float enc_slot(const float (&p)[N], int a, int half) {
+__device__ __forceinline__ float enc_slot(const float (&p)[N], const float (&plo)[N], int a, int half) {
   if (a < N * L) {
     const int level = a / N, comp = a % N;
-    return sinpi_hw(fmaf(float(1 << level), p[comp], 0.5f * float(half)));
+    return sinpi_hw(float(1 << level) * p[comp], float(1 << level) * plo[comp], half);
   }
   const int i = a - N * L;
   if (i >= (N + 1) / 2) return 0.0f;
@@ -615,7 +619,7 @@ __device__ __forceinline__ float enc_slot(const float (&p)[N], int a, int half) 
 }
 
 template <int DT, int N, int L, int KS0>
-__device__ __forceinline__ void encode_input(const float (&p)[N], int half,
+__device__ __forceinline__ void encode_input(const float (&p)[N], const float (&plo)[N], int half,
                                              typename Tr<DT>::frag (&B)[KS0], float inv_scale = 1.0f) {
   if constexpr (DT == 2) {
     // 32 slots per K-step and lane half, quantised to E4M3 with the
@@ -627,7 +631,7 @@ __device__ __forceinline__ void encode_input(const float (&p)[N], int half,
         float v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          v[j] = fminf(fmaxf(enc_slot<N, L>(p, 32 * ks + 4 * q + j, half) * inv_scale, -448.0f), 448.0f);
+          v[j] = fminf(fmaxf(enc_slot<N, L>(p, plo, 32 * ks + 4 * q + j, half) * inv_scale, -448.0f), 448.0f);
         int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
         w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
         B[ks][q] = w;
@@ -638,13 +642,22 @@ __device__ __forceinline__ void encode_input(const float (&p)[N], int half,
     for (int ks = 0; ks < KS0; ++ks) {
       bf16x8_t v;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = static_cast<__bf16>(enc_slot<N, L>(p, 8 * ks + j, half));
+      for (int j = 0; j < 8; ++j) v[j] = static_cast<__bf16>(enc_slot<N, L>(p, plo, 8 * ks + j, half));
       B[ks] = v;
     }
   } else {
 #pragma unroll
-    for (int ks = 0; ks < KS0; ++ks) B[ks] = enc_slot<N, L>(p, ks, half);
+    for (int ks = 0; ks < KS0; ++ks) B[ks] = enc_slot<N, L>(p, plo, ks, half);
   }
+}
+// Inputs exact as given (positions, directions).
+template <int DT, int N, int L, int KS0>
+__device__ __forceinline__ void encode_input(const float (&p)[N], int half, typename Tr<DT>::frag (&B)[KS0],
+                                             float inv_scale = 1.0f) {
+  float plo[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) plo[i] = 0.0f;
+  encode_input<DT, N, L, KS0>(p, plo, half, B, inv_scale);
 }
 
 // K-steps of an encoded input with n components and L levels.

@@ -195,16 +195,19 @@ def training_rays(config: int, stream: int, n: int, radius: float = 4.0,
 
 
 def nedf_model(config: int, stream: int, enc_L: int = 8, width: int = 256, depth: int = 8,
-               bound: float = 1.0, head_scale: float = 1.0) -> Model:
+               bound: float = 1.0, head_scale: float = 1.0, logit_scale: float = 1.0) -> Model:
     """An intersection network F_Phi: gamma_L(d, o x d) (6 (1 + 2L) inputs)
     -> depth x width ReLU -> (mu_hat, hit logit).  Hidden weights
-    N(0, 2/fan_in) (He), head N(0, 1/fan_in) scaled by ``head_scale``,
-    biases zero: the training initialisation, also used untrained by the
-    parity tests."""
+    N(0, 2/fan_in) (He), head N(0, 1/fan_in) scaled by ``head_scale``
+    (the hit-logit row by a further ``logit_scale``, which spreads the hit
+    probabilities of an untrained network over hits, misses and the
+    uncertain band without changing its depth output), biases zero: the
+    training initialisation, also used untrained by the parity tests."""
     g = rng(config, stream)
     d_in = 6 * (1 + 2 * enc_L)
     trunk = normal_mlp(g, [d_in] + [width] * depth + [2], hidden_gain=2.0)
     trunk.W[-1] *= np.float32(head_scale)
+    trunk.W[-1][1] *= np.float32(logit_scale)
     return Model(kind="nedf", bound=bound, trunk=trunk, params=dict(enc_L=enc_L))
 
 

@@ -6,81 +6,102 @@ import pytest
 
 import synthetic as syn
 from oracle import (camera_rays, march_compose, nedf_pair, secant_refine, shade_deferred, shadow_factor,
-                    to_local)
+                    to_local, pluecker, f32_record)
 from oracle.render import march_instance
-from tests.gpu_util import need_gpu, gpu_scene, per_instance, compare_depth_id, log
+from tests.gpu_util import need_gpu, gpu_scene, per_instance, log, pair_oracle, near_flags, refine_with_stability
 
 pytestmark = pytest.mark.gpu
 
 GEMM = {"f32": None, "bf16": "bf16"}
-# band around decision thresholds inside which a float32/bfloat16 result may
-# legitimately fall on the other side
-BAND = {"f32": 1e-4, "bf16": 2e-2}
-DEPTH_TOL = {"f32": 2e-4, "bf16": 5e-3}
-
-
+# band around the decision thresholds (routing probability 0.2 / 0.8, marched
+# opacity 0.5) inside which a result may legitimately fall on the other side,
+# beyond the computed probability ambiguity of reduced-precision networks:
+# several times the largest measured opacity difference
+BAND = {"f32": 1e-4, "bf16": 2e-3}
+# stated depth tolerances (scene units): float32 path 1e-4, bfloat16 path 5e-3
+DEPTH_TOL = {"f32": 1e-4, "bf16": 5e-3}
 def _np(t):
     import torch
     torch.cuda.synchronize()
     return t.cpu().numpy()
 
 
-def _nedf_scene(n_inst=6, size=48, head_scale=4.0):
+def _nedf_scene(n_inst=6, size=48, head_scale=1.0, logit_scale=4.0):
     models, insts, cam = syn.sdf_scene(3, n_inst, width=size, height=size)
-    nedfs = [syn.nedf_model(3, 200 + k, head_scale=head_scale) for k in range(len(models))]
+    nedfs = [syn.nedf_model(3, 200 + k, head_scale=head_scale, logit_scale=logit_scale)
+             for k in range(len(models))]
     return models, nedfs, insts, cam
 
 
+def _f32_rays(cam):
+    """Camera rays rounded to float32: the same single-precision rays go to
+    the library (as ray arrays) and, exactly, to the oracle."""
+    o, d = camera_rays(cam)
+    return o.astype(np.float32), d.astype(np.float32)
+
+
+def _gpu_rays(o32, d32):
+    import torch
+    from paper_2308_04669_amd import api
+    return api.array_rays(torch.from_numpy(o32).cuda(), torch.from_numpy(d32).cuda())
+
+
 def _oracle_pairs(models, nedfs, insts, o, d, dtype, n_samples):
-    """Per-instance oracle (hit, D, p, path, A-of-fallback) for every ray."""
+    """Per-instance oracle (hit, D, p, path, A-of-fallback, ambiguity) for
+    every ray, through each instance's single-precision record."""
+    o = np.asarray(o, np.float64)
+    d = np.asarray(d, np.float64)
     res = []
     for inst in insts:
-        hit, D, p, path = nedf_pair(nedfs[inst.model], models[inst.model], inst, o, d, p_lo=0.2, p_hi=0.8,
-                                    n_samples=n_samples, gemm=GEMM[dtype])
-        v, A, _ = march_instance(models[inst.model], inst, o, d, n_samples, None, GEMM[dtype])
-        res.append((hit, D, p, path, np.where(path == 1, A, np.nan)))
+        rec = f32_record(inst)
+        res.append(pair_oracle(models[rec.model], nedfs[rec.model], rec, o, d, n_samples, dtype))
     return res
 
 
 def _infer_compare(depth_g, id_g, res, dtype, label):
+    """Element-wise parity of depth and ID.  A pixel's ID is exempt when a
+    routing probability or a fallback opacity lies in a band around its
+    threshold, or its two nearest candidate depths lie within the tolerance
+    (plus their rounding ambiguity) of each other.  Its depth is exempt only
+    when the winning pair's bfloat16 result is not fixed by the method (its
+    ambiguity exceeds half the tolerance).  Every other hit is held to the
+    stated tolerance."""
     n = depth_g.shape[0]
-    Ds = np.array([np.where(r[0], r[1], np.inf) for r in res])
+    Ds = np.array([np.where(r.hit, r.D, np.inf) for r in res])
+    amb = np.array([np.where(r.hit, r.amb, 0.0) for r in res])
     best = Ds.min(axis=0)
     id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
     band = BAND[dtype]
+    tol = DEPTH_TOL[dtype]
     near = np.zeros(n, bool)
-    for hit, D, p, path, A in res:
-        near |= np.abs(p - 0.2) <= band
-        near |= np.abs(p - 0.8) <= band
-        near |= np.abs(A - 0.5) <= band
-        near |= (path == 0) & (np.abs(D) <= 1e-3)
-    srt = np.sort(Ds, axis=0)
+    for r in res:
+        near |= near_flags(r, band)
+        near |= (r.path == 0) & (np.abs(r.D) <= 1e-3)
+    order = np.argsort(Ds, axis=0, kind="stable")
+    srt = np.take_along_axis(Ds, order, axis=0)
+    amb_s = np.take_along_axis(amb, order, axis=0)
     gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
-    exempt = near | (gap <= DEPTH_TOL[dtype])
-    bad = (id_g != id_o) & ~exempt
-    both = (id_g == id_o) & (id_o >= 0)
+    exempt_id = near | (gap <= tol + amb_s[0] + amb_s[1])
+    win_amb = np.where(id_o >= 0, amb[np.maximum(id_o, 0), np.arange(n)], 0.0)
+    exempt_depth = win_amb > tol / 2
+    bad = (id_g != id_o) & ~exempt_id
+    both = (id_g == id_o) & (id_o >= 0) & ~exempt_depth
     err = np.abs(depth_g[both] - best[both])
-    st = dict(n=n, hits=int((id_o >= 0).sum()), exempt=int(exempt.sum()), id_mismatch=int(bad.sum()),
+    hits = int((id_o >= 0).sum())
+    st = dict(n=n, hits=hits, exempt_id=int(exempt_id.sum()),
+              exempt_depth=int((exempt_depth & (id_o >= 0)).sum()), id_mismatch=int(bad.sum()),
+              checked=int(both.sum()),
               depth_max_err=float(err.max()) if err.size else 0.0,
-              depth_p99_err=float(np.quantile(err, 0.99)) if err.size else 0.0,
               depth_med_err=float(np.median(err)) if err.size else 0.0,
-              paths=[int(sum(((r[3] == k) & np.isfinite(r[1] if k == 0 else r[3])).sum() for r in res))
+              paths=[int(sum(((r.path == k) & (np.isfinite(r.D) if k == 0 else True)).sum() for r in res))
                      for k in (0, 1)])
     log(f"[{label}] {st}")
     assert st["id_mismatch"] == 0, st
-    if dtype == "f32":
-        assert st["depth_max_err"] <= DEPTH_TOL[dtype], st
-    else:
-        # BF16: the emulating oracle rounds the same operands, but the float32
-        # line coordinates (|o_l| up to ~13, error ~1e-6) feed encoding
-        # frequencies up to 2^7 pi, so top-level features land on the other
-        # side of a bf16 rounding boundary for a few rays; with a 4x-scaled
-        # random head this moves about 1% of the network depths by up to a
-        # few hundredths.  Criterion: >= 95% within 5e-3, none beyond 5e-2.
-        frac_ok = float(np.mean(err <= DEPTH_TOL[dtype])) if err.size else 1.0
-        log(f"[{label}] fraction within {DEPTH_TOL[dtype]}: {frac_ok:.4f}")
-        assert st["depth_med_err"] <= 1e-3 and frac_ok >= 0.95, st
-        assert st["depth_max_err"] <= 5e-2, st
+    assert st["depth_max_err"] <= tol, st
+    # the exemptions stay a small minority of the hits
+    assert st["exempt_depth"] <= 0.05 * max(hits, 1), st
+    miss = id_o < 0
+    assert np.all(np.isinf(depth_g[miss & ~exempt_id])), "miss pixels must have +inf depth"
     return st
 
 
@@ -89,19 +110,36 @@ def test_infer_network_and_fallback(dtype):
     need_gpu()
     from paper_2308_04669_amd import api
     models, nedfs, insts, cam = _nedf_scene()
-    log(f"case: infer random NeDF {dtype} 48x48, 6 instances")
+    log(f"case: infer random NeDF {dtype} 48x48, 6 instances, float32 ray arrays")
+    o32, d32 = _f32_rays(cam)
     sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
     ws = api.Workspace()
-    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0, n_samples=128,
+    depth, ident = api.infer_depth_id(sc, _gpu_rays(o32, d32), dtype=dtype, refine_steps=0, n_samples=128,
                                       ws=ws)
     stats = api.ws_counters(ws)
     depth, ident = _np(depth).astype(np.float64), _np(ident)
-    o, d = camera_rays(cam)
-    res = _oracle_pairs(models, nedfs, insts, o, d, dtype, 128)
+    res = _oracle_pairs(models, nedfs, insts, o32, d32, dtype, 128)
     st = _infer_compare(depth, ident, res, dtype, f"infer {dtype}")
     log(f"routing {stats}")
     assert stats["nedf_hits"] > 0 and stats["fallback"] > 0 and stats["nedf_misses"] > 0
     assert st["hits"] > 100
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_infer_camera_rays(dtype):
+    """In-kernel camera rays (the benchmarked ray source) against the
+    oracle's rays from the single-precision camera basis: the same
+    element-wise parity as for ray arrays."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene()
+    log(f"case: infer {dtype} camera rays 48x48")
+    sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
+    dc, ic = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0, n_samples=128)
+    dc, ic = _np(dc).astype(np.float64), _np(ic)
+    o, d = camera_rays(cam, basis="f32")
+    res = _oracle_pairs(models, nedfs, insts, o, d, dtype, 128)
+    _infer_compare(dc, ic, res, dtype, f"infer camera {dtype}")
 
 
 def test_counters_reset_for_small_ray_counts():
@@ -144,36 +182,106 @@ def test_pair_capacity_overflow_is_reported():
     assert api.ws_counters(ws2)["culled_pairs"] > 1024
 
 
+# refinement: a pixel is exempt when one of its seeds' surface values lies
+# within this band of zero (the bracket test could go either way) or an
+# iterate lies within the depth tolerance of the guard interval's ends
+REFINE_FBAND = {"f32": 1e-2, "bf16": 0.25}
+
+
+def _refine_oracle(models, insts, o, d, ids, D_start, dtype):
+    """Oracle refinement of every hit pixel from the given start depths,
+    with the decision margins of each pixel."""
+    ref = D_start.copy()
+    fmin = np.full(D_start.shape, np.inf)
+    gmin = np.full(D_start.shape, np.inf)
+    for k, inst in enumerate(insts):
+        sel = np.nonzero(ids == k)[0]
+        if sel.size:
+            rec = f32_record(inst)
+            ref[sel], fmin[sel], gmin[sel] = secant_refine(models[rec.model], rec, o[sel], d[sel], D_start[sel],
+                                                           h=0.05, steps=3, gemm=GEMM[dtype], margins=True)
+    return ref, fmin, gmin
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_infer_secant_refinement(dtype):
+    """Refinement from the library's own unrefined depths, element by element
+    against the oracle's refinement of those depths."""
     need_gpu()
     from paper_2308_04669_amd import api
     models, nedfs, insts, cam = _nedf_scene()
     log(f"case: infer refinement {dtype}")
+    o32, d32 = _f32_rays(cam)
     sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
-    d0, i0 = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0)
-    d3, i3 = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=3, refine_h=0.05)
+    d0, i0 = api.infer_depth_id(sc, _gpu_rays(o32, d32), dtype=dtype, refine_steps=0)
+    d3, i3 = api.infer_depth_id(sc, _gpu_rays(o32, d32), dtype=dtype, refine_steps=3, refine_h=0.05)
     d0, i0, d3, i3 = _np(d0).astype(np.float64), _np(i0), _np(d3).astype(np.float64), _np(i3)
     assert np.array_equal(i0, i3)
-    o, d = camera_rays(cam)
-    ref = d0.copy()
-    for k, inst in enumerate(insts):
-        sel = np.nonzero(i0 == k)[0]
-        if sel.size:
-            ref[sel] = secant_refine(models[inst.model], inst, o[sel], d[sel], d0[sel], h=0.05, steps=3,
-                                     gemm=GEMM[dtype])
+    ref, fmin, gmin = _refine_oracle(models, insts, o32, d32, i0, d0, dtype)
+    tol = DEPTH_TOL[dtype]
     hit = i0 >= 0
+    exempt = hit & ((fmin <= REFINE_FBAND[dtype]) | (gmin <= tol))
     moved = hit & (ref != d0)
-    err = np.abs(d3[hit] - ref[hit])
-    log(f"[refine {dtype}] hits={int(hit.sum())} moved={int(moved.sum())} max_err={err.max():.3e} "
-        f"median_err={np.median(err):.3e}")
+    chk = hit & ~exempt
+    err = np.abs(d3[chk] - ref[chk])
+    log(f"[refine {dtype}] hits={int(hit.sum())} moved={int(moved.sum())} exempt={int(exempt.sum())} "
+        f"max_err={err.max():.3e} median_err={np.median(err):.3e}")
     assert moved.sum() > 20
-    tol = 1e-3 if dtype == "f32" else 2e-2
-    assert np.quantile(err, 0.99) <= tol and np.median(err) <= tol / 10
+    assert exempt.sum() <= 0.05 * hit.sum()
+    assert err.max() <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_infer_refinement_end_to_end(dtype):
+    """Network depth and ID, fallback and refinement end to end: the
+    library's refined depth against the oracle refining the oracle's own
+    network/marcher depth."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene()
+    log(f"case: infer + refinement end to end {dtype}")
+    o32, d32 = _f32_rays(cam)
+    sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
+    d3, i3 = api.infer_depth_id(sc, _gpu_rays(o32, d32), dtype=dtype, refine_steps=3, refine_h=0.05,
+                                n_samples=128)
+    d3, i3 = _np(d3).astype(np.float64), _np(i3)
+    res = _oracle_pairs(models, nedfs, insts, o32, d32, dtype, 128)
+    Ds = np.array([np.where(r.hit, r.D, np.inf) for r in res])
+    amb = np.array([np.where(r.hit, r.amb, 0.0) for r in res])
+    best = Ds.min(axis=0)
+    id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
+    ref, fmin, gmin = _refine_oracle(models, insts, o32, d32, id_o, np.where(id_o >= 0, best, 0.0), dtype)
+    tol = DEPTH_TOL[dtype]
+    n = d3.shape[0]
+    near = np.zeros(n, bool)
+    for r in res:
+        near |= near_flags(r, BAND[dtype])
+    order = np.argsort(Ds, axis=0, kind="stable")
+    srt = np.take_along_axis(Ds, order, axis=0)
+    amb_s = np.take_along_axis(amb, order, axis=0)
+    gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
+    win_amb = np.where(id_o >= 0, amb[np.maximum(id_o, 0), np.arange(n)], 0.0)
+    # the start depth enters the refinement only through the seeds' bracket
+    # test and the guard: decisions, exempt within their bands (the guard's
+    # widened by how far the library's start may lie from the oracle's)
+    exempt = (near | (gap <= tol + amb_s[0] + amb_s[1]) | (fmin <= REFINE_FBAND[dtype]) | (gmin <= 2 * tol + win_amb)
+              | (win_amb > tol / 2))
+    bad_id = (i3 != id_o) & ~exempt
+    chk = (i3 == id_o) & (id_o >= 0) & ~exempt
+    err = np.abs(d3[chk] - ref[chk])
+    hits = int((id_o >= 0).sum())
+    log(f"[refine e2e {dtype}] hits={hits} checked={int(chk.sum())} exempt={int((exempt & (id_o >= 0)).sum())} "
+        f"id_mismatch={int(bad_id.sum())} max_err={err.max():.3e} median_err={np.median(err):.3e}")
+    assert bad_id.sum() == 0
+    assert chk.sum() >= 0.8 * hits
+    assert err.max() <= tol
 
 
 @pytest.mark.parametrize("dtype,K", [("f32", 1), ("f32", 8), ("bf16", 8)])
 def test_shade_deferred_parity(dtype, K):
+    """Deferred shading of the library's own depth and ID buffers against
+    the oracle shading its own marcher depth and IDs; pixels whose ID is a
+    near-tie or near the opacity threshold are exempt."""
     need_gpu()
     from paper_2308_04669_amd import api
     models, insts, cam, _ = syn.config2_scene(width=40, height=36)
@@ -182,15 +290,24 @@ def test_shade_deferred_parity(dtype, K):
     depth, ident, _ = api.march_depth(sc, api.camera_rays(cam), n_samples=192, dtype=dtype)
     rgb = api.shade_deferred(sc, api.camera_rays(cam), depth, ident, K=K, h=0.05, clear_rgb=(0.1, 0.2, 0.3),
                              dtype=dtype)
-    depth, ident, rgb = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(rgb).astype(np.float64)
-    o, d = camera_rays(cam)
-    ref = shade_deferred(models, insts, o, d, depth, ident, K=K, h=0.05, clear=(0.1, 0.2, 0.3),
-                         gemm=GEMM[dtype])
-    err = np.abs(rgb - ref).max(axis=1)
-    hit = ident >= 0
-    log(f"[shade {dtype} K={K}] hits={int(hit.sum())} max_err={err.max():.3e}")
+    ident, rgb = _np(ident).astype(np.int64), _np(rgb).astype(np.float64)
+    o, d = camera_rays(cam, basis="f32")
+    recs = [f32_record(i) for i in insts]
+    As, Ds, _ = per_instance(models, recs, o, d, 192, gemm=GEMM[dtype])
+    best = Ds.min(axis=0)
+    id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
+    srt = np.sort(Ds, axis=0)
+    gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
+    exempt = (np.abs(As - 0.5) <= BAND[dtype]).any(axis=0) | (gap <= DEPTH_TOL[dtype])
+    ref = shade_deferred(models, recs, o, d, np.where(id_o >= 0, best, np.inf), id_o, K=K, h=0.05,
+                         clear=(0.1, 0.2, 0.3), gemm=GEMM[dtype])
+    assert np.all((ident == id_o) | exempt)
+    chk = (ident == id_o) & ~exempt
+    err = np.abs(rgb[chk] - ref[chk]).max(axis=1)
+    hit = chk & (id_o >= 0)
+    log(f"[shade {dtype} K={K}] hits={int(hit.sum())} exempt={int(exempt.sum())} max_err={err.max():.3e}")
     assert hit.sum() > 50
-    assert np.all(rgb[~hit] == np.array([0.1, 0.2, 0.3], np.float32))
+    assert np.all(rgb[(id_o < 0) & ~exempt] == np.array([0.1, 0.2, 0.3], np.float32))
     tol = 2e-4 if dtype == "f32" else 2e-2
     assert err.max() <= tol
 
@@ -204,6 +321,10 @@ def _shadow_compare(fac_g, ref, margin, label):
 
 
 def test_shadow_marcher_two_spheres():
+    """Alg. 2 with marcher shadow rays on two analytic spheres: the
+    library's factors from its own depth buffer against the oracle's from
+    its own; pixels whose occlusion test lies within 1e-3 of the threshold
+    (or whose hit is near the opacity threshold) are exempt."""
     need_gpu()
     from paper_2308_04669_amd import api
     a, _ = syn.config1_models()
@@ -215,57 +336,91 @@ def test_shadow_marcher_two_spheres():
     depth, ident, _ = api.march_depth(sc, api.camera_rays(cam), n_samples=256)
     fac = api.shadow(sc, api.camera_rays(cam), depth, ident, [light], eps=0.05, beta=0.5, method="march",
                      dtype="f32", n_samples=256)
-    depth, ident, fac = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(fac).astype(np.float64)
-    o, d = camera_rays(cam)
-    fn = lambda oo, dd: march_compose([a], insts, oo, dd, 256)[0]
-    ref = shadow_factor(fn, o, d, depth, ident, [light], eps=0.05, beta=0.5)
-    # margin: pixels whose shadow-ray depth lies within 1e-3 of the occlusion threshold
-    hitp = np.nonzero(ident >= 0)[0]
-    x = o[hitp] + depth[hitp, None] * d[hitp]
+    ident, fac = _np(ident).astype(np.int64), _np(fac).astype(np.float64)
+    o, d = camera_rays(cam, basis="f32")
+    recs = [f32_record(i) for i in insts]
+    As, Ds, _ = per_instance([a], recs, o, d, 256)
+    best = Ds.min(axis=0)
+    id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
+    fn = lambda oo, dd: march_compose([a], recs, oo, dd, 256)[0]
+    ref = shadow_factor(fn, o, d, np.where(id_o >= 0, best, np.inf), id_o, [light], eps=0.05, beta=0.5)
+    hitp = np.nonzero(id_o >= 0)[0]
+    x = o[hitp] + best[hitp, None] * d[hitp]
     v = x - light
     dist = np.linalg.norm(v, axis=1)
     DL = fn(np.broadcast_to(light, v.shape).copy(), v / dist[:, None])
-    margin = np.zeros(len(depth), bool)
-    margin[hitp] = np.abs(DL + 0.05 - dist) <= 1e-3
+    margin = (np.abs(As - 0.5) <= 1e-4).any(axis=0) | (ident != id_o)
+    margin[hitp] |= np.abs(DL + 0.05 - dist) <= 1e-3
+    assert ((ident != id_o) & ~(np.abs(As - 0.5) <= 1e-4).any(axis=0)).sum() == 0
     _shadow_compare(fac, ref, margin, "shadow two spheres")
     assert (ref < 1).sum() > 20
 
 
+def _oracle_depth_id(res, dtype):
+    """Per-pixel oracle depth and ID from per-instance results, with the
+    pixels whose ID is not fixed (threshold bands, near-ties) and the
+    winner's rounding ambiguity."""
+    Ds = np.array([np.where(r.hit, r.D, np.inf) for r in res])
+    amb = np.array([np.where(r.hit, r.amb, 0.0) for r in res])
+    n = Ds.shape[1]
+    best = Ds.min(axis=0)
+    id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
+    near = np.zeros(n, bool)
+    for r in res:
+        near |= near_flags(r, BAND[dtype])
+    order = np.argsort(Ds, axis=0, kind="stable")
+    srt = np.take_along_axis(Ds, order, axis=0)
+    amb_s = np.take_along_axis(amb, order, axis=0)
+    if Ds.shape[0] > 1:
+        gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
+        tie = gap <= DEPTH_TOL[dtype] + amb_s[0] + amb_s[1]
+    else:
+        tie = np.zeros(n, bool)
+    win_amb = np.where(id_o >= 0, amb[np.maximum(id_o, 0), np.arange(n)], 0.0)
+    return best, id_o, near | tie, win_amb
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_shadow_nedf_and_composite(dtype):
+    """Shadow factors (Alg. 2, intersection-network shadow rays) of the
+    library's own depth buffer against the oracle's shadow rays from the
+    oracle's own depth buffer; a pixel is exempt when its ID is not fixed or
+    its occlusion test lies within the two depth tolerances (and rounding
+    ambiguities) of the threshold."""
     need_gpu()
     import torch
     from paper_2308_04669_amd import api
     models, nedfs, insts, cam = _nedf_scene(n_inst=5, size=40)
     light = np.array([3.0, 6.0, -2.0])
+    eps = 0.05
     log(f"case: shadow NeDF {dtype}")
+    o32, d32 = _f32_rays(cam)
     sc = gpu_scene(models, insts, dtype, nedf_models=nedfs)
-    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype=dtype, refine_steps=0)
+    rays = _gpu_rays(o32, d32)
+    depth, ident = api.infer_depth_id(sc, rays, dtype=dtype, refine_steps=0)
     rgb_in = torch.rand((depth.numel(), 3), device="cuda")
     rgb = rgb_in.clone()
-    fac = api.shadow(sc, api.camera_rays(cam), depth, ident, [light], eps=0.05, beta=0.5, method="nedf",
-                     dtype=dtype, rgb_inout=rgb)
-    depth, ident, fac = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(fac).astype(np.float64)
+    fac = api.shadow(sc, rays, depth, ident, [light], eps=eps, beta=0.5, method="nedf", dtype=dtype,
+                     rgb_inout=rgb)
+    ident, fac = _np(ident).astype(np.int64), _np(fac).astype(np.float64)
     assert np.allclose(_np(rgb), _np(rgb_in) * fac[:, None], rtol=1e-6, atol=0)
-    o, d = camera_rays(cam)
-    hitp = np.nonzero(ident >= 0)[0]
-    x = o[hitp] + depth[hitp, None] * d[hitp]
+    o, d = o32.astype(np.float64), d32.astype(np.float64)
+    best, id_o, ex_id, win_amb = _oracle_depth_id(_oracle_pairs(models, nedfs, insts, o, d, dtype, 128), dtype)
+    hitp = np.nonzero(id_o >= 0)[0]
+    x = o[hitp] + best[hitp, None] * d[hitp]
     v = x - light
     dist = np.linalg.norm(v, axis=1)
     ds = v / dist[:, None]
     so = np.broadcast_to(light, v.shape).copy()
-    res = _oracle_pairs(models, nedfs, insts, so, ds, dtype, 128)
-    Ds = np.array([np.where(r[0], r[1], np.inf) for r in res])
-    DL = Ds.min(axis=0)
-    ref = np.ones(len(depth))
-    ref[hitp] = np.where(DL + 0.05 < dist, 0.5, 1.0)
-    band = BAND[dtype]
-    near = np.zeros(hitp.size, bool)
-    for hit, D, p, path, A in res:
-        near |= (np.abs(p - 0.2) <= band) | (np.abs(p - 0.8) <= band) | (np.abs(A - 0.5) <= band)
-    margin = np.zeros(len(depth), bool)
-    margin[hitp] = near | (np.abs(DL + 0.05 - dist) <= (DEPTH_TOL[dtype] if dtype == "f32" else 5e-2))
+    DL, _, ex_s, amb_s = _oracle_depth_id(_oracle_pairs(models, nedfs, insts, so, ds, dtype, 128), dtype)
+    ref = np.ones(len(o))
+    ref[hitp] = np.where(DL + eps < dist, 0.5, 1.0)
+    tol = DEPTH_TOL[dtype]
+    margin = ex_id | (ident != id_o)
+    margin[hitp] |= ex_s | (np.abs(DL + eps - dist) <= 2 * tol + win_amb[hitp] + amb_s)
+    assert (margin & (ident != id_o) & ~ex_id).sum() == 0
     _shadow_compare(fac, ref, margin, f"shadow nedf {dtype}")
+    assert margin.sum() <= 0.1 * len(o)
 
 
 def test_fp8_calibration_matches_oracle():
@@ -283,43 +438,49 @@ def test_fp8_calibration_matches_oracle():
     assert rel[1::2].max() <= 2e-2          # activation amax: bfloat16 forward vs float64
 
 
-def test_infer_fp8_network_parity():
+def test_infer_fp8_network_and_refine_parity():
+    """FP8 (E4M3, per-layer scales) intersection networks with bfloat16
+    fallback and 3-step refinement on the bfloat16 density field, element by
+    element against the oracle emulating the same roundings.  E4M3 keeps 3
+    mantissa bits, so a network depth is fixed by the method only up to the
+    oracle's computed rounding ambiguity: IDs must agree outside near-ties
+    and bands, a refined depth within 5e-3 of the oracle's refinement of its
+    own start (where the bracket decision is stable), an unrefined depth
+    within 5e-3 plus its ambiguity."""
     need_gpu()
     from paper_2308_04669_amd import api
     from oracle import fp8_calibrate
     models, nedfs, insts, cam = _nedf_scene()
-    log("case: infer FP8 networks, BF16 fallback")
+    log("case: infer FP8 networks, BF16 fallback, refinement")
     cal_o, cal_d = syn.training_rays(5, 2, 8192)
     scales = [fp8_calibrate(n, cal_o.astype(np.float64), cal_d.astype(np.float64)) for n in nedfs]
     objs = [api.object_from_model(m, "bf16", nedf_model=n, nedf_dtype="fp8", nedf_scales=s.reshape(-1))
             for m, n, s in zip(models, nedfs, scales)]
     sc = api.make_scene(objs, insts)
     ws = api.Workspace()
-    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype="bf16", refine_steps=0, ws=ws)
+    o32, d32 = _f32_rays(cam)
+    depth, ident = api.infer_depth_id(sc, _gpu_rays(o32, d32), dtype="bf16", refine_steps=3, ws=ws)
     depth, ident = _np(depth).astype(np.float64), _np(ident)
-    o, d = camera_rays(cam)
-    res = []
-    for inst in insts:
-        hit, D, p, path = nedf_pair(nedfs[inst.model], models[inst.model], inst, o, d, n_samples=128,
-                                    gemm="bf16", net_scales=[tuple(x) for x in scales[inst.model]])
-        v, A, _ = march_instance(models[inst.model], inst, o, d, 128, None, "bf16")
-        res.append((hit, D, p, path, np.where(path == 1, A, np.nan)))
-    Ds = np.array([np.where(r[0], r[1], np.inf) for r in res])
-    best = Ds.min(axis=0)
-    id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
-    near = np.zeros(len(depth), bool)
-    for hit, D, p, path, A in res:
-        near |= (np.abs(p - 0.2) <= 0.08) | (np.abs(p - 0.8) <= 0.08) | (np.abs(A - 0.5) <= 0.02)
-    srt = np.sort(Ds, axis=0)
-    gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
-    exempt = near | (gap <= 5e-2)
-    mism = (ident != id_o) & ~exempt
-    both = (ident == id_o) & (id_o >= 0)
-    err = np.abs(depth[both] - best[both])
-    st = dict(hits=int((id_o >= 0).sum()), exempt=int(exempt.sum()), id_mismatch=int(mism.sum()),
-              med=float(np.median(err)), p95=float(np.quantile(err, 0.95)), max=float(err.max()),
-              id_agree=float(np.mean(ident == id_o)))
-    log(f"[infer fp8] {st} routing {api.ws_counters(ws)}")
-    # E4M3 keeps 3 mantissa bits: a one-code flip of an activation is a 6-12% step
-    assert st["id_mismatch"] <= max(3, int(0.01 * len(depth)))
-    assert st["med"] <= 5e-3 and st["p95"] <= 5e-2
+    o, d = o32.astype(np.float64), d32.astype(np.float64)
+    recs = [f32_record(i) for i in insts]
+    res = [pair_oracle(models[r.model], nedfs[r.model], r, o, d, 128, "bf16",
+                       scales=[tuple(x) for x in scales[r.model]]) for r in recs]
+    best, id_o, ex_id, win_amb = _oracle_depth_id(res, "bf16")
+    tol = DEPTH_TOL["bf16"]
+    ref, moved, unstable, spread = refine_with_stability(models, recs, id_o, o, d, np.where(id_o >= 0, best, 0.0),
+                                                         tol + win_amb)
+    bad = (ident != id_o) & ~ex_id
+    chk = (ident == id_o) & (id_o >= 0) & ~ex_id & ~unstable & (spread <= tol / 2)
+    allow = tol + np.where(moved, 0.0, win_amb)
+    err = np.abs(depth - ref)
+    hits = int((id_o >= 0).sum())
+    log(f"[infer fp8+refine] hits={hits} exempt_id={int(ex_id.sum())} id_mismatch={int(bad.sum())} "
+        f"checked={int(chk.sum())} refined={int((chk & moved).sum())} "
+        f"max_err_refined={err[chk & moved].max() if (chk & moved).any() else 0:.3e} "
+        f"max_err_unrefined={err[chk & ~moved].max() if (chk & ~moved).any() else 0:.3e} "
+        f"median_amb={np.median(win_amb[id_o >= 0]):.3e} routing {api.ws_counters(ws)}")
+    assert bad.sum() == 0
+    # E4M3 leaves the routing of about a fifth of these hits open (measured
+    # 77 % checked)
+    assert chk.sum() >= 0.7 * hits
+    assert np.all(err[chk] <= allow[chk])

@@ -1,16 +1,25 @@
-"""Parity at full batched-composition size: 1,000 instances of 4 SDF-biased
-NeRF objects at 1920 x 1080, the BF16 intersection-network path with marcher
-fallback in the launch configuration the benchmark times, checked on seeded
-sampled pixels against the FP64 oracle evaluated pixel by pixel."""
+"""Parity at full size, in the launch configuration the benchmark times:
+1,000 instances of 4 SDF-biased NeRF objects at 1920 x 1080 (bfloat16
+intersection networks with marcher fallback, 3-step secant refinement,
+K = 8 deferred shading, shadow rays to two lights) and the precision-stress
+scene (64 instances at 3840 x 2160, FP8 networks).  Seeded sampled pixels are
+checked element by element against the FP64 oracle, which composes each
+sampled ray front to back over the instances (exact pruning with a margin,
+so that every candidate that could tie the winner is evaluated)."""
 import numpy as np
 import pytest
 
 import synthetic as syn
-from oracle import camera_rays, nedf_pair, secant_refine, shade_deferred
-from oracle.render import march_instance
-from tests.gpu_util import need_gpu, gpu_scene, log
+from oracle import camera_rays, f32_record, shade_deferred
+from oracle.render import depth_lower_bound
+from tests.gpu_util import need_gpu, gpu_scene, log, pair_oracle, refine_with_stability
 
 pytestmark = pytest.mark.gpu
+
+TOL = 5e-3     # bfloat16 depth tolerance (scene units)
+BAND = 2e-3    # band around the routing (0.2, 0.8) and opacity (0.5) thresholds, beyond the
+               # computed probability ambiguity: 4x the largest measured opacity difference
+N_PIX = 256
 
 
 def _np(t):
@@ -19,127 +28,178 @@ def _np(t):
     return t.cpu().numpy()
 
 
-def _candidates(models, nedfs, insts, o, d, n_samples):
-    """Per-instance oracle candidates for the sampled rays: lists of
-    (instance, hit, D, p, path, A) restricted to instances whose bounding
-    sphere some sampled ray meets."""
-    from oracle import to_local
-    out = []
-    for k, inst in enumerate(insts):
-        o_l, d_l = to_local(inst, o, d)
-        m = np.linalg.norm(np.cross(o_l, d_l), axis=-1)
-        if not np.any(m < models[inst.model].bound):
-            continue
-        hit, D, p, path = nedf_pair(nedfs[inst.model], models[inst.model], inst, o, d, p_lo=0.2, p_hi=0.8,
-                                    n_samples=n_samples, gemm="bf16")
-        A = np.full(o.shape[0], np.nan)
-        fb = np.nonzero(path == 1)[0]
-        if fb.size:
-            _, Af, _ = march_instance(models[inst.model], inst, o[fb], d[fb], n_samples, None, "bf16")
-            A[fb] = Af
-        # world distance at which the ray enters the bounding sphere
-        l = models[inst.model].bound
-        t_perp = -np.sum(o_l * d_l, axis=-1)
-        t_in = inst.s * (t_perp - np.sqrt(np.maximum(l * l - m * m, 0.0)))
-        out.append((k, hit, D, p, path, A, np.where(m < l, t_in, np.inf)))
-    return out
+def _nets(config, n):
+    return [syn.nedf_model(config, 200 + k, head_scale=1.0, logit_scale=16.0) for k in range(n)]
 
 
-def _candidates_sparse(models, nedfs, insts, o, d, n_samples, t_max=None):
-    """As _candidates, but each instance's oracle runs only on the rays that
-    meet its bounding sphere, and (given t_max per ray) enter it no farther
-    than t_max; the others get no hit, p = 0, t_in = inf."""
-    from oracle import to_local
+def pruned_oracle(models, nedfs, insts, o, d, scales=None, margin=0.5, t_max=None, n_samples=128):
+    """Depth and ID of each ray by the oracle, front to back: candidates in
+    increasing order of their depth lower bound, each evaluated while its
+    bound is within ``margin`` of the best depth so far (pairs farther away
+    can neither win nor tie).  With ``t_max`` only candidates whose bound is
+    below t_max + margin count (occluders of a shadow ray).  Returns a dict:
+    best, id, second (second-smallest hit depth), amb (winner's and
+    runner-up's rounding ambiguity), near (some evaluated pair lies in a
+    threshold band), recs, pairs evaluated."""
+    recs = [f32_record(i) for i in insts]
     n = o.shape[0]
-    out = []
-    for k, inst in enumerate(insts):
-        o_l, d_l = to_local(inst, o, d)
-        m = np.linalg.norm(np.cross(o_l, d_l), axis=-1)
-        l = models[inst.model].bound
-        meet = m < l
-        if t_max is not None:
-            tp = -np.sum(o_l * d_l, axis=-1)
-            t_enter = inst.s * (tp - np.sqrt(np.maximum(l * l - m * m, 0.0)))
-            meet &= t_enter <= t_max
-        sel = np.nonzero(meet)[0]
-        if sel.size == 0:
-            continue
-        hit = np.zeros(n, bool)
-        D = np.full(n, np.inf)
-        p = np.zeros(n)
-        path = np.full(n, -1)
-        A = np.full(n, np.nan)
-        h_, D_, p_, path_ = nedf_pair(nedfs[inst.model], models[inst.model], inst, o[sel], d[sel], p_lo=0.2,
-                                      p_hi=0.8, n_samples=n_samples, gemm="bf16")
-        hit[sel], D[sel], p[sel], path[sel] = h_, D_, p_, path_
-        fb = sel[path_ == 1]
-        if fb.size:
-            _, Af, _ = march_instance(models[inst.model], inst, o[fb], d[fb], n_samples, None, "bf16")
-            A[fb] = Af
-        t_perp = -np.sum(o_l * d_l, axis=-1)
-        t_in = np.where(meet, inst.s * (t_perp - np.sqrt(np.maximum(l * l - m * m, 0.0))), np.inf)
-        out.append((k, hit, D, p, path, A, t_in))
+    lb = np.array([depth_lower_bound(models[r.model].bound, r, o, d) for r in recs])
+    if t_max is not None:
+        lb = np.where(lb <= t_max + margin, lb, np.inf)
+    best = np.full(n, np.inf)
+    second = np.full(n, np.inf)
+    bid = np.full(n, -1, np.int64)
+    amb_b = np.zeros(n)
+    amb_2 = np.zeros(n)
+    # smallest depth a pair could report if a decision inside a threshold
+    # band went the other way, per ray: it matters only if it can reach the
+    # winner
+    near_alt = np.full(n, np.inf)
+    alt_b = np.full(n, np.inf)
+    kept = []
+    miss_b = np.zeros(n, bool)
+    dev_b = np.zeros(n)
+    order = np.argsort(lb, axis=0, kind="stable")
+    cols = np.arange(n)
+    evaluated = 0
+    for r in range(len(recs)):
+        k_r = order[r]
+        b_r = lb[k_r, cols]
+        need = np.isfinite(b_r) & (b_r <= best + margin)
+        if not need.any():
+            break
+        for k in np.unique(k_r[need]):
+            idx = np.nonzero(need & (k_r == k))[0]
+            rec = recs[k]
+            sc = None if scales is None else [tuple(x) for x in scales[rec.model]]
+            r_ = pair_oracle(models[rec.model], nedfs[rec.model], rec, o[idx], d[idx], n_samples, "bf16", sc,
+                             band=BAND)
+            hit, D, amb, alt = r_.hit, r_.D, r_.amb, r_.alt
+            kept.append((k, idx, r_))
+            evaluated += idx.size
+            Dh = np.where(hit, D, np.inf)
+            cur, cid = best[idx], bid[idx]
+            better = (Dh < cur) | ((Dh == cur) & np.isfinite(Dh) & (k < cid))
+            # the displaced best becomes the runner-up
+            sec_new = np.where(better, cur, np.minimum(second[idx], Dh))
+            amb2_new = np.where(better, amb_b[idx], np.where(Dh < second[idx], amb, amb_2[idx]))
+            second[idx], amb_2[idx] = sec_new, amb2_new
+            # banded alternatives: the winner's own change its depth, the
+            # others' could change the ID
+            near_alt[idx] = np.minimum(near_alt[idx], np.where(better, alt_b[idx], alt))
+            alt_b[idx] = np.where(better, alt, alt_b[idx])
+            miss_b[idx] = np.where(better, r_.alt_miss, miss_b[idx])
+            dev_b[idx] = np.where(better, r_.alt_dev, dev_b[idx])
+            best[idx] = np.where(better, Dh, cur)
+            amb_b[idx] = np.where(better, amb, amb_b[idx])
+            bid[idx] = np.where(better, k, cid)
+    near = (near_alt <= np.where(np.isfinite(best), best + TOL + amb_b, np.inf)) | miss_b
+    # the winner could report its banded alternative depth instead
+    self_alt = (np.isfinite(alt_b) & (np.abs(alt_b - best) > TOL / 2)) | (dev_b > TOL / 2)
+    return dict(best=best, id=np.where(np.isfinite(best), bid, -1), second=second, amb=amb_b, amb2=amb_2,
+                near=near, self_alt=self_alt, recs=recs, evaluated=evaluated, kept=kept)
+
+
+def _id_exempt(orc):
+    gap = orc["second"] - np.where(np.isfinite(orc["best"]), orc["best"], 0.0)
+    return orc["near"] | (gap <= TOL + orc["amb"] + orc["amb2"])
+
+
+def _frame(models, nedfs, insts, cam, objs=None, shade=False, lights=None, eps=None):
+    from paper_2308_04669_amd import api
+    sc = api.make_scene(objs, insts) if objs is not None else gpu_scene(models, insts, "bf16", nedf_models=nedfs)
+    rays = api.camera_rays(cam)
+    ws = api.Workspace()
+    depth, ident = api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, n_samples=128, ws=ws)
+    assert api.check_status(ws) == 0
+    out = dict(routing=api.ws_counters(ws))
+    if shade:
+        out["rgb"] = _np(api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, clear_rgb=(0.1, 0.2, 0.3),
+                                            dtype="bf16")).astype(np.float64)
+    if lights is not None:
+        out["fac"] = _np(api.shadow(sc, rays, depth, ident, lights, eps, beta=0.5, method="nedf", dtype="bf16",
+                                    n_samples=128)).astype(np.float64)
+    out["depth"] = _np(depth).astype(np.float64)
+    out["id"] = _np(ident).astype(np.int64)
     return out
+
+
+def _depth_parity(models, nedfs, insts, cam, gpu, pix, label, scales=None):
+    o, d = camera_rays(cam, pix, basis="f32")
+    orc = pruned_oracle(models, nedfs, insts, o, d, scales=scales)
+    ref, moved, unstable, spread = refine_with_stability(models, orc["recs"], orc["id"], o, d, orc["best"],
+                                                         TOL + orc["amb"])
+    ex_id = _id_exempt(orc)
+    id_o = orc["id"]
+    ig, dg = gpu["id"][pix], gpu["depth"][pix]
+    bad = (ig != id_o) & ~ex_id
+    # a refined depth is the surface root inside the seeds' bracket, fixed
+    # unless the bracket or guard decision (or convergence) depends on where
+    # inside its uncertainty the start lies; an unrefined depth is the
+    # network's, exempt where its rounding is left open
+    ex_depth = unstable | (spread > TOL / 2) | orc["self_alt"]
+    if scales is None:
+        ex_depth |= ~moved & (orc["amb"] > TOL / 2)
+        allow = np.full(len(pix), TOL)
+    else:
+        # E4M3 (3 mantissa bits): most unrefined network depths are left
+        # open by more than the tolerance; an unrefined pixel is held to the
+        # tolerance plus its computed ambiguity instead of being exempted
+        allow = TOL + np.where(moved, 0.0, orc["amb"])
+    chk = (ig == id_o) & (id_o >= 0) & ~ex_id & ~ex_depth
+    err = np.abs(dg[chk] - ref[chk])
+    over = err - (allow[chk] - TOL)
+    hits = int((id_o >= 0).sum())
+    log(f"[{label}] pixels={len(pix)} hits={hits} pairs={orc['evaluated']} exempt_id={int(ex_id.sum())} "
+        f"exempt_depth={int((ex_depth & (id_o >= 0)).sum())} id_mismatch={int(bad.sum())} checked={int(chk.sum())} "
+        f"refined={int((moved & chk).sum())} max_err={err.max() if err.size else 0:.3e} "
+        f"median_err={np.median(err) if err.size else 0:.3e} max_err_beyond_ambiguity={over.max() if err.size else 0:.3e} "
+        f"routing={gpu['routing']}")
+    worst = np.argsort(-(np.abs(dg - ref) - allow) * (chk | bad))[:4]
+    for w in worst:
+        if chk[w] or bad[w]:
+            log(f"  pixel {int(pix[w])}: id gpu {int(ig[w])} oracle {int(id_o[w])} depth gpu {dg[w]:.6f} "
+                f"oracle {orc['best'][w]:.6f} refined {ref[w]:.6f} moved {bool(moved[w])} amb {orc['amb'][w]:.3e} "
+                f"second {orc['second'][w]:.6f} amb2 {orc['amb2'][w]:.3e} near {bool(orc['near'][w])}")
+            for k, idx, r_ in orc["kept"]:
+                j = np.nonzero(idx == w)[0]
+                if j.size and k in (int(ig[w]), int(id_o[w])):
+                    j = j[0]
+                    log(f"    pair k={k} hit {bool(r_.hit[j])} D {r_.D[j]:.6f} p {r_.p[j]:.6f} path {int(r_.path[j])} "
+                        f"A {r_.A[j]:.4f} amb {r_.amb[j]:.3e} amb_p {r_.amb_p[j]:.3e} geo {bool(r_.geo[j])} "
+                        f"alt {r_.alt[j]:.6f}")
+    assert hits >= len(pix) // 4
+    assert bad.sum() == 0
+    # E4M3 leaves the routing and depth of about a third of the pixels of
+    # this scene open (measured 32 %); bfloat16 under 10 %
+    cap = 0.1 if scales is None else 0.4
+    assert (ex_id | (ex_depth & (id_o >= 0))).sum() <= cap * len(pix)
+    assert np.all(err <= allow[chk])
+    miss = (id_o < 0) & ~ex_id
+    assert np.all(np.isinf(dg[miss]))
+    return o, d, orc, ref, chk
 
 
 def test_batched_scene_full_frame_sampled_parity():
+    """Depth and ID of the 1080p frame (network, fallback and refinement)
+    on 256 seeded pixels: IDs bit-exact outside near-ties and threshold
+    bands, refined depths within 5e-3 scene units."""
     need_gpu()
-    from paper_2308_04669_amd import api
     models, insts, cam, _ = syn.config4_scene()
-    nedfs = [syn.nedf_model(4, 200 + k, head_scale=16.0) for k in range(len(models))]
-    log("case: batched scene 1920x1080, 1000 instances, BF16 depth+ID (network + fallback)")
-    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
-    ws = api.Workspace()
-    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype="bf16", refine_steps=0, n_samples=128,
-                                      ws=ws)
-    st = api.ws_counters(ws)
-    assert api.check_status(ws) == 0
-    log(f"routing {st}")
-    pix = syn.pixel_subset(4, cam.n_rays, 32)
-    dg, ig = _np(depth)[pix].astype(np.float64), _np(ident)[pix].astype(np.int64)
-    o, d = camera_rays(cam, pix)
-    cands = _candidates(models, nedfs, insts, o, d, 128)
-    n = len(pix)
-    Ds = np.array([np.where(c[1], c[2], np.inf) for c in cands])
-    ks = np.array([c[0] for c in cands])
-    best = Ds.min(axis=0)
-    id_o = np.where(np.isfinite(best), ks[Ds.argmin(axis=0)], -1)
-    scale = np.array([insts[k].s for k in ks])
-    # exemptions: a decision within a BF16 band of a threshold on an instance
-    # that could be the nearest (its bounding sphere starts before the
-    # winning depth), or a near-tie
-    win_s = np.where(id_o >= 0, scale[np.maximum(Ds.argmin(axis=0), 0)], 1.0)
-    near = np.zeros(n, bool)
-    for _, hit, D, p, path, A, t_in in cands:
-        flip = (np.abs(p - 0.2) <= 2e-2) | (np.abs(p - 0.8) <= 2e-2) | (np.abs(A - 0.5) <= 2e-2)
-        near |= flip & (t_in <= best + 5e-3 * win_s)
-    srt = np.sort(Ds, axis=0)
-    gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
-    exempt = near | (gap <= 5e-3 * win_s)
-    bad = (ig != id_o) & ~exempt
-    both = (ig == id_o) & (id_o >= 0)
-    err_world = np.abs(dg[both] - best[both])
-    err_local = err_world / win_s[both]
-    log(f"[batched bf16] pixels={n} hits={int((id_o >= 0).sum())} exempt={int(exempt.sum())} "
-        f"id_mismatch={int(bad.sum())} "
-        f"candidates/pixel={sum(np.isfinite(c[6]).sum() for c in cands) / max(n, 1):.1f} "
-        f"max_err_world={err_world.max() if err_world.size else 0:.3e} "
-        f"max_err_local={err_local.max() if err_local.size else 0:.3e}")
-    assert (id_o >= 0).sum() >= n // 2
-    assert bad.sum() == 0
-    # depths compared in each instance's local units (world error / s): the
-    # emulating oracle rounds the same BF16 operands, residual differences
-    # are rounding-boundary flips (see the small-scene BF16 criterion)
-    assert np.median(err_local) <= 1e-3 and np.mean(err_local <= 5e-3) >= 0.9
-    assert err_local.max() <= 5e-2
+    nedfs = _nets(4, len(models))
+    log("case: batched scene 1920x1080, 1000 instances, BF16 depth+ID + refinement, 256 pixels")
+    gpu = _frame(models, nedfs, insts, cam)
+    pix = syn.pixel_subset(4, cam.n_rays, N_PIX)
+    _depth_parity(models, nedfs, insts, cam, gpu, pix, "batched bf16")
 
 
 def test_tiled_culling_keeps_every_pair():
     """Camera rays are culled per 16 x 16 tile (frustum test, then the exact
     per-ray test); the same rays given as arrays go through the untiled
-    per-ray test.  Every pair must survive the tile test: pair counts agree
-    up to the few grazing rays whose float32 directions differ between the
-    in-kernel camera and the uploaded arrays, and so do depth and ID."""
+    per-ray test.  The library's camera rays are the faithfully rounded
+    directions of the single-precision camera, so the oracle's rays from
+    that camera rounded to float32 are the same rays: pair counts, depth and
+    ID agree exactly."""
     need_gpu()
     import torch
     from paper_2308_04669_amd import api
@@ -150,7 +210,7 @@ def test_tiled_culling_keeps_every_pair():
     ws_c, ws_a = api.Workspace(), api.Workspace()
     d_c, i_c, _ = api.march_depth(sc, api.camera_rays(cam), n_samples=64, dtype="f32", ws=ws_c)
     n_c = api.ws_counters(ws_c)["pairs"]
-    o, d = camera_rays(cam)
+    o, d = camera_rays(cam, basis="f32")
     ot = torch.from_numpy(o.astype(np.float32)).cuda()
     dt = torch.from_numpy(d.astype(np.float32)).cuda()
     d_a, i_a, _ = api.march_depth(sc, api.array_rays(ot, dt), n_samples=64, dtype="f32", ws=ws_a)
@@ -159,143 +219,90 @@ def test_tiled_culling_keeps_every_pair():
     differ = int(np.sum(i_c != i_a))
     log(f"[tiled cull] pairs tiled={n_c} per-ray={n_a} id differences={differ} of {i_c.size}")
     assert n_c > 10 * i_c.size
-    assert abs(n_c - n_a) <= max(10, 1e-4 * n_a)
-    assert differ <= max(5, 1e-4 * i_c.size)
+    assert abs(n_c - n_a) <= max(2, 1e-6 * n_a)
+    assert differ <= 2
 
 
 def test_batched_scene_full_frame_shading_sampled_parity():
-    """K = 8 deferred shading of the 1080p, 1,000-instance frame in the launch
-    configuration the benchmark times (BF16, two workgroups per CU), checked
-    on seeded sampled pixels against the FP64 oracle (BF16-emulating GEMMs)
-    given the same depth and ID buffers."""
+    """K = 8 deferred shading of the 1080p frame: the library's colours (of
+    its own depth and ID buffers) against the oracle shading its own refined
+    depth and IDs, on 256 seeded pixels; pixels whose ID or refined depth is
+    exempt in the depth parity are exempt here."""
     need_gpu()
-    from paper_2308_04669_amd import api
     models, insts, cam, _ = syn.config4_scene()
-    nedfs = [syn.nedf_model(4, 200 + k, head_scale=16.0) for k in range(len(models))]
-    log("case: batched scene 1920x1080, 1000 instances, BF16 shading K=8 on the frame's depth/ID")
-    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
-    rays = api.camera_rays(cam)
-    depth, ident = api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, n_samples=128)
-    rgb = api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, clear_rgb=(0.1, 0.2, 0.3), dtype="bf16")
-    depth, ident, rgb = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(rgb).astype(np.float64)
-    pix = syn.pixel_subset(4, cam.n_rays, 64)
-    o, d = camera_rays(cam, pix)
-    ref = shade_deferred(models, insts, o, d, depth[pix], ident[pix], K=8, h=0.05, clear=(0.1, 0.2, 0.3),
-                         gemm="bf16")
-    got = rgb[pix]
-    hit = ident[pix] >= 0
-    err = np.abs(got - ref).max(axis=1)
-    log(f"[batched shade bf16] pixels={len(pix)} hits={int(hit.sum())} max_err={err.max():.3e}")
-    assert hit.sum() >= len(pix) // 2
-    assert np.all(got[~hit] == np.array([0.1, 0.2, 0.3], np.float32))
+    nedfs = _nets(4, len(models))
+    log("case: batched scene 1920x1080, 1000 instances, BF16 shading K=8, 256 pixels")
+    gpu = _frame(models, nedfs, insts, cam, shade=True)
+    pix = syn.pixel_subset(4, cam.n_rays, N_PIX, stream=8)
+    o, d, orc, ref, chk = _depth_parity(models, nedfs, insts, cam, gpu, pix, "batched bf16 (shading)")
+    id_o = orc["id"]
+    rgb_o = shade_deferred(models, orc["recs"], o, d, np.where(id_o >= 0, ref, np.inf), id_o, K=8, h=0.05,
+                           clear=(0.1, 0.2, 0.3), gemm="bf16")
+    got = gpu["rgb"][pix]
+    sel = chk | ((id_o < 0) & (gpu["id"][pix] < 0) & ~_id_exempt(orc))
+    err = np.abs(got[sel] - rgb_o[sel]).max(axis=1)
+    log(f"[batched shade bf16] checked={int(sel.sum())} max_err={err.max():.3e} median_err={np.median(err):.3e}")
+    assert np.all(got[(id_o < 0) & sel] == np.array([0.1, 0.2, 0.3], np.float32))
     assert err.max() <= 2e-2
 
 
 def test_batched_scene_full_frame_shadow_sampled_parity():
-    """Shadow rays to the two lights of the 1080p, 1,000-instance frame (BF16
-    intersection networks with marcher fallback, occlusion-aware pruning),
-    checked on seeded sampled pixels against the FP64 oracle's composition
-    along each shadow ray.  Exempt: a decision within a BF16 band of a
-    threshold on an instance that could occlude, or an occluder depth within
-    a small band of the cut |L - x| - eps."""
+    """Shadow factors of the 1080p frame for its two lights (intersection-
+    network shadow rays with fallback and occlusion-aware pruning): the
+    library's factors against the oracle's shadow rays from the oracle's
+    own refined hit points, on 256 seeded pixels.  Exempt: the primary
+    pixel's ID or depth exempt, a shadow ray's own threshold bands, or an
+    occluder depth within the two tolerances (and ambiguities) of the cut
+    |L - x| - eps."""
     need_gpu()
-    from paper_2308_04669_amd import api
     models, insts, cam, lights = syn.config4_scene()
-    nedfs = [syn.nedf_model(4, 200 + k, head_scale=16.0) for k in range(len(models))]
+    nedfs = _nets(4, len(models))
     extent = syn.scene_extent(insts, [m.bound for m in models])
     eps = 0.01 * extent
-    log("case: batched scene 1920x1080, 1000 instances, BF16 shadow rays to 2 lights")
-    sc = gpu_scene(models, insts, "bf16", nedf_models=nedfs)
-    rays = api.camera_rays(cam)
-    depth, ident = api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, n_samples=128)
-    fac = api.shadow(sc, rays, depth, ident, lights, eps, beta=0.5, method="nedf", dtype="bf16", n_samples=128)
-    depth, ident, fac = _np(depth).astype(np.float64), _np(ident).astype(np.int64), _np(fac).astype(np.float64)
-    pix = syn.pixel_subset(4, cam.n_rays, 32, stream=9)
-    pix = pix[ident[pix] >= 0]
-    o, d = camera_rays(cam, pix)
-    x = o + depth[pix, None] * d
-    ref = np.ones(len(pix))
-    exempt = np.zeros(len(pix), bool)
+    log("case: batched scene 1920x1080, 1000 instances, BF16 shadow rays to 2 lights, 256 pixels")
+    gpu = _frame(models, nedfs, insts, cam, lights=lights, eps=eps)
+    pix = syn.pixel_subset(4, cam.n_rays, N_PIX, stream=9)
+    o, d, orc, ref, chk = _depth_parity(models, nedfs, insts, cam, gpu, pix, "batched bf16 (shadow)")
+    hp = np.nonzero(chk)[0]
+    x = o[hp] + ref[hp, None] * d[hp]
+    fac_o = np.ones(len(hp))
+    exempt = np.zeros(len(hp), bool)
     for L in np.asarray(lights, np.float64).reshape(-1, 3):
         v = x - L
         dist = np.linalg.norm(v, axis=1)
         ds = v / dist[:, None]
-        os_ = np.broadcast_to(L, ds.shape).copy()
+        so = np.broadcast_to(L, ds.shape).copy()
         cut = dist - eps
-        # instances entered beyond the cut (plus the exemption band) cannot occlude
-        cands = _candidates_sparse(models, nedfs, insts, os_, ds, 128, t_max=cut + 5e-3 * max(i.s for i in insts))
-        best = np.full(len(pix), np.inf)
-        near = np.zeros(len(pix), bool)
-        for k, hit, D, p, path, A, t_in in cands:
-            best = np.minimum(best, np.where(hit, D, np.inf))
-            flip = (np.abs(p - 0.2) <= 2e-2) | (np.abs(p - 0.8) <= 2e-2) | (np.abs(A - 0.5) <= 2e-2)
-            near |= flip & (t_in <= cut + 5e-3 * insts[k].s)
-            near |= hit & (np.abs(D - cut) <= 5e-3 * insts[k].s)
-        occl = best < cut
-        ref = np.where(occl, ref * 0.5, ref)
-        exempt |= near
-    bad = (fac[pix] != ref) & ~exempt
-    log(f"[batched shadow bf16] pixels={len(pix)} shadowed={int((ref < 1).sum())} exempt={int(exempt.sum())} "
+        sh = pruned_oracle(models, nedfs, insts, so, ds, t_max=cut)
+        occl = sh["best"] < cut
+        fac_o = np.where(occl, fac_o * 0.5, fac_o)
+        exempt |= _id_exempt(sh) & (sh["best"] <= cut + 0.5)
+        exempt |= np.abs(sh["best"] - cut) <= 2 * TOL + sh["amb"]
+    got = gpu["fac"][pix][hp]
+    bad = (got != fac_o) & ~exempt
+    log(f"[batched shadow bf16] pixels={len(hp)} shadowed={int((fac_o < 1).sum())} exempt={int(exempt.sum())} "
         f"mismatch={int(bad.sum())}")
-    assert len(pix) >= 12 and bad.sum() == 0
-    assert exempt.sum() <= len(pix) // 3
+    assert len(hp) >= 64 and bad.sum() == 0
+    assert exempt.sum() <= 0.1 * len(hp)
 
 
 def test_precision_scene_fp8_refine_sampled_parity():
     """The precision-stress configuration at full size: 64 instances at
     3840 x 2160, FP8 intersection networks (per-layer scales from the
-    oracle's calibration), BF16 fallback and 3-step secant refinement on the
-    BF16 density field, checked on seeded sampled pixels against the FP64
-    oracle emulating the same FP8/BF16 roundings."""
+    oracle's calibration), bfloat16 fallback and 3-step secant refinement on
+    the bfloat16 density field, on 256 seeded pixels against the oracle
+    emulating the same E4M3/bfloat16 roundings: IDs bit-exact outside
+    near-ties and bands, refined depths within 5e-3 scene units."""
     need_gpu()
     from paper_2308_04669_amd import api
-    from oracle import fp8_calibrate, to_local
+    from oracle import fp8_calibrate
     models, insts, cam, _ = syn.config5_scene()
-    nedfs = [syn.nedf_model(5, 200 + k, head_scale=16.0) for k in range(len(models))]
+    nedfs = _nets(5, len(models))
     cal_o, cal_d = syn.training_rays(5, 2, 8192)
     scales = [fp8_calibrate(n, cal_o.astype(np.float64), cal_d.astype(np.float64)) for n in nedfs]
-    log("case: precision scene 3840x2160, 64 instances, FP8 networks + BF16 fallback + refinement")
+    log("case: precision scene 3840x2160, 64 instances, FP8 networks + BF16 fallback + refinement, 256 pixels")
     objs = [api.object_from_model(m, "bf16", nedf_model=n, nedf_dtype="fp8", nedf_scales=sc_.reshape(-1))
             for m, n, sc_ in zip(models, nedfs, scales)]
-    sc = api.make_scene(objs, insts)
-    depth, ident = api.infer_depth_id(sc, api.camera_rays(cam), dtype="bf16", refine_steps=3, n_samples=128)
-    depth, ident = _np(depth).astype(np.float64), _np(ident).astype(np.int64)
-    pix = syn.pixel_subset(5, cam.n_rays, 48)
-    o, d = camera_rays(cam, pix)
-    n = len(pix)
-    Ds, ks, flips = [], [], np.zeros(n, bool)
-    for k, inst in enumerate(insts):
-        o_l, d_l = to_local(inst, o, d)
-        if not np.any(np.linalg.norm(np.cross(o_l, d_l), axis=-1) < models[inst.model].bound):
-            continue
-        hit, D, p, path = nedf_pair(nedfs[inst.model], models[inst.model], inst, o, d, n_samples=128,
-                                    gemm="bf16", net_scales=[tuple(x) for x in scales[inst.model]])
-        A = np.full(n, np.nan)
-        fb = np.nonzero(path == 1)[0]
-        if fb.size:
-            _, A[fb], _ = march_instance(models[inst.model], inst, o[fb], d[fb], 128, None, "bf16")
-        flips |= (np.abs(p - 0.2) <= 0.08) | (np.abs(p - 0.8) <= 0.08) | (np.abs(A - 0.5) <= 0.02)
-        Ds.append(np.where(hit, D, np.inf))
-        ks.append(k)
-    Ds, ks = np.array(Ds), np.array(ks)
-    best = Ds.min(axis=0)
-    id_o = np.where(np.isfinite(best), ks[Ds.argmin(axis=0)], -1)
-    ref = best.copy()
-    for k in np.unique(id_o[id_o >= 0]):
-        sel = np.nonzero(id_o == k)[0]
-        inst = insts[k]
-        ref[sel] = secant_refine(models[inst.model], inst, o[sel], d[sel], best[sel], h=0.05, steps=3, gemm="bf16")
-    srt = np.sort(Ds, axis=0)
-    gap = np.where(np.isfinite(srt[1]), srt[1] - np.where(np.isfinite(srt[0]), srt[0], 0), np.inf)
-    s_win = np.array([insts[k].s if k >= 0 else 1.0 for k in id_o])
-    exempt = flips | (gap <= 5e-2 * s_win)
-    ig = ident[pix]
-    bad = (ig != id_o) & ~exempt
-    both = (ig == id_o) & (id_o >= 0)
-    err = np.abs(depth[pix][both] - ref[both]) / s_win[both]
-    log(f"[precision fp8+refine] pixels={n} hits={int((id_o >= 0).sum())} exempt={int(exempt.sum())} "
-        f"id_mismatch={int(bad.sum())} med_err_local={np.median(err):.2e} max_err_local={err.max():.2e}")
-    assert (id_o >= 0).sum() >= n // 4
-    assert bad.sum() <= max(1, n // 50)
-    # E4M3 keeps 3 mantissa bits; refinement pulls both sides onto the same iso-surface
-    assert np.median(err) <= 5e-3 and np.quantile(err, 0.95) <= 5e-2
+    gpu = _frame(models, nedfs, insts, cam, objs=objs)
+    pix = syn.pixel_subset(5, cam.n_rays, N_PIX)
+    _depth_parity(models, nedfs, insts, cam, gpu, pix, "precision fp8+refine", scales=scales)
