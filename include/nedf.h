@@ -294,6 +294,25 @@ int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, cons
                             float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream);
 
 /*
+ * nedf_infer_depth_id for callers that cannot allocate device memory (code
+ * under HIP graph capture, fixed-memory serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, with the workspace taken
+ * from a fixed device array of nedf_static_scratch_bytes() (64 MiB) that
+ * every GPU the library runs on holds until the process ends.  The caller
+ * still passes inputs and outputs.  A call whose worst case, every ray
+ * meeting every instance (nedf_workspace_size(NEDF_OP_INFER, scene, rays, 0)
+ * bytes), exceeds the array is rejected with NEDF_ERR_WORKSPACE before any
+ * work, so no pair list can overflow.  Calls no hipMalloc or hipFree and
+ * records no profiling events.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (several streams or host threads)
+ * race; calls in sequence on a stream do not (each clears what it uses).
+ */
+int32_t nedf_infer_depth_id_static(const nedf_scene* scene, const nedf_rays* rays,
+                                   const nedf_infer_opts* opts, float* depth, int32_t* id,
+                                   nedf_stream_t stream);
+size_t nedf_static_scratch_bytes(void);
+
+/*
  * Deferred shading (Eq. 8, Alg. 1 step 2): every pixel with a valid id is
  * shaded by its object's NeRF colour branch at K samples around its depth,
  * composited locally (K = 1 is the single evaluation of Eq. 8); pixels

@@ -99,6 +99,9 @@ SIGNATURES = [
     ("nedf_ws_counters", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
     ("nedf_infer_depth_id", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(InferOpts), C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nedf_infer_depth_id_static", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(InferOpts),
+                                               C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("nedf_static_scratch_bytes", C.c_size_t, []),
     ("nedf_shade_deferred", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p,
                                         C.POINTER(ShadeOpts), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("nedf_shadow", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p, C.c_void_p,

@@ -303,6 +303,26 @@ def infer_depth_id(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_lo: flo
     return depth, ident
 
 
+def infer_depth_id_static(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_lo: float = 0.2, p_hi: float = 0.8,
+                          refine_steps: int = 3, refine_h: float = 0.05, n_samples: int = 128, out=None):
+    """``infer_depth_id`` through the entry point that takes no workspace and
+    allocates nothing on the device (a fixed per-GPU scratch array); ``out``
+    (depth, ident) lets the caller provide the outputs too."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    if out is None:
+        depth = torch.empty(n, dtype=torch.float32, device=dev)
+        ident = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        depth, ident = out
+    sc = scene.struct()
+    opts = infer_opts(dtype, p_lo, p_hi, refine_steps, refine_h, n_samples)
+    A.check(lib.nedf_infer_depth_id_static(C.byref(sc), C.byref(rays), C.byref(opts), _ptr(depth), _ptr(ident),
+                                           _stream()), "nedf_infer_depth_id_static")
+    return depth, ident
+
+
 def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, K: int = 8,
                    h: float = 0.05, clear_rgb=(0.0, 0.0, 0.0), dtype: str = "bf16", ws: Workspace | None = None,
                    out: torch.Tensor | None = None, pair_capacity: int = 0) -> torch.Tensor:

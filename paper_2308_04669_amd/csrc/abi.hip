@@ -60,10 +60,14 @@ hipEvent_t prof_event() {
 }
 }  // namespace
 
-bool prof_on() { return g_prof_on; }
+// Set while a fixed-memory entry point runs on this thread: it records no
+// profiling events (creating them could allocate).
+thread_local bool g_prof_suppress = false;
+
+bool prof_on() { return g_prof_on && !g_prof_suppress; }
 
 void prof_mark(const char* name, void* stream, bool begin) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || g_prof_suppress) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<size_t>& open = g_prof_open[stream];
@@ -449,8 +453,9 @@ extern "C" int32_t nedf_march_depth(const nedf_scene* scene, const nedf_rays* ra
   return NEDF_OK;
 }
 
-extern "C" int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
-                                       float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream) {
+namespace {
+int32_t infer_impl(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts, float* depth,
+                   int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream, const char* who) {
   int32_t st = check_infer_opts(opts);
   if (st) return st;
   Prepared P;
@@ -472,8 +477,69 @@ extern "C" int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays*
   P.k.id = id;
   run_infer(P, opts->dtype, *opts, static_cast<hipStream_t>(stream));
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "nedf_infer_depth_id");
+  if (e != hipSuccess) return hip_fail(e, who);
   return NEDF_OK;
+}
+}  // namespace
+
+extern "C" int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                                       float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream) {
+  return infer_impl(scene, rays, opts, depth, id, ws, ws_bytes, stream, "nedf_infer_depth_id");
+}
+
+// ---- fixed-memory variant -----------------------------------------------------
+// The workspace of nedf_infer_depth_id_static: a file-scope device array, one
+// copy on every GPU the library runs on, held until the process ends.  Host
+// code never passes the array's name to a kernel (in host code it is a
+// host-side stand-in); it looks up each device's address once, with that
+// device current, and uses that pointer.
+constexpr size_t NEDF_STATIC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[NEDF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int32_t scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "nedf_infer_depth_id_static: hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(NEDF_ERR_UNSUPPORTED, "nedf_infer_depth_id_static: device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                               "nedf_infer_depth_id_static: hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NEDF_OK;
+}
+}  // namespace
+
+extern "C" size_t nedf_static_scratch_bytes(void) { return NEDF_STATIC_SCRATCH_BYTES; }
+
+extern "C" int32_t nedf_infer_depth_id_static(const nedf_scene* scene, const nedf_rays* rays,
+                                              const nedf_infer_opts* opts, float* depth, int32_t* id,
+                                              nedf_stream_t stream) {
+  if (!scene || !rays) return fail(NEDF_ERR_NULL, "nedf_infer_depth_id_static: NULL scene or rays");
+  // the worst case (every ray meets every instance) must fit, so that no
+  // pair list can overflow
+  const size_t need = nedf_workspace_size(NEDF_OP_INFER, scene, rays, 0);
+  if (need == 0) return NEDF_ERR_NULL;
+  if (need > NEDF_STATIC_SCRATCH_BYTES)
+    return fail(NEDF_ERR_WORKSPACE, "nedf_infer_depth_id_static: n_rays x n_instances pairs need " +
+                                        std::to_string(need) + " bytes of workspace, beyond the fixed " +
+                                        std::to_string(NEDF_STATIC_SCRATCH_BYTES) + " (use nedf_infer_depth_id)");
+  void* ws = nullptr;
+  int32_t st = scratch_of_current_device(&ws);
+  if (st) return st;
+  g_prof_suppress = true;
+  st = infer_impl(scene, rays, opts, depth, id, ws, NEDF_STATIC_SCRATCH_BYTES, stream, "nedf_infer_depth_id_static");
+  g_prof_suppress = false;
+  return st;
 }
 
 extern "C" int32_t nedf_shade_deferred(const nedf_scene* scene, const nedf_rays* rays, const float* depth,

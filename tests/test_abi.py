@@ -110,3 +110,25 @@ def test_tuning_table_host_logic():
     rep = A.TuneReport()
     # NULL arguments and a bad repetition count are rejected before any launch
     assert lib.nedf_autotune(1, 1, None, None, None, None, None, None, 0, 1, None, C.byref(rep)) == 1
+
+
+def test_static_entry_point_rejects_oversized_calls_on_the_host():
+    """The fixed-memory entry point rejects a call whose worst-case pair list
+    (every ray meeting every instance) exceeds its 64 MiB scratch, before
+    any device work (so this runs without a GPU)."""
+    from paper_2308_04669_amd import _abi as A
+    lib = A.load()
+    assert lib.nedf_static_scratch_bytes() == 64 << 20
+    sc = A.Scene()
+    sc.n_objects = 1
+    sc.n_inst = 1000
+    rays = A.Rays()
+    rays.kind = 0
+    rays.camera.width, rays.camera.height = 1920, 1080
+    rays.camera.fov_y_deg = 40.0
+    rays.camera.at[2] = -1.0
+    rays.camera.up[1] = 1.0
+    opts = A.InferOpts()
+    st = lib.nedf_infer_depth_id_static(C.byref(sc), C.byref(rays), C.byref(opts), None, None, None)
+    assert st == 5  # NEDF_ERR_WORKSPACE
+    assert b"64" in lib.nedf_last_error() or b"67108864" in lib.nedf_last_error()
