@@ -95,7 +95,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="frame", choices=["frame", "marcher", "precision"])
+    p.add_argument("--workload", default="frame", choices=["frame", "marcher", "precision", "nedf"])
     p.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
     # frame workload
     p.add_argument("--width", type=int, default=1920)
@@ -112,6 +112,9 @@ def parse():
     p.add_argument("--samples", type=int, default=192)
     p.add_argument("--size", type=int, default=800)
     p.add_argument("--f32-steps", type=int, default=2)
+    # intersection-network workload
+    p.add_argument("--labels", type=int, default=10_000_000)
+    p.add_argument("--quality-pixels", type=int, default=4096)
     # oracle baseline and counters
     p.add_argument("--cpu-pixels", type=int, default=0, help="0: the workload's default sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -588,6 +591,138 @@ def marcher_bench(args):
     return line
 
 
+# ---------------------------------------------------------------------------
+# intersection-network workload (one object at a time)
+# ---------------------------------------------------------------------------
+
+def nedf_bench(args):
+    """Density A (analytic sphere) and B' (density B masked to |x| <= 1), one
+    at a time: 10 M labels per object from the library's FP32 marcher (128
+    samples on the bounding chord; origins on the sphere of radius 4 aimed
+    into the ball of radius 1.2), training of the intersection network
+    (batch 65,536, bfloat16 matrix cores, float32 master weights, Adam with a
+    cosine learning rate), then the 800 x 800 view of the config-1 camera:
+    BF16 network + marcher fallback for p in [0.2, 0.8] + 3-step refinement
+    (A; B' has no surface to refine) against the plain FP32 marcher on the
+    same view, and the depth quality against the FP64 oracle marcher on a
+    seeded pixel subset (hit agreement, median depth error / scene extent)."""
+    import torch
+    import synthetic as syn
+    from oracle import camera_rays, march_compose
+    from paper_2308_04669_amd import api
+
+    a, b = syn.config1_models()
+    bp = syn.Model(kind=b.kind, bound=1.0, trunk=b.trunk, params=dict(b.params, masked=True))
+    ident = syn.Instance(model=0, R=np.eye(3), T=np.zeros(3), s=1.0)
+    cam = syn.config1_camera(args.size, args.size)
+    n = cam.n_rays
+    extent = syn.scene_extent([ident], [1.0])
+    B = args.train_batch
+    per, tot_px, tot_s, tot_m = {}, 0, 0.0, 0.0
+    train_ms, train_steps = 0.0, 0
+    for k, (name, m) in enumerate((("A", a), ("B'", bp))):
+        sc_l = api.make_scene([api.object_from_model(m, "f32")], [ident])
+        n_lab = args.labels // B * B
+        o, d = syn.training_rays(3, 300 + k, n_lab)
+        ot, dt = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+        del o, d
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        depth, idn, _ = api.march_depth(sc_l, api.array_rays(ot, dt), n_samples=128, dtype="f32", opacity=False,
+                                        ws=api.Workspace())
+        hit = (idn >= 0).to(torch.uint8)
+        depth = torch.where(idn >= 0, depth, torch.zeros_like(depth))
+        torch.cuda.synchronize()
+        t_label = time.perf_counter() - t0
+        init = syn.nedf_model(3, 200 + k)
+        tr = api.Trainer(init.trunk.W, init.trunk.b, enc_L=init.params["enc_L"])
+        nb = n_lab // B
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for it in range(args.train_steps):
+            j = it % nb
+            lr = 5e-5 + 0.5 * (5e-4 - 5e-5) * (1.0 + math.cos(math.pi * it / max(args.train_steps, 1)))
+            loss = tr.step(ot[j * B:(j + 1) * B], dt[j * B:(j + 1) * B], depth[j * B:(j + 1) * B],
+                           hit[j * B:(j + 1) * B], lr=lr, bound=m.bound)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_train = e0.elapsed_time(e1)
+        train_ms += ms_train
+        train_steps += args.train_steps
+        W_, b_ = tr.export(0)
+        net = syn.Model(kind="nedf", bound=1.0, params=dict(enc_L=init.params["enc_L"]),
+                        trunk=syn.MLPWeights([w.astype(np.float32) for w in W_], [x.astype(np.float32) for x in b_]))
+        del ot, dt, depth, idn, hit
+        # the view: intersection network path and the plain FP32 marcher
+        sc = api.make_scene([api.object_from_model(m, "bf16", nedf_model=net)], [ident])
+        sc32 = api.make_scene([api.object_from_model(m, "f32")], [ident])
+        rays = api.camera_rays(cam)
+        ws = api.Workspace()
+        dep = torch.empty(n, dtype=torch.float32, device="cuda")
+        idt = torch.empty(n, dtype=torch.int32, device="cuda")
+        for _ in range(args.warmup):
+            api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, ws=ws, out=(dep, idt))
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            api.infer_depth_id(sc, rays, dtype="bf16", refine_steps=3, ws=ws, out=(dep, idt))
+        e1.record()
+        torch.cuda.synchronize()
+        ms_nedf = e0.elapsed_time(e1) / args.steps
+        st = api.ws_counters(ws)
+        ws32 = api.Workspace()
+        api.march_depth(sc32, rays, n_samples=128, dtype="f32", ws=ws32)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.f32_steps):
+            api.march_depth(sc32, rays, n_samples=128, dtype="f32", ws=ws32)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_march = e0.elapsed_time(e1) / args.f32_steps
+        # quality against the FP64 oracle marcher
+        pix = syn.pixel_subset(3, n, args.quality_pixels, stream=11 + k)
+        o_q, d_q = camera_rays(cam, pix)
+        ref_d, ref_id, _ = march_compose([m], [ident], o_q, d_q, 128)
+        g_d = dep.cpu().numpy()[pix].astype(np.float64)
+        g_id = idt.cpu().numpy()[pix]
+        both = (g_id >= 0) & (ref_id >= 0)
+        err = np.abs(g_d[both] - ref_d[both])
+        evald = max(st["nedf_hits"] + st["fallback"] + st["nedf_misses"], 1)
+        per[name] = {
+            "label_rays": n_lab, "label_s": t_label, "train_steps": args.train_steps,
+            "train_ms_per_step": ms_train / args.train_steps, "loss_last": float(loss[0]),
+            "nedf_ms": ms_nedf, "nedf_rays_per_s": n / (ms_nedf * 1e-3),
+            "fp32_marcher_ms": ms_march, "fp32_marcher_rays_per_s": n / (ms_march * 1e-3),
+            "vs_fp32_marcher": ms_march / ms_nedf,
+            "fallback_frac": st["fallback"] / evald,
+            "quality": {"pixels": int(len(pix)), "reference": "FP64 oracle marcher, 128 samples on the chord",
+                        "hit_agreement": float(np.mean((g_id >= 0) == (ref_id >= 0))),
+                        "median_depth_err_frac_extent": float(np.median(err)) / extent if err.size else 0.0,
+                        "p99_depth_err_frac_extent": float(np.quantile(err, 0.99)) / extent if err.size else 0.0,
+                        "extent": extent}}
+        log(f"nedf {name}: {per[name]}")
+        tot_px += n
+        tot_s += ms_nedf * 1e-3
+        tot_m += ms_march * 1e-3
+    ms_step = train_ms / max(train_steps, 1)
+    flop_step = 3.0 * 2.0 * MAC_NEDF * B
+    return {
+        "metric": METRIC, "value": tot_px / tot_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * tot_s / 2, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (config-1 densities; intersection networks trained in setup on the library's own "
+                "FP32 marcher labels)",
+        "config": {"workload": f"intersection networks of density A and B' (masked), one object each, "
+                               f"{args.size}x{args.size} config-1 view, BF16 network + fallback [0.2, 0.8] + "
+                               f"3-step refinement; {args.labels} labels per object, {args.train_steps} Adam "
+                               f"steps of {B}"},
+        "vs_fp32_marcher": tot_m / tot_s,
+        "training": {"ms_per_step": ms_step, "batch": B, "tflops": flop_step / (ms_step * 1e-3) / 1e12,
+                     "roofline_frac": flop_step / (ms_step * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"]},
+        "objects": per,
+    }
+
+
 def marcher_cpu_baseline(n_pixels: int, n_samples: int, size: int):
     """FP64 oracle marcher on a seeded pixel subset of the same frame."""
     import synthetic as syn
@@ -618,6 +753,9 @@ def main():
         line, ctx = frame_bench(args)
     elif args.workload == "precision":
         line, ctx = precision_bench(args), None
+        args.no_cpu_baseline = True
+    elif args.workload == "nedf":
+        line, ctx = nedf_bench(args), None
         args.no_cpu_baseline = True
     else:
         line, ctx = marcher_bench(args), None

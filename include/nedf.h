@@ -359,7 +359,7 @@ int32_t nedf_train_init(const nedf_mlp_shape* shape, const float* const* W, cons
                         void* state, size_t state_bytes, nedf_stream_t stream);
 
 /*
- * One training step on B local rays (B a multiple of 64): forward pass in
+ * One training step on B local rays (B a multiple of 256): forward pass in
  * bfloat16 on the matrix cores with float32 accumulation, loss
  *   L = (1/B) sum_i [alpha_i (mu_hat_i - mu*_i)^2 + w_hit BCEwithLogits(z_i, alpha_i)]
  * with mu* = (t_perp - depth_label) / bound and alpha = hit_label (Eq. 6,
@@ -388,7 +388,7 @@ size_t nedf_fp8_calibrate_workspace_size(const nedf_mlp_shape* shape, int32_t B)
 /*
  * Per-layer E4M3 scales of a network (width 256, n_out 2): a bfloat16 forward
  * pass over B calibration rays (o_l, d_l device float32 [B][3], B a multiple
- * of 64) records the largest |activation| entering every hidden layer; the
+ * of 256) records the largest |activation| entering every hidden layer; the
  * weight scale is the largest |weight| of that layer.  scales (device float32
  * [2 n_hidden]) receives {w_scale, a_scale} = amax / 448 per hidden layer,
  * the layout nedf_pack_mlp expects for NEDF_FP8 (after a copy to the host).

@@ -744,7 +744,7 @@ extern "C" int32_t nedf_train_step(const nedf_mlp_shape* shape, void* state, con
   if (st) return st;
   if (!state || !o_l || !d_l || !depth_label || !hit_label || !opts || !loss_out || !ws)
     return fail(NEDF_ERR_NULL, "nedf_train_step: NULL argument");
-  if (B <= 0 || B % 64 != 0) return fail(NEDF_ERR_SHAPE, "batch must be a positive multiple of 64");
+  if (B <= 0 || B % 256 != 0) return fail(NEDF_ERR_SHAPE, "batch must be a positive multiple of 256");
   if (!aligned16(state) || !aligned16(o_l) || !aligned16(d_l) || !aligned16(depth_label) || !aligned16(ws))
     return fail(NEDF_ERR_ALIGN, "nedf_train_step: misaligned pointer");
   if (ws_bytes < train_ws_bytes(*shape, B)) return fail(NEDF_ERR_WORKSPACE, "workspace smaller than nedf_train_workspace_size()");
@@ -784,7 +784,7 @@ extern "C" int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* 
   int32_t st = check_train_shape(shape);
   if (st) return st;
   if (!W || !b || !o_l || !d_l || !scales || !ws) return fail(NEDF_ERR_NULL, "nedf_fp8_calibrate: NULL argument");
-  if (B <= 0 || B % 64 != 0) return fail(NEDF_ERR_SHAPE, "calibration batch must be a positive multiple of 64");
+  if (B <= 0 || B % 256 != 0) return fail(NEDF_ERR_SHAPE, "calibration batch must be a positive multiple of 256");
   if (!aligned16(ws) || !aligned16(o_l) || !aligned16(d_l)) return fail(NEDF_ERR_ALIGN, "nedf_fp8_calibrate: misaligned pointer");
   if (ws_bytes < fp8_calibrate_ws_bytes(*shape, B)) return fail(NEDF_ERR_WORKSPACE, "workspace smaller than nedf_fp8_calibrate_workspace_size()");
   hipError_t e = launch_fp8_calibrate(*shape, W, b, o_l, d_l, B, scales, static_cast<uint8_t*>(ws),

@@ -3,6 +3,7 @@
 // (inverse of Eq. 2), bfloat16 matrix-core GEMMs with fused epilogues for the
 // forward pass, the ReLU-masked data gradients and split-K weight gradients,
 // the head + loss kernel and Adam on float32 master weights.
+#include <algorithm>
 #include <cstring>
 
 #include "device_common.h"
@@ -20,38 +21,49 @@ __device__ __forceinline__ float bf16_val(uint16_t u) { return __uint_as_float(u
 // ---- input encoding and labels ------------------------------------------------
 // Features in natural order [p, sin(2^0 pi p), cos(2^0 pi p), ...] of the
 // Pluecker (d, o x d) or xyz input, zero padded to Kpad; labels
-// mu* = (t_perp - D) / l and alpha = hit.
+// mu* = (t_perp - D) / l and alpha = hit.  One thread per sample and group
+// of 8 features (one 16-byte store; a sample's row is written by
+// consecutive threads).
 __global__ void k_train_encode(const float* o_l, const float* d_l, const float* depth, const uint8_t* hit,
                                int B, int in_kind, int L, int Kpad, float bound, uint16_t* H, float* mu,
                                float* alpha) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int groups = Kpad / 8;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = tid / groups, grp = tid % groups;
   if (s >= B) return;
   const float o[3] = {o_l[3 * s], o_l[3 * s + 1], o_l[3 * s + 2]};
   const float d[3] = {d_l[3 * s], d_l[3 * s + 1], d_l[3 * s + 2]};
-  float p[6], plo[6] = {0, 0, 0, 0, 0, 0};
+  float p[6], plo[6] = {0, 0, 0, 0, 0, 0}, tperp = 0.0f;
   int n;
   if (in_kind == NEDF_IN_PLUECKER) {
     n = 6;
-    float tp;
-    line_of_local(o, d, p, plo, tp);
+    line_of_local(o, d, p, plo, tperp);
   } else {
     n = 3;
+    float pl[6], pllo[6];
+    line_of_local(o, d, pl, pllo, tperp);
     p[0] = o[0]; p[1] = o[1]; p[2] = o[2];
   }
-  uint16_t* row = H + size_t(s) * Kpad;
-  for (int f = 0; f < Kpad; ++f) {
-    float v = 0.0f;
-    if (f < n) {
-      v = p[f];
-    } else if (f < n * (1 + 2 * L)) {
-      const int q = f - n, level = q / (2 * n), w = q % (2 * n), c = w % n;
-      v = sinpi_hw(float(1 << level) * p[c], float(1 << level) * plo[c], w >= n ? 1 : 0);
+  uint32_t packed[4];
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    float v2[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int f = 8 * grp + e + u;
+      float v = 0.0f;
+      if (f < n) {
+        v = p[f];
+      } else if (f < n * (1 + 2 * L)) {
+        const int q = f - n, level = q / (2 * n), w = q % (2 * n), c = w % n;
+        v = sinpi_hw(float(1 << level) * p[c], float(1 << level) * plo[c], w >= n ? 1 : 0);
+      }
+      v2[u] = v;
     }
-    row[f] = bf16_bits(v);
+    packed[e / 2] = uint32_t(bf16_bits(v2[0])) | (uint32_t(bf16_bits(v2[1])) << 16);
   }
-  if (!depth) return;  // calibration: no labels
-  float pl[6], pllo[6], tperp;
-  line_of_local(o, d, pl, pllo, tperp);
+  *reinterpret_cast<uint4*>(H + size_t(s) * Kpad + 8 * grp) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  if (!depth || grp != 0) return;  // calibration: no labels
   const bool h = hit[s] != 0;
   alpha[s] = h ? 1.0f : 0.0f;
   mu[s] = h ? (tperp - depth[s]) / bound : 0.0f;
@@ -85,143 +97,386 @@ __global__ void k_fp8_scales(const uint32_t* amax_w, const uint32_t* amax_a, int
 }
 
 // ---- GEMM ---------------------------------------------------------------------
-// C[M][N] = A[M][K] B[K][N] on 32x32x16 bf16 matrix cores, 64x64 tile per
-// workgroup (4 waves, 32x32 each), K tiles of 32 staged in LDS with K
-// contiguous.  AT: 0 A stored [M][K], 1 stored [K][M].  BT: 0 B stored
-// [K][N], 1 stored [N][K].  Split-K over blockIdx.z.
+// C[M][N] = sum_k A(m, k) B(n, k) on 32x32x16 bf16 matrix cores with float32
+// accumulation.  A workgroup computes a 128 x BN tile (BN = 128 or 256) with
+// one wave per 64 x 64 block (2 x 2 blocks of 32 x 32); K runs in stages of
+// 64, staged in LDS as [row][k] (k contiguous; rows padded to 72 elements, so
+// that the 16-byte fragment reads of a wave's 16-lane groups fall on distinct
+// banks) and double-buffered.  Global loads run two stages ahead of the
+// matrix cores (two register sets), so a stage's loads have two stages of
+// multiplies to arrive in.  An operand is stored either k-contiguous (KC:
+// X[row][k], copied 16 bytes at a time) or row-contiguous (RC: X[k][row],
+// loaded as 8 x 8 blocks and transposed in registers by byte permutes on the
+// way to LDS; only with BN = 128).  bfloat16 outputs go through LDS after the
+// last stage and leave as whole 16-byte row pieces.  M is a multiple of 128,
+// N of BN and K of 64 per split.
+enum { KC = 0, RC = 1 };
+constexpr int GT_BM = 128, GT_BK = 64, GT_LD = 72;  // rows per tile, K stage, LDS row stride (bf16)
+
 struct GemmArgs {
   const uint16_t* A;
   const uint16_t* B;
   int M, N, K, lda, ldb;
   int k_per_split;
   // epilogue
-  const float* bias;     // EPI 0
-  const uint16_t* mask;  // EPI 1 ([M][ldm] bf16, > 0 keeps)
+  const float* bias;     // EPI 0: out16 = relu(acc + bias[col])
+  const uint16_t* mask;  // EPI 1: out16 = acc * (mask[row][col] > 0), mask [M][ldm]
   int ldm;
   uint16_t* out16;       // EPI 0/1 [M][ldo]
-  float* out32;          // EPI 2 [M][ldo] (atomic add), columns < n_valid
-  int ldo, n_valid;
+  float* part;           // EPI 2: part[split][M][N] float32
+  float* colsum;         //        colsum[split][M] (A is RC: sums over k of A(m, k))
+  int ldo;
 };
 
-constexpr int GT_BM = 64, GT_BN = 64, GT_BK = 32, GT_LD = 40;  // LDS row stride (bf16), 80 bytes
+// 8 x 8 transpose of bfloat16: v[j] holds 8 consecutive rows at k = j; w[r]
+// gets the 8 values of row r in k order.
+__device__ __forceinline__ void transpose8x8(const uint4 (&v)[8], uint4 (&w)[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t sel = (r & 1) ? 0x07060302u : 0x05040100u;
+    uint32_t d[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const uint32_t lo = reinterpret_cast<const uint32_t*>(&v[2 * p])[r >> 1];
+      const uint32_t hi = reinterpret_cast<const uint32_t*>(&v[2 * p + 1])[r >> 1];
+      d[p] = __builtin_amdgcn_perm(hi, lo, sel);
+    }
+    w[r] = make_uint4(d[0], d[1], d[2], d[3]);
+  }
+}
 
-template <int AT, int BT, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[GT_BM * GT_LD];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[GT_BN * GT_LD];
+// Register staging of one operand's stage (ROWS rows x 64 k) by NT threads.
+template <int LAYOUT, int ROWS, int NT>
+struct Stage;
+// Staging registers are plain 4 x 32-bit vectors (not the HIP vector
+// classes, which the compiler keeps in memory here).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int ROWS, int NT>
+struct Stage<KC, ROWS, NT> {
+  static constexpr int PER = ROWS * 8 / NT;  // 16-byte chunks per thread
+  u32x4 v[PER];
+  // chunk c = t + NT i: row c / 8, k 8 (c % 8)
+  __device__ __forceinline__ void load(const uint16_t* X, int ld, int row0, int k0, int t, bool) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = t + NT * i;
+      v[i] = *reinterpret_cast<const u32x4*>(X + size_t(row0 + (c >> 3)) * ld + k0 + 8 * (c & 7));
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t* S, int t, bool, float*) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = t + NT * i;
+      *reinterpret_cast<u32x4*>(S + (c >> 3) * GT_LD + 8 * (c & 7)) = v[i];
+    }
+  }
+};
+template <int ROWS, int NT>
+struct Stage<RC, ROWS, NT> {
+  // block b of ROWS: rows 8 (b % (ROWS / 8)), k 8 (b / (ROWS / 8)); one
+  // block per thread of the operand's half of the workgroup
+  static constexpr int RB = ROWS / 8;
+  uint4 v[8];
+  __device__ __forceinline__ void load(const uint16_t* X, int ld, int row0, int k0, int b, bool mine) {
+    if (!mine) return;
+    const int rb = b % RB, kb = b / RB;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      v[j] = *reinterpret_cast<const uint4*>(X + size_t(k0 + 8 * kb + j) * ld + row0 + 8 * rb);
+  }
+  __device__ __forceinline__ void store(uint16_t* S, int b, bool mine, float* colsum8) const {
+    if (!mine) return;
+    const int rb = b % RB, kb = b / RB;
+    uint4 w[8];
+    transpose8x8(v, w);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      *reinterpret_cast<uint4*>(S + (8 * rb + r) * GT_LD + 8 * kb) = w[r];
+      if (colsum8) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(&w[r]);
+        float s = 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s += __uint_as_float(q[e] << 16) + __uint_as_float(q[e] & 0xFFFF0000u);
+        colsum8[r] += s;
+      }
+    }
+  }
+};
+
+template <int AL, int BL, int EPI, bool COLSUM, int BN>
+__global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
+  constexpr int NT = BN * 2;            // threads: (128 / 64) x (BN / 64) waves
+  constexpr int WN = BN / 64;           // waves along N
+  constexpr int SA = GT_BM * GT_LD, SB = BN * GT_LD;
+  static_assert(AL == KC || BN == 128, "row-contiguous operands need BN = 128");
+  static_assert(BL == KC || BN == 128, "row-contiguous operands need BN = 128");
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * (SA + SB)];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.x * GT_BM, n0 = blockIdx.y * GT_BN;
+  const int wm = wave / WN, wn = wave % WN;
+  const int m0 = blockIdx.x * GT_BM, n0 = blockIdx.y * BN;
   const int kb = blockIdx.z * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
-  f32x16_t acc = {};
-  for (int k0 = kb; k0 < ke; k0 += GT_BK) {
-    // A tile -> As[m][k]
-    if (AT == 0) {
-      const int m = t >> 2, kk = (t & 3) * 8;
-      const uint4 v = *reinterpret_cast<const uint4*>(g.A + size_t(m0 + m) * g.lda + k0 + kk);
-      *reinterpret_cast<uint4*>(As + m * GT_LD + kk) = v;
-    } else {
-      const int k = t >> 3, mm = (t & 7) * 8;
-      const uint4 v = *reinterpret_cast<const uint4*>(g.A + size_t(k0 + k) * g.lda + m0 + mm);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+  const int n_stages = (ke - kb) / GT_BK;
+  // row-contiguous operands: A's blocks by threads 0..127, B's by 128..255
+  const int rc = t & 127;
+  const bool a_mine = AL == KC || t < 128;
+  const bool b_mine = BL == KC || (AL == RC ? t >= 128 : t < 128);
+  const int ta = AL == KC ? t : rc, tb = BL == KC ? t : rc;
+  // two register sets, named (not indexed) so that they stay in registers
+  Stage<AL, GT_BM, NT> ra0, ra1;
+  Stage<BL, BN, NT> rb0, rb1;
+  float cs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  f32x16_t acc[2][2];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) As[(mm + i) * GT_LD + k] = e[i];
-    }
-    // B tile -> Bs[n][k]
-    if (BT == 1) {
-      const int n = t >> 2, kk = (t & 3) * 8;
-      const uint4 v = *reinterpret_cast<const uint4*>(g.B + size_t(n0 + n) * g.ldb + k0 + kk);
-      *reinterpret_cast<uint4*>(Bs + n * GT_LD + kk) = v;
-    } else {
-      const int k = t >> 3, nn = (t & 7) * 8;
-      const uint4 v = *reinterpret_cast<const uint4*>(g.B + size_t(k0 + k) * g.ldb + n0 + nn);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[(nn + i) * GT_LD + k] = e[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < GT_BK / 16; ++ks) {
-      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(As + (wm * 32 + (lane & 31)) * GT_LD + ks * 16 + 8 * (lane >> 5));
-      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(Bs + (wn * 32 + (lane & 31)) * GT_LD + ks * 16 + 8 * (lane >> 5));
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-    __syncthreads();
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16_t{};
+  if (n_stages <= 0) return;  // never launched so (K a multiple of 64 per split)
+  ra0.load(g.A, g.lda, m0, kb, ta, a_mine);
+  rb0.load(g.B, g.ldb, n0, kb, tb, b_mine);
+  {
+    const int k1 = kb + min(1, n_stages - 1) * GT_BK;
+    ra1.load(g.A, g.lda, m0, k1, ta, a_mine);
+    rb1.load(g.B, g.ldb, n0, k1, tb, b_mine);
   }
-  // accumulator (row i, col j) of the 32x32 block: lane holds col = lane % 32
-  const int col = n0 + wn * 32 + (lane & 31);
+  if (n_stages > 0) {
+    ra0.store(lds, ta, a_mine, COLSUM ? cs : nullptr);
+    rb0.store(lds + SA, tb, b_mine, nullptr);
+  }
+  __syncthreads();
+  // one stage: multiply LDS buffer BUF; register set CUR (stage s, then
+  // free) takes stage s + 2; set NXT (stage s + 1) goes to buffer BUF ^ 1.
+  // Written out for each parity (a macro, not a function), so that both
+  // register sets stay named registers.
+#define NEDF_GEMM_STAGE(S_, BUF, RA_CUR, RB_CUR, RA_NXT, RB_NXT)                                           \
+  {                                                                                                       \
+    {                                                                                                     \
+      /* unconditional (the last stage again past the end): a conditional */                            \
+      /* load would keep the register set in memory */                                                    \
+      const int kl = kb + min((S_) + 2, n_stages - 1) * GT_BK;                                            \
+      RA_CUR.load(g.A, g.lda, m0, kl, ta, a_mine);                                                        \
+      RB_CUR.load(g.B, g.ldb, n0, kl, tb, b_mine);                                                        \
+    }                                                                                                     \
+    const uint16_t* A_ = lds + (BUF) * (SA + SB) + (wm * 64 + (lane & 31)) * GT_LD + 8 * (lane >> 5);      \
+    const uint16_t* B_ = lds + (BUF) * (SA + SB) + SA + (wn * 64 + (lane & 31)) * GT_LD + 8 * (lane >> 5); \
+    _Pragma("unroll") for (int ks = 0; ks < GT_BK / 16; ++ks) {                                           \
+      bf16x8_t a[2], b[2];                                                                                \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                     \
+        a[i] = *reinterpret_cast<const bf16x8_t*>(A_ + 32 * i * GT_LD + 16 * ks);                         \
+        b[i] = *reinterpret_cast<const bf16x8_t*>(B_ + 32 * i * GT_LD + 16 * ks);                         \
+      }                                                                                                   \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i)                                                       \
+      _Pragma("unroll") for (int j = 0; j < 2; ++j)                                                       \
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j], a[i], acc[i][j], 0, 0, 0);              \
+    }                                                                                                     \
+    if ((S_) + 1 < n_stages) {                                                                            \
+      RA_NXT.store(lds + ((BUF) ^ 1) * (SA + SB), ta, a_mine, COLSUM ? cs : nullptr);                     \
+      RB_NXT.store(lds + ((BUF) ^ 1) * (SA + SB) + SA, tb, b_mine, nullptr);                              \
+    }                                                                                                     \
+    __syncthreads();                                                                                      \
+  }
+  // operands swapped in the matrix-core call (B tile first): the accumulators
+  // of lane l then hold row m = l % 32 of the block and, per group of four
+  // registers, four consecutive columns
+  // the stage count is even (K a multiple of 128 per split), so both copies
+  // run every iteration
+#pragma unroll 1
+  for (int s = 0; s < n_stages; s += 2) {
+    NEDF_GEMM_STAGE(s, 0, ra0, rb0, ra1, rb1)
+    NEDF_GEMM_STAGE(s + 1, 1, ra1, rb1, ra0, rb0)
+  }
+#undef NEDF_GEMM_STAGE
+  // accumulator r of block (i, j): row 64 wm + 32 i + lane % 32, column
+  // 64 wn + 32 j + 8 (r / 4) + 4 (lane / 32) + r % 4 of the tile
+  if constexpr (EPI == 2) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = m0 + wm * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-    const float v = acc[r];
-    if (EPI == 0) {
-      g.out16[size_t(row) * g.ldo + col] = bf16_bits(fmaxf(v + g.bias[col], 0.0f));
-    } else if (EPI == 1) {
-      const bool keep = bf16_val(g.mask[size_t(row) * g.ldm + col]) > 0.0f;
-      g.out16[size_t(row) * g.ldo + col] = bf16_bits(keep ? v : 0.0f);
-    } else {
-      if (col < g.n_valid) atomicAdd(&g.out32[size_t(row) * g.ldo + col], v);
+    for (int i = 0; i < 2; ++i) {
+      const int row = m0 + wm * 64 + 32 * i + (lane & 31);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = n0 + wn * 64 + 32 * j + 8 * q + 4 * (lane >> 5);
+          *reinterpret_cast<float4*>(g.part + (size_t(blockIdx.z) * g.M + row) * g.N + col) =
+              make_float4(acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]);
+        }
+    }
+  } else {
+    // bfloat16 tile in LDS ([128][BN + 8]), then 16-byte row pieces
+    constexpr int LO = BN + 8;
+    static_assert(GT_BM * LO <= 2 * (SA + SB), "output tile must fit the stage buffers");
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 64 + 32 * i + (lane & 31);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = wn * 64 + 32 * j + 8 * q + 4 * (lane >> 5);
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * q + e];
+          if constexpr (EPI == 0) {
+            const float4 bb = *reinterpret_cast<const float4*>(g.bias + n0 + c);
+            v[0] = fmaxf(v[0] + bb.x, 0.f); v[1] = fmaxf(v[1] + bb.y, 0.f);
+            v[2] = fmaxf(v[2] + bb.z, 0.f); v[3] = fmaxf(v[3] + bb.w, 0.f);
+          }
+          *reinterpret_cast<uint2*>(lds + r * LO + c) =
+              make_uint2(uint32_t(bf16_bits(v[0])) | (uint32_t(bf16_bits(v[1])) << 16),
+                         uint32_t(bf16_bits(v[2])) | (uint32_t(bf16_bits(v[3])) << 16));
+        }
+    }
+    __syncthreads();
+    constexpr int CH = GT_BM * BN / 8;  // 16-byte pieces of the tile
+#pragma unroll
+    for (int i = 0; i < CH / NT; ++i) {
+      const int c = t + NT * i;
+      const int r = c / (BN / 8), c8 = 8 * (c % (BN / 8));
+      uint4 v = *reinterpret_cast<const uint4*>(lds + r * LO + c8);
+      if constexpr (EPI == 1) {
+        const uint4 mk = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
+        const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+        uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t lo = __uint_as_float(mw[e] << 16) > 0.f ? 0x0000FFFFu : 0u;
+          const uint32_t hi = __uint_as_float(mw[e] & 0xFFFF0000u) > 0.f ? 0xFFFF0000u : 0u;
+          vw[e] &= lo | hi;
+        }
+        v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+      }
+      *reinterpret_cast<uint4*>(g.out16 + size_t(m0 + r) * g.ldo + n0 + c8) = v;
+    }
+  }
+  if constexpr (COLSUM) {
+    // column sums of A over this split's k, one set per m tile (written by
+    // the workgroups of the first n tile): the 8 threads of one row block
+    // (k blocks 0..7) combine in a fixed order
+    __shared__ float s_cs[128][8];
+    if (t < 128) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) s_cs[8 * (rc % 16) + r][rc / 16] = cs[r];
+    }
+    __syncthreads();
+    if (blockIdx.y == 0 && t < 128) {
+      float s_ = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s_ += s_cs[t][q];
+      g.colsum[size_t(blockIdx.z) * g.M + m0 + t] = s_;
     }
   }
 }
 
+template <int AL, int BL, int EPI, bool COLSUM = false, int BN = 256>
+void gemm(const GemmArgs& g, int splits, hipStream_t s) {
+  dim3 grid(g.M / GT_BM, g.N / BN, splits);
+  hipLaunchKernelGGL((k_gemm<AL, BL, EPI, COLSUM, BN>), grid, dim3(BN * 2), 0, s, g);
+}
+
+// Weight and bias gradients of every hidden layer from the split partials,
+// summed over the splits in order (deterministic): gW[m][k] for k < K, gb[m].
+struct ReduceLayer {
+  const float* part;   // [S][M][N]
+  const float* csum;   // [S][M]
+  float* gW;           // [M][K]
+  float* gb;           // [M]
+  int M, N, K;
+};
+struct ReduceArgs {
+  ReduceLayer L[NEDF_MAX_LAYERS];
+  int n_layers, S;
+};
+__global__ void k_reduce_grads(ReduceArgs r) {
+  const ReduceLayer& L = r.L[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int MN = L.M * L.N;
+  if (i < MN) {
+    const int m = i / L.N, n = i % L.N;
+    if (n < L.K) {
+      float s = 0.f;
+      for (int q = 0; q < r.S; ++q) s += L.part[size_t(q) * MN + i];
+      L.gW[size_t(m) * L.K + n] = s;
+    }
+  } else if (i < MN + L.M) {
+    const int m = i - MN;
+    float s = 0.f;
+    for (int q = 0; q < r.S; ++q) s += L.csum[size_t(q) * L.M + m];
+    L.gb[m] = s;
+  }
+}
+
 // ---- head and loss ------------------------------------------------------------
-// One block of 256 threads per 256 samples; width must be 256.  Phase 1: the
-// (mu_hat, z) head and the loss terms per sample; phase 2: per feature, the
-// head gradients and G = (g_mu W_h0 + g_z W_h1) * (H > 0).
+// One block of 256 threads per HEAD_ROWS samples; width must be 256.  Phase 1
+// (one thread per sample): the (mu_hat, z) head and the loss terms; phase 2
+// (thread k owns feature k): the head weight gradients and
+// G = (g_mu W_h0 + g_z W_h1) * (H > 0).  Every block writes its partial sums
+// (head weight and bias gradients, loss terms) to its own row of `part`
+// [blocks][HEAD_PART]; k_reduce_head adds the rows in a fixed order.
+constexpr int HEAD_PART = 520;  // 512 weight grads, 2 bias grads, 3 loss terms (total, mse, bce)
+constexpr int HEAD_ROWS = 64;
 __global__ __launch_bounds__(256) void k_head_loss(const uint16_t* H, const float* Wh, const float* bh,
                                                    const float* mu, const float* alpha, int B, float w_hit,
-                                                   float* loss, uint16_t* G, float* gWh, float* gbh) {
+                                                   uint16_t* G, float* part) {
   __shared__ float sW[2][256];
-  __shared__ float sg[2][256];
-  __shared__ float red[3][256];
+  __shared__ float sg[2][HEAD_ROWS];
+  __shared__ float red[2][HEAD_ROWS];
   const int t = threadIdx.x;
-  const int s0 = blockIdx.x * 256;
+  const int s0 = blockIdx.x * HEAD_ROWS;
   sW[0][t] = Wh[t];
   sW[1][t] = Wh[256 + t];
   __syncthreads();
-  const int s = s0 + t;
-  float lm = 0.f, lb = 0.f;
-  sg[0][t] = 0.f;
-  sg[1][t] = 0.f;
-  if (s < B) {
-    const uint16_t* row = H + size_t(s) * 256;
-    float a0 = bh[0], a1 = bh[1];
-    for (int k = 0; k < 256; ++k) {
-      const float h = bf16_val(row[k]);
-      a0 = fmaf(sW[0][k], h, a0);
-      a1 = fmaf(sW[1][k], h, a1);
+  if (t < HEAD_ROWS) {
+    const int s = s0 + t;
+    float lm = 0.f, lb = 0.f, g0 = 0.f, g1 = 0.f;
+    if (s < B) {
+      const uint4* row = reinterpret_cast<const uint4*>(H + size_t(s) * 256);
+      float a0 = bh[0], a1 = bh[1];
+      for (int k8 = 0; k8 < 32; ++k8) {
+        const uint4 q = row[k8];
+        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
+          const int k = 8 * k8 + 2 * e;
+          a0 = fmaf(sW[0][k], h0, a0);
+          a1 = fmaf(sW[1][k], h0, a1);
+          a0 = fmaf(sW[0][k + 1], h1, a0);
+          a1 = fmaf(sW[1][k + 1], h1, a1);
+        }
+      }
+      const float al = alpha[s], m = mu[s];
+      const float e = a0 - m;
+      lm = al * e * e;
+      lb = fmaxf(a1, 0.f) + log1pf(expf(-fabsf(a1))) - al * a1;
+      const float invB = 1.0f / float(B);
+      g0 = 2.0f * al * e * invB;
+      g1 = w_hit * (1.0f / (1.0f + expf(-a1)) - al) * invB;
     }
-    const float al = alpha[s], m = mu[s];
-    const float e = a0 - m;
-    lm = al * e * e;
-    lb = fmaxf(a1, 0.f) + log1pf(expf(-fabsf(a1))) - al * a1;
-    const float invB = 1.0f / float(B);
-    sg[0][t] = 2.0f * al * e * invB;
-    sg[1][t] = w_hit * (1.0f / (1.0f + expf(-a1)) - al) * invB;
+    sg[0][t] = g0;
+    sg[1][t] = g1;
+    red[0][t] = lm;
+    red[1][t] = lb;
   }
-  red[0][t] = lm;
-  red[1][t] = lb;
-  red[2][t] = 0.f;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = HEAD_ROWS / 2; off > 0; off >>= 1) {
     if (t < off) {
       red[0][t] += red[0][t + off];
       red[1][t] += red[1][t + off];
     }
     __syncthreads();
   }
+  float* P = part + size_t(blockIdx.x) * HEAD_PART;
   if (t == 0) {
     const float invB = 1.0f / float(B);
-    atomicAdd(&loss[1], red[0][0] * invB);
-    atomicAdd(&loss[2], red[1][0] * invB);
-    atomicAdd(&loss[0], (red[0][0] + w_hit * red[1][0]) * invB);
+    P[514] = (red[0][0] + w_hit * red[1][0]) * invB;
+    P[515] = red[0][0] * invB;
+    P[516] = red[1][0] * invB;
   }
   // phase 2: thread t owns feature k = t
   const int k = t;
   float gw0 = 0.f, gw1 = 0.f;
-  const int ns = min(256, B - s0);
+  const int ns = min(HEAD_ROWS, B - s0);
   for (int i = 0; i < ns; ++i) {
     const size_t idx = size_t(s0 + i) * 256 + k;
     const float h = bf16_val(H[idx]);
@@ -230,22 +485,28 @@ __global__ __launch_bounds__(256) void k_head_loss(const uint16_t* H, const floa
     gw1 = fmaf(g1, h, gw1);
     G[idx] = bf16_bits(h > 0.0f ? fmaf(g0, sW[0][k], g1 * sW[1][k]) : 0.0f);
   }
-  atomicAdd(&gWh[k], gw0);
-  atomicAdd(&gWh[256 + k], gw1);
+  P[k] = gw0;
+  P[256 + k] = gw1;
   if (t < 2) {
     float sum = 0.f;
     for (int i = 0; i < ns; ++i) sum += sg[t][i];
-    atomicAdd(&gbh[t], sum);
+    P[512 + t] = sum;
   }
 }
 
-// Bias gradient: column sums of G [B][N] (N = blockDim).
-__global__ void k_colsum(const uint16_t* G, int B, int N, int rows_per_block, float* gb) {
-  const int n = threadIdx.x;
-  const int r0 = blockIdx.x * rows_per_block, r1 = min(B, r0 + rows_per_block);
-  float sum = 0.f;
-  for (int r = r0; r < r1; ++r) sum += bf16_val(G[size_t(r) * N + n]);
-  atomicAdd(&gb[n], sum);
+// Head gradients and loss from the per-block partials: one wave per output,
+// lane l adding blocks l, l + 64, ... in order, then a fixed butterfly.
+__global__ void k_reduce_head(const float* part, int n_blocks, float* gWh, float* gbh, float* loss) {
+  const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= 517) return;
+  float s = 0.f;
+  for (int q = lane; q < n_blocks; q += 64) s += part[size_t(q) * HEAD_PART + j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane != 0) return;
+  if (j < 512) gWh[j] = s;
+  else if (j < 514) gbh[j - 512] = s;
+  else loss[j - 514] = s;
 }
 
 __global__ void k_zero_f32(float* p, size_t n) {
@@ -253,22 +514,41 @@ __global__ void k_zero_f32(float* p, size_t n) {
   if (i < n) p[i] = 0.f;
 }
 
-// Adam (Kingma & Ba 2015) with bias correction, step t = *step + 1; the
-// bfloat16 copy of weight matrices is refreshed in the same pass.
-__global__ void k_adam(float* p, float* m, float* v, const float* g, int n, const int64_t* step, float lr,
-                       float b1, float b2, float eps, uint16_t* w16, int K, int Kpad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float t = float(*step + 1);
-  const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-  p[i] = pi;
-  if (w16) w16[size_t(i / K) * Kpad + (i % K)] = bf16_bits(pi);
+// Adam (Kingma & Ba 2015) with bias correction, step t = *step + 1, over every
+// parameter array of the network in one launch (segments listed in AdamArgs;
+// a block never spans two segments); the bfloat16 copy of weight matrices is
+// refreshed in the same pass.
+struct AdamSeg {
+  float *p, *m, *v;
+  const float* g;
+  uint16_t* w16;  // or null: [N][Kpad] copy
+  uint16_t* w16t; // or null: [Kpad][N] copy
+  int n, K, Kpad, N;
+  int block0;     // first block of this segment
+};
+struct AdamArgs {
+  AdamSeg seg[2 * (NEDF_MAX_LAYERS + 1)];
+  int n_seg;
+  const int64_t* step;
+  float lr, b1, b2, eps;
+};
+__global__ void k_adam(AdamArgs a) {
+  int si = 0;
+  while (si + 1 < a.n_seg && int(blockIdx.x) >= a.seg[si + 1].block0) ++si;
+  const AdamSeg& S = a.seg[si];
+  const int i = (int(blockIdx.x) - S.block0) * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const float t = float(*a.step + 1);
+  const float bc1 = 1.0f - powf(a.b1, t), bc2 = 1.0f - powf(a.b2, t);
+  const float gi = S.g[i];
+  const float mi = a.b1 * S.m[i] + (1.0f - a.b1) * gi;
+  const float vi = a.b2 * S.v[i] + (1.0f - a.b2) * gi * gi;
+  S.m[i] = mi;
+  S.v[i] = vi;
+  const float pi = S.p[i] - a.lr * (mi / bc1) / (sqrtf(vi / bc2) + a.eps);
+  S.p[i] = pi;
+  if (S.w16) S.w16[size_t(i / S.K) * S.Kpad + (i % S.K)] = bf16_bits(pi);
+  if (S.w16t) S.w16t[size_t(i % S.K) * S.N + (i / S.K)] = bf16_bits(pi);
 }
 
 __global__ void k_step_inc(int64_t* step) {
@@ -277,36 +557,41 @@ __global__ void k_step_inc(int64_t* step) {
 
 // Initial state: master weights from float32 arrays, moments and gradients
 // zero, bfloat16 copies (zero padded).
-__global__ void k_copy_w(const float* src, float* dst, uint16_t* w16, int N, int K, int Kpad) {
+__global__ void k_copy_w(const float* src, float* dst, uint16_t* w16, uint16_t* w16t, int N, int K, int Kpad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * Kpad) return;
   const int r = i / Kpad, c = i % Kpad;
-  if (c < K) {
-    const float v = src[r * K + c];
-    if (dst) dst[r * K + c] = v;
-    if (w16) w16[i] = bf16_bits(v);
-  } else if (w16) {
-    w16[i] = 0;
-  }
+  const float v = c < K ? src[r * K + c] : 0.0f;
+  if (c < K && dst) dst[r * K + c] = v;
+  if (w16) w16[i] = bf16_bits(v);
+  if (w16t) w16t[size_t(c) * N + r] = bf16_bits(v);
 }
 
 unsigned blocks(size_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
-template <int AT, int BT, int EPI>
-void gemm(const GemmArgs& g, int splits, hipStream_t s) {
-  dim3 grid(g.M / GT_BM, (g.N + GT_BN - 1) / GT_BN, splits);
-  hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), grid, dim3(256), 0, s, g);
-}
 
 }  // namespace
 
+// Split-K count of the weight-gradient GEMMs (batch dimension).
+int wgrad_splits(int B) {
+  int S = B / 1024;
+  if (S < 1) S = 1;
+  if (S > 64) S = 64;
+  while (S > 1 && (B % (S * GT_BK) != 0)) --S;
+  return S;
+}
+
 size_t train_ws_bytes(const nedf_mlp_shape& sh, int B) {
   const nedf_train_layout tl = nedf_train_layout_of(sh);
+  const int S = wgrad_splits(B);
   size_t off = 0;
   off = nedf_tl_align(off + size_t(B) * tl.L[0].Kpad * 2);           // H_in
   off = nedf_tl_align(off + size_t(B) * sh.width * 2 * sh.n_hidden);  // H_0..H_{n-1}
   off = nedf_tl_align(off + size_t(B) * sh.width * 2 * 2);            // G ping-pong
   off = nedf_tl_align(off + size_t(B) * 4 * 2);                       // mu, alpha
+  for (int l = 0; l < sh.n_hidden; ++l)                                // weight-gradient partials
+    off = nedf_tl_align(off + size_t(S) * sh.width * (tl.L[l].Kpad + 1) * 4);
+  off = nedf_tl_align(off + size_t((B + HEAD_ROWS - 1) / HEAD_ROWS) * HEAD_PART * 4);  // head partials
   return off;
 }
 
@@ -318,9 +603,11 @@ hipError_t launch_train_init(const nedf_mlp_shape& sh, const float* const* W, co
   for (int i = 0; i < tl.n_layers; ++i) {
     const nedf_train_layer& l = tl.L[i];
     hipLaunchKernelGGL(k_copy_w, dim3(blocks(size_t(l.N) * l.Kpad)), dim3(256), 0, s, W[i],
-                       reinterpret_cast<float*>(st + l.W), reinterpret_cast<uint16_t*>(st + l.W16), l.N, l.K, l.Kpad);
+                       reinterpret_cast<float*>(st + l.W), reinterpret_cast<uint16_t*>(st + l.W16),
+                       reinterpret_cast<uint16_t*>(st + l.W16T), l.N, l.K, l.Kpad);
     hipLaunchKernelGGL(k_copy_w, dim3(blocks(size_t(l.N))), dim3(256), 0, s, b[i],
-                       reinterpret_cast<float*>(st + l.b), static_cast<uint16_t*>(nullptr), 1, l.N, l.N);
+                       reinterpret_cast<float*>(st + l.b), static_cast<uint16_t*>(nullptr),
+                       static_cast<uint16_t*>(nullptr), 1, l.N, l.N);
   }
   return hipGetLastError();
 }
@@ -331,6 +618,7 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   const nedf_train_layout tl = nedf_train_layout_of(sh);
   const int W = sh.width, NH = sh.n_hidden;
   const int K0p = tl.L[0].Kpad;
+  const int S = wgrad_splits(B);
   size_t off = 0;
   uint16_t* Hin = reinterpret_cast<uint16_t*>(ws + off);
   off = nedf_tl_align(off + size_t(B) * K0p * 2);
@@ -341,19 +629,21 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   off = nedf_tl_align(off + size_t(B) * W * 2 * 2);
   float* mu = reinterpret_cast<float*>(ws + off);
   float* alpha = mu + B;
+  off = nedf_tl_align(off + size_t(B) * 4 * 2);
+  float* wpart[NEDF_MAX_LAYERS];
+  for (int l = 0; l < NH; ++l) {
+    wpart[l] = reinterpret_cast<float*>(ws + off);
+    off = nedf_tl_align(off + size_t(S) * W * (tl.L[l].Kpad + 1) * 4);
+  }
+  float* hpart = reinterpret_cast<float*>(ws + off);
+  const int hblocks = (B + HEAD_ROWS - 1) / HEAD_ROWS;
   auto Hl = [&](int l) { return Hs + size_t(l) * B * W; };
   auto F = [&](size_t o) { return reinterpret_cast<float*>(st + o); };
   auto U = [&](size_t o) { return reinterpret_cast<uint16_t*>(st + o); };
 
   prof_mark("train.step", s, true);
-  // zero gradients and the loss
-  for (int i = 0; i < tl.n_layers; ++i) {
-    const nedf_train_layer& l = tl.L[i];
-    hipLaunchKernelGGL(k_zero_f32, dim3(blocks(size_t(l.N) * l.K)), dim3(256), 0, s, F(l.gW), size_t(l.N) * l.K);
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, F(l.gb), size_t(l.N));
-  }
-  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss, size_t(3));
-  hipLaunchKernelGGL(k_train_encode, dim3(blocks(B)), dim3(256), 0, s, o_l, d_l, depth, hit, B, sh.in_kind, sh.enc_L,
+  hipLaunchKernelGGL(k_train_encode, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l, depth, hit, B,
+                     sh.in_kind, sh.enc_L,
                      K0p, bound, Hin, mu, alpha);
   // forward: H_l = relu(H_{l-1} W_l^T + b_l)
   for (int l = 0; l < NH; ++l) {
@@ -367,53 +657,65 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     g.bias = F(tl.L[l].b);
     g.out16 = Hl(l);
     g.ldo = W;
-    gemm<0, 1, 0>(g, 1, s);
+    gemm<KC, KC, 0>(g, 1, s);
   }
   // head, loss, G_{NH-1}
   const nedf_train_layer& hd = tl.L[NH];
-  hipLaunchKernelGGL(k_head_loss, dim3(blocks(B)), dim3(256), 0, s, Hl(NH - 1), F(hd.W), F(hd.b), mu, alpha, B,
-                     w_hit, loss, G0, F(hd.gW), F(hd.gb));
+  hipLaunchKernelGGL(k_head_loss, dim3(hblocks), dim3(256), 0, s, Hl(NH - 1), F(hd.W), F(hd.b), mu, alpha, B,
+                     w_hit, G0, hpart);
+  hipLaunchKernelGGL(k_reduce_head, dim3((517 + 3) / 4), dim3(256), 0, s, hpart, hblocks, F(hd.gW), F(hd.gb), loss);
   // backward through the hidden layers
+  ReduceArgs ra{};
+  ra.n_layers = NH;
+  ra.S = S;
   uint16_t* Gc = G0;
   uint16_t* Gn = G1;
   for (int l = NH - 1; l >= 0; --l) {
     const nedf_train_layer& L = tl.L[l];
-    // weight gradient dW_l = G_l^T H_{l-1}   (split-K over the batch)
+    // weight gradient partials dW_l = G_l^T H_{l-1} over S batch splits, and
+    // the column sums of G_l (bias gradient) per split
     GemmArgs w{};
-    w.A = Gc; w.lda = W;                            // stored [B][W] = [K][M]
+    w.A = Gc; w.lda = W;                            // stored [B][W] = [K][M]: row-contiguous
     w.B = l == 0 ? Hin : Hl(l - 1);
-    w.ldb = l == 0 ? K0p : W;                       // stored [B][Kpad] = [K][N]
+    w.ldb = l == 0 ? K0p : W;                       // stored [B][Kpad] = [K][N]: row-contiguous
     w.M = W; w.N = L.Kpad; w.K = B;
-    const int splits = (B >= 4096 && B % 1024 == 0) ? B / 1024 : 1;
-    w.k_per_split = (B + splits - 1) / splits;
-    w.out32 = F(L.gW);
-    w.ldo = L.K;
-    w.n_valid = L.K;
-    gemm<1, 0, 2>(w, splits, s);
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(B, 256)), dim3(W), 0, s, Gc, B, W, 256, F(L.gb));
+    w.k_per_split = B / S;
+    w.part = wpart[l];
+    w.colsum = wpart[l] + size_t(S) * W * L.Kpad;
+    gemm<RC, RC, 2, true, 128>(w, S, s);
+    ra.L[l] = ReduceLayer{w.part, w.colsum, F(L.gW), F(L.gb), W, L.Kpad, L.K};
     if (l > 0) {
       // data gradient G_{l-1} = (G_l W_l) * (H_{l-1} > 0)
       GemmArgs d{};
-      d.A = Gc; d.lda = W;                          // [B][W]
-      d.B = U(L.W16); d.ldb = L.Kpad;               // W_l [W][Kpad] = [K][N]
+      d.A = Gc; d.lda = W;                          // [B][W]: k-contiguous
+      d.B = U(L.W16T); d.ldb = W;                   // W_l^T [Kpad][W] = [N][K]: k-contiguous
       d.M = B; d.N = W; d.K = W;
       d.k_per_split = W;
       d.mask = Hl(l - 1); d.ldm = W;
       d.out16 = Gn; d.ldo = W;
-      gemm<0, 0, 1>(d, 1, s);
+      gemm<KC, KC, 1>(d, 1, s);
       uint16_t* tmp = Gc; Gc = Gn; Gn = tmp;
     }
   }
-  // Adam on every parameter array
-  const int64_t* step = reinterpret_cast<const int64_t*>(st);
+  {
+    int maxmn = 0;
+    for (int l = 0; l < NH; ++l) maxmn = std::max(maxmn, W * tl.L[l].Kpad + W);
+    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(maxmn), NH), dim3(256), 0, s, ra);
+  }
+  // Adam on every parameter array, one launch
+  AdamArgs aa{};
+  aa.step = reinterpret_cast<const int64_t*>(st);
+  aa.lr = lr; aa.b1 = b1; aa.b2 = b2; aa.eps = eps;
+  int nb = 0;
   for (int i = 0; i < tl.n_layers; ++i) {
     const nedf_train_layer& L = tl.L[i];
-    const int nw = L.N * L.K;
-    hipLaunchKernelGGL(k_adam, dim3(blocks(nw)), dim3(256), 0, s, F(L.W), F(L.mW), F(L.vW), F(L.gW), nw, step, lr, b1,
-                       b2, eps, U(L.W16), L.K, L.Kpad);
-    hipLaunchKernelGGL(k_adam, dim3(blocks(L.N)), dim3(256), 0, s, F(L.b), F(L.mb), F(L.vb), F(L.gb), L.N, step, lr,
-                       b1, b2, eps, static_cast<uint16_t*>(nullptr), 1, 1);
+    aa.seg[aa.n_seg++] = AdamSeg{F(L.W), F(L.mW), F(L.vW), F(L.gW), U(L.W16), U(L.W16T), L.N * L.K, L.K, L.Kpad,
+                                 L.N, nb};
+    nb += int(blocks(size_t(L.N) * L.K));
+    aa.seg[aa.n_seg++] = AdamSeg{F(L.b), F(L.mb), F(L.vb), F(L.gb), nullptr, nullptr, L.N, 1, 1, 1, nb};
+    nb += int(blocks(size_t(L.N)));
   }
+  hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, s, aa);
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, reinterpret_cast<int64_t*>(st));
   prof_mark("train.step", s, false);
   return hipGetLastError();
@@ -438,7 +740,8 @@ hipError_t launch_fp8_calibrate(const nedf_mlp_shape& sh, const float* const* W,
   uint16_t* Hin = reinterpret_cast<uint16_t*>(fw);
   uint16_t* Hs = reinterpret_cast<uint16_t*>(fw + nedf_tl_align(size_t(B) * K0p * 2));
   float* mu = nullptr;
-  hipLaunchKernelGGL(k_train_encode, dim3(blocks(B)), dim3(256), 0, s, o_l, d_l, static_cast<const float*>(nullptr),
+  hipLaunchKernelGGL(k_train_encode, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l,
+                     static_cast<const float*>(nullptr),
                      static_cast<const uint8_t*>(nullptr), B, sh.in_kind, sh.enc_L, K0p, 1.0f, Hin, mu, mu);
   hipLaunchKernelGGL(k_amax16, dim3(256), dim3(256), 0, s, Hin, size_t(B) * K0p, amax + NEDF_MAX_LAYERS);
   for (int l = 0; l < NH; ++l) {
@@ -452,7 +755,7 @@ hipError_t launch_fp8_calibrate(const nedf_mlp_shape& sh, const float* const* W,
     g.bias = reinterpret_cast<const float*>(st + tl.L[l].b);
     g.out16 = Hs + size_t(l) * B * W_;
     g.ldo = W_;
-    gemm<0, 1, 0>(g, 1, s);
+    gemm<KC, KC, 0>(g, 1, s);
     if (l + 1 < NH) hipLaunchKernelGGL(k_amax16, dim3(256), dim3(256), 0, s, g.out16, size_t(B) * W_, amax + NEDF_MAX_LAYERS + l + 1);
     hipLaunchKernelGGL(k_amax32, dim3(64), dim3(256), 0, s, reinterpret_cast<const float*>(st + tl.L[l].W),
                        size_t(tl.L[l].N) * tl.L[l].K, amax + l);

@@ -1,7 +1,7 @@
 // Device layout of an intersection network's training state: float32 master
-// weights and biases, Adam moments, last-step gradients and a bfloat16 copy
-// of every weight matrix (K padded to a multiple of 64 with zeros) for the
-// matrix-core GEMMs.  Layer i is [N][K] row-major (PyTorch layout); layers
+// weights and biases, Adam moments, last-step gradients and bfloat16 copies
+// of every weight matrix for the matrix-core GEMMs, [N][Kpad] and transposed
+// [Kpad][N] (K padded to a multiple of 64 with zeros).  Layer i is [N][K] row-major (PyTorch layout); layers
 // 0..n_hidden-1 are the hidden layers, layer n_hidden the head.
 #pragma once
 #include <stddef.h>
@@ -12,7 +12,7 @@
 
 struct nedf_train_layer {
   int32_t N, K, Kpad;
-  size_t W, b, mW, vW, gW, mb, vb, gb, W16;  // byte offsets in the state buffer
+  size_t W, b, mW, vW, gW, mb, vb, gb, W16, W16T;  // byte offsets in the state buffer
 };
 
 struct nedf_train_layout {
@@ -44,6 +44,7 @@ static inline nedf_train_layout nedf_train_layout_of(const nedf_mlp_shape& s) {
     l.vb = off; off = nedf_tl_align(off + nb);
     l.gb = off; off = nedf_tl_align(off + nb);
     l.W16 = off; off = nedf_tl_align(off + size_t(l.N) * l.Kpad * 2);
+    l.W16T = off; off = nedf_tl_align(off + size_t(l.N) * l.Kpad * 2);
   }
   t.total = off;
   return t;
