@@ -101,7 +101,8 @@ def parse():
     p.add_argument("--width", type=int, default=1920)
     p.add_argument("--height", type=int, default=1080)
     p.add_argument("--instances", type=int, default=1000)
-    p.add_argument("--train-steps", type=int, default=1500)
+    p.add_argument("--train-steps", type=int, default=None,
+                   help="Adam steps per object (default 1500 for the frame, 20000 for --workload nedf)")
     p.add_argument("--train-batch", type=int, default=65536)
     p.add_argument("--label-batches", type=int, default=16)
     p.add_argument("--fallback-samples", type=int, default=128)
@@ -749,6 +750,8 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.train_steps is None:
+        args.train_steps = 20000 if args.workload == "nedf" else 1500
     if args.workload == "frame":
         line, ctx = frame_bench(args)
     elif args.workload == "precision":
