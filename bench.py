@@ -104,7 +104,7 @@ def parse():
     p.add_argument("--train-steps", type=int, default=None,
                    help="Adam steps per object (default 1500 for the frame, 20000 for --workload nedf)")
     p.add_argument("--train-batch", type=int, default=65536)
-    p.add_argument("--label-batches", type=int, default=16)
+    p.add_argument("--label-batches", type=int, default=153, help="labels per object = batches x batch (10 M)")
     p.add_argument("--fallback-samples", type=int, default=128)
     p.add_argument("--marcher-pixels", type=int, default=2048)
     p.add_argument("--no-shading", action="store_true", help="depth+ID only in the timed frame")
@@ -116,6 +116,8 @@ def parse():
     # intersection-network workload
     p.add_argument("--labels", type=int, default=10_000_000)
     p.add_argument("--quality-pixels", type=int, default=4096)
+    p.add_argument("--fp64-pixels", type=int, default=256,
+                   help="frame: seeded pixels judged by the FP64 oracle marcher (inside the CPU-baseline leg)")
     # oracle baseline and counters
     p.add_argument("--cpu-pixels", type=int, default=0, help="0: the workload's default sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -320,10 +322,11 @@ def frame_bench(args):
     dn, idn_ = depth[pix_t].cpu().numpy().astype(np.float64), ident[pix_t].cpu().numpy()
     dm, im = dm.cpu().numpy().astype(np.float64), im.cpu().numpy()
     agree = float(np.mean((dn < np.inf) == (im >= 0)))
-    both = (idn_ >= 0) & (im >= 0)
+    both = (idn_ == im) & (im >= 0)
     med = float(np.median(np.abs(dn[both] - dm[both]))) if both.any() else float("inf")
     quality = {"pixels": int(len(pix)), "hit_agreement": agree, "id_agreement": float(np.mean(idn_ == im)),
                "median_depth_err": med, "median_depth_err_frac_extent": med / extent, "extent": extent,
+               "depth_err_over": "pixels with the same ID",
                "reference": "library FP32 marcher, 192 samples per pair"}
 
     # dominant kernel of the timed frames, per launch: the network runs once
@@ -378,7 +381,8 @@ def frame_bench(args):
         "training": train,
         "setup_train_s": setup_train_s,
     }
-    return line, (models, nets, insts, cam, config)
+    depth_np, ident_np = depth.cpu().numpy(), ident.cpu().numpy()
+    return line, (models, nets, insts, cam, config, depth_np, ident_np, extent)
 
 
 def subset_rays(cam, px, py):
@@ -400,20 +404,69 @@ def subset_rays(cam, px, py):
     return np.ascontiguousarray(o, np.float32), np.ascontiguousarray(d, np.float32)
 
 
-def frame_cpu_baseline(ctx, n_pixels):
+def frame_cpu_baseline(ctx, n_pixels, quality_pixels):
     """FP64 oracle of the depth+ID path (intersection network, marcher
-    fallback, refinement) on a seeded pixel sample of the same frame."""
+    fallback) timed on a seeded pixel sample of the same frame; and, on a
+    second seeded sample, the FP64 oracle marcher (192 samples per pair,
+    front to back with exact pruning) as the judge of the frame's depth and
+    ID buffers, with every ID disagreement classified."""
     import synthetic as syn
-    from oracle import camera_rays, nedf_compose
-    models, nets, insts, cam, config = ctx
+    from oracle import camera_rays, f32_record, nedf_compose, nedf_pair, march_compose_pruned
+    from oracle.render import march_instance
+    models, nets, insts, cam, config, depth_g, ident_g, extent = ctx
     pix = syn.pixel_subset(config, cam.n_rays, n_pixels)
     o, d = camera_rays(cam, pix)
     t0 = time.perf_counter()
     nedf_compose(nets, models, insts, o, d, n_samples=128)
     dt = time.perf_counter() - t0
-    return {"value": n_pixels / dt, "unit": "rays/s", "cores": int(host_threads()), "kind": "oracle",
+    base = {"value": n_pixels / dt, "unit": "rays/s", "cores": int(host_threads()), "kind": "oracle",
             "sample": f"{n_pixels} seeded pixels of the same {cam.width}x{cam.height} frame, depth+ID "
                       f"(intersection network, marcher fallback), FP64 NumPy, {dt:.1f} s"}
+    # the FP64 oracle marcher as the judge (rays of the single-precision camera)
+    qp = syn.pixel_subset(config, cam.n_rays, quality_pixels, stream=13)
+    oq, dq = camera_rays(cam, qp, basis="f32")
+    recs = [f32_record(i) for i in insts]
+    t0 = time.perf_counter()
+    ref_d, ref_id, n_pairs = march_compose_pruned(models, recs, oq, dq, 192)
+    t_ref = time.perf_counter() - t0
+    g_d, g_id = depth_g[qp].astype(np.float64), ident_g[qp].astype(np.int64)
+    same = (g_id == ref_id) & (ref_id >= 0)
+    err = np.abs(g_d[same] - ref_d[same])
+    tol = 0.01 * extent
+    mism = np.nonzero((g_id != ref_id) & (g_id >= 0) & (ref_id >= 0))[0]
+    near_tie, routes = 0, {"network_miss": 0, "fallback_band": 0, "network_hit_deeper": 0, "inside": 0}
+    for i in mism:
+        # the oracle marcher's depth of the instance the frame chose: a near-tie
+        # when it lies within 1 % of the extent of the winner's
+        kg = int(g_id[i])
+        v, A, D = march_instance(models[recs[kg].model], recs[kg], oq[i:i + 1], dq[i:i + 1], 192)
+        if v[0] and A[0] >= 0.5 and abs(D[0] - ref_d[i]) <= tol:
+            near_tie += 1
+            continue
+        # how the intersection network (bfloat16 emulation) routed the marcher's winner
+        kr = int(ref_id[i])
+        hit, Dn, pr, path = nedf_pair(nets[recs[kr].model], models[recs[kr].model], recs[kr], oq[i:i + 1],
+                                      dq[i:i + 1], n_samples=128, gemm="bf16")
+        if path[0] == 1 and not np.isfinite(pr[0]):
+            routes["inside"] += 1
+        elif path[0] == 1:
+            routes["fallback_band"] += 1
+        elif not hit[0]:
+            routes["network_miss"] += 1
+        else:
+            routes["network_hit_deeper"] += 1
+    base["quality_fp64"] = {
+        "pixels": int(len(qp)), "reference": "FP64 oracle marcher, 192 samples per pair, exact pruning",
+        "oracle_s": t_ref, "pairs_marched": int(n_pairs),
+        "hit_agreement": float(np.mean((g_id >= 0) == (ref_id >= 0))),
+        "id_agreement": float(np.mean(g_id == ref_id)),
+        "median_depth_err_frac_extent": float(np.median(err)) / extent if err.size else None,
+        "p90_depth_err_frac_extent": float(np.quantile(err, 0.9)) / extent if err.size else None,
+        "depth_err_over": "pixels with the same ID",
+        "id_mismatch": {"total": int(len(mism)), "near_tie_within_1pct_extent": near_tie,
+                        "other_by_network_route_of_the_marcher_winner": routes},
+    }
+    return base
 
 
 # ---------------------------------------------------------------------------
@@ -751,7 +804,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     if args.train_steps is None:
-        args.train_steps = 20000 if args.workload == "nedf" else 1500
+        args.train_steps = 20000 if args.workload == "nedf" else 6000
     if args.workload == "frame":
         line, ctx = frame_bench(args)
     elif args.workload == "precision":
@@ -770,7 +823,8 @@ def main():
         line["copy_calibration_bytes"] = args.copy_mib << 20
     if not args.no_cpu_baseline:
         if args.workload == "frame":
-            line["cpu_baseline"] = frame_cpu_baseline(ctx, args.cpu_pixels or 2000)
+            line["cpu_baseline"] = frame_cpu_baseline(ctx, args.cpu_pixels or 2000, args.fp64_pixels)
+            line["quality_fp64"] = line["cpu_baseline"].pop("quality_fp64")
         else:
             line["cpu_baseline"] = marcher_cpu_baseline(args.cpu_pixels or 6000, args.samples, args.size)
     print(json.dumps(line), flush=True)
