@@ -108,6 +108,8 @@ def parse():
     p.add_argument("--fallback-samples", type=int, default=128)
     p.add_argument("--marcher-pixels", type=int, default=2048)
     p.add_argument("--no-shading", action="store_true", help="depth+ID only in the timed frame")
+    p.add_argument("--rs-sigma", type=float, default=0.5,
+                   help="frame: outlier threshold of the rs / wo rs shading comparison (1 %% of sigma_max)")
     p.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing beside the eager frames")
     # marcher workload
     p.add_argument("--samples", type=int, default=192)
@@ -302,6 +304,38 @@ def frame_bench(args):
         graph = {"ms_per_step": gms, "rays_per_s": n / (gms * 1e-3), "replays": args.steps}
         assert api.check_status(ws) == 0, "graph replay reported a device status error"
 
+    # outlier processing in deferred shading (the paper's "rs" / "wo rs"):
+    # shading alone, timed with and without resampling of the pixels whose
+    # density stays below rs_sigma at all K samples
+    rs = None
+    if not args.no_shading:
+        depth_id()
+        torch.cuda.synchronize()
+        rgb_rs = torch.empty_like(rgb)
+        ws_rs = api.Workspace()
+        times = {}
+        for name, thr in (("wo_rs", 0.0), ("rs", args.rs_sigma)):
+            out = rgb if thr == 0.0 else rgb_rs
+            api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, dtype=args.dtype, ws=ws_rs, out=out,
+                               rs_sigma=thr, rs_samples=32)
+            torch.cuda.synchronize()
+            r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            r0.record()
+            for _ in range(args.steps):
+                api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, dtype=args.dtype, ws=ws_rs, out=out,
+                                   rs_sigma=thr, rs_samples=32)
+            r1.record()
+            torch.cuda.synchronize()
+            times[name] = r0.elapsed_time(r1) / args.steps
+        n_rs = api.ws_counters(ws_rs)["fallback"]
+        hits = int((ident >= 0).sum())
+        diff = (rgb_rs - rgb).abs().max(dim=1).values
+        rs = {"rs_sigma": args.rs_sigma, "rs_samples": 32, "shade_ms_wo_rs": times["wo_rs"],
+              "shade_ms_rs": times["rs"], "resampled_pixels": int(n_rs),
+              "resampled_frac_of_hits": n_rs / max(hits, 1),
+              "mean_abs_rgb_change_resampled": float(diff[diff > 0].mean()) if bool((diff > 0).any()) else 0.0}
+        log(f"outlier resampling {rs}")
+
     # plain FP32 marcher on a seeded pixel subset of the same scene
     g = np.random.default_rng(4669 + 1000 * config + 77)
     pix = np.sort(g.choice(n, size=min(args.marcher_pixels, n), replace=False))
@@ -378,6 +412,7 @@ def frame_bench(args):
         "stages_ms_per_step": per,
         "autotune": tune,
         "graph": graph,
+        "outlier_resampling": rs,
         "training": train,
         "setup_train_s": setup_train_s,
     }

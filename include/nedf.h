@@ -171,6 +171,10 @@ typedef struct nedf_shade_opts {
   float h;                  /* half width in world units, default 0.05 */
   float clear_rgb[3];       /* colour of pixels without an ID */
   int32_t dtype;
+  float rs_sigma;           /* outlier threshold (Sec. "Deferred Shading"): a pixel whose density is below
+                               it at every one of its K samples did not reach the surface and is shaded
+                               again by volume rendering over the bounding chord; 0 = off */
+  int32_t rs_samples;       /* samples over the chord for those pixels: 8, 16 or 32 */
 } nedf_shade_opts;
 
 /* Options of the shadow step (Alg. 2). */

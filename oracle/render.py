@@ -218,41 +218,70 @@ def secant_refine(dens_model, inst, o, d, D_hat, h=0.05, steps=3, gemm=None, mar
     return (out, fmin, gmin) if margins else out
 
 
+def _shade_window(model, inst, o, d, t_lo, step, K, gemm):
+    """Local compositing of K samples t_j = t_lo + (j + 1/2) step (world
+    units, per ray) of one instance's NeRF: colour sum w_j c_j / sum w_j, or
+    c at the sample nearest the window's centre (lower j on a tie) when
+    sum w < 1e-6; also the largest density among the samples."""
+    t = t_lo[:, None] + (np.arange(K) + 0.5)[None, :] * step[:, None]
+    x = o[:, None, :] + t[..., None] * d[:, None, :]
+    o_l, d_l = to_local(inst, x.reshape(-1, 3), np.repeat(d, K, axis=0))
+    sig, col = nerf_eval(model, o_l, d_l, gemm=gemm)
+    sig = sig.reshape(-1, K)
+    col = col.reshape(-1, K, 3)
+    sd = sig * (step / inst.s)[:, None]
+    tau = np.cumsum(sd, axis=1) - sd
+    w = np.exp(-tau) * (-np.expm1(-sd))
+    ws = w.sum(axis=1)
+    near = (K - 1) // 2
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c = (w[..., None] * col).sum(axis=1) / np.where(ws > 0, ws, 1.0)[:, None]
+    c = np.where((ws < 1e-6)[:, None], col[:, near, :], c)
+    return c, sig.max(axis=1)
+
+
 def shade_deferred(models, insts, o, d, depth, ident, K=8, h=0.05, clear=(0.0, 0.0, 0.0),
-                   gemm=None):
+                   gemm=None, rs_sigma=0.0, rs_samples=32, return_outliers=False):
     """Deferred shading (Eq. 8, Alg. 1 step 2): each pixel with a valid ID is
     shaded by that instance's NeRF near its depth.  Reading (K samples):
     t_j = D - h + (j + 1/2) 2h/K in world units, evaluated in local space
     with local direction; weights from local compositing with step
     (2h/K)/s; rgb = sum w_j c_j / sum w_j, or c at the sample nearest D
     (lower j on a tie) when sum w < 1e-6.  K = 1 is the single evaluation of
-    Eq. 8.  Pixels without an ID get the clear colour."""
+    Eq. 8.  Pixels without an ID get the clear colour.
+
+    Outlier processing (Sec. "Deferred Shading": a density that is extremely
+    small at the estimated depth means it missed the surface, and such
+    pixels can be resampled with the volume rendering equation).  Reading:
+    with rs_sigma > 0 a pixel whose density is below rs_sigma at every one
+    of its K samples (for K = 1, at D itself) is shaded again by the same
+    compositing over the whole chord of the instance's bounding sphere with
+    rs_samples midpoint samples.  ``return_outliers`` also returns the mask
+    of such pixels."""
     o = np.asarray(o, F64)
     d = np.asarray(d, F64)
     n = o.shape[0]
     rgb = np.tile(np.asarray(clear, F64), (n, 1))
-    step = 2.0 * h / K
+    outl = np.zeros(n, bool)
     for k, inst in enumerate(insts):
         idx = np.nonzero(ident == k)[0]
         if idx.size == 0:
             continue
         model = models[inst.model]
-        t = depth[idx, None] - h + (np.arange(K) + 0.5)[None, :] * step
-        x = o[idx, None, :] + t[..., None] * d[idx, None, :]
-        o_l, d_l = to_local(inst, x.reshape(-1, 3), np.repeat(d[idx], K, axis=0))
-        sig, col = nerf_eval(model, o_l, d_l, gemm=gemm)
-        sig = sig.reshape(-1, K)
-        col = col.reshape(-1, K, 3)
-        sd = sig * (step / inst.s)
-        tau = np.cumsum(sd, axis=1) - sd
-        w = np.exp(-tau) * (-np.expm1(-sd))
-        ws = w.sum(axis=1)
-        near = (K - 1) // 2
-        with np.errstate(invalid="ignore", divide="ignore"):
-            c = (w[..., None] * col).sum(axis=1) / np.where(ws > 0, ws, 1.0)[:, None]
-        c = np.where((ws < 1e-6)[:, None], col[:, near, :], c)
+        step = np.full(idx.size, 2.0 * h / K)
+        c, smax = _shade_window(model, inst, o[idx], d[idx], depth[idx] - h, step, K, gemm)
+        if rs_sigma > 0:
+            r = np.nonzero(smax < rs_sigma)[0]
+            if r.size:
+                o_l, d_l = to_local(inst, o[idx[r]], d[idx[r]])
+                a_, b_, valid = sphere_chord(o_l, d_l, model.bound)
+                r, a_, b_ = r[valid], a_[valid], b_[valid]
+                if r.size:
+                    c[r], _ = _shade_window(model, inst, o[idx[r]], d[idx[r]], inst.s * a_,
+                                            inst.s * (b_ - a_) / rs_samples, rs_samples, gemm)
+                    outl[idx[r]] = True
         rgb[idx] = c
-    return rgb
+    return (rgb, outl) if return_outliers else rgb
 
 
 def shadow_factor(depth_fn, o, d, depth, ident, lights, eps, beta=0.5):

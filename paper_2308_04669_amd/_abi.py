@@ -62,7 +62,8 @@ class InferOpts(C.Structure):
 
 
 class ShadeOpts(C.Structure):
-    _fields_ = [("K", C.c_int32), ("h", C.c_float), ("clear_rgb", C.c_float * 3), ("dtype", C.c_int32)]
+    _fields_ = [("K", C.c_int32), ("h", C.c_float), ("clear_rgb", C.c_float * 3), ("dtype", C.c_int32),
+                ("rs_sigma", C.c_float), ("rs_samples", C.c_int32)]
 
 
 class ShadowOpts(C.Structure):

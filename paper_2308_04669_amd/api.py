@@ -325,14 +325,17 @@ def infer_depth_id_static(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_
 
 def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, K: int = 8,
                    h: float = 0.05, clear_rgb=(0.0, 0.0, 0.0), dtype: str = "bf16", ws: Workspace | None = None,
-                   out: torch.Tensor | None = None, pair_capacity: int = 0) -> torch.Tensor:
-    """Deferred shading of every pixel with a valid ID; returns rgb [n, 3]."""
+                   out: torch.Tensor | None = None, pair_capacity: int = 0, rs_sigma: float = 0.0,
+                   rs_samples: int = 32) -> torch.Tensor:
+    """Deferred shading of every pixel with a valid ID (pixels whose density
+    stays below ``rs_sigma`` at every sample are shaded again over the
+    bounding chord with ``rs_samples`` samples); returns rgb [n, 3]."""
     lib = A.load()
     n = n_rays(rays)
     dev = scene.inst_w2l.device
     rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
     sc = scene.struct()
-    opts = A.ShadeOpts(K=K, h=h, dtype=A.DTYPES[dtype])
+    opts = A.ShadeOpts(K=K, h=h, dtype=A.DTYPES[dtype], rs_sigma=rs_sigma, rs_samples=rs_samples)
     for i in range(3):
         opts.clear_rgb[i] = float(clear_rgb[i])
     # one (pixel, instance) pair per pixel at most

@@ -549,6 +549,9 @@ extern "C" int32_t nedf_shade_deferred(const nedf_scene* scene, const nedf_rays*
   const int K = opts->K;
   if (!(K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32)) return fail(NEDF_ERR_SHAPE, "K must be 1, 2, 4, 8, 16 or 32");
   if (!(opts->h > 0.0f)) return fail(NEDF_ERR_SHAPE, "h must be positive");
+  if (!(opts->rs_sigma >= 0.0f)) return fail(NEDF_ERR_SHAPE, "rs_sigma must be >= 0");
+  if (opts->rs_sigma > 0.0f && !(opts->rs_samples == 8 || opts->rs_samples == 16 || opts->rs_samples == 32))
+    return fail(NEDF_ERR_SHAPE, "rs_samples must be 8, 16 or 32");
   Prepared P;
   int32_t st = prepare_scene(scene, opts->dtype, P);
   if (st) return st;
@@ -570,10 +573,12 @@ extern "C" int32_t nedf_shade_deferred(const nedf_scene* scene, const nedf_rays*
   k.rgb = rgb;
   k.shade_K = K;
   k.shade_h = opts->h;
+  k.rs_sigma = opts->rs_sigma;
+  k.shade_chord = 0;
   for (int c = 0; c < 3; ++c) k.clear_rgb[c] = opts->clear_rgb[c];
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, k.status);
-  stage_shade(k, s, id, P.nerf, opts->dtype);
+  stage_shade(k, s, id, P.nerf, opts->dtype, opts->rs_sigma > 0.0f ? opts->rs_samples : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "nedf_shade_deferred");
   return NEDF_OK;

@@ -249,7 +249,12 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_shade(KArgs a) {
   const int K = a.shade_K;  // 1, 2, 4, 8, 16 or 32
   const int ppw = 32 / K;
   const int slot = lane & 31, q = slot / K, j = slot % K;
-  PairList* PL = &a.C->A;
+  // first pass: the binned pixels (list A), outliers pushed to list B;
+  // second pass (chord mode): list B
+  const bool chord = a.shade_chord != 0;
+  PairList* PL = chord ? &a.C->B : &a.C->A;
+  const uint2* prs_list = chord ? a.pairsB : a.pairs;
+  PairList* RS = &a.C->B;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&PL->work_counter, 1);
     __syncthreads();
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_shade(KArgs a) {
     const int obj = item_object(PL, a.n_obj, item);
     const int local = (item - PL->item_start[obj]) * (ppw * NW) + wave * ppw + q;
     const bool valid = local < PL->cnt[obj];
-    const uint2 pr = a.pairs[PL->off[obj] + (valid ? local : 0)];
+    const uint2 pr = prs_list[PL->off[obj] + (valid ? local : 0)];
     const ObjDesc& od = a.obj[obj];
     const uint8_t* blob = od.blob;
     const nedf_blob_header* hb = reinterpret_cast<const nedf_blob_header*>(blob);
@@ -270,9 +275,21 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_shade(KArgs a) {
     float o[3], d[3], ol[3], dl[3];
     make_ray(a.rays, pr.x, o, d);
     to_local(g, o, d, ol, dl);
-    const float D = a.depth[pr.x];
-    const float step = 2.0f * a.shade_h / float(K);
-    const float t = D - a.shade_h + (float(j) + 0.5f) * step;
+    // sample window in world units: [D - h, D + h], or (chord mode) the
+    // chord of the bounding sphere
+    float t_lo, step;
+    {
+      float ca = 0.0f, cb = 0.0f;
+      if (chord && sphere_chord(ol, dl, od.bound, ca, cb)) {
+        t_lo = g.s * ca;
+        step = g.s * (cb - ca) / float(K);
+      } else {
+        const float D = a.depth[pr.x];
+        t_lo = D - a.shade_h;
+        step = 2.0f * a.shade_h / float(K);
+      }
+    }
+    const float t = t_lo + (float(j) + 0.5f) * step;
     const float tl = t * g.inv_s;
     float p[3] = {fmaf(tl, dl[0], ol[0]), fmaf(tl, dl[1], ol[1]), fmaf(tl, dl[2], ol[2])};
     typename T::frag Benc[NB][KS0];
@@ -319,6 +336,24 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_shade(KArgs a) {
     const int near = (K - 1) / 2;
     const int src = (lane & ~(K - 1)) + near;
     const float n0 = __shfl(c[0], src), n1 = __shfl(c[1], src), n2 = __shfl(c[2], src);
+    if (!chord && a.rs_sigma > 0.0f) {
+      // outlier (Sec. "Deferred Shading"): density below the threshold at
+      // every sample of the pixel; pushed to the object's segment of list B
+      float smax = sig;
+      for (int off = 1; off < K; off <<= 1) smax = fmaxf(smax, __shfl_xor(smax, off));
+      const bool outlier = valid && half == 0 && j == 0 && smax < a.rs_sigma;
+      const uint64_t m = __ballot(outlier);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) {
+          base = atomicAdd(&RS->cnt[obj], __popcll(m));
+          atomicAdd(&a.C->stats[1], __popcll(m));
+        }
+        base = __shfl(base, leader);
+        if (outlier) a.pairsB[RS->off[obj] + base + __popcll(m & ((1ull << lane) - 1ull))] = pr;
+      }
+    }
     if (valid && half == 0 && j == 0) {
       float* out = a.rgb + 3 * size_t(pr.x);
       if (sw < 1e-6f) {
@@ -424,18 +459,75 @@ void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ml
   prof_mark("infer.refine", s, false);
 }
 
-void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype) {
+namespace {
+void launch_shade(const KArgs& k, hipStream_t s, int dtype) {
+  if (dtype == NEDF_BF16)
+    hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, 2, 1, 8>), dim3(cu_count2()), dim3(512), 0, s, k);
+  else
+    hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128, eng::sb_default<0>(), 1, 4>), dim3(cu_count2()), dim3(256),
+                       0, s, k);
+}
+}  // namespace
+
+// List B takes the outliers of the first shading pass in the segments of
+// list A (an object's outliers are a subset of its pixels); its counts and the
+// resampling count start at zero.
+__global__ void k_rs_prepare(KArgs a) {
+  const int m = threadIdx.x;
+  PairList* A = &a.C->A;
+  PairList* B = &a.C->B;
+  if (m <= a.n_obj) B->off[m] = A->off[m];
+  if (m < a.n_obj) {
+    B->cnt[m] = 0;
+    B->fill[m] = 0;
+  }
+  if (m == 0) {
+    B->total_items = B->work_counter = B->total_pairs = 0;
+    a.C->stats[1] = 0;
+  }
+}
+
+// Work items of the outlier list (segments fixed by k_rs_prepare).
+__global__ void k_rs_items(KArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  PairList* L = &a.C->B;
+  int items = 0, total = 0;
+  for (int m = 0; m < a.n_obj; ++m) {
+    L->item_start[m] = items;
+    const int c = L->cnt[m];
+    if ((a.item_mask >> m) & 1u) items += (c + a.item_pairs - 1) / a.item_pairs;
+    total += c;
+  }
+  L->item_start[a.n_obj] = items;
+  L->total_items = items;
+  L->total_pairs = total;
+  L->work_counter = 0;
+}
+
+void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype, int rs_samples) {
   prof_mark("shade", s, true);
   hipLaunchKernelGGL(k_clear_rgb, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids);
   if (nerf_mask) {
     // BF16: one workgroup of 8 waves per CU sharing each weight copy; FP32: 4 waves
     const int nw = dtype == NEDF_BF16 ? 8 : 4;
     stage_bin_pixels(k, s, ids, nerf_mask, (32 / k.shade_K) * nw);
-    if (dtype == NEDF_BF16)
-      hipLaunchKernelGGL((k_shade<1, 256, 8, 10, 4, 128, 2, 1, 8>), dim3(cu_count2()), dim3(512), 0, s, k);
-    else
-      hipLaunchKernelGGL((k_shade<0, 256, 8, 10, 4, 128, eng::sb_default<0>(), 1, 4>), dim3(cu_count2()), dim3(256),
-                         0, s, k);
+    KArgs k1 = k;
+    k1.shade_chord = 0;
+    if (rs_samples > 0) hipLaunchKernelGGL(k_rs_prepare, dim3(1), dim3(NEDF_MAX_OBJECTS + 64), 0, s, k1);
+    else k1.rs_sigma = 0.0f;
+    launch_shade(k1, s, dtype);
+    if (rs_samples > 0) {
+      // second pass: the outliers, volume-rendered over the bounding chord
+      prof_mark("shade.resample", s, true);
+      KArgs k2 = k;
+      k2.shade_chord = 1;
+      k2.shade_K = rs_samples;
+      k2.item_mask = nerf_mask;
+      k2.item_pairs = (32 / rs_samples) * nw;
+      hipLaunchKernelGGL(k_rs_items, dim3(1), dim3(64), 0, s, k2);
+      launch_shade(k2, s, dtype);
+      prof_mark("shade.resample", s, false);
+    }
   }
   prof_mark("shade", s, false);
 }

@@ -82,7 +82,11 @@ void stage_finalize(const KArgs& k, hipStream_t s);
 void stage_bin_pixels(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mask, int per);
 void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mlp_mask, uint32_t sphere_mask,
                   int dtype);
-void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype);
+// rs_samples > 0: pixels whose density stays below k.rs_sigma at every one of
+// their K samples are shaded again by volume rendering over the bounding
+// chord with rs_samples samples.
+void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype,
+                 int rs_samples = 0);
 void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float* so, float* sd,
                        float* dist);
 void stage_shadow_init(const KArgs& k, hipStream_t s, float* shadow);

@@ -49,6 +49,8 @@ struct KArgs {
   int32_t refine_steps;
   int32_t shade_K;
   float shade_h;
+  float rs_sigma;       // outlier threshold of deferred shading (0: off)
+  int32_t shade_chord;  // second pass: samples over the bounding chord of list B's pixels
   float clear_rgb[3];
   float* rgb;
 };

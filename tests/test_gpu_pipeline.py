@@ -484,3 +484,49 @@ def test_infer_fp8_network_and_refine_parity():
     # 77 % checked)
     assert chk.sum() >= 0.7 * hits
     assert np.all(err[chk] <= allow[chk])
+
+
+def test_shade_outlier_resampling_parity():
+    """Outlier processing in deferred shading (Sec. "Deferred Shading"): with
+    an untrained intersection network many depths miss the surface; pixels
+    whose density stays below the threshold at every one of their K samples
+    are shaded again over the bounding chord.  The library's colours (of its
+    own float32 depth and ID buffers) against the oracle's (of its own), and
+    the outlier sets, element by element; exempt: ID near-ties and pixels
+    whose outlier decision changes within 1e-3 of the threshold."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene()
+    log("case: shade f32 K=8 with outlier resampling (32 chord samples)")
+    o32, d32 = _f32_rays(cam)
+    rays = _gpu_rays(o32, d32)
+    sc = gpu_scene(models, insts, "f32", nedf_models=nedfs)
+    depth, ident = api.infer_depth_id(sc, rays, dtype="f32", refine_steps=0)
+    thr = 1.0
+    ws = api.Workspace()
+    rgb = api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, clear_rgb=(0.1, 0.2, 0.3), dtype="f32", ws=ws,
+                             rs_sigma=thr, rs_samples=32)
+    n_rs = api.ws_counters(ws)["fallback"]
+    rgb0 = api.shade_deferred(sc, rays, depth, ident, K=8, h=0.05, clear_rgb=(0.1, 0.2, 0.3), dtype="f32")
+    ident_g, rgb, rgb0 = _np(ident).astype(np.int64), _np(rgb).astype(np.float64), _np(rgb0).astype(np.float64)
+    o, d = o32.astype(np.float64), d32.astype(np.float64)
+    best, id_o, ex_id, _ = _oracle_depth_id(_oracle_pairs(models, nedfs, insts, o, d, "f32", 128), "f32")
+    recs = [f32_record(i) for i in insts]
+    dep_o = np.where(id_o >= 0, best, np.inf)
+    ref, outl = shade_deferred(models, recs, o, d, dep_o, id_o, K=8, h=0.05, clear=(0.1, 0.2, 0.3), rs_sigma=thr,
+                               rs_samples=32, return_outliers=True)
+    _, lo = shade_deferred(models, recs, o, d, dep_o, id_o, K=8, h=0.05, rs_sigma=thr * (1 - 1e-3), rs_samples=32,
+                           return_outliers=True)
+    _, hi = shade_deferred(models, recs, o, d, dep_o, id_o, K=8, h=0.05, rs_sigma=thr * (1 + 1e-3), rs_samples=32,
+                           return_outliers=True)
+    exempt = ex_id | (lo != hi)
+    chk = (ident_g == id_o) & ~exempt
+    err = np.abs(rgb[chk] - ref[chk]).max(axis=1)
+    changed = np.abs(rgb - rgb0).max(axis=1) > 0
+    log(f"[shade rs f32] hits={int((id_o >= 0).sum())} outliers oracle={int(outl.sum())} library={n_rs} "
+        f"changed_by_rs={int(changed.sum())} exempt={int(exempt.sum())} max_err={err.max():.3e}")
+    assert outl.sum() > 50
+    assert ((ident_g != id_o) & ~ex_id).sum() == 0
+    assert abs(n_rs - int(outl.sum())) <= int((lo != hi).sum())
+    assert np.array_equal(changed[chk & (id_o >= 0)], outl[chk & (id_o >= 0)])
+    assert err.max() <= 2e-4
