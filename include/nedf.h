@@ -183,6 +183,11 @@ typedef struct nedf_shadow_opts {
   float beta;               /* attenuation 0 < beta < 1 per shadowing light */
   int32_t method;           /* 0 = NeDF path (nedf_infer_opts), 1 = plain marcher */
   nedf_infer_opts infer;    /* depth method of the shadow rays */
+  uint32_t directional_mask;  /* bit m set: light m is directional (lights[m] is its direction of travel,
+                                 normalised by the library); otherwise a point light at lights[m] */
+  float dir_distance;       /* directional lights: shadow rays start this far from x against the light
+                               direction (must exceed the distance from any hit point to the farthest
+                               bounding sphere along that direction) */
 } nedf_shadow_opts;
 
 /* ---------------------------------------------------------------- helpers */
@@ -328,10 +333,13 @@ int32_t nedf_shade_deferred(const nedf_scene* scene, const nedf_rays* rays, cons
                             size_t ws_bytes, nedf_stream_t stream);
 
 /*
- * Shadow step (Alg. 2) for n_lights point lights (host float32 [n_lights][3],
- * at most 8): for each pixel with a valid id, x = o + D d; a ray from each
- * light towards x is resolved like step 1 over all instances (depth D_L);
- * D_L + eps < |L - x| multiplies the pixel's factor by beta.
+ * Shadow step (Alg. 2) for n_lights point or directional lights (host float32
+ * [n_lights][3], at most 8; directional_mask in the options): for each pixel
+ * with a valid id, x = o + D d; a ray from each light towards x (for a
+ * directional light with direction l: from x - dir_distance l along l, an
+ * orthographic shadow ray) is resolved like step 1 over all instances (depth D_L);
+ * D_L + eps < |L - x| (directional: < dir_distance) multiplies the pixel's
+ * factor by beta.
  *   shadow [n] float32 output multiplier; rgb_inout [n][3] (nullable) is
  *   multiplied by it (final composite: colour buffer x shadow buffer).
  */

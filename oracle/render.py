@@ -284,12 +284,19 @@ def shade_deferred(models, insts, o, d, depth, ident, K=8, h=0.05, clear=(0.0, 0
     return (rgb, outl) if return_outliers else rgb
 
 
-def shadow_factor(depth_fn, o, d, depth, ident, lights, eps, beta=0.5):
+def shadow_factor(depth_fn, o, d, depth, ident, lights, eps, beta=0.5, directional=None, dir_distance=0.0):
     """Shadow step (Alg. 2): for each pixel with a valid ID, x = o + D d; for
     each point light L cast a ray from L towards x and get its depth D_L as
     in step 1 (``depth_fn(origins, dirs) -> depth``, all instances).  The
     pixel is shadowed by L when D_L + eps < |L - x|; each shadowing light
-    multiplies the factor by beta (reading for several lights)."""
+    multiplies the factor by beta (reading for several lights).
+
+    Directional lights (Introduction: parallel light as well as point
+    lights): where ``directional[m]`` is set, lights[m] is the direction of
+    travel l (normalised here); the shadow ray starts at x - R l with
+    R = ``dir_distance`` (beyond every bounding sphere) and runs along l,
+    the orthographic counterpart of the point light's ray; shadowed when
+    D_L + eps < R."""
     o = np.asarray(o, F64)
     d = np.asarray(d, F64)
     n = o.shape[0]
@@ -298,8 +305,15 @@ def shadow_factor(depth_fn, o, d, depth, ident, lights, eps, beta=0.5):
     if idx.size == 0:
         return fac
     x = o[idx] + depth[idx, None] * d[idx]
-    for L in lights:
+    for m, L in enumerate(lights):
         L = np.asarray(L, F64)
+        if directional is not None and directional[m]:
+            lv = L / np.linalg.norm(L)
+            ds = np.broadcast_to(lv, x.shape).copy()
+            DL = depth_fn(x - dir_distance * lv, ds)
+            occl = DL + eps < dir_distance
+            fac[idx] = np.where(occl, fac[idx] * beta, fac[idx])
+            continue
         v = x - L
         dist = np.linalg.norm(v, axis=1)
         ds = v / dist[:, None]

@@ -67,7 +67,8 @@ class ShadeOpts(C.Structure):
 
 
 class ShadowOpts(C.Structure):
-    _fields_ = [("eps", C.c_float), ("beta", C.c_float), ("method", C.c_int32), ("infer", InferOpts)]
+    _fields_ = [("eps", C.c_float), ("beta", C.c_float), ("method", C.c_int32), ("infer", InferOpts),
+                ("directional_mask", C.c_uint32), ("dir_distance", C.c_float)]
 
 
 class TrainOpts(C.Structure):

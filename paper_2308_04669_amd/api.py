@@ -351,9 +351,12 @@ def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: to
 def shadow(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, lights, eps: float,
            beta: float = 0.5, method: str = "nedf", dtype: str = "bf16", n_samples: int = 128,
            p_lo: float = 0.2, p_hi: float = 0.8, rgb_inout: torch.Tensor | None = None,
-           ws: Workspace | None = None, out: torch.Tensor | None = None, pair_capacity: int = 0) -> torch.Tensor:
-    """Shadow step of Alg. 2 for point lights; returns the multiplier [n]
-    and multiplies ``rgb_inout`` by it when given."""
+           ws: Workspace | None = None, out: torch.Tensor | None = None, pair_capacity: int = 0,
+           directional=None, dir_distance: float = 0.0) -> torch.Tensor:
+    """Shadow step of Alg. 2 for point lights (and directional lights: the
+    entries of ``lights`` whose flag in ``directional`` is set are directions
+    of travel, with shadow rays starting ``dir_distance`` back along them);
+    returns the multiplier [n] and multiplies ``rgb_inout`` by it when given."""
     lib = A.load()
     n = n_rays(rays)
     dev = scene.inst_w2l.device
@@ -361,7 +364,12 @@ def shadow(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tens
     L = np.ascontiguousarray(np.asarray(lights, np.float32).reshape(-1, 3))
     sc = scene.struct()
     io = infer_opts(dtype, p_lo, p_hi, 0, 0.05, n_samples)
-    opts = A.ShadowOpts(eps=eps, beta=beta, method=0 if method == "nedf" else 1, infer=io)
+    mask = 0
+    for i, f in enumerate(directional or []):
+        if f:
+            mask |= 1 << i
+    opts = A.ShadowOpts(eps=eps, beta=beta, method=0 if method == "nedf" else 1, infer=io, directional_mask=mask,
+                        dir_distance=dir_distance)
     nbytes = lib.nedf_workspace_size(A.OPS["shadow"], C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
     buf = ws.get(nbytes)

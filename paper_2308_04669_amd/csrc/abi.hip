@@ -593,6 +593,10 @@ extern "C" int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, c
   if (!(opts->beta > 0.0f && opts->beta < 1.0f)) return fail(NEDF_ERR_SHAPE, "beta must be in (0, 1)");
   if (!(opts->eps >= 0.0f)) return fail(NEDF_ERR_SHAPE, "eps must be >= 0");
   if (opts->method != 0 && opts->method != 1) return fail(NEDF_ERR_SHAPE, "method must be 0 (NeDF) or 1 (marcher)");
+  if (n_lights < 32 && (opts->directional_mask >> n_lights) != 0)
+    return fail(NEDF_ERR_SHAPE, "directional_mask names a light beyond n_lights");
+  if (opts->directional_mask && !(opts->dir_distance > 0.0f))
+    return fail(NEDF_ERR_SHAPE, "directional lights need dir_distance > 0");
   int32_t st = opts->method == 0 ? check_infer_opts(&opts->infer) : check_march_opts(&opts->infer.march);
   if (st) return st;
   const int32_t dtype = opts->method == 0 ? opts->infer.dtype : opts->infer.march.dtype;
@@ -638,7 +642,14 @@ extern "C" int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, c
   Ps.k.ray_grid_w = rs.kind == 0 ? rs.width : 0;
   prof_mark("shadow", s, true);
   for (int m = 0; m < n_lights; ++m) {
-    stage_shadow_rays(Pp.k, s, id, lights + 3 * m, so, sd, dist);
+    const bool dirl = (opts->directional_mask >> m) & 1u;
+    float Lm[3] = {lights[3 * m], lights[3 * m + 1], lights[3 * m + 2]};
+    if (dirl) {
+      const float nrm = std::sqrt(Lm[0] * Lm[0] + Lm[1] * Lm[1] + Lm[2] * Lm[2]);
+      if (!(nrm > 0.0f)) return fail(NEDF_ERR_SHAPE, "a directional light needs a nonzero direction");
+      for (float& v : Lm) v /= nrm;
+    }
+    stage_shadow_rays(Pp.k, s, id, Lm, dirl ? opts->dir_distance : 0.0f, so, sd, dist);
     if (opts->method == 0) {
       apply_march_opts(Ps.k, opts->infer.march);
       nedf_infer_opts io = opts->infer;

@@ -368,17 +368,31 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_shade(KArgs a) {
 // ---- shadows --------------------------------------------------------------------
 // Shadow ray of pixel p for light Lm: origin Lm, direction towards
 // x = o + D d; pixels without an ID get a NaN ray (culled everywhere).
-__global__ void k_shadow_rays(KArgs a, const int32_t* ids, float lx, float ly, float lz, float* so, float* sd,
-                              float* dist) {
+// Shadow rays of one light (Alg. 2) for the hit pixels: from a point light
+// at (lx, ly, lz) towards x = o + D d, or (dir_dist > 0) for a directional
+// light of unit direction of travel (lx, ly, lz), from x - dir_dist l along
+// l (parallel, orthographic rays); dist gets the distance from the origin to
+// x.  Pixels without a hit get a NaN direction (culled as no candidate).
+__global__ void k_shadow_rays(KArgs a, const int32_t* ids, float lx, float ly, float lz, float dir_dist, float* so,
+                              float* sd, float* dist) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= a.n_rays) return;
   float o[3], d[3];
   make_ray(a.rays, p, o, d);
   const float D = a.depth[p];
   const bool hit = ids[p] >= 0;
-  const float x = fmaf(D, d[0], o[0]) - lx, y = fmaf(D, d[1], o[1]) - ly, z = fmaf(D, d[2], o[2]) - lz;
-  const float r = sqrtf(x * x + y * y + z * z);
   const float nan = __int_as_float(0x7fc00000);
+  const float px = fmaf(D, d[0], o[0]), py = fmaf(D, d[1], o[1]), pz = fmaf(D, d[2], o[2]);
+  if (dir_dist > 0.0f) {
+    so[3 * p + 0] = fmaf(-dir_dist, lx, px);
+    so[3 * p + 1] = fmaf(-dir_dist, ly, py);
+    so[3 * p + 2] = fmaf(-dir_dist, lz, pz);
+    sd[3 * p + 0] = hit ? lx : nan; sd[3 * p + 1] = hit ? ly : nan; sd[3 * p + 2] = hit ? lz : nan;
+    dist[p] = hit ? dir_dist : 0.f;
+    return;
+  }
+  const float x = px - lx, y = py - ly, z = pz - lz;
+  const float r = sqrtf(x * x + y * y + z * z);
   const float inv = hit && r > 0.f ? 1.0f / r : nan;
   so[3 * p + 0] = lx; so[3 * p + 1] = ly; so[3 * p + 2] = lz;
   sd[3 * p + 0] = x * inv; sd[3 * p + 1] = y * inv; sd[3 * p + 2] = z * inv;
@@ -532,10 +546,10 @@ void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ner
   prof_mark("shade", s, false);
 }
 
-void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float* so, float* sd,
-                       float* dist) {
-  hipLaunchKernelGGL(k_shadow_rays, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids, L[0], L[1], L[2], so, sd,
-                     dist);
+void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float dir_dist, float* so,
+                       float* sd, float* dist) {
+  hipLaunchKernelGGL(k_shadow_rays, dim3(grid_n(k.n_rays)), dim3(256), 0, s, k, ids, L[0], L[1], L[2], dir_dist, so,
+                     sd, dist);
 }
 
 void stage_shadow_init(const KArgs& k, hipStream_t s, float* shadow) {

@@ -87,8 +87,8 @@ void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t ml
 // chord with rs_samples samples.
 void stage_shade(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t nerf_mask, int dtype,
                  int rs_samples = 0);
-void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float* so, float* sd,
-                       float* dist);
+void stage_shadow_rays(const KArgs& k, hipStream_t s, const int32_t* ids, const float L[3], float dir_dist, float* so,
+                       float* sd, float* dist);
 void stage_shadow_init(const KArgs& k, hipStream_t s, float* shadow);
 void stage_shadow_apply(const KArgs& k, hipStream_t s, const int32_t* ids, const float* depth_l, const float* dist,
                         float eps, float beta, float* shadow);

@@ -530,3 +530,64 @@ def test_shade_outlier_resampling_parity():
     assert abs(n_rs - int(outl.sum())) <= int((lo != hi).sum())
     assert np.array_equal(changed[chk & (id_o >= 0)], outl[chk & (id_o >= 0)])
     assert err.max() <= 2e-4
+
+
+@pytest.mark.parametrize("method", ["march", "nedf"])
+def test_shadow_directional_light(method):
+    """Directional-light shadows (orthographic shadow rays from x - R l along
+    l): the library's factors of its own depth buffer against the oracle's
+    of its own; exempt: ID near-ties and occlusion tests within the two
+    tolerances of the cut R - eps (float32)."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    l = np.array([0.2, -1.0, 0.3])
+    R = 30.0
+    eps = 0.05
+    if method == "march":
+        a, _ = syn.config1_models()
+        models, nedfs = [a], None
+        insts = [syn.Instance(0, np.eye(3), np.zeros(3), 1.0),
+                 syn.Instance(0, np.eye(3), np.array([0.0, 1.2, 0.0]), 1.0)]
+        cam = syn.Camera(eye=(3.0, 0.6, 3.0), at=(0.0, 0.6, 0.0), up=(0, 1, 0), fov_y_deg=40.0, width=40,
+                         height=40)
+    else:
+        models, nedfs, insts, cam = _nedf_scene(n_inst=5, size=40)
+    log(f"case: directional light shadows, {method}")
+    o32, d32 = _f32_rays(cam)
+    rays = _gpu_rays(o32, d32)
+    sc = gpu_scene(models, insts, "f32", nedf_models=nedfs)
+    if method == "march":
+        depth, ident, _ = api.march_depth(sc, rays, n_samples=256)
+    else:
+        depth, ident = api.infer_depth_id(sc, rays, dtype="f32", refine_steps=0)
+    fac = api.shadow(sc, rays, depth, ident, [l], eps=eps, beta=0.5, method=method, dtype="f32", n_samples=256,
+                     directional=[True], dir_distance=R)
+    ident_g, fac = _np(ident).astype(np.int64), _np(fac).astype(np.float64)
+    o, d = o32.astype(np.float64), d32.astype(np.float64)
+    recs = [f32_record(i) for i in insts]
+    if method == "march":
+        As, Ds, _ = per_instance(models, recs, o, d, 256)
+        best = Ds.min(axis=0)
+        id_o = np.where(np.isfinite(best), Ds.argmin(axis=0), -1)
+        ex_id = (np.abs(As - 0.5) <= 1e-4).any(axis=0)
+        fn = lambda oo, dd: march_compose(models, recs, oo, dd, 256)[0]
+        amb_fn = None
+    else:
+        best, id_o, ex_id, _ = _oracle_depth_id(_oracle_pairs(models, nedfs, insts, o, d, "f32", 128), "f32")
+        fn = None
+    hitp = np.nonzero(id_o >= 0)[0]
+    x = o[hitp] + best[hitp, None] * d[hitp]
+    lv = l / np.linalg.norm(l)
+    so, ds = x - R * lv, np.broadcast_to(lv, x.shape).copy()
+    if method == "march":
+        DL = fn(so, ds)
+        ex_s = np.zeros(hitp.size, bool)
+    else:
+        DL, _, ex_s, _ = _oracle_depth_id(_oracle_pairs(models, nedfs, insts, so, ds, "f32", 128), "f32")
+    ref = np.ones(len(o))
+    ref[hitp] = np.where(DL + eps < R, 0.5, 1.0)
+    margin = ex_id | (ident_g != id_o)
+    margin[hitp] |= ex_s | (np.abs(DL + eps - R) <= 1e-3)
+    assert ((ident_g != id_o) & ~ex_id).sum() == 0
+    _shadow_compare(fac, ref, margin, f"shadow directional {method}")
+    assert (ref < 1).sum() > 20 and margin.sum() <= 0.05 * len(o)

@@ -206,3 +206,46 @@ def test_shadow_two_spheres_brute_force():
     assert clear_occl.sum() > 10 and clear_lit.sum() > 10
     assert np.all(fac[ident < 0] == 1.0)
     assert set(np.unique(fac)).issubset({1.0, 0.5})
+
+
+def test_shadow_directional_light_two_spheres():
+    """A directional light (parallel rays travelling along l) over two
+    analytic spheres: a hit point is shadowed exactly when the line from it
+    back towards the light meets the other sphere (closed form: distance of
+    that sphere's centre from the line below its radius, centre on the
+    light's side), away from grazing lines and self-shadowing sides."""
+    a, _ = syn.config1_models()
+    models = [a]
+    insts = [syn.Instance(0, np.eye(3), np.array([0.0, 0.0, 0.0]), 1.0),
+             syn.Instance(0, np.eye(3), np.array([0.0, 1.2, 0.0]), 1.0)]
+    l = np.array([0.15, -1.0, 0.1])
+    l /= np.linalg.norm(l)
+    cam = syn.Camera(eye=(3.0, 0.6, 3.0), at=(0.0, 0.6, 0.0), up=(0, 1, 0), fov_y_deg=40.0, width=40, height=40)
+    o, d = camera_rays(cam)
+    N = 256
+    depth, ident, _ = march_compose(models, insts, o, d, N)
+    depth_fn = lambda oo, dd: march_compose(models, insts, oo, dd, N)[0]
+    R = 10.0
+    fac = shadow_factor(depth_fn, o, d, depth, ident, [l], eps=0.05, beta=0.5, directional=[True], dir_distance=R)
+    idx = np.nonzero(ident >= 0)[0]
+    x = o[idx] + depth[idx, None] * d[idx]
+    occl = np.zeros(idx.size, bool)
+    graze = np.zeros(idx.size, bool)
+    for k, inst in enumerate(insts):
+        c = inst.T
+        s_ = (c - x) @ (-l)                     # along the line towards the light
+        dist_c = np.linalg.norm((c - x) - s_[:, None] * (-l), axis=1)
+        other = ident[idx] != k
+        occl |= other & (s_ > 0) & (dist_c < 0.5)
+        graze |= other & (np.abs(dist_c - 0.5) < 0.08)
+    own = np.array([insts[k].T for k in ident[idx]])
+    nrm = (x - own) / np.linalg.norm(x - own, axis=1, keepdims=True)
+    facing = nrm @ (-l)
+    got = fac[idx] < 1.0
+    sure_occl = occl & ~graze
+    sure_lit = ~occl & ~graze & (facing > 0.3)
+    assert sure_occl.sum() > 10 and sure_lit.sum() > 10
+    assert np.all(got[sure_occl]) and not np.any(got[sure_lit])
+    # the same light as a point light far away along -l gives nearly the same shadows
+    far = shadow_factor(depth_fn, o, d, depth, ident, [-1e4 * l], eps=0.05, beta=0.5)
+    assert np.mean(far[idx] == fac[idx]) > 0.98
