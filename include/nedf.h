@@ -303,6 +303,41 @@ int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, cons
                             float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream);
 
 /*
+ * Buffer reuse while one object is manipulated (Sec. "CUDA implementation":
+ * the other objects' rendering is frozen and their buffers reused).  The
+ * depth of nedf_infer_depth_id is the minimum over instances of a per-pair
+ * key; split the instances into disjoint sets, keep the keys of the sets that
+ * do not move, recompute only the moving set's keys each frame, and merge.
+ *
+ * nedf_infer_keys: the first half of nedf_infer_depth_id (culling, the
+ * intersection networks, the marcher fallback) on `scene`, typically a
+ * subset of the full scene's instances, writing for every ray the key
+ * (float bits of the world depth << 32) | instance, or 0x7F800000FFFFFFFF
+ * (no hit), into keys [n] (device, uint64, 16-byte aligned, written whole).
+ * inst_gid (device int32 [scene->n_inst], or NULL for the identity) gives the
+ * index each instance of `scene` has in the full scene; that index is what
+ * the key carries, and what breaks ties.  The refinement options are not
+ * used here.  ws as for nedf_infer_depth_id on `scene`; the pair-list status
+ * is read with nedf_check_status(ws).
+ *
+ * nedf_compose_keys: merges 1..8 key buffers (device uint64 [n] each, the
+ * key_sets array itself on the host) by their per-ray minimum and finishes
+ * as nedf_infer_depth_id does (depth/id, then secant refinement on the full
+ * `scene`, which must hold every instance the keys name).  For disjoint sets
+ * covering the full scene, and the same rays and options, depth and id are
+ * bit-identical to one nedf_infer_depth_id call on the full scene.  A key
+ * naming an instance >= scene->n_inst is dropped and sets NEDF_ERR_SHAPE in
+ * the status word of ws (nedf_check_status).  ws: as for
+ * nedf_infer_depth_id on the full scene.
+ */
+int32_t nedf_infer_keys(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                        const int32_t* inst_gid, uint64_t* keys, void* ws, size_t ws_bytes,
+                        nedf_stream_t stream);
+int32_t nedf_compose_keys(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                          const uint64_t* const* key_sets, int32_t n_sets, float* depth, int32_t* id,
+                          void* ws, size_t ws_bytes, nedf_stream_t stream);
+
+/*
  * nedf_infer_depth_id for callers that cannot allocate device memory (code
  * under HIP graph capture, fixed-memory serving loops, harnesses that forbid
  * hipMalloc): the same computation and results, with the workspace taken

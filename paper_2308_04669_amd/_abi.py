@@ -104,6 +104,11 @@ SIGNATURES = [
     ("nedf_infer_depth_id_static", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(InferOpts),
                                                C.c_void_p, C.c_void_p, C.c_void_p]),
     ("nedf_static_scratch_bytes", C.c_size_t, []),
+    ("nedf_infer_keys", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(InferOpts), C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("nedf_compose_keys", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.POINTER(InferOpts),
+                                      C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_size_t, C.c_void_p]),
     ("nedf_shade_deferred", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p,
                                         C.POINTER(ShadeOpts), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("nedf_shadow", C.c_int32, [C.POINTER(Scene), C.POINTER(Rays), C.c_void_p, C.c_void_p, C.c_void_p,

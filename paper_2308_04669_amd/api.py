@@ -323,6 +323,65 @@ def infer_depth_id_static(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_
     return depth, ident
 
 
+def subset_scene(scene: SceneGPU, idx) -> tuple[SceneGPU, torch.Tensor]:
+    """The instances ``idx`` of ``scene`` as a scene of their own (same
+    objects), with the int32 device tensor of their indices in ``scene`` for
+    ``infer_keys``."""
+    dev = scene.inst_w2l.device
+    ix = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
+    sub = SceneGPU(scene.objects, scene.inst_object[ix].contiguous(), scene.inst_G[ix].contiguous(),
+                   scene.inst_w2l[ix].contiguous())
+    return sub, ix.to(torch.int32).contiguous()
+
+
+def infer_keys(scene: SceneGPU, rays: A.Rays, inst_gid: torch.Tensor | None = None, dtype: str = "bf16",
+               p_lo: float = 0.2, p_hi: float = 0.8, n_samples: int = 128, ws: Workspace | None = None,
+               pair_capacity: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per-ray depth keys (int64 [n]; float bits of the depth << 32 | instance
+    index in the full scene, all ones in the low word for no hit) of the
+    instances of ``scene``: the part of ``infer_depth_id`` that
+    ``compose_keys`` can reuse across frames."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    keys = out if out is not None else torch.empty(n, dtype=torch.int64, device=dev)
+    sc = scene.struct()
+    opts = infer_opts(dtype, p_lo, p_hi, 0, 0.05, n_samples)
+    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), int(pair_capacity))
+    ws = ws or Workspace(dev)
+    buf = ws.get(nbytes)
+    A.check(lib.nedf_infer_keys(C.byref(sc), C.byref(rays), C.byref(opts), _ptr(inst_gid), _ptr(keys),
+                                buf.data_ptr(), int(nbytes), _stream()), "nedf_infer_keys")
+    return keys
+
+
+def compose_keys(scene: SceneGPU, rays: A.Rays, key_sets, dtype: str = "bf16", refine_steps: int = 3,
+                 refine_h: float = 0.05, n_samples: int = 128, ws: Workspace | None = None, out=None):
+    """Depth and ID of the full ``scene`` from the keys of disjoint instance
+    sets (``infer_keys``), merged by their minimum and refined.  Returns
+    (depth float32 [n], id int32 [n])."""
+    lib = A.load()
+    n = n_rays(rays)
+    dev = scene.inst_w2l.device
+    if out is None:
+        depth = torch.empty(n, dtype=torch.float32, device=dev)
+        ident = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        depth, ident = out
+    sets = list(key_sets)
+    for k in sets:
+        assert k.dtype == torch.int64 and k.is_contiguous() and k.numel() == n
+    arr = (C.c_void_p * len(sets))(*[k.data_ptr() for k in sets])
+    sc = scene.struct()
+    opts = infer_opts(dtype, 0.2, 0.8, refine_steps, refine_h, n_samples)
+    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), 0)
+    ws = ws or Workspace(dev)
+    buf = ws.get(nbytes)
+    A.check(lib.nedf_compose_keys(C.byref(sc), C.byref(rays), C.byref(opts), arr, len(sets), _ptr(depth),
+                                  _ptr(ident), buf.data_ptr(), int(nbytes), _stream()), "nedf_compose_keys")
+    return depth, ident
+
+
 def shade_deferred(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tensor, K: int = 8,
                    h: float = 0.05, clear_rgb=(0.0, 0.0, 0.0), dtype: str = "bf16", ws: Workspace | None = None,
                    out: torch.Tensor | None = None, pair_capacity: int = 0, rs_sigma: float = 0.0,

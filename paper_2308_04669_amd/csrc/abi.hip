@@ -322,8 +322,8 @@ void run_march(const Prepared& P, int dtype, hipStream_t s) {
   stage_finalize(P.k, s);
 }
 
-// NeDF depth (+ fallback, + refinement) into k.depth / k.id.
-void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream_t s) {
+// NeDF depth keys (+ fallback) of every pair into k.keys.
+void run_infer_keys(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream_t s) {
   KArgs k = P.k;
   k.p_lo = o.p_lo;
   k.p_hi = o.p_hi;
@@ -335,6 +335,11 @@ void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream
   if (P.nedf) stage_nedf(k, s, P.nedf_dtype, P.nedf, tune_value(NEDF_TUNE_SLABS, P.nedf_dtype));
   // uncertain pairs: marcher on list B
   stage_march(k, s, true, P.analytic, dtype, (P.mlp & P.nedf) ? P.W : 0, P.H, P.L);
+}
+
+// Keys -> depth / id, then refinement of the winners.
+void run_finish(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream_t s) {
+  KArgs k = P.k;
   stage_finalize(k, s);
   if (o.refine_steps > 0 && k.id) {
     k.refine_h = o.refine_h;
@@ -342,6 +347,12 @@ void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream
     const uint32_t mlp_ok = refine_supported(dtype, P.dshape) ? P.sdf_mlp : 0u;
     if (mlp_ok | P.sphere) stage_refine(k, s, k.id, mlp_ok, P.sphere, dtype);
   }
+}
+
+// NeDF depth (+ fallback, + refinement) into k.depth / k.id.
+void run_infer(const Prepared& P, int dtype, const nedf_infer_opts& o, hipStream_t s) {
+  run_infer_keys(P, dtype, o, s);
+  run_finish(P, dtype, o, s);
 }
 
 }  // namespace
@@ -485,6 +496,75 @@ int32_t infer_impl(const nedf_scene* scene, const nedf_rays* rays, const nedf_in
 extern "C" int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
                                        float* depth, int32_t* id, void* ws, size_t ws_bytes, nedf_stream_t stream) {
   return infer_impl(scene, rays, opts, depth, id, ws, ws_bytes, stream, "nedf_infer_depth_id");
+}
+
+// ---- buffer reuse under manipulation -------------------------------------------
+extern "C" int32_t nedf_infer_keys(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                                   const int32_t* inst_gid, uint64_t* keys, void* ws, size_t ws_bytes,
+                                   nedf_stream_t stream) {
+  int32_t st = check_infer_opts(opts);
+  if (st) return st;
+  Prepared P;
+  st = prepare_scene(scene, opts->dtype, P);
+  if (st) return st;
+  if (P.mlp & ~P.nedf) return fail(NEDF_ERR_UNSUPPORTED, "every MLP object needs an intersection network (use nedf_march_depth)");
+  RaySrcHost rs;
+  st = check_rays(rays, rs);
+  if (st) return st;
+  if (rs.n == 0) return NEDF_OK;
+  if (!keys) return fail(NEDF_ERR_NULL, "nedf_infer_keys: keys is NULL");
+  if (!aligned16(keys) || (inst_gid && !aligned16(inst_gid)))
+    return fail(NEDF_ERR_ALIGN, "nedf_infer_keys: keys and inst_gid must be 16-byte aligned");
+  WsLayout lay;
+  st = prepare_ws(P, rs, 0, ws, ws_bytes, lay);
+  if (st) return st;
+  set_rays(P.k, rs);
+  apply_march_opts(P.k, opts->march);
+  P.k.inst_gid = inst_gid;
+  P.k.keys = keys;  // the stages build the keys in the caller's buffer
+  run_infer_keys(P, opts->dtype, *opts, static_cast<hipStream_t>(stream));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "nedf_infer_keys");
+  return NEDF_OK;
+}
+
+extern "C" int32_t nedf_compose_keys(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
+                                     const uint64_t* const* key_sets, int32_t n_sets, float* depth, int32_t* id,
+                                     void* ws, size_t ws_bytes, nedf_stream_t stream) {
+  int32_t st = check_infer_opts(opts);
+  if (st) return st;
+  if (n_sets < 1 || n_sets > MAX_KEY_SETS) return fail(NEDF_ERR_SHAPE, "nedf_compose_keys: n_sets must be 1..8");
+  if (!key_sets) return fail(NEDF_ERR_NULL, "nedf_compose_keys: key_sets is NULL");
+  KeySets ks{};
+  ks.n = n_sets;
+  for (int j = 0; j < n_sets; ++j) {
+    if (!key_sets[j]) return fail(NEDF_ERR_NULL, "nedf_compose_keys: a key set is NULL");
+    if (!aligned16(key_sets[j])) return fail(NEDF_ERR_ALIGN, "nedf_compose_keys: key sets must be 16-byte aligned");
+    ks.p[j] = key_sets[j];
+  }
+  Prepared P;
+  st = prepare_scene(scene, opts->dtype, P);
+  if (st) return st;
+  RaySrcHost rs;
+  st = check_rays(rays, rs);
+  if (st) return st;
+  if (rs.n == 0) return NEDF_OK;
+  if (!depth || !id) return fail(NEDF_ERR_NULL, "depth and id are required");
+  if (!aligned16(depth) || !aligned16(id)) return fail(NEDF_ERR_ALIGN, "output buffers must be 16-byte aligned");
+  WsLayout lay;
+  st = prepare_ws(P, rs, 0, ws, ws_bytes, lay);
+  if (st) return st;
+  set_rays(P.k, rs);
+  apply_march_opts(P.k, opts->march);
+  P.k.depth = depth;
+  P.k.id = id;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, P.k.status);
+  stage_merge_keys(P.k, s, ks);
+  run_finish(P, opts->dtype, *opts, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "nedf_compose_keys");
+  return NEDF_OK;
 }
 
 // ---- fixed-memory variant -----------------------------------------------------

@@ -902,6 +902,36 @@ __global__ void k_finalize(KArgs a) {
   if (a.opacity) a.opacity[i] = __uint_as_float(a.opac[i]);
 }
 
+// Buffer reuse (Sec. "CUDA implementation"): the depth keys of several
+// disjoint instance sets, each computed on its own, merged by their minimum
+// into the workspace's keys, which then hold what one pass over the union
+// would have left there (the minimum is order-free and every pair's key
+// depends on its ray and instance alone).  Keys naming an instance at or
+// beyond n_inst are dropped and flag NEDF_ERR_SHAPE in the status word
+// (cleared by the caller beforehand).  Also clears the counters as k_init.
+__global__ void k_merge_keys(KArgs a, KeySets ks) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < a.n_rays) {
+    uint64_t m = NEDF_KEY_EMPTY;
+    bool bad = false;
+    for (int j = 0; j < ks.n; ++j) {
+      const uint64_t k = ks.p[j][i];
+      if (k == NEDF_KEY_EMPTY) continue;
+      if (uint32_t(k & 0xffffffffu) >= uint32_t(a.n_inst)) {
+        bad = true;
+        continue;
+      }
+      m = k < m ? k : m;
+    }
+    a.keys[i] = m;
+    a.opac[i] = 0u;
+    if (bad) set_status(a.status, NEDF_ERR_SHAPE);
+  }
+  constexpr int64_t words = int64_t(sizeof(WsCounters) / 4);
+  for (int64_t w = i; w < words; w += int64_t(gridDim.x) * blockDim.x)
+    reinterpret_cast<int32_t*>(a.C)[w] = w == int64_t(offsetof(WsCounters, dmin_bits) / 4) ? 0x7F800000 : 0;
+}
+
 int cu_count() {
   static int ncu = 0;
   if (ncu == 0) {
@@ -1089,6 +1119,12 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
     prof_mark("net", s, false);
   }
   prof_mark("infer.nedf", s, false);
+}
+
+void stage_merge_keys(const KArgs& k, hipStream_t s, const KeySets& ks) {
+  prof_mark("compose.merge", s, true);
+  hipLaunchKernelGGL(k_merge_keys, dim3(grid_for(k.n_rays)), dim3(256), 0, s, k, ks);
+  prof_mark("compose.merge", s, false);
 }
 
 void stage_finalize(const KArgs& k, hipStream_t s) {

@@ -79,6 +79,12 @@ void stage_march(const KArgs& k, hipStream_t s, bool list_b, uint32_t analytic_m
 // slabs (objects in nedf_mask).
 void stage_nedf(const KArgs& k, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs);
 void stage_finalize(const KArgs& k, hipStream_t s);
+constexpr int MAX_KEY_SETS = 8;
+struct KeySets {
+  const uint64_t* p[MAX_KEY_SETS];
+  int32_t n;
+};
+void stage_merge_keys(const KArgs& k, hipStream_t s, const KeySets& ks);
 void stage_bin_pixels(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mask, int per);
 void stage_refine(const KArgs& k, hipStream_t s, const int32_t* ids, uint32_t mlp_mask, uint32_t sphere_mask,
                   int dtype);

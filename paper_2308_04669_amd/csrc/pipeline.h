@@ -15,6 +15,9 @@ struct KArgs {
   ObjDesc obj[NEDF_MAX_OBJECTS];
   const int32_t* inst_object;
   const float* w2l;
+  // instance index written into the depth keys (null: the scene's own
+  // index); lets keys of a subset of a scene carry the full scene's indices
+  const int32_t* inst_gid;
   int32_t n_samples, clip;
   float t_near, t_far, hit_thr;
   uint32_t item_mask;    // objects whose pairs the matrix-core stage takes
@@ -95,7 +98,8 @@ __device__ __forceinline__ float mlp_surface(const ObjDesc& od, float u, float x
 }
 
 __device__ __forceinline__ void emit_key(const KArgs& a, uint32_t ray, uint32_t inst, float D) {
-  atomicMin(reinterpret_cast<unsigned long long*>(&a.keys[ray]), (unsigned long long)pack_key(D, int(inst)));
+  const int gid = a.inst_gid ? a.inst_gid[inst] : int(inst);
+  atomicMin(reinterpret_cast<unsigned long long*>(&a.keys[ray]), (unsigned long long)pack_key(D, gid));
 }
 
 // Work item -> (object, first pair) of list L (items of `per` pairs).
