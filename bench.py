@@ -111,6 +111,8 @@ def parse():
     p.add_argument("--rs-sigma", type=float, default=0.5,
                    help="frame: outlier threshold of the rs / wo rs shading comparison (1 %% of sigma_max)")
     p.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing beside the eager frames")
+    p.add_argument("--no-manip", action="store_true",
+                   help="skip the buffer-reuse timing (one instance moved, the others' keys kept)")
     # marcher workload
     p.add_argument("--samples", type=int, default=192)
     p.add_argument("--size", type=int, default=800)
@@ -336,6 +338,73 @@ def frame_bench(args):
               "mean_abs_rgb_change_resampled": float(diff[diff > 0].mean()) if bool((diff > 0).any()) else 0.0}
         log(f"outlier resampling {rs}")
 
+    # buffer reuse while one object is manipulated: the keys of the other
+    # instances are computed once and kept; a manipulation frame recomputes
+    # the moving instance's keys, min-merges and refines, against the full
+    # depth+ID pass on the same moved scene (results must be bit-identical)
+    manip = None
+    if not args.no_manip:
+        depth_id()
+        torch.cuda.synchronize()
+        cnt = torch.bincount(ident[ident >= 0].long(), minlength=len(insts))
+        mover = int(cnt.argmax())
+        static_idx = [k for k in range(len(insts)) if k != mover]
+        G = sc.inst_G.clone()
+        G[mover, 9] += 0.03 * extent
+        G[mover, 10] -= 0.02 * extent
+        sc_m = api.SceneGPU(sc.objects, sc.inst_object, G, api.compose_transforms(G))
+        sub_s, gid_s = api.subset_scene(sc_m, static_idx)
+        sub_m, gid_m = api.subset_scene(sc_m, [mover])
+        ws_s, ws_m, ws_c, ws_f = (api.Workspace() for _ in range(4))
+        keys_s = torch.empty(n, dtype=torch.int64, device=dev)
+        keys_m = torch.empty(n, dtype=torch.int64, device=dev)
+        d_m = torch.empty(n, dtype=torch.float32, device=dev)
+        i_m = torch.empty(n, dtype=torch.int32, device=dev)
+        d_f = torch.empty(n, dtype=torch.float32, device=dev)
+        i_f = torch.empty(n, dtype=torch.int32, device=dev)
+        kw = dict(dtype=args.dtype, n_samples=args.fallback_samples)
+
+        # pair lists sized from this frame's culled pairs, not rays x instances
+        cap = int(st["culled_pairs"] * 1.25) + (1 << 20)
+
+        def static_pass():
+            api.infer_keys(sub_s, rays, gid_s, ws=ws_s, out=keys_s, pair_capacity=cap, **kw)
+
+        def manip_frame():
+            sc_m.inst_w2l = api.compose_transforms(sc_m.inst_G)
+            sub_m.inst_w2l = sc_m.inst_w2l[mover:mover + 1]
+            api.infer_keys(sub_m, rays, gid_m, ws=ws_m, out=keys_m, **kw)
+            api.compose_keys(sc_m, rays, [keys_s, keys_m], refine_steps=3, ws=ws_c, out=(d_m, i_m), **kw)
+
+        def full_frame():
+            sc_m.inst_w2l = api.compose_transforms(sc_m.inst_G)
+            api.infer_depth_id(sc_m, rays, refine_steps=3, ws=ws_f, out=(d_f, i_f), pair_capacity=cap, **kw)
+
+        res = {}
+        for name, fn in (("static_keys_once", static_pass), ("manipulation_frame", manip_frame),
+                         ("full_depth_id", full_frame)):
+            fn()
+            torch.cuda.synchronize()
+            m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            m0.record()
+            for _ in range(args.steps):
+                fn()
+            m1.record()
+            torch.cuda.synchronize()
+            res[name] = m0.elapsed_time(m1) / args.steps
+        for w_ in (ws_s, ws_m, ws_c, ws_f):
+            assert api.check_status(w_) == 0, "buffer-reuse leg reported a device status error"
+        same = bool(torch.equal(i_m, i_f) and torch.equal(d_m.view(torch.int32), d_f.view(torch.int32)))
+        manip = {"moved_instance": mover, "moved_instance_pixels": int(cnt[mover]),
+                 "ms_static_keys_once": res["static_keys_once"], "ms_manipulation_frame": res["manipulation_frame"],
+                 "ms_full_depth_id": res["full_depth_id"],
+                 "speedup": res["full_depth_id"] / max(res["manipulation_frame"], 1e-9),
+                 "bit_identical_to_full": same}
+        log(f"buffer reuse {manip}")
+        assert same, "buffer-reuse depth/ID differ from the full pass"
+        del ws_s, ws_m, ws_c, ws_f, keys_s, keys_m
+        torch.cuda.empty_cache()
+
     # plain FP32 marcher on a seeded pixel subset of the same scene
     g = np.random.default_rng(4669 + 1000 * config + 77)
     pix = np.sort(g.choice(n, size=min(args.marcher_pixels, n), replace=False))
@@ -413,6 +482,7 @@ def frame_bench(args):
         "autotune": tune,
         "graph": graph,
         "outlier_resampling": rs,
+        "buffer_reuse": manip,
         "training": train,
         "setup_train_s": setup_train_s,
     }

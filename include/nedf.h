@@ -327,8 +327,9 @@ int32_t nedf_infer_depth_id(const nedf_scene* scene, const nedf_rays* rays, cons
  * covering the full scene, and the same rays and options, depth and id are
  * bit-identical to one nedf_infer_depth_id call on the full scene.  A key
  * naming an instance >= scene->n_inst is dropped and sets NEDF_ERR_SHAPE in
- * the status word of ws (nedf_check_status).  ws: as for
- * nedf_infer_depth_id on the full scene.
+ * the status word of ws (nedf_check_status).  ws: the refinement bins at
+ * most one pair per ray, so nedf_workspace_size(NEDF_OP_INFER, scene, rays,
+ * n) bytes suffice.
  */
 int32_t nedf_infer_keys(const nedf_scene* scene, const nedf_rays* rays, const nedf_infer_opts* opts,
                         const int32_t* inst_gid, uint64_t* keys, void* ws, size_t ws_bytes,

@@ -356,7 +356,8 @@ def infer_keys(scene: SceneGPU, rays: A.Rays, inst_gid: torch.Tensor | None = No
 
 
 def compose_keys(scene: SceneGPU, rays: A.Rays, key_sets, dtype: str = "bf16", refine_steps: int = 3,
-                 refine_h: float = 0.05, n_samples: int = 128, ws: Workspace | None = None, out=None):
+                 refine_h: float = 0.05, n_samples: int = 128, ws: Workspace | None = None, out=None,
+                 pair_capacity: int = 0):
     """Depth and ID of the full ``scene`` from the keys of disjoint instance
     sets (``infer_keys``), merged by their minimum and refined.  Returns
     (depth float32 [n], id int32 [n])."""
@@ -374,7 +375,8 @@ def compose_keys(scene: SceneGPU, rays: A.Rays, key_sets, dtype: str = "bf16", r
     arr = (C.c_void_p * len(sets))(*[k.data_ptr() for k in sets])
     sc = scene.struct()
     opts = infer_opts(dtype, 0.2, 0.8, refine_steps, refine_h, n_samples)
-    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), 0)
+    # the refinement bins at most one pair per ray
+    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), int(pair_capacity or max(n, 1)))
     ws = ws or Workspace(dev)
     buf = ws.get(nbytes)
     A.check(lib.nedf_compose_keys(C.byref(sc), C.byref(rays), C.byref(opts), arr, len(sets), _ptr(depth),
