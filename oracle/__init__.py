@@ -28,6 +28,8 @@ from .render import (march, march_compose, nedf_pair, nedf_compose, secant_refin
                      compose_pruned, march_compose_pruned, nedf_compose_pruned,
                      shade_deferred, shadow_factor, composite)
 from .train import nedf_loss_and_grads, adam_step
+from .classifier import (line_points, encode_points, segment, segment_inverse, classifier_forward,
+                         classifier_decode, classifier_eval, classifier_loss_and_grads)
 
 __all__ = [
     "camera_rays", "to_local", "pluecker", "encode", "sphere_chord", "inverse_transform", "f32_record",
@@ -36,4 +38,6 @@ __all__ = [
     "march", "march_compose", "nedf_pair", "nedf_compose", "secant_refine", "depth_lower_bound",
     "compose_pruned", "march_compose_pruned", "nedf_compose_pruned",
     "shade_deferred", "shadow_factor", "composite", "nedf_loss_and_grads", "adam_step",
+    "line_points", "encode_points", "segment", "segment_inverse", "classifier_forward", "classifier_decode",
+    "classifier_eval", "classifier_loss_and_grads",
 ]

@@ -173,7 +173,14 @@ def nerf_eval(model, x, d, gemm=None):
 
 def nedf_eval(model, o_l, d_l, gemm=None, scales=None):
     """Intersection network F_Phi (Eq. 1) in its regression form: input
-    gamma_L of the line coordinates (d, o x d), output (mu_hat, hit logit z)."""
+    gamma_L of the line coordinates (d, o x d), output (mu_hat, hit logit z).
+    A ``nedf16`` model is the multi-level classifier (Eq. 3-4), decoded to
+    the same (mu / l, z) form."""
+    if model.kind == "nedf16":
+        from .classifier import classifier_eval
+        if scales is not None:
+            raise ValueError("the classifier network has no E4M3 form")
+        return classifier_eval(model, o_l, d_l, gemm=gemm)
     pl, _ = pluecker(np.asarray(o_l, F64), np.asarray(d_l, F64))
     out = mlp_forward(encode(pl, model.params["enc_L"]), model.trunk, gemm=gemm, scales=scales)
     return out[..., 0], out[..., 1]

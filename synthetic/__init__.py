@@ -62,6 +62,8 @@ class Model:
                   (optionally masked to |x| <= bound) or ``sdf`` (SDF-biased)
     * ``nerf``    density trunk as ``mlp`` plus an RGB branch
     * ``nedf``    ray -> (mu_hat, hit logit) network on gamma_L(Pluecker)
+    * ``nedf16``  ray -> (hit logit, coarse and fine bin logits): residual
+                  network on gamma_L of points along the ray
     """
     kind: str
     bound: float = 1.0
@@ -209,6 +211,35 @@ def nedf_model(config: int, stream: int, enc_L: int = 8, width: int = 256, depth
     trunk.W[-1] *= np.float32(head_scale)
     trunk.W[-1][1] *= np.float32(logit_scale)
     return Model(kind="nedf", bound=bound, trunk=trunk, params=dict(enc_L=enc_L))
+
+
+def classifier_model(config: int, stream: int, enc_L: int = 10, n_points: int = 16, width: int = 256,
+                     n_blocks: int = 16, n_coarse: int = 64, n_fine: int = 128, bound: float = 1.0,
+                     block_scale: float = 0.25, bias_std: float = 0.0, tail_scale: float = 1.0) -> Model:
+    """An intersection network in the multi-level classifier form: input
+    n_points x 3 (1 + 2 enc_L) values; layers, in order: head [width, in],
+    then per residual block two [width, width] layers, then the tail
+    [1 + n_coarse + n_fine, width] (rows: hit logit, coarse bins, fine bins).
+    Head and first block layers N(0, 2/fan_in) (He), second block layers the
+    same times ``block_scale`` (keeps the residual stream's growth over the
+    blocks moderate), tail N(0, 1/fan_in) times ``tail_scale``; biases
+    N(0, bias_std^2) (zero: the training initialisation)."""
+    g = rng(config, stream)
+    d_in = n_points * 3 * (1 + 2 * enc_L)
+    W, b = [], []
+
+    def layer(n_out, n_in, std):
+        W.append((g.standard_normal((n_out, n_in)) * std).astype(np.float32))
+        b.append((g.standard_normal(n_out) * bias_std).astype(np.float32))
+
+    layer(width, d_in, math.sqrt(2.0 / d_in))
+    for _ in range(n_blocks):
+        layer(width, width, math.sqrt(2.0 / width))
+        layer(width, width, math.sqrt(2.0 / width) * block_scale)
+    layer(1 + n_coarse + n_fine, width, math.sqrt(1.0 / width) * tail_scale)
+    return Model(kind="nedf16", bound=bound, trunk=MLPWeights(W, b),
+                 params=dict(enc_L=enc_L, n_points=n_points, n_blocks=n_blocks, n_coarse=n_coarse,
+                             n_fine=n_fine))
 
 
 def sdf_scene(config: int, n_inst: int, n_models: int = 4, width: int = 64, height: int = 64,
