@@ -79,7 +79,14 @@ typedef enum nedf_sigma_mode {
 
 typedef enum nedf_input_kind {
   NEDF_IN_XYZ = 0,       /* gamma_L(x), 3 (1 + 2L) features (density / NeRF trunk) */
-  NEDF_IN_PLUECKER = 1   /* gamma_L(d, o x d), 6 (1 + 2L) features (intersection network) */
+  NEDF_IN_PLUECKER = 1,  /* gamma_L(d, o x d), 6 (1 + 2L) features (intersection network) */
+  NEDF_IN_POINTS16 = 2   /* intersection network in the multi-level classifier form (Sec. "Intersection
+                            network", Eq. 3-4, appendix architecture): gamma_L of 16 points on the line,
+                            l ((2k + 1) / 16 - 1) from the tangency point along d, divided by l
+                            (16 x 3 (1 + 2L) features); ReLU head to `width`, n_hidden residual blocks
+                            h + ReLU(W2 ReLU(W1 h + b1) + b2), linear tail of n_out = 193 rows: hit
+                            logit, 64 coarse and 128 fine bin logits.  Instantiated: L = 10, width 256,
+                            16 blocks, F32 and BF16. */
 } nedf_input_kind;
 
 /*
@@ -205,7 +212,8 @@ size_t nedf_mlp_packed_bytes(const nedf_mlp_shape* shape, int32_t dtype);
  * Pack float32 weights into the blob layout the GPU kernels read (matrix-core
  * fragment order, per-lane bias and head tables).  HOST only: W[i]/b[i] are
  * HOST pointers to layer i in PyTorch layout [out][in] / [out], layers in
- * order (hidden layers, head, then colour-branch hidden and colour head).
+ * order (hidden layers, head, then colour-branch hidden and colour head; for
+ * NEDF_IN_POINTS16: head, the two layers of each residual block, tail).
  * `out` is a HOST buffer of nedf_mlp_packed_bytes() bytes; the caller uploads
  * it to the device.  For NEDF_FP8, `fp8_scales` (host, 2 per hidden layer:
  * weight scale, activation scale) is required; otherwise it is ignored.

@@ -215,3 +215,46 @@ def nedf_accumulation_sensitivity(model, o_l, d_l, scales=None, with_p=False):
     kw = dict(gemm="bf16") if scales is None else dict(scales=scales)
     dmu, dp = _head_delta(mlp_forward(x, model.trunk, acc="f32", **kw), mlp_forward(x, model.trunk, **kw))
     return (dmu, dp) if with_p else dmu
+
+
+def classifier_decision_ambiguity(model, o_l, d_l, gemm=None, margin=2.0):
+    """How far the decoded mu (local units) and the hit probability of the
+    classifier-form network may move when its argmax decisions or its hit
+    logit are taken with another summation order (Eq. 4 decodes by argmax, a
+    decision the logits' rounding can flip on a near-tie).  The logits are
+    computed with float64 and with float32 accumulation; eps is ``margin``
+    times the larger of the pair's largest logit difference and a batch-wide
+    floor: the 90th percentile of it in float32 (unrounded activations: the
+    difference is a smooth function of the summation order), its maximum
+    with ``gemm="bf16"``, where a summation difference can move one of the
+    ~8,000 rounded activations of a pair across a rounding boundary, a jump
+    of one bfloat16 step that the other order may take at another pair (in
+    the batch's measured tail).  A coarse bin j with v_c* - v_j <= eps moves mu by
+    |j - c*| 2l / N_c, a fine bin by |f - f*| 2l / (N_c N_f); the returned
+    mu deviation is the largest coarse move plus the largest fine move.
+    Returns (mu_dev [n], p_dev [n])."""
+    from .classifier import classifier_forward, encode_points, line_points
+    from .fields import sigmoid
+    l = model.bound
+    nc, nf = model.params["n_coarse"], model.params["n_fine"]
+    feats = encode_points(line_points(o_l, d_l, l, model.params["n_points"]), model.params["enc_L"])
+    a0, c0, f0 = classifier_forward(model, feats, gemm=gemm)
+    a1, c1, f1 = classifier_forward(model, feats, gemm=gemm, acc="f32")
+    dl = np.maximum(np.abs(c1 - c0).max(axis=1), np.abs(f1 - f0).max(axis=1))
+    da = np.abs(a1 - a0)
+    if dl.size == 0:
+        return np.zeros(0), np.zeros(0)
+    q = 0.9 if gemm is None else 1.0
+    eps = margin * np.maximum(dl, np.quantile(dl, q))
+    eps_a = margin * np.maximum(da, np.quantile(da, q))
+
+    def largest_move(v, step):
+        best = np.argmax(v, axis=1)
+        top = v[np.arange(v.shape[0]), best]
+        near = (top[:, None] - v) <= eps[:, None]
+        dist = np.abs(np.arange(v.shape[1])[None, :] - best[:, None]) * near
+        return dist.max(axis=1) * step
+
+    mu_dev = largest_move(c0, 2.0 * l / nc) + largest_move(f0, 2.0 * l / (nc * nf))
+    p_dev = np.maximum(np.abs(sigmoid(a0 + eps_a) - sigmoid(a0)), np.abs(sigmoid(a0 - eps_a) - sigmoid(a0)))
+    return mu_dev, p_dev

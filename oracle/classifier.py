@@ -93,26 +93,36 @@ def _layers(model):
     return W, b
 
 
-def classifier_forward(model, feats, gemm=None, keep=False):
+def classifier_forward(model, feats, gemm=None, keep=False, acc=None):
     """Network on encoded inputs [n, D_i].  Returns (alpha_hat [n],
     coarse logits [n, N_c], fine logits [n, N_f]) and, with ``keep``, the
-    activations needed by back-propagation."""
+    activations needed by back-propagation.  ``acc="f32"`` sums every
+    matrix product in float32 (in the BLAS routine's order) instead of
+    float64: one of the orders a single-precision accumulator may take, used
+    only to measure how much a result depends on that order, never as the
+    expected value."""
     rnd = _rnd(gemm)
     W, b = _layers(model)
     nb = model.params["n_blocks"]
     nc = model.params["n_coarse"]
+
+    def mm(h, w):
+        if acc == "f32":
+            return (h.astype(np.float32) @ w.T.astype(np.float32)).astype(F64)
+        return h @ w.T
+
     x = rnd(np.asarray(feats, F64))
     acts = {"x": x, "h": [], "a": [], "r": []}
-    h = rnd(np.maximum(x @ rnd(W[0]).T + b[0], 0.0))
+    h = rnd(np.maximum(mm(x, rnd(W[0])) + b[0], 0.0))
     acts["h"].append(h)
     for k in range(nb):
-        a = rnd(np.maximum(h @ rnd(W[1 + 2 * k]).T + b[1 + 2 * k], 0.0))
-        r = np.maximum(a @ rnd(W[2 + 2 * k]).T + b[2 + 2 * k], 0.0)
+        a = rnd(np.maximum(mm(h, rnd(W[1 + 2 * k])) + b[1 + 2 * k], 0.0))
+        r = np.maximum(mm(a, rnd(W[2 + 2 * k])) + b[2 + 2 * k], 0.0)
         h = rnd(h + r)
         acts["a"].append(a)
         acts["r"].append(r)
         acts["h"].append(h)
-    out = h @ rnd(W[-1]).T + b[-1]
+    out = mm(h, rnd(W[-1])) + b[-1]
     res = (out[:, 0], out[:, 1:1 + nc], out[:, 1 + nc:])
     return (res, acts) if keep else res
 

@@ -16,7 +16,7 @@ STATUS = {0: "OK", 1: "NULL", 2: "SHAPE", 3: "DTYPE", 4: "ALIGN", 5: "WORKSPACE"
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 FIELDS = {"sphere": 0, "slab": 1, "mlp": 2}
 SIGMA_MODES = {"softplus": 0, "softplus_masked": 1, "sdf": 2}
-IN_KINDS = {"xyz": 0, "pluecker": 1}
+IN_KINDS = {"xyz": 0, "pluecker": 1, "points16": 2}
 OPS = {"march": 0, "infer": 1, "shade": 2, "shadow": 3}
 TUNE_KERNELS = {"march": 0, "nedf": 1, "slabs": 2}
 

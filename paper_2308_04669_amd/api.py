@@ -139,6 +139,11 @@ def object_from_model(model, dtype: str = "bf16", device=None, nedf_model=None, 
 
 def _pack_nedf(nedf_model, dtype, device, fp8_scales=None) -> PackedMLP:
     t = nedf_model.trunk
+    if nedf_model.kind == "nedf16":
+        # classifier form: head, two layers per residual block, tail
+        nshape = mlp_shape("points16", nedf_model.params["enc_L"], t.W[0].shape[0], nedf_model.params["n_blocks"],
+                           t.W[-1].shape[0])
+        return pack_mlp(t.W, t.b, nshape, dtype, device)
     nshape = mlp_shape("pluecker", nedf_model.params["enc_L"], t.W[0].shape[0], len(t.W) - 1, 2)
     return pack_mlp(t.W, t.b, nshape, dtype, device, fp8_scales=fp8_scales)
 

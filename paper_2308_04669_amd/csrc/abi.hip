@@ -178,6 +178,7 @@ struct Prepared {
   KArgs k;
   int32_t nedf_dtype = -1;            // precision of the intersection networks
   uint32_t analytic = 0, mlp = 0, nedf = 0, sphere = 0, sdf_mlp = 0, nerf = 0;
+  bool nedf_cls = false;  // intersection networks in the classifier form
   int32_t W = 0, H = 0, L = 0;        // density network shape (0 if none)
   nedf_mlp_shape dshape{};
 };
@@ -236,14 +237,22 @@ int32_t prepare_scene(const nedf_scene* sc, int32_t dtype, Prepared& P) {
     if (o.nedf.blob) {
       const nedf_mlp_shape& s = o.nedf.shape;
       if (!aligned16(o.nedf.blob)) return fail(NEDF_ERR_ALIGN, "intersection network blob must be 16-byte aligned");
-      if (s.in_kind != NEDF_IN_PLUECKER || s.n_out != 2) return fail(NEDF_ERR_SHAPE, "intersection network must take Pluecker coordinates and output (mu, logit)");
+      const bool cls = s.in_kind == NEDF_IN_POINTS16;
+      if (!cls && (s.in_kind != NEDF_IN_PLUECKER || s.n_out != 2))
+        return fail(NEDF_ERR_SHAPE, "intersection network must take Pluecker coordinates and output (mu, logit), "
+                                    "or be a classifier-form network");
       if (o.nedf.dtype != dtype && o.nedf.dtype != NEDF_FP8)
         return fail(NEDF_ERR_DTYPE, "intersection network dtype must be the call's dtype or FP8");
       if (P.nedf_dtype >= 0 && o.nedf.dtype != P.nedf_dtype)
         return fail(NEDF_ERR_UNSUPPORTED, "all intersection networks of one call must share a dtype");
+      if (P.nedf && cls != P.nedf_cls)
+        return fail(NEDF_ERR_UNSUPPORTED, "all intersection networks of one call must share a form");
       P.nedf_dtype = o.nedf.dtype;
-      if (!nedf_net_supported(o.nedf.dtype, s.width, s.n_hidden, s.enc_L))
-        return fail(NEDF_ERR_UNSUPPORTED, "intersection network shape not instantiated (width 256, 8 hidden, L8)");
+      P.nedf_cls = cls;
+      if (cls ? !nedf_cls_supported(o.nedf.dtype, s) : !nedf_net_supported(o.nedf.dtype, s.width, s.n_hidden, s.enc_L))
+        return fail(NEDF_ERR_UNSUPPORTED, cls ? "classifier network not instantiated (F32/BF16, width 256, L10, "
+                                                "1..64 blocks, 193 outputs)"
+                                              : "intersection network shape not instantiated (width 256, 8 hidden, L8)");
       P.nedf |= 1u << i;
     }
   }
@@ -332,7 +341,7 @@ void run_infer_keys(const Prepared& P, int dtype, const nedf_infer_opts& o, hipS
   // analytic objects without a network are marched directly
   const uint32_t direct = P.analytic & ~P.nedf;
   if (direct) stage_march(k, s, false, direct, dtype, 0, 0, 0);
-  if (P.nedf) stage_nedf(k, s, P.nedf_dtype, P.nedf, tune_value(NEDF_TUNE_SLABS, P.nedf_dtype));
+  if (P.nedf) stage_nedf(k, s, P.nedf_dtype, P.nedf, tune_value(NEDF_TUNE_SLABS, P.nedf_dtype), P.nedf_cls);
   // uncertain pairs: marcher on list B
   stage_march(k, s, true, P.analytic, dtype, (P.mlp & P.nedf) ? P.W : 0, P.H, P.L);
 }

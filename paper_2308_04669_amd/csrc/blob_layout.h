@@ -87,3 +87,29 @@ int nedf_enc_feature(int n, int L, int a, int h) {
   int c = 2 * i + h;
   return (i < (n + 1) / 2 && c < n) ? c : -1;
 }
+
+// ---- classifier-form intersection network (in_kind NEDF_IN_POINTS16) --------
+// Head: the 16 points' encodings are consumed point by point, so the head
+// layer is stored as chunks that each cover a few K-steps of all 8 output
+// blocks: chunk c, block fb, 16-byte LDS read r sits at (fb * 4 + r) * 1024
+// (BF16: read r is K-step r of point c; F32: two chunks per point, read r
+// holds K-steps 4 r .. 4 r + 3 of the chunk's 16).  A point's 32 argument
+// slots follow the first-layer slot order above with n = 3.  Head bias:
+// [block][lane half][16] float in accumulator order.  Residual layers: as
+// hidden layers above (8 chunks of fragments + bias each).  Tail: 7 chunks,
+// rows reordered to coarse bins 0..63, fine bins 64..191, hit logit 192,
+// zero rows 193..223.
+#define NEDF_CLS_MAGIC 0x534C434Eu  // "NCLS"
+#define NEDF_CLS_POINTS 16
+#define NEDF_CLS_COARSE 64
+#define NEDF_CLS_FINE 128
+#define NEDF_CLS_TAIL_BLOCKS 7
+#define NEDF_CLS_HIT_ROW 192
+
+struct nedf_cls_header {
+  uint32_t magic, version, dtype, in_kind;
+  uint32_t enc_L, width, n_blocks, n_points;
+  uint32_t ks_point, ks_chunk, n_head_chunks, head_chunk_bytes;  // head: K-steps per point / per chunk
+  uint32_t hidden_chunk_bytes, tail_chunk_bytes, pad0, pad1;
+  uint64_t off_head, off_head_bias, off_hidden, hidden_layer_bytes, off_tail, total_bytes;
+};

@@ -25,6 +25,10 @@ __device__ __forceinline__ uint64_t uniform_load_u64(const void* p) {
   typedef __attribute__((address_space(4))) const uint64_t cu64;
   return *(cu64*)uniform_ptr(p);
 }
+__device__ __forceinline__ uint32_t uniform_load_u32(const void* p) {
+  typedef __attribute__((address_space(4))) const uint32_t cu32;
+  return *(cu32*)uniform_ptr(p);
+}
 __device__ __forceinline__ float uniform_load_f32(const void* p) {
   typedef __attribute__((address_space(4))) const float cf32;
   return *(cf32*)uniform_ptr(p);
@@ -209,6 +213,46 @@ __device__ __forceinline__ void local_line(const W2L& g, const float o[3], const
                    ((ol[0].hi * dl[0].lo + ol[0].lo * dl[0].hi) + (ol[1].hi * dl[1].lo + ol[1].lo * dl[1].hi) +
                     (ol[2].hi * dl[2].lo + ol[2].lo * dl[2].hi));
   tperp = -(t.hi + lo);
+}
+
+// The points of the classifier-form network (16 points on the line around
+// its tangency point): the tangency point p_perp = o_l + t_perp d_l
+// (t_perp = -o_l . d_l) divided by l, and d_l, each as hi + lo from the same
+// compensated record transform as local_line; point k is then
+// q + c_k d_l with c_k = (2k + 1) / 16 - 1.
+__device__ __forceinline__ void local_points_frame(const W2L& g, const float o[3], const float d[3],
+                                                   const float dlo[3], float l, f2 q[3], f2 dv[3], float& tperp,
+                                                   float ol_out[3]) {
+#pragma clang fp contract(off)
+  const float zero[3] = {0.0f, 0.0f, 0.0f};
+  f2 ol[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float a0 = g.rt[3 * r + 0], a1 = g.rt[3 * r + 1], a2 = g.rt[3 * r + 2];
+    const f2 a = dot3_c(a0, a1, a2, o, zero);
+    const f2 qq = two_prod(a.hi, g.inv_s);
+    const float qlo = fmaf(a.lo, g.inv_s, qq.lo);
+    const f2 t = two_sum(qq.hi, g.c[r]);
+    ol[r] = fast_two_sum(t.hi, t.lo + qlo);
+    dv[r] = dot3_c(a0, a1, a2, d, dlo);
+    ol_out[r] = ol[r].hi;
+  }
+  const f2 p0 = two_prod(ol[0].hi, dv[0].hi), p1 = two_prod(ol[1].hi, dv[1].hi), p2 = two_prod(ol[2].hi, dv[2].hi);
+  const f2 s = two_sum(p0.hi, p1.hi);
+  const f2 t = two_sum(s.hi, p2.hi);
+  const float lo = ((p0.lo + p1.lo) + p2.lo) + (s.lo + t.lo) +
+                   ((ol[0].hi * dv[0].lo + ol[0].lo * dv[0].hi) + (ol[1].hi * dv[1].lo + ol[1].lo * dv[1].hi) +
+                    (ol[2].hi * dv[2].lo + ol[2].lo * dv[2].hi));
+  const f2 tp = fast_two_sum(-t.hi, -lo);
+  tperp = tp.hi;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const f2 pr = two_prod(tp.hi, dv[r].hi);
+    const f2 sm = two_sum(ol[r].hi, pr.hi);
+    const f2 pp = fast_two_sum(sm.hi, sm.lo + ((pr.lo + ol[r].lo) + (tp.hi * dv[r].lo + tp.lo * dv[r].hi)));
+    const float qh = pp.hi / l;
+    q[r] = {qh, (fmaf(-qh, l, pp.hi) + pp.lo) / l};
+  }
 }
 
 // Line coordinates of a ray given in local space (o, d single precision,

@@ -1022,6 +1022,12 @@ bool nedf_net_supported(int dtype, int width, int n_hidden, int L) {
   return width == 256 && n_hidden == 8 && L == 8;
 }
 
+bool nedf_cls_supported(int dtype, const nedf_mlp_shape& s) {
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
+  return s.in_kind == NEDF_IN_POINTS16 && s.width == 256 && s.enc_L == 10 && s.n_hidden >= 1 && s.n_hidden <= 64 &&
+         s.n_out == 1 + NEDF_CLS_COARSE + NEDF_CLS_FINE;
+}
+
 bool shade_supported(int dtype, const nedf_mlp_shape& s) {
   if (dtype != NEDF_F32 && dtype != NEDF_BF16) return false;
   return s.width == 256 && s.n_hidden == 8 && s.enc_L == 10 && s.rgb_width == 128 && s.dir_L == 4;
@@ -1098,7 +1104,7 @@ void stage_march(const KArgs& k0, hipStream_t s, bool list_b, uint32_t analytic_
   }
 }
 
-void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs) {
+void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs, bool classifier) {
   KArgs k = k0;
   prof_mark("infer.nedf", s, true);
   k.L = &k.C->S;
@@ -1106,14 +1112,15 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
   k.item_mask = nedf_mask;
   // launch shape from the tuning table, fixed for all slabs of the stage
   const int v = dtype == NEDF_F32 ? 11 : tune_value(NEDF_TUNE_NEDF, dtype);
-  k.item_pairs = 32 * tune_waves(v) * nedf_rows(v);
+  k.item_pairs = classifier ? 32 * 4 : 32 * tune_waves(v) * nedf_rows(v);
   for (int slab = 0; slab < n_slabs; ++slab) {
     hipLaunchKernelGGL(k_slab_begin, dim3(1), dim3(64), 0, s, k);
     if (slab == 0) hipLaunchKernelGGL(k_slab_first, dim3(2048), dim3(256), 0, s, k0, nedf_mask, n_slabs);
     else hipLaunchKernelGGL(k_slab_next, dim3(2048), dim3(256), 0, s, k0, slab);
     hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(64), 0, s, k, k.L);
     prof_mark("net", s, true);
-    if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s, v);
+    if (classifier) launch_nedf_cls(k, s, dtype);
+    else if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s, v);
     else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s, v);
     else launch_nedf_net<0>(k, s, v);
     prof_mark("net", s, false);

@@ -77,7 +77,11 @@ void stage_march(const KArgs& k, hipStream_t s, bool list_b, uint32_t analytic_m
                  int L);
 // Intersection-network stage over list A, front to back in n_slabs depth
 // slabs (objects in nedf_mask).
-void stage_nedf(const KArgs& k, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs);
+void stage_nedf(const KArgs& k, hipStream_t s, int dtype, uint32_t nedf_mask, int n_slabs,
+                bool classifier = false);
+// Classifier-form networks (NEDF_IN_POINTS16) over the current slab list.
+void launch_nedf_cls(const KArgs& k, hipStream_t s, int dtype);
+bool nedf_cls_supported(int dtype, const nedf_mlp_shape& s);
 void stage_finalize(const KArgs& k, hipStream_t s);
 constexpr int MAX_KEY_SETS = 8;
 struct KeySets {

@@ -233,6 +233,55 @@ __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
   }
 }
 
+// Residual epilogue: the block's B-operand words already hold the residual
+// stream h; they become h + ReLU(acc), rounded to the operand type once the
+// single-precision sum is formed (F32 and BF16 only).
+template <int DT, int NB, int KSO>
+__device__ __forceinline__ void epi_residual(int fb, const f32x16_t (&acc)[NB], typename Tr<DT>::frag (&Bout)[NB][KSO]) {
+  static_assert(DT == 0 || DT == 1, "residual epilogue: F32 or BF16");
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    if constexpr (DT == 1) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        bf16x8_t v = Bout[nb][2 * fb + q];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = static_cast<__bf16>(static_cast<float>(v[j]) + fmaxf(acc[nb][8 * q + j], 0.0f));
+        Bout[nb][2 * fb + q] = v;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Bout[nb][16 * fb + r] = Bout[nb][16 * fb + r] + fmaxf(acc[nb][r], 0.0f);
+    }
+  }
+}
+
+// Classifier epilogue: running first-maximum of the coarse bins (features
+// 0..63) and fine bins (64..191) of this lane's sample over its own
+// features, and the hit logit (feature 192).  st[nb] = {best coarse value,
+// its bin, best fine value, its bin, hit logit}; a lane's features increase
+// with r, so a strict comparison keeps the first maximum.
+template <int NB, int NOUT>
+__device__ __forceinline__ void epi_argmax(int fb, const f32x16_t (&acc)[NB], float (&st)[NB][NOUT]) {
+  static_assert(NOUT >= 5, "argmax state needs five values");
+  const int half = (threadIdx.x & 63) >> 5;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int f = 32 * fb + 8 * (r / 4) + 4 * half + (r % 4);
+      const float v = acc[nb][r];
+      if (f < NEDF_CLS_COARSE) {
+        if (v > st[nb][0]) { st[nb][0] = v; st[nb][1] = float(f); }
+      } else if (f < NEDF_CLS_COARSE + NEDF_CLS_FINE) {
+        if (v > st[nb][2]) { st[nb][2] = v; st[nb][3] = float(f - NEDF_CLS_COARSE); }
+      } else if (f == NEDF_CLS_HIT_ROW) {
+        st[nb][4] = v;
+      }
+    }
+  }
+}
+
 // Forces the B-operand words written by epi_hidden(fb) to be computed before
 // this point in the instruction stream (an empty volatile asm that reads them).
 template <int DT, int NB, int KSO>
@@ -290,6 +339,8 @@ __device__ __forceinline__ void static_for(F&& f) {
 // head modes one group per head row; D groups are kept in flight ahead of the
 // group being consumed.
 // MODE 0: hidden epilogue into Bout.  MODE 1: head epilogue.  MODE 2: both.
+// MODE 3: residual epilogue into Bout (Bout holds the stream on entry).
+// MODE 4: classifier epilogue into `partial` (see epi_argmax).
 template <int DT, int NB, int KS_IN, int FB, int CB_THIS, int CB_NEXT, int KSO, int NOUT, int MODE,
           int CHUNK, int FB_NEXT = FB, int SBX = sb_default<DT>(), int NW = WAVES>
 __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_IN],
@@ -312,14 +363,18 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   static_assert((KS_IN * T::FRAG) % 1024 == 0, "K-steps must fill whole LDS reads");
   constexpr int G = 4;
   constexpr int NG = (R + G - 1) / G;
-  constexpr int NH = MODE >= 1 ? NOUT : 0;
+  constexpr int NH = (MODE == 1 || MODE == 2) ? NOUT : 0;
   constexpr int PER = 1 + NG + NH;  // read groups per block
   constexpr int E = SB * PER;       // read groups per superchunk
   constexpr int D = 3;              // groups issued ahead of consumption
   constexpr int BIAS = KS_IN * T::FRAG;
   // hidden-layer epilogues are deferred by one block so that their vector
   // work overlaps the next block's matrix ops
-  constexpr bool DEFER = (MODE == 0);
+  constexpr bool DEFER = (MODE == 0 || MODE == 3);
+  auto epi_deferred = [&](int fbx, const f32x16_t(&ax)[NB]) __attribute__((always_inline)) {
+    if constexpr (MODE == 3) epi_residual<DT, NB, KSO>(fbx, ax, Bout);
+    else epi_hidden<DT, NB, KSO>(fbx, ax, Bout, qscale);
+  };
   f32x16_t prev[NB];
   // Read groups of a superchunk in consumption order: the bias of its first
   // block, then per block k its fragment groups, with the bias of block k + 1
@@ -410,7 +465,7 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
       constexpr int g = q.idx;
       mma_group<DT, NB, KS_IN, G>(cw, g * G, R, Bin, acc);
       if constexpr (DEFER && g == 0) {
-        if (fb > 0) epi_hidden<DT, NB, KSO>(fb - 1, prev, Bout, qscale);
+        if (fb > 0) epi_deferred(fb - 1, prev);
       }
       // interleave vector work (epilogues, accumulator set-up) with the
       // matrix ops instead of letting it pile up between two of them
@@ -428,6 +483,8 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
           for (int nb = 0; nb < NB; ++nb) prev[nb] = acc[nb];
         } else if constexpr (MODE == 2) {
           epi_hidden<DT, NB, KSO>(fb, acc, Bout, qscale);
+        } else if constexpr (MODE == 4) {
+          epi_argmax<NB, NOUT>(fb, acc, partial);
         }
       }
     } else {
@@ -518,7 +575,7 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
     }
     cur = cur + 1 >= NBUF ? cur + 1 - NBUF : cur + 1;
   }
-  if constexpr (DEFER) epi_hidden<DT, NB, KSO>(FB - 1, prev, Bout, qscale);
+  if constexpr (DEFER) epi_deferred(FB - 1, prev);
 }
 
 // ---- whole trunk ------------------------------------------------------------

@@ -232,9 +232,153 @@ void pack_head(const float* W, int n_out, int in_width, int ks_count, int frag_b
     }
 }
 
+// ---- classifier-form intersection network ------------------------------------
+struct ClsPlan {
+  nedf_cls_header h;
+  nedf_blob_header hb;  // dtype-only header for the shared fragment packer
+  bool ok = false;
+  std::string why;
+};
+
+ClsPlan plan_cls(const nedf_mlp_shape* s, int32_t dtype) {
+  ClsPlan p;
+  std::memset(&p.h, 0, sizeof(p.h));
+  std::memset(&p.hb, 0, sizeof(p.hb));
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16) { p.why = "classifier networks pack as F32 or BF16"; return p; }
+  if (s->width != 256) { p.why = "classifier width must be 256"; return p; }
+  if (s->enc_L != 10) { p.why = "classifier encoding must have 10 levels"; return p; }
+  if (s->n_hidden < 1 || s->n_hidden > 64) { p.why = "residual blocks must be 1..64"; return p; }
+  if (s->n_out != 1 + NEDF_CLS_COARSE + NEDF_CLS_FINE) { p.why = "classifier n_out must be 193"; return p; }
+  if (s->rgb_width) { p.why = "classifier networks have no colour branch"; return p; }
+  const bool bf = dtype == NEDF_BF16;
+  nedf_cls_header& h = p.h;
+  h.magic = NEDF_CLS_MAGIC;
+  h.version = 1;
+  h.dtype = uint32_t(dtype);
+  h.in_kind = NEDF_IN_POINTS16;
+  h.enc_L = uint32_t(s->enc_L);
+  h.width = uint32_t(s->width);
+  h.n_blocks = uint32_t(s->n_hidden);
+  h.n_points = NEDF_CLS_POINTS;
+  const int slots = nedf_enc_slots(3, s->enc_L);  // 32
+  h.ks_point = bf ? uint32_t(slots / 8) : uint32_t(slots);
+  h.ks_chunk = bf ? 4u : 16u;
+  h.n_head_chunks = NEDF_CLS_POINTS * h.ks_point / h.ks_chunk;
+  const uint32_t frag = bf ? 1024u : 256u;
+  h.head_chunk_bytes = 8u * h.ks_chunk * frag;
+  const uint32_t ksh = bf ? uint32_t(s->width / 16) : uint32_t(s->width / 2);
+  h.hidden_chunk_bytes = ksh * frag + 128u;
+  h.tail_chunk_bytes = h.hidden_chunk_bytes;
+  size_t off = align256(sizeof(nedf_cls_header));
+  h.off_head = off;
+  off = align256(off + size_t(h.n_head_chunks) * h.head_chunk_bytes);
+  h.off_head_bias = off;
+  off = align256(off + 1024);
+  h.off_hidden = off;
+  h.hidden_layer_bytes = align256(size_t(8) * h.hidden_chunk_bytes);
+  off += size_t(2 * s->n_hidden) * h.hidden_layer_bytes;
+  h.off_tail = off;
+  off = align256(off + size_t(NEDF_CLS_TAIL_BLOCKS) * h.tail_chunk_bytes);
+  h.total_bytes = off;
+  p.hb.dtype = uint32_t(dtype);
+  p.hb.frag_bytes = frag;
+  p.hb.ks_hidden = ksh;
+  p.ok = true;
+  return p;
+}
+
+// Head fragments: column 63 p + e of W is feature e of point p's encoding.
+void pack_cls_head(const nedf_cls_header& h, const float* W, int cols, uint8_t* dst) {
+  const bool bf = h.dtype == NEDF_BF16;
+  const int per_point = 3 * (1 + 2 * int(h.enc_L));
+  const int cpp = int(h.ks_point / h.ks_chunk);  // chunks per point
+  const int slots = nedf_enc_slots(3, int(h.enc_L));
+  for (uint32_t c = 0; c < h.n_head_chunks; ++c) {
+    const int pt = int(c) / cpp;
+    const int ks0 = (int(c) % cpp) * int(h.ks_chunk);
+    uint8_t* chunk = dst + size_t(c) * h.head_chunk_bytes;
+    for (int fb = 0; fb < 8; ++fb)
+      for (int r = 0; r < 4; ++r) {
+        uint8_t* rd = chunk + size_t(fb * 4 + r) * 1024;
+        for (int l = 0; l < 64; ++l) {
+          const int row = 32 * fb + (l % 32), hh = l / 32;
+          if (bf) {
+            uint16_t* out = reinterpret_cast<uint16_t*>(rd + l * 16);
+            for (int j = 0; j < 8; ++j) {
+              const int a = 8 * (ks0 + r) + j;
+              const int f = a < slots ? nedf_enc_feature(3, int(h.enc_L), a, hh) : -1;
+              const int col = f < 0 ? -1 : per_point * pt + f;
+              out[j] = (col >= 0 && col < cols) ? bf16_rne(W[size_t(row) * cols + col]) : uint16_t(0);
+            }
+          } else {
+            float* out = reinterpret_cast<float*>(rd + l * 16);
+            for (int i = 0; i < 4; ++i) {
+              const int a = ks0 + 4 * r + i;
+              const int f = a < slots ? nedf_enc_feature(3, int(h.enc_L), a, hh) : -1;
+              const int col = f < 0 ? -1 : per_point * pt + f;
+              out[i] = (col >= 0 && col < cols) ? W[size_t(row) * cols + col] : 0.0f;
+            }
+          }
+        }
+      }
+  }
+}
+
+int32_t pack_cls(const nedf_mlp_shape* shape, int32_t dtype, const float* const* W, const float* const* b,
+                 void* out, size_t out_bytes) {
+  ClsPlan p = plan_cls(shape, dtype);
+  if (!p.ok) return nedf::fail(NEDF_ERR_SHAPE, "nedf_pack_mlp: " + p.why);
+  const nedf_cls_header& h = p.h;
+  if (out_bytes < h.total_bytes) return nedf::fail(NEDF_ERR_WORKSPACE, "nedf_pack_mlp: output buffer too small");
+  const int nl = 2 * shape->n_hidden + 2;
+  for (int i = 0; i < nl; ++i)
+    if (!W[i] || !b[i]) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: NULL layer pointer");
+  uint8_t* base = static_cast<uint8_t*>(out);
+  std::memset(base, 0, h.total_bytes);
+  std::memcpy(base, &h, sizeof(h));
+  const int Wd = shape->width;
+  const int in_cols = NEDF_CLS_POINTS * 3 * (1 + 2 * shape->enc_L);
+  pack_cls_head(h, W[0], in_cols, base + h.off_head);
+  float* hb = reinterpret_cast<float*>(base + h.off_head_bias);
+  for (int fb = 0; fb < 8; ++fb)
+    for (int hh = 0; hh < 2; ++hh)
+      for (int r = 0; r < 16; ++r) hb[(fb * 2 + hh) * 16 + r] = b[0][nedf_acc_feature(fb, hh, r)];
+  const int ksh = int(p.hb.ks_hidden), fragb = int(p.hb.frag_bytes);
+  for (int i = 0; i < 2 * shape->n_hidden; ++i) {
+    uint8_t* dst = base + h.off_hidden + size_t(i) * h.hidden_layer_bytes;
+    pack_fragments(p.hb, 1, W[1 + i], Wd, Wd, ksh, h.hidden_chunk_bytes, dst);
+    pack_bias(b[1 + i], Wd, ksh, fragb, h.hidden_chunk_bytes, dst);
+  }
+  // tail rows in kernel order: coarse, fine, hit logit, zeros
+  const int rows = 32 * NEDF_CLS_TAIL_BLOCKS;
+  std::vector<float> Wt(size_t(rows) * Wd, 0.0f), bt(rows, 0.0f);
+  const float* Ws = W[nl - 1];
+  const float* bs = b[nl - 1];
+  for (int r = 0; r < rows; ++r) {
+    int src = -1;
+    if (r < NEDF_CLS_COARSE + NEDF_CLS_FINE) src = 1 + r;
+    else if (r == NEDF_CLS_HIT_ROW) src = 0;
+    if (src < 0) continue;
+    std::memcpy(&Wt[size_t(r) * Wd], Ws + size_t(src) * Wd, sizeof(float) * Wd);
+    bt[r] = bs[src];
+  }
+  uint8_t* dst = base + h.off_tail;
+  pack_fragments(p.hb, 1, Wt.data(), rows, Wd, ksh, h.tail_chunk_bytes, dst);
+  pack_bias(bt.data(), rows, ksh, fragb, h.tail_chunk_bytes, dst);
+  return NEDF_OK;
+}
+
 }  // namespace
 
 extern "C" size_t nedf_mlp_packed_bytes(const nedf_mlp_shape* shape, int32_t dtype) {
+  if (shape && shape->in_kind == NEDF_IN_POINTS16) {
+    ClsPlan c = plan_cls(shape, dtype);
+    if (!c.ok) {
+      nedf::set_error(c.why);
+      return 0;
+    }
+    return size_t(c.h.total_bytes);
+  }
   Plan p = plan_blob(shape, dtype);
   if (!p.ok) {
     nedf::set_error(p.why);
@@ -247,6 +391,7 @@ extern "C" int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, con
                                  const float* const* b, const float* fp8_scales, void* out,
                                  size_t out_bytes) {
   if (!shape || !W || !b || !out) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: NULL argument");
+  if (shape->in_kind == NEDF_IN_POINTS16) return pack_cls(shape, dtype, W, b, out, out_bytes);
   if (dtype == NEDF_FP8 && !fp8_scales) return nedf::fail(NEDF_ERR_NULL, "nedf_pack_mlp: FP8 needs per-layer scales");
   Plan p = plan_blob(shape, dtype);
   if (!p.ok) return nedf::fail(dtype == NEDF_F32 || dtype == NEDF_BF16 ? NEDF_ERR_SHAPE : NEDF_ERR_DTYPE,

@@ -146,7 +146,14 @@ def pair_oracle(dens, net, rec, o, d, n_samples, dtype, scales=None, band=2e-2):
     # every pair on which the network ran (routed to it, or to the marcher
     # by its probability)
     sel = np.nonzero(np.isfinite(p))[0]
-    if dtype != "f32" and sel.size:
+    if net.kind == "nedf16" and sel.size:
+        # classifier form: argmax decisions and the hit logit near a tie
+        from oracle.ambiguity import classifier_decision_ambiguity
+        o_l, d_l = to_local(rec, o[sel], d[sel])
+        mu_dev, p_dev = classifier_decision_ambiguity(net, o_l, d_l, gemm=gemm)
+        amb[sel] = rec.s * mu_dev
+        amb_p[sel] = p_dev
+    elif dtype != "f32" and sel.size:
         o_l, d_l = to_local(rec, o[sel], d[sel])
         pl, _ = pluecker(o_l, d_l)
         a_in, _, p_in = nedf_input_ambiguity(net, o_l, d_l, coord_err(o_l, pl), SIN_ERR, scales=scales,
