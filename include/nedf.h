@@ -393,8 +393,9 @@ int32_t nedf_shadow(const nedf_scene* scene, const nedf_rays* rays, const float*
 
 /* ------------------------------------------------------------- training */
 
-/* Adam and loss settings of nedf_train_step (Eq. 6 regression form; the
- * paper trains with Adam at lr 5e-4). */
+/* Adam and loss settings of nedf_train_step (Eq. 6 regression form, or the
+ * classifier form for NEDF_IN_POINTS16 networks; the paper trains with Adam
+ * at lr 5e-4). */
 typedef struct nedf_train_opts {
   float lr, beta1, beta2, eps;  /* Adam (Kingma & Ba 2015), bias-corrected */
   float w_hit;                  /* weight of the hit BCE term (0.1 in Eq. 6) */
@@ -403,7 +404,8 @@ typedef struct nedf_train_opts {
 
 /* Bytes of the device training state of a network (float32 master weights,
  * Adam moments, last-step gradients, bfloat16 weight copies, step counter).
- * The network must have n_out = 2 and width 256. */
+ * The network must have width 256 and n_out = 2 (regression form) or be a
+ * classifier-form network (NEDF_IN_POINTS16, L10, 1..16 blocks). */
 size_t nedf_train_state_bytes(const nedf_mlp_shape* shape);
 
 /* Device workspace bytes of nedf_train_step for a batch of B rays. */
@@ -425,6 +427,12 @@ int32_t nedf_train_init(const nedf_mlp_shape* shape, const float* const* W, cons
  *   depth_label  device float32 [B] local depth of the first surface
  *   hit_label    device uint8 [B]
  *   loss_out     device float32 [3]: total, masked MSE, BCE (before the update)
+ * A classifier-form network (NEDF_IN_POINTS16: head, 2 layers per residual
+ * block, 1..16 blocks, tail of 193 rows) trains on Eq. 6 itself: target bins
+ * (c, f) = S(mu*) (u = (mu* + 1) / 2, c = floor(64 u), f = floor(128 (64 u - c)),
+ * clamped), L = (1/B) sum_i [alpha_i (mean_j BCE(v_c,ij, [j = c_i]) +
+ * mean_j BCE(v_f,ij, [j = f_i])) + w_hit BCE(alpha_hat_i, alpha_i)], and
+ * loss_out = total, bin term, hit term.
  */
 int32_t nedf_train_step(const nedf_mlp_shape* shape, void* state, const float* o_l, const float* d_l,
                         const float* depth_label, const uint8_t* hit_label, int32_t B,

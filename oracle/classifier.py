@@ -183,6 +183,7 @@ def classifier_loss_and_grads(model, o_l, d_l, mu_label, hit_label, w_hit=0.1, g
     g[:, 0] = w_hit * (sigmoid(ah) - alpha) / B
     g[:, 1:1 + nc] = alpha[:, None] * (sigmoid(vc) - yc) / (nc * B)
     g[:, 1 + nc:] = alpha[:, None] * (sigmoid(vf) - yf) / (nf * B)
+    g = rnd(g)                              # enters the tail's two matrix products
     W, _ = _layers(model)
     Wm = [rnd(w) for w in W]
     n = len(W)

@@ -489,7 +489,9 @@ class Trainer:
         lib = A.load()
         self.dev = _device(device)
         width = W[0].shape[0]
-        self.shape = mlp_shape(in_kind, enc_L, width, len(W) - 1, W[-1].shape[0])
+        # classifier form: head, two layers per residual block, tail
+        n_hidden = (len(W) - 2) // 2 if in_kind == "points16" else len(W) - 1
+        self.shape = mlp_shape(in_kind, enc_L, width, n_hidden, W[-1].shape[0])
         self._s = A.MlpShape(**{k: int(v) for k, v in self.shape.items()})
         n = lib.nedf_train_state_bytes(C.byref(self._s))
         if n == 0:

@@ -808,6 +808,13 @@ extern "C" int32_t nedf_profile_read(int32_t max_stages, char* names, double* to
 namespace {
 int32_t check_train_shape(const nedf_mlp_shape* s) {
   if (!s) return fail(NEDF_ERR_NULL, "shape is NULL");
+  if (s->in_kind == NEDF_IN_POINTS16) {
+    if (s->width != 256 || s->enc_L != 10 || s->rgb_width != 0 || s->n_out != 1 + NEDF_CLS_COARSE + NEDF_CLS_FINE)
+      return fail(NEDF_ERR_UNSUPPORTED, "classifier training needs width 256, L10, 193 outputs");
+    if (s->n_hidden < 1 || 2 * s->n_hidden + 2 > NEDF_TRAIN_MAX_LAYERS)
+      return fail(NEDF_ERR_SHAPE, "classifier training takes 1..16 residual blocks");
+    return NEDF_OK;
+  }
   if (s->width != 256 || s->n_out != 2 || s->rgb_width != 0) return fail(NEDF_ERR_UNSUPPORTED, "training needs width 256, n_out 2, no colour branch");
   if (s->n_hidden < 1 || s->n_hidden > NEDF_MAX_LAYERS) return fail(NEDF_ERR_SHAPE, "n_hidden must be 1..16");
   if (s->in_kind != NEDF_IN_PLUECKER && s->in_kind != NEDF_IN_XYZ) return fail(NEDF_ERR_SHAPE, "bad in_kind");
@@ -880,6 +887,10 @@ extern "C" int32_t nedf_train_export(const nedf_mlp_shape* shape, const void* st
 
 extern "C" size_t nedf_fp8_calibrate_workspace_size(const nedf_mlp_shape* shape, int32_t B) {
   if (check_train_shape(shape) || B <= 0) return 0;
+  if (shape->in_kind == NEDF_IN_POINTS16) {
+    set_error("FP8 calibration covers the regression-form network");
+    return 0;
+  }
   return fp8_calibrate_ws_bytes(*shape, B);
 }
 
@@ -888,6 +899,8 @@ extern "C" int32_t nedf_fp8_calibrate(const nedf_mlp_shape* shape, const float* 
                                       size_t ws_bytes, nedf_stream_t stream) {
   int32_t st = check_train_shape(shape);
   if (st) return st;
+  if (shape->in_kind == NEDF_IN_POINTS16)
+    return fail(NEDF_ERR_UNSUPPORTED, "nedf_fp8_calibrate: FP8 calibration covers the regression-form network");
   if (!W || !b || !o_l || !d_l || !scales || !ws) return fail(NEDF_ERR_NULL, "nedf_fp8_calibrate: NULL argument");
   if (B <= 0 || B % 256 != 0) return fail(NEDF_ERR_SHAPE, "calibration batch must be a positive multiple of 256");
   if (!aligned16(ws) || !aligned16(o_l) || !aligned16(d_l)) return fail(NEDF_ERR_ALIGN, "nedf_fp8_calibrate: misaligned pointer");

@@ -126,6 +126,15 @@ struct GemmArgs {
   float* part;           // EPI 2: part[split][M][N] float32
   float* colsum;         //        colsum[split][M] (A is RC: sums over k of A(m, k))
   int ldo;
+  // EPI 3: out32 = acc + bias[col] (float32 logits)
+  // EPI 4: v = acc (+ resid32); out32 = v (if set); out16 = v * (mask > 0)
+  //        (if set): the float32 gradient stream of a residual network
+  // EPI 5: r = relu(acc + bias[col]); out16 = resid16 + r rounded once,
+  //        out16b = r (a residual block's second layer)
+  float* out32;
+  const float* resid32;
+  const uint16_t* resid16;
+  uint16_t* out16b;
 };
 
 // 8 x 8 transpose of bfloat16: v[j] holds 8 consecutive rows at k = j; w[r]
@@ -289,7 +298,54 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
 #undef NEDF_GEMM_STAGE
   // accumulator r of block (i, j): row 64 wm + 32 i + lane % 32, column
   // 64 wn + 32 j + 8 (r / 4) + 4 (lane / 32) + r % 4 of the tile
-  if constexpr (EPI == 2) {
+  if constexpr (EPI >= 3) {
+    // straight from the accumulators: four consecutive columns per store
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = m0 + wm * 64 + 32 * i + (lane & 31);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = n0 + wn * 64 + 32 * j + 8 * q + 4 * (lane >> 5);
+          const size_t o = size_t(row) * g.ldo + col;
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * q + e];
+          if constexpr (EPI == 3) {
+            const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
+            *reinterpret_cast<float4*>(g.out32 + o) = make_float4(v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w);
+          } else if constexpr (EPI == 4) {
+            if (g.resid32) {
+              const float4 r = *reinterpret_cast<const float4*>(g.resid32 + o);
+              v[0] += r.x; v[1] += r.y; v[2] += r.z; v[3] += r.w;
+            }
+            if (g.out32) *reinterpret_cast<float4*>(g.out32 + o) = make_float4(v[0], v[1], v[2], v[3]);
+            if (g.out16) {
+              const uint2 mk = *reinterpret_cast<const uint2*>(g.mask + size_t(row) * g.ldm + col);
+              const float m0v = __uint_as_float(mk.x << 16), m1v = __uint_as_float(mk.x & 0xFFFF0000u);
+              const float m2v = __uint_as_float(mk.y << 16), m3v = __uint_as_float(mk.y & 0xFFFF0000u);
+              *reinterpret_cast<uint2*>(g.out16 + o) =
+                  make_uint2(uint32_t(bf16_bits(m0v > 0.f ? v[0] : 0.f)) | (uint32_t(bf16_bits(m1v > 0.f ? v[1] : 0.f)) << 16),
+                             uint32_t(bf16_bits(m2v > 0.f ? v[2] : 0.f)) | (uint32_t(bf16_bits(m3v > 0.f ? v[3] : 0.f)) << 16));
+            }
+          } else {
+            const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
+            const float r0 = fmaxf(v[0] + bb.x, 0.f), r1 = fmaxf(v[1] + bb.y, 0.f);
+            const float r2 = fmaxf(v[2] + bb.z, 0.f), r3 = fmaxf(v[3] + bb.w, 0.f);
+            const uint2 h = *reinterpret_cast<const uint2*>(g.resid16 + o);
+            const float h0 = __uint_as_float(h.x << 16), h1 = __uint_as_float(h.x & 0xFFFF0000u);
+            const float h2 = __uint_as_float(h.y << 16), h3 = __uint_as_float(h.y & 0xFFFF0000u);
+            *reinterpret_cast<uint2*>(g.out16 + o) =
+                make_uint2(uint32_t(bf16_bits(h0 + r0)) | (uint32_t(bf16_bits(h1 + r1)) << 16),
+                           uint32_t(bf16_bits(h2 + r2)) | (uint32_t(bf16_bits(h3 + r3)) << 16));
+            *reinterpret_cast<uint2*>(g.out16b + o) =
+                make_uint2(uint32_t(bf16_bits(r0)) | (uint32_t(bf16_bits(r1)) << 16),
+                           uint32_t(bf16_bits(r2)) | (uint32_t(bf16_bits(r3)) << 16));
+          }
+        }
+    }
+  } else if constexpr (EPI == 2) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int row = m0 + wm * 64 + 32 * i + (lane & 31);
@@ -557,17 +613,151 @@ __global__ void k_step_inc(int64_t* step) {
 
 // Initial state: master weights from float32 arrays, moments and gradients
 // zero, bfloat16 copies (zero padded).
-__global__ void k_copy_w(const float* src, float* dst, uint16_t* w16, uint16_t* w16t, int N, int K, int Kpad) {
+__global__ void k_copy_w(const float* src, float* dst, uint16_t* w16, uint16_t* w16t, int N, int K, int Kpad,
+                         int Nsrc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * Kpad) return;
   const int r = i / Kpad, c = i % Kpad;
-  const float v = c < K ? src[r * K + c] : 0.0f;
+  const float v = (c < K && r < Nsrc) ? src[r * K + c] : 0.0f;
   if (c < K && dst) dst[r * K + c] = v;
   if (w16) w16[i] = bf16_bits(v);
   if (w16t) w16t[size_t(c) * N + r] = bf16_bits(v);
 }
 
 unsigned blocks(size_t n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+// ---- classifier-form network (NEDF_IN_POINTS16) ---------------------------------
+// Encoded input of the 16 line points (natural order: point-major, each
+// [x, sin(2^0 pi x), cos(2^0 pi x), ...], 63 values) zero padded to Kpad, and
+// labels mu* = (t_perp - D) / l, alpha = hit.  The points come from the
+// compensated frame of the inference kernel, applied to the local ray.
+__global__ void k_train_encode_points(const float* o_l, const float* d_l, const float* depth, const uint8_t* hit,
+                                      int B, int L, int Kpad, float bound, uint16_t* H, float* mu,
+                                      float* alpha) {
+  const int groups = Kpad / 8;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = tid / groups, grp = tid % groups;
+  if (s >= B) return;
+  const float o[3] = {o_l[3 * s], o_l[3 * s + 1], o_l[3 * s + 2]};
+  const float d[3] = {d_l[3 * s], d_l[3 * s + 1], d_l[3 * s + 2]};
+  const float zero[3] = {0.f, 0.f, 0.f};
+  W2L id{};
+  id.rt[0] = id.rt[4] = id.rt[8] = 1.0f;
+  id.s = id.inv_s = 1.0f;
+  f2 q[3], dv[3];
+  float tperp, ol[3];
+  local_points_frame(id, o, d, zero, bound, q, dv, tperp, ol);
+  const int per = 3 * (1 + 2 * L);
+  uint32_t packed[4];
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    float v2[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int f = 8 * grp + e + u;
+      float v = 0.0f;
+      if (f < NEDF_CLS_POINTS * per) {
+        const int p = f / per, e2 = f % per;
+        const float cp = float(2 * p + 1) * 0.0625f - 1.0f;
+        float x[3], xlo[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma clang fp contract(off)
+          const f2 pp = two_prod(cp, dv[r].hi);
+          const f2 sm = two_sum(q[r].hi, pp.hi);
+          x[r] = sm.hi;
+          xlo[r] = sm.lo + ((pp.lo + q[r].lo) + cp * dv[r].lo);
+        }
+        if (e2 < 3) {
+          v = x[e2];
+        } else {
+          const int qq = e2 - 3, level = qq / 6, w = qq % 6, c = w % 3;
+          v = sinpi_hw(float(1 << level) * x[c], float(1 << level) * xlo[c], w >= 3 ? 1 : 0);
+        }
+      }
+      v2[u] = v;
+    }
+    packed[e / 2] = uint32_t(bf16_bits(v2[0])) | (uint32_t(bf16_bits(v2[1])) << 16);
+  }
+  *reinterpret_cast<uint4*>(H + size_t(s) * Kpad + 8 * grp) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  if (grp != 0) return;
+  const bool h = hit[s] != 0;
+  alpha[s] = h ? 1.0f : 0.0f;
+  mu[s] = h ? (tperp - depth[s]) / bound : 0.0f;
+}
+
+// Loss of Eq. 6 in the classifier form and its gradient at the tail's
+// outputs: one wave per sample (logits [B][ld], rows: hit logit, 64 coarse,
+// 128 fine bins), target bins from S of mu*; binary cross-entropy with
+// logits, bins averaged per level and counted for hits only, the hit term
+// weighted by w_hit, all divided by B.  G gets the gradient in bfloat16 (zero
+// past the 193 outputs); part[block] = (total, bins, hit) of its four samples.
+constexpr int CLS_OUT = 1 + NEDF_CLS_COARSE + NEDF_CLS_FINE;
+__device__ __forceinline__ float softplus_f(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__global__ __launch_bounds__(256) void k_cls_loss(const float* logits, int ld, const float* mu, const float* alpha,
+                                                  int B, float w_hit, uint16_t* G, float* part) {
+  __shared__ float red[4][3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int s = blockIdx.x * 4 + w;
+  float lb = 0.f, lh = 0.f;
+  if (s < B) {
+    const float al = alpha[s];
+    // S: u = (mu + l) / 2l with mu* = mu / l
+    const float u = (mu[s] + 1.0f) * 0.5f;
+    const int c = min(max(int(floorf(float(NEDF_CLS_COARSE) * u)), 0), NEDF_CLS_COARSE - 1);
+    const int f = min(max(int(floorf(float(NEDF_CLS_FINE) * (float(NEDF_CLS_COARSE) * u - float(c)))), 0),
+                      NEDF_CLS_FINE - 1);
+    const float invB = 1.0f / float(B);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = lane + 64 * k;
+      if (j >= ld) break;
+      float g = 0.f;
+      if (j < CLS_OUT) {
+        const float z = logits[size_t(s) * ld + j];
+        const float sg = 1.0f / (1.0f + expf(-z));
+        if (j == 0) {
+          lh += softplus_f(z) - al * z;
+          g = w_hit * (sg - al) * invB;
+        } else if (j <= NEDF_CLS_COARSE) {
+          const float y = (j - 1 == c) ? 1.f : 0.f;
+          lb += al * (softplus_f(z) - y * z) * (1.0f / NEDF_CLS_COARSE);
+          g = al * (sg - y) * (invB / NEDF_CLS_COARSE);
+        } else {
+          const float y = (j - 1 - NEDF_CLS_COARSE == f) ? 1.f : 0.f;
+          lb += al * (softplus_f(z) - y * z) * (1.0f / NEDF_CLS_FINE);
+          g = al * (sg - y) * (invB / NEDF_CLS_FINE);
+        }
+      }
+      G[size_t(s) * ld + j] = bf16_bits(g);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lb += __shfl_xor(lb, off);
+    lh += __shfl_xor(lh, off);
+  }
+  if (lane == 0) {
+    red[w][0] = lb + w_hit * lh;
+    red[w][1] = lb;
+    red[w][2] = lh;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int i = threadIdx.x;
+    part[size_t(blockIdx.x) * 3 + i] = ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
+  }
+}
+
+// loss[i] = (sum over blocks of part[block][i]) / B, blocks added in a fixed
+// order (lane l takes blocks l, l + 64, ...; then a fixed butterfly).
+__global__ void k_cls_loss_reduce(const float* part, int n_blocks, int B, float* loss) {
+  const int i = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (i >= 3) return;
+  float s = 0.f;
+  for (int q = lane; q < n_blocks; q += 64) s += part[size_t(q) * 3 + i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) loss[i] = s / float(B);
+}
 
 
 }  // namespace
@@ -581,7 +771,10 @@ int wgrad_splits(int B) {
   return S;
 }
 
+size_t train_ws_bytes_cls(const nedf_mlp_shape& sh, int B);
+
 size_t train_ws_bytes(const nedf_mlp_shape& sh, int B) {
+  if (sh.in_kind == NEDF_IN_POINTS16) return train_ws_bytes_cls(sh, B);
   const nedf_train_layout tl = nedf_train_layout_of(sh);
   const int S = wgrad_splits(B);
   size_t off = 0;
@@ -604,17 +797,24 @@ hipError_t launch_train_init(const nedf_mlp_shape& sh, const float* const* W, co
     const nedf_train_layer& l = tl.L[i];
     hipLaunchKernelGGL(k_copy_w, dim3(blocks(size_t(l.N) * l.Kpad)), dim3(256), 0, s, W[i],
                        reinterpret_cast<float*>(st + l.W), reinterpret_cast<uint16_t*>(st + l.W16),
-                       reinterpret_cast<uint16_t*>(st + l.W16T), l.N, l.K, l.Kpad);
+                       reinterpret_cast<uint16_t*>(st + l.W16T), l.N, l.K, l.Kpad, l.Nsrc);
+    // the bias as one row of N values, of which the caller's array holds Nsrc
     hipLaunchKernelGGL(k_copy_w, dim3(blocks(size_t(l.N))), dim3(256), 0, s, b[i],
                        reinterpret_cast<float*>(st + l.b), static_cast<uint16_t*>(nullptr),
-                       static_cast<uint16_t*>(nullptr), 1, l.N, l.N);
+                       static_cast<uint16_t*>(nullptr), 1, l.Nsrc, l.N, 1);
   }
   return hipGetLastError();
 }
 
+hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const float* o_l, const float* d_l,
+                                 const float* depth, const uint8_t* hit, int B, float lr, float b1, float b2,
+                                 float eps, float w_hit, float bound, float* loss, uint8_t* ws, hipStream_t s);
+
 hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float* o_l, const float* d_l,
                              const float* depth, const uint8_t* hit, int B, float lr, float b1, float b2, float eps,
                              float w_hit, float bound, float* loss, uint8_t* ws, hipStream_t s) {
+  if (sh.in_kind == NEDF_IN_POINTS16)
+    return launch_train_step_cls(sh, st, o_l, d_l, depth, hit, B, lr, b1, b2, eps, w_hit, bound, loss, ws, s);
   const nedf_train_layout tl = nedf_train_layout_of(sh);
   const int W = sh.width, NH = sh.n_hidden;
   const int K0p = tl.L[0].Kpad;
@@ -721,6 +921,186 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   return hipGetLastError();
 }
 
+// ---- classifier-form training step ----------------------------------------------
+namespace {
+struct ClsTrainWs {
+  uint16_t *X, *H, *A, *R, *G16a, *G16b;
+  float *LG, *Gh, *mu, *alpha, *wpart, *lpart;
+  size_t end;
+};
+ClsTrainWs cls_train_ws(const nedf_mlp_shape& sh, int B, uint8_t* base) {
+  const nedf_train_layout tl = nedf_train_layout_of(sh);
+  const int W = sh.width, NB = sh.n_hidden, K0p = tl.L[0].Kpad, S = wgrad_splits(B);
+  ClsTrainWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    uint8_t* p = base ? base + off : nullptr;
+    off = nedf_tl_align(off + bytes);
+    return p;
+  };
+  w.X = reinterpret_cast<uint16_t*>(take(size_t(B) * K0p * 2));
+  w.H = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * (NB + 1)));
+  w.A = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * NB));
+  w.R = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * NB));
+  w.G16a = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2));
+  w.G16b = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2));
+  w.LG = reinterpret_cast<float*>(take(size_t(B) * W * 4));
+  w.Gh = reinterpret_cast<float*>(take(size_t(B) * W * 4));
+  w.mu = reinterpret_cast<float*>(take(size_t(B) * 4));
+  w.alpha = reinterpret_cast<float*>(take(size_t(B) * 4));
+  w.wpart = reinterpret_cast<float*>(take(size_t(S) * W * (K0p + 1) * 4));
+  w.lpart = reinterpret_cast<float*>(take(size_t(B / 4 + 1) * 3 * 4));
+  w.end = off;
+  return w;
+}
+}  // namespace
+
+size_t train_ws_bytes_cls(const nedf_mlp_shape& sh, int B) { return cls_train_ws(sh, B, nullptr).end; }
+
+// One Adam step of a classifier-form network (Eq. 6): forward through the
+// head, the residual blocks (skip addition in the second layer's epilogue)
+// and the tail; loss and tail gradient; backward with a float32 gradient
+// stream for the skip path (each block adds its branch's data gradient to
+// it in the GEMM epilogue, which also forms the next masked bfloat16
+// gradient); weight gradients by split-K GEMMs reduced in order, per layer.
+hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const float* o_l, const float* d_l,
+                                 const float* depth, const uint8_t* hit, int B, float lr, float b1, float b2,
+                                 float eps, float w_hit, float bound, float* loss, uint8_t* ws, hipStream_t s) {
+  const nedf_train_layout tl = nedf_train_layout_of(sh);
+  const int W = sh.width, NB = sh.n_hidden;
+  const int K0p = tl.L[0].Kpad;
+  const int S = wgrad_splits(B);
+  const ClsTrainWs w = cls_train_ws(sh, B, ws);
+  auto F = [&](size_t o) { return reinterpret_cast<float*>(st + o); };
+  auto U = [&](size_t o) { return reinterpret_cast<uint16_t*>(st + o); };
+  auto Hk = [&](int k) { return w.H + size_t(k) * B * W; };
+  auto Ak = [&](int k) { return w.A + size_t(k) * B * W; };
+  auto Rk = [&](int k) { return w.R + size_t(k) * B * W; };
+  const int tail = tl.n_layers - 1;
+  prof_mark("train.step", s, true);
+  hipLaunchKernelGGL(k_train_encode_points, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l, depth,
+                     hit, B, sh.enc_L, K0p, bound, w.X, w.mu, w.alpha);
+  // forward
+  {
+    GemmArgs g{};
+    g.A = w.X; g.lda = K0p;
+    g.B = U(tl.L[0].W16); g.ldb = K0p;
+    g.M = B; g.N = W; g.K = K0p; g.k_per_split = K0p;
+    g.bias = F(tl.L[0].b);
+    g.out16 = Hk(0); g.ldo = W;
+    gemm<KC, KC, 0>(g, 1, s);
+  }
+  for (int k = 0; k < NB; ++k) {
+    const nedf_train_layer &L1 = tl.L[1 + 2 * k], &L2 = tl.L[2 + 2 * k];
+    GemmArgs g{};
+    g.A = Hk(k); g.lda = W;
+    g.B = U(L1.W16); g.ldb = W;
+    g.M = B; g.N = W; g.K = W; g.k_per_split = W;
+    g.bias = F(L1.b);
+    g.out16 = Ak(k); g.ldo = W;
+    gemm<KC, KC, 0>(g, 1, s);
+    GemmArgs r{};
+    r.A = Ak(k); r.lda = W;
+    r.B = U(L2.W16); r.ldb = W;
+    r.M = B; r.N = W; r.K = W; r.k_per_split = W;
+    r.bias = F(L2.b);
+    r.resid16 = Hk(k);
+    r.out16 = Hk(k + 1); r.out16b = Rk(k); r.ldo = W;
+    gemm<KC, KC, 5>(r, 1, s);
+  }
+  {
+    GemmArgs g{};
+    g.A = Hk(NB); g.lda = W;
+    g.B = U(tl.L[tail].W16); g.ldb = W;
+    g.M = B; g.N = W; g.K = W; g.k_per_split = W;
+    g.bias = F(tl.L[tail].b);
+    g.out32 = w.LG; g.ldo = W;
+    gemm<KC, KC, 3>(g, 1, s);
+  }
+  const int lblocks = (B + 3) / 4;
+  hipLaunchKernelGGL(k_cls_loss, dim3(lblocks), dim3(256), 0, s, w.LG, W, w.mu, w.alpha, B, w_hit, w.G16a, w.lpart);
+  hipLaunchKernelGGL(k_cls_loss_reduce, dim3(1), dim3(256), 0, s, w.lpart, lblocks, B, loss);
+  // weight gradient of layer i from its output gradient G and its input X
+  auto wgrad = [&](int i, const uint16_t* G, const uint16_t* X, int ldx) {
+    const nedf_train_layer& L = tl.L[i];
+    GemmArgs g{};
+    g.A = G; g.lda = W;
+    g.B = X; g.ldb = ldx;
+    g.M = W; g.N = L.Kpad; g.K = B;
+    g.k_per_split = B / S;
+    g.part = w.wpart;
+    g.colsum = w.wpart + size_t(S) * W * L.Kpad;
+    gemm<RC, RC, 2, true, 128>(g, S, s);
+    ReduceArgs ra{};
+    ra.n_layers = 1;
+    ra.S = S;
+    ra.L[0] = ReduceLayer{g.part, g.colsum, F(L.gW), F(L.gb), W, L.Kpad, L.K};
+    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(size_t(W) * L.Kpad + W), 1), dim3(256), 0, s, ra);
+  };
+  // data gradient through layer i: out = G W_i, plus epilogue options
+  auto dgrad = [&](int i, const uint16_t* G) {
+    GemmArgs g{};
+    g.A = G; g.lda = W;
+    g.B = U(tl.L[i].W16T); g.ldb = W;
+    g.M = B; g.N = W; g.K = W; g.k_per_split = W;
+    g.ldo = W; g.ldm = W;
+    return g;
+  };
+  // tail
+  wgrad(tail, w.G16a, Hk(NB), W);
+  {
+    GemmArgs g = dgrad(tail, w.G16a);
+    g.out32 = w.Gh;
+    g.mask = Rk(NB - 1);
+    g.out16 = w.G16b;  // gradient at the last block's second pre-activation
+    gemm<KC, KC, 4>(g, 1, s);
+  }
+  for (int k = NB - 1; k >= 0; --k) {
+    const int i1 = 1 + 2 * k, i2 = 2 + 2 * k;
+    wgrad(i2, w.G16b, Ak(k), W);
+    {
+      GemmArgs g = dgrad(i2, w.G16b);
+      g.mask = Ak(k);
+      g.out16 = w.G16a;  // gradient at the first layer's pre-activation
+      gemm<KC, KC, 1>(g, 1, s);
+    }
+    wgrad(i1, w.G16a, Hk(k), W);
+    {
+      GemmArgs g = dgrad(i1, w.G16a);
+      g.resid32 = w.Gh;
+      g.out32 = w.Gh;                         // skip path plus the branch
+      g.mask = k > 0 ? Rk(k - 1) : Hk(0);     // next: block k-1's second layer, or the head
+      g.out16 = w.G16b;
+      gemm<KC, KC, 4>(g, 1, s);
+    }
+  }
+  wgrad(0, w.G16b, w.X, K0p);
+  // Adam, in launches of at most one argument block of segments
+  AdamArgs aa{};
+  aa.step = reinterpret_cast<const int64_t*>(st);
+  aa.lr = lr; aa.b1 = b1; aa.b2 = b2; aa.eps = eps;
+  int nb = 0;
+  auto flush = [&]() {
+    if (aa.n_seg) hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, s, aa);
+    aa.n_seg = 0;
+    nb = 0;
+  };
+  constexpr int MAXSEG = int(sizeof(aa.seg) / sizeof(aa.seg[0]));
+  for (int i = 0; i < tl.n_layers; ++i) {
+    if (aa.n_seg + 2 > MAXSEG) flush();
+    const nedf_train_layer& L = tl.L[i];
+    aa.seg[aa.n_seg++] = AdamSeg{F(L.W), F(L.mW), F(L.vW), F(L.gW), U(L.W16), U(L.W16T), L.N * L.K, L.K, L.Kpad,
+                                 L.N, nb};
+    nb += int(blocks(size_t(L.N) * L.K));
+    aa.seg[aa.n_seg++] = AdamSeg{F(L.b), F(L.mb), F(L.vb), F(L.gb), nullptr, nullptr, L.N, 1, 1, 1, nb};
+    nb += int(blocks(size_t(L.N)));
+  }
+  flush();
+  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, reinterpret_cast<int64_t*>(st));
+  prof_mark("train.step", s, false);
+  return hipGetLastError();
+}
+
 // Per-layer E4M3 scales of a network from a calibration batch: the bfloat16
 // forward pass of the training path records amax of every hidden layer's
 // input; weight scales from the float32 weights.  ws holds a temporary
@@ -774,9 +1154,9 @@ hipError_t launch_train_export(const nedf_mlp_shape& sh, const uint8_t* st, floa
   for (int i = 0; i < tl.n_layers; ++i) {
     const nedf_train_layer& l = tl.L[i];
     const size_t ow = grads ? l.gW : l.W, ob = grads ? l.gb : l.b;
-    hipError_t e = hipMemcpyAsync(W[i], st + ow, size_t(l.N) * l.K * 4, hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMemcpyAsync(W[i], st + ow, size_t(l.Nsrc) * l.K * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(b[i], st + ob, size_t(l.N) * 4, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(b[i], st + ob, size_t(l.Nsrc) * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
