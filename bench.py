@@ -52,6 +52,9 @@ MAC_PER_SAMPLE = 63 * 256 + 7 * 256 * 256 + 256
 MAC_RGB = (256 + 27) * 128 + 128 * 3
 # intersection network per pair: 102 x 256 + 7 x 256x256 + 256 x 2
 MAC_NEDF = 102 * 256 + 7 * 256 * 256 + 256 * 2
+# classifier-form network per pair: head 1,008 -> 256, 16 residual blocks of
+# two 256 x 256 layers, tail 256 -> 193
+MAC_CLS = 1008 * 256 + 32 * 256 * 256 + 256 * 193
 
 
 # HBM bytes per launch of a matrix-core kernel in the timed frames, from the
@@ -95,7 +98,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="frame", choices=["frame", "marcher", "precision", "nedf"])
+    p.add_argument("--workload", default="frame", choices=["frame", "marcher", "precision", "nedf", "ablation"])
     p.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
     # frame workload
     p.add_argument("--width", type=int, default=1920)
@@ -122,6 +125,9 @@ def parse():
     p.add_argument("--quality-pixels", type=int, default=4096)
     p.add_argument("--fp64-pixels", type=int, default=256,
                    help="frame: seeded pixels judged by the FP64 oracle marcher (inside the CPU-baseline leg)")
+    # regression-vs-classifier workload
+    p.add_argument("--ablation-steps", type=int, default=4000, help="Adam steps per network and object")
+    p.add_argument("--ablation-size", type=int, default=384, help="side of each object's evaluation view")
     # oracle baseline and counters
     p.add_argument("--cpu-pixels", type=int, default=0, help="0: the workload's default sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -882,6 +888,147 @@ def nedf_bench(args):
     }
 
 
+# --------------------------------------------------------------------------
+# regression vs multi-level classifier (the paper's Fig. 3 ablation)
+# --------------------------------------------------------------------------
+def ablation_bench(args):
+    """Both intersection-network forms trained through the library on the
+    same marcher labels of each config-4 object, then judged against the
+    FP32 marcher on a held-out view of the object: depth error over pixels
+    where both hit, split into pixels at a depth discontinuity (a 4-neighbour
+    misses, or its depth differs by more than 5 % of the bounding radius) and
+    the others, and the share of pixels off by more than 10 % of the radius
+    (floaters).  The networks decide every pair themselves (p_lo = p_hi =
+    0.5, no refinement).  Then the classifier networks replace the regression
+    ones in the 1920 x 1080, 1,000-instance frame, whose depth+ID pass is
+    timed with each form."""
+    import torch
+    import synthetic as syn
+    from paper_2308_04669_amd import api
+
+    config = 4
+    models, insts, cam, _ = syn.batched_scene(config, args.instances, args.width, args.height)
+    ident = syn.Instance(model=0, R=np.eye(3), T=np.zeros(3), s=1.0)
+    B, nb, T = args.train_batch, args.label_batches, args.ablation_steps
+    out = {"objects": []}
+    reg_nets, cls_nets = [], []
+    times = {"regression": 0.0, "classifier": 0.0}
+    for k, m in enumerate(models):
+        sc = api.make_scene([api.object_from_model(m, "f32")], [ident])
+        o, d = syn.training_rays(config, 300 + k, nb * B)
+        ot, dt = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+        depth, idn, _ = api.march_depth(sc, api.array_rays(ot, dt), n_samples=128, dtype="f32", opacity=False,
+                                        ws=api.Workspace())
+        hit = (idn >= 0).to(torch.uint8)
+        depth = torch.where(idn >= 0, depth, torch.zeros_like(depth))
+        forms = {"regression": (syn.nedf_model(config, 200 + k), "pluecker", 8),
+                 "classifier": (syn.classifier_model(config, 500 + k), "points16", 10)}
+        res = {}
+        for name, (init, kind, L) in forms.items():
+            tr = api.Trainer(init.trunk.W, init.trunk.b, enc_L=L, in_kind=kind)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for it in range(T):
+                j = it % nb
+                lr = 5e-5 + 0.5 * (5e-4 - 5e-5) * (1.0 + math.cos(math.pi * it / max(T, 1)))
+                loss = tr.step(ot[j * B:(j + 1) * B], dt[j * B:(j + 1) * B], depth[j * B:(j + 1) * B],
+                               hit[j * B:(j + 1) * B], lr=lr, bound=m.bound)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+            times[name] += dt_s
+            W, bb = tr.export(0)
+            net = syn.Model(kind=init.kind, bound=m.bound, params=dict(init.params),
+                            trunk=syn.MLPWeights([w.astype(np.float32) for w in W], [x.astype(np.float32) for x in bb]))
+            (reg_nets if name == "regression" else cls_nets).append(net)
+            res[name] = {"train_s": dt_s, "loss_last": float(loss[0])}
+            log(f"object {k} {name}: {T} steps in {dt_s:.1f} s, loss {float(loss[0]):.4f}")
+        # held-out view: the object alone, seen from a seeded direction
+        g = np.random.default_rng(4669 + 1000 * config + 600 + k)
+        v = g.standard_normal(3)
+        v /= np.linalg.norm(v)
+        view = syn.Camera(eye=tuple(3.2 * m.bound * v), at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0) if abs(v[1]) < 0.9
+                          else (1.0, 0.0, 0.0), fov_y_deg=45.0, width=args.ablation_size, height=args.ablation_size)
+        rays = api.camera_rays(view)
+        dm, im, _ = api.march_depth(sc, rays, n_samples=192, dtype="f32", opacity=False)
+        dm, im = dm.cpu().numpy().astype(np.float64), im.cpu().numpy()
+        S = args.ablation_size
+        Dm = np.where(im >= 0, dm, np.inf).reshape(S, S)
+        edge = np.zeros((S, S), bool)
+        for sh in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+            nb_ = np.roll(Dm, sh, axis=(0, 1))
+            edge |= ~np.isfinite(nb_) | (np.abs(nb_ - Dm) > 0.05 * m.bound)
+        edge = edge.reshape(-1)
+        for name, net in (("regression", reg_nets[-1]), ("classifier", cls_nets[-1])):
+            spec = api.object_from_model(m, "bf16", nedf_model=net, nedf_dtype="bf16")
+            scn = api.make_scene([spec], [ident])
+            dn, idn_ = api.infer_depth_id(scn, rays, dtype="bf16", p_lo=0.5, p_hi=0.5, refine_steps=0)
+            dn, idn_ = dn.cpu().numpy().astype(np.float64), idn_.cpu().numpy()
+            both = (im >= 0) & (idn_ >= 0)
+            err = np.abs(dn - dm)
+            e_edge, e_in = err[both & edge], err[both & ~edge]
+            res[name].update({
+                "hit_agreement": float(np.mean((im >= 0) == (idn_ >= 0))),
+                "median_err_interior": float(np.median(e_in)) / m.bound if e_in.size else None,
+                "median_err_edge": float(np.median(e_edge)) / m.bound if e_edge.size else None,
+                "p90_err_edge": float(np.quantile(e_edge, 0.9)) / m.bound if e_edge.size else None,
+                "floater_frac": float(np.mean(err[both] > 0.1 * m.bound)) if both.any() else None,
+                "floater_frac_edge": float(np.mean(e_edge > 0.1 * m.bound)) if e_edge.size else None})
+        res["pixels_hit"] = int((im >= 0).sum())
+        res["edge_pixels_hit"] = int(((im >= 0) & edge).sum())
+        out["objects"].append(res)
+        log(f"object {k}: {json.dumps(res)}")
+    # the frame's depth+ID pass with each form
+    frame = {}
+    rays = api.camera_rays(cam)
+    n = args.width * args.height
+    for name, nets in (("regression", reg_nets), ("classifier", cls_nets)):
+        objs = [api.object_from_model(m, "bf16", nedf_model=nn, nedf_dtype="bf16") for m, nn in zip(models, nets)]
+        scn = api.make_scene(objs, insts)
+        ws = api.Workspace()
+        for _ in range(max(args.warmup, 1)):
+            api.infer_depth_id(scn, rays, dtype="bf16", refine_steps=3, n_samples=args.fallback_samples, ws=ws)
+        torch.cuda.synchronize()
+        st = api.ws_counters(ws)
+        api.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            api.infer_depth_id(scn, rays, dtype="bf16", refine_steps=3, n_samples=args.fallback_samples, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        stages = api.profile_read()
+        api.profile_enable(False)
+        ms = e0.elapsed_time(e1) / args.steps
+        ev = st["nedf_hits"] + st["fallback"] + st["nedf_misses"]
+        net_ms = stages.get("infer.nedf/net", (0.0, 1))[0] / args.steps
+        mac = MAC_CLS if name == "classifier" else MAC_NEDF
+        tflops = 2.0 * mac * ev / (net_ms * 1e-3) / 1e12 if net_ms > 0 else 0.0
+        frame[name] = {"depth_id_ms": ms, "rays_per_s": n / (ms * 1e-3), "network_pairs": int(ev),
+                       "fallback_pairs": int(st["fallback"]), "network_ms": net_ms, "network_tflops": tflops,
+                       "network_frac_of_bf16_peak": tflops / PEAK_TFLOPS["bf16"]}
+        log(f"frame {name}: {json.dumps(frame[name])}")
+    cls = frame["classifier"]
+    keys = ("median_err_interior", "median_err_edge", "p90_err_edge", "floater_frac", "floater_frac_edge")
+    mean = {nm: {k: float(np.mean([o[nm][k] for o in out["objects"] if o[nm][k] is not None])) for k in keys}
+            for nm in ("regression", "classifier")}
+    return {
+        "metric": "classifier-form NeDF depth+ID rays/s (1920x1080, 1000 instances) and regression-vs-classifier "
+                  "depth error at discontinuities",
+        "value": cls["rays_per_s"], "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": cls["depth_id_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic (seeded SDF-biased NeRF objects; both network forms trained in setup "
+                                  "on the library's FP32 marcher labels)",
+        "config": {"workload": f"regression (Pluecker gamma8, 8x256) vs classifier (16 points gamma10, 16 residual "
+                               f"blocks, 64 x 128 bins) NeDF, {T} Adam steps of {B} rays per object and form; "
+                               f"frame {args.width}x{args.height}, {args.instances} instances"},
+        "roofline": {"bound": "mfma", "achieved": cls["network_tflops"], "peak": PEAK_TFLOPS["bf16"],
+                     "unit": "TFLOP/s", "frac": cls["network_frac_of_bf16_peak"], "traffic": None,
+                     "kernel": "infer.nedf/net (classifier form)", "flop_per_pair": 2 * MAC_CLS},
+        "mean_over_objects": mean, "objects": out["objects"], "frame": frame,
+        "train_ms_per_step": {k: 1e3 * v / (T * len(models)) for k, v in times.items()},
+    }
+
+
 def marcher_cpu_baseline(n_pixels: int, n_samples: int, size: int):
     """FP64 oracle marcher on a seeded pixel subset of the same frame."""
     import synthetic as syn
@@ -917,6 +1064,9 @@ def main():
         args.no_cpu_baseline = True
     elif args.workload == "nedf":
         line, ctx = nedf_bench(args), None
+        args.no_cpu_baseline = True
+    elif args.workload == "ablation":
+        line, ctx = ablation_bench(args), None
         args.no_cpu_baseline = True
     else:
         line, ctx = marcher_bench(args), None
