@@ -533,6 +533,20 @@ def frame_cpu_baseline(ctx, n_pixels, quality_pixels):
     base = {"value": n_pixels / dt, "unit": "rays/s", "cores": int(host_threads()), "kind": "oracle",
             "sample": f"{n_pixels} seeded pixels of the same {cam.width}x{cam.height} frame, depth+ID "
                       f"(intersection network, marcher fallback), FP64 NumPy, {dt:.1f} s"}
+    # the same oracle on one host thread (BLAS limited to one thread), on the
+    # first tenth of the sample
+    try:
+        from threadpoolctl import threadpool_limits
+        n1 = max(n_pixels // 10, 1)
+        o1, d1 = camera_rays(cam, pix[:n1])
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            nedf_compose(nets, models, insts, o1, d1, n_samples=128)
+            dt1 = time.perf_counter() - t0
+        base["value_1core"] = n1 / dt1
+        base["sample_1core"] = f"first {n1} pixels of the sample, one thread, {dt1:.1f} s"
+    except ImportError:
+        pass
     # the FP64 oracle marcher as the judge (rays of the single-precision camera)
     qp = syn.pixel_subset(config, cam.n_rays, quality_pixels, stream=13)
     oq, dq = camera_rays(cam, qp, basis="f32")

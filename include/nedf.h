@@ -94,7 +94,14 @@ typedef enum nedf_input_kind {
  *   in (encoded) -> n_hidden x [Linear(width) + ReLU] -> Linear(n_out)
  * and, when rgb_width > 0, a colour branch
  *   concat(h_last, gamma_dirL(d)) -> Linear(rgb_width) + ReLU -> Linear(3) -> sigmoid.
- * Supported: width in {64, 256}; n_hidden 1..16; n_out 1..2; rgb_width in {0, 128}.
+ * The packer accepts width in {64, 256}, n_hidden 1..16, n_out 1..2 and
+ * rgb_width in {0, 128}; the kernels are instantiated for these shapes only
+ * (other packed shapes are rejected with NEDF_ERR_UNSUPPORTED by the calls):
+ *   density / NeRF trunk (xyz): width 64, 3 hidden, L6; width 256, 8 hidden,
+ *     L10 (with the colour branch rgb_width 128, dir_L 4 for shading);
+ *   intersection network (Pluecker): width 256, 8 hidden, L8 (F32, BF16, FP8);
+ *   classifier form (NEDF_IN_POINTS16): width 256, L10, 1..64 residual
+ *     blocks, n_out 193 (F32, BF16; training 1..16 blocks).
  */
 typedef struct nedf_mlp_shape {
   int32_t in_kind;    /* nedf_input_kind */

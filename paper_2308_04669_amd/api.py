@@ -239,11 +239,20 @@ def n_rays(rays: A.Rays) -> int:
 # ---------------------------------------------------------------- entry points
 class Workspace:
     """Caller-owned device workspace, grown on demand (allocation happens here,
-    in the binding, never inside a library call)."""
+    in the binding, never inside a library call).  ``pair_hint`` sizes the
+    pair lists of calls that pass no explicit capacity: instead of the
+    library's worst case (every ray against every instance) it is the given
+    count, and ``ws_counters`` updates it to 1.25 x the culled pairs it reads
+    plus 2^20 (a frame sized from the previous frame's culling).  A call
+    whose lists overflow reports NEDF_ERR_CAPACITY through ``check_status``."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, pair_hint: int = 0):
         self.dev = _device(device)
         self.buf = torch.empty(0, dtype=torch.uint8, device=self.dev)
+        self.pair_hint = int(pair_hint)
+
+    def capacity(self, pair_capacity: int) -> int:
+        return int(pair_capacity) if pair_capacity else self.pair_hint
 
     def get(self, nbytes: int) -> torch.Tensor:
         nbytes = max(int(nbytes), 256)
@@ -269,8 +278,8 @@ def march_depth(scene: SceneGPU, rays: A.Rays, n_samples: int = 128, clip_to_bou
     sc = scene.struct()
     opts = A.MarchOpts(n_samples=n_samples, clip_to_bound=int(clip_to_bound), t_near=t_near, t_far=t_far,
                        hit_threshold=hit_threshold, dtype=A.DTYPES[dtype])
-    nbytes = lib.nedf_workspace_size(A.OPS["march"], C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
+    nbytes = lib.nedf_workspace_size(A.OPS["march"], C.byref(sc), C.byref(rays), ws.capacity(pair_capacity))
     buf = ws.get(nbytes)
     A.check(lib.nedf_march_depth(C.byref(sc), C.byref(rays), C.byref(opts), _ptr(depth), _ptr(ident),
                                  _ptr(opac), buf.data_ptr(), int(nbytes), _stream()), "nedf_march_depth")
@@ -300,8 +309,8 @@ def infer_depth_id(scene: SceneGPU, rays: A.Rays, dtype: str = "bf16", p_lo: flo
         depth, ident = out
     sc = scene.struct()
     opts = infer_opts(dtype, p_lo, p_hi, refine_steps, refine_h, n_samples)
-    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
+    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), ws.capacity(pair_capacity))
     buf = ws.get(nbytes)
     A.check(lib.nedf_infer_depth_id(C.byref(sc), C.byref(rays), C.byref(opts), _ptr(depth), _ptr(ident),
                                     buf.data_ptr(), int(nbytes), _stream()), "nedf_infer_depth_id")
@@ -352,8 +361,8 @@ def infer_keys(scene: SceneGPU, rays: A.Rays, inst_gid: torch.Tensor | None = No
     keys = out if out is not None else torch.empty(n, dtype=torch.int64, device=dev)
     sc = scene.struct()
     opts = infer_opts(dtype, p_lo, p_hi, 0, 0.05, n_samples)
-    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
+    nbytes = lib.nedf_workspace_size(A.OPS["infer"], C.byref(sc), C.byref(rays), ws.capacity(pair_capacity))
     buf = ws.get(nbytes)
     A.check(lib.nedf_infer_keys(C.byref(sc), C.byref(rays), C.byref(opts), _ptr(inst_gid), _ptr(keys),
                                 buf.data_ptr(), int(nbytes), _stream()), "nedf_infer_keys")
@@ -436,6 +445,8 @@ def shadow(scene: SceneGPU, rays: A.Rays, depth: torch.Tensor, ident: torch.Tens
             mask |= 1 << i
     opts = A.ShadowOpts(eps=eps, beta=beta, method=0 if method == "nedf" else 1, infer=io, directional_mask=mask,
                         dir_distance=dir_distance)
+    # shadow rays meet other instances than the primary rays: only an explicit
+    # capacity sizes their lists (the workspace's hint is the primary pass's)
     nbytes = lib.nedf_workspace_size(A.OPS["shadow"], C.byref(sc), C.byref(rays), int(pair_capacity))
     ws = ws or Workspace(dev)
     buf = ws.get(nbytes)
@@ -456,6 +467,8 @@ def ws_counters(ws: Workspace) -> dict:
     lib = A.load()
     out = (C.c_int64 * 7)()
     A.check(lib.nedf_ws_counters(ws.buf.data_ptr(), _stream(), out), "nedf_ws_counters")
+    if int(out[6]) > 0:
+        ws.pair_hint = int(1.25 * int(out[6])) + (1 << 20)
     return dict(pairs=int(out[0]), items=int(out[1]), nedf_hits=int(out[2]), fallback=int(out[3]),
                 nedf_misses=int(out[4]), fallback_marched=int(out[5]), culled_pairs=int(out[6]))
 
