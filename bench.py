@@ -116,6 +116,8 @@ def parse():
     p.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing beside the eager frames")
     p.add_argument("--no-manip", action="store_true",
                    help="skip the buffer-reuse timing (one instance moved, the others' keys kept)")
+    p.add_argument("--no-precision", action="store_true",
+                   help="skip the per-dtype leg (FP32 / BF16 / FP8 networks at 3840x2160, 64 instances)")
     # marcher workload
     p.add_argument("--samples", type=int, default=192)
     p.add_argument("--size", type=int, default=800)
@@ -411,6 +413,17 @@ def frame_bench(args):
         del ws_s, ws_m, ws_c, ws_f, keys_s, keys_m
         torch.cuda.empty_cache()
 
+    # precision leg: the same four objects and trained networks, 64 instances
+    # at 3840 x 2160 (the precision-stress placement), depth+ID per network
+    # dtype (FP32, BF16, FP8 with and without refinement)
+    precision = None
+    if not args.no_precision:
+        _, insts5, cam5, _ = syn.batched_scene(5, 64, 3840, 2160)
+        runs5, extent5, npix5 = precision_runs(models, nets, insts5, cam5, 5, args)
+        precision = {"workload": "64 instances of the frame's 4 objects, 3840x2160 (placement of the precision "
+                                 "stress scene), depth+ID", "extent": extent5, "judge_pixels": npix5,
+                     "per_dtype": runs5}
+
     # plain FP32 marcher on a seeded pixel subset of the same scene
     g = np.random.default_rng(4669 + 1000 * config + 77)
     pix = np.sort(g.choice(n, size=min(args.marcher_pixels, n), replace=False))
@@ -489,6 +502,7 @@ def frame_bench(args):
         "graph": graph,
         "outlier_resampling": rs,
         "buffer_reuse": manip,
+        "precision": precision,
         "training": train,
         "setup_train_s": setup_train_s,
     }
@@ -598,17 +612,17 @@ def frame_cpu_baseline(ctx, n_pixels, quality_pixels):
 # precision workload
 # ---------------------------------------------------------------------------
 
-def precision_bench(args):
+def precision_runs(models, nets, insts, cam, config, args):
+    """Depth+ID of one scene with the intersection networks in FP32, BF16,
+    FP8 (+ refinement) and FP8: rays/s, the network stage's per-frame time
+    and matrix-core rate against its dtype's dense peak, and depth/ID quality
+    against the FP32 marcher on seeded pixels."""
     import torch
     import synthetic as syn
     from paper_2308_04669_amd import api
 
-    config = 5
-    W, H = (args.width, args.height) if args.width != 1920 else (3840, 2160)
-    n_inst = args.instances if args.instances != 1000 else 64
-    models, insts, cam, _ = syn.batched_scene(config, n_inst, W, H)
+    W, H = cam.width, cam.height
     n = W * H
-    nets, train = train_nedfs(models, config, args)
     scales = []
     for k, net in enumerate(nets):
         o, d = syn.training_rays(config, 500 + k, 65536)
@@ -627,6 +641,7 @@ def precision_bench(args):
     pix_t = torch.from_numpy(pix).cuda()
     runs = {}
     ws = api.Workspace()
+    peak = {"f32": PEAK_TFLOPS["f32"], "bf16": PEAK_TFLOPS["bf16"], "fp8": PEAK_TFLOPS["fp8"]}
     for name, dens_dt, nedf_dt, refine in (("f32", "f32", "f32", 3), ("bf16", "bf16", "bf16", 3),
                                            ("fp8+refine", "bf16", "fp8", 3), ("fp8", "bf16", "fp8", 0)):
         objs = [api.object_from_model(m, dens_dt, nedf_model=nn, nedf_dtype=nedf_dt,
@@ -647,32 +662,55 @@ def precision_bench(args):
         step()
         torch.cuda.synchronize()
         st = api.ws_counters(ws)
+        api.profile_enable(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(args.steps):
             step()
         e1.record()
         torch.cuda.synchronize()
+        stages = api.profile_read()
+        api.profile_enable(False)
         assert api.check_status(ws) == 0
         ms = e0.elapsed_time(e1) / args.steps
+        ev = st["nedf_hits"] + st["fallback"] + st["nedf_misses"]
+        net_ms, net_n = stages.get("infer.nedf/net", (0.0, 1))
+        net_ms /= args.steps
+        tflops = 2.0 * MAC_NEDF * ev / (net_ms * 1e-3) / 1e12 if net_ms > 0 else 0.0
         dn, idn = depth[pix_t].cpu().numpy().astype(np.float64), ident[pix_t].cpu().numpy()
         both = (idn >= 0) & (im >= 0)
         err = np.abs(dn[both] - dm[both])
         runs[name] = {"rays_per_s": n / (ms * 1e-3), "ms": ms,
+                      "network_ms_per_frame": net_ms, "network_launches_per_frame": net_n // max(args.steps, 1),
+                      "network_pairs": int(ev), "network_tflops": tflops,
+                      "network_frac_of_peak": tflops / peak[nedf_dt], "network_peak_tflops": peak[nedf_dt],
                       "hit_agreement": float(np.mean((idn >= 0) == (im >= 0))),
                       "id_agreement": float(np.mean(idn == im)),
                       "median_depth_err_frac_extent": float(np.median(err)) / extent if err.size else None,
                       "p90_depth_err_frac_extent": float(np.quantile(err, 0.9)) / extent if err.size else None,
-                      "fallback_frac": st["fallback"] / max(st["nedf_hits"] + st["fallback"] + st["nedf_misses"], 1)}
+                      "fallback_frac": st["fallback"] / max(ev, 1)}
         log(f"precision {name}: {runs[name]}")
+    return runs, extent, len(pix)
+
+
+def precision_bench(args):
+    import synthetic as syn
+
+    config = 5
+    W, H = (args.width, args.height) if args.width != 1920 else (3840, 2160)
+    n_inst = args.instances if args.instances != 1000 else 64
+    models, insts, cam, _ = syn.batched_scene(config, n_inst, W, H)
+    nets, train = train_nedfs(models, config, args)
+    runs, extent, n_pix = precision_runs(models, nets, insts, cam, config, args)
+    fp8 = runs["fp8+refine"]
     line = {
         "metric": METRIC,
-        "value": runs["fp8+refine"]["rays_per_s"],
+        "value": fp8["rays_per_s"],
         "unit": "rays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": 1,
-        "ms_per_step": runs["fp8+refine"]["ms"],
+        "ms_per_step": fp8["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -680,7 +718,10 @@ def precision_bench(args):
         "data": "synthetic (seeded SDF-biased NeRF objects; intersection networks trained in setup)",
         "config": {"workload": f"precision stress: {n_inst} instances of 4 SDF-biased NeRF objects, {W}x{H}, "
                                f"depth+ID per intersection-network dtype",
-                   "extent": extent, "judge": f"library FP32 marcher, 192 samples, {len(pix)} seeded pixels"},
+                   "extent": extent, "judge": f"library FP32 marcher, 192 samples, {n_pix} seeded pixels"},
+        "roofline": {"bound": "mfma", "achieved": fp8["network_tflops"], "peak": PEAK_TFLOPS["fp8"],
+                     "unit": "TFLOP/s", "frac": fp8["network_frac_of_peak"], "traffic": None,
+                     "kernel": "infer.nedf/net (FP8)"},
         "per_dtype": runs,
         "training": train,
     }
