@@ -641,9 +641,11 @@ def precision_runs(models, nets, insts, cam, config, args):
     pix_t = torch.from_numpy(pix).cuda()
     runs = {}
     ws = api.Workspace()
-    peak = {"f32": PEAK_TFLOPS["f32"], "bf16": PEAK_TFLOPS["bf16"], "fp8": PEAK_TFLOPS["fp8"]}
+    peak = {"f32": PEAK_TFLOPS["f32"], "bf16": PEAK_TFLOPS["bf16"], "fp8": PEAK_TFLOPS["fp8"],
+            "fp8mx": PEAK_TFLOPS["fp8"]}
     for name, dens_dt, nedf_dt, refine in (("f32", "f32", "f32", 3), ("bf16", "bf16", "bf16", 3),
-                                           ("fp8+refine", "bf16", "fp8", 3), ("fp8", "bf16", "fp8", 0)):
+                                           ("fp8+refine", "bf16", "fp8", 3), ("fp8", "bf16", "fp8", 0),
+                                           ("fp8mx+refine", "bf16", "fp8mx", 3), ("fp8mx", "bf16", "fp8mx", 0)):
         objs = [api.object_from_model(m, dens_dt, nedf_model=nn, nedf_dtype=nedf_dt,
                                       nedf_scales=sc.reshape(-1) if nedf_dt == "fp8" else None)
                 for m, nn, sc in zip(models, nets, scales)]
@@ -651,8 +653,9 @@ def precision_runs(models, nets, insts, cam, config, args):
         depth = torch.empty(n, dtype=torch.float32, device="cuda")
         ident = torch.empty(n, dtype=torch.int32, device="cuda")
         io = api.infer_opts(dens_dt, refine_steps=refine, n_samples=args.fallback_samples)
-        api.autotune("nedf", nedf_dt, scn, rays, io, reps=1, ws=ws)
-        api.autotune("slabs", nedf_dt, scn, rays, io, reps=1, ws=ws)
+        if nedf_dt != "fp8mx":  # MX runs its one launch shape and the FP8 slab count
+            api.autotune("nedf", nedf_dt, scn, rays, io, reps=1, ws=ws)
+            api.autotune("slabs", nedf_dt, scn, rays, io, reps=1, ws=ws)
 
         def step():
             scn.inst_w2l = api.compose_transforms(scn.inst_G)

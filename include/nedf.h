@@ -60,7 +60,12 @@ typedef enum nedf_status {
 typedef enum nedf_dtype {
   NEDF_F32 = 0,   /* float32 matrix cores (v_mfma_f32_32x32x2_f32) */
   NEDF_BF16 = 1,  /* bfloat16 inputs, float32 accumulate */
-  NEDF_FP8 = 2    /* OCP E4M3FN inputs with per-layer scales, float32 accumulate */
+  NEDF_FP8 = 2,   /* OCP E4M3FN inputs with per-layer scales, float32 accumulate */
+  NEDF_FP8_MX = 3 /* OCP MX: E4M3FN inputs with one power-of-two (E8M0) scale per 32 values along the
+                     reduction, float32 accumulate; weight scales packed per output row, activation
+                     scales formed in the kernel per sample (largest magnitude of the block,
+                     exponent floor(log2 amax) - 8, values saturating at +-448).  Intersection network
+                     (regression form) only; needs no calibration. */
 } nedf_dtype;
 
 /* Density field families of an object (local/canonical space). */
@@ -171,7 +176,8 @@ typedef struct nedf_march_opts {
 /* Options of the NeDF path (Eq. 1, 2, 7 with marcher fallback and refinement). */
 typedef struct nedf_infer_opts {
   int32_t dtype;            /* precision of fallback/refinement density fields; the intersection
-                               networks run in their blob's dtype (this dtype or NEDF_FP8) */
+                               networks run in their blob's dtype (this dtype, NEDF_FP8 or
+                               NEDF_FP8_MX) */
   float p_lo, p_hi;         /* hit probability band sent to the marcher (inclusive), default 0.2 / 0.8 */
   int32_t refine_steps;     /* secant updates on the winning pixel (0 = off), default 3 */
   float refine_h;           /* seed offset in the object's own units (world offset refine_h * s for an

@@ -258,3 +258,121 @@ def classifier_decision_ambiguity(model, o_l, d_l, gemm=None, margin=2.0):
     mu_dev = largest_move(c0, 2.0 * l / nc) + largest_move(f0, 2.0 * l / (nc * nf))
     p_dev = np.maximum(np.abs(sigmoid(a0 + eps_a) - sigmoid(a0)), np.abs(sigmoid(a0 - eps_a) - sigmoid(a0)))
     return mu_dev, p_dev
+
+
+def nedf_mx_ambiguity(model, o_l, d_l, coord_err, sin_err, max_alternatives=32):
+    """MX block-scaled E4M3 networks (``oracle.mx``): for each ray, the
+    largest change of clamp(mu_hat) and of sigmoid(z) when a quantisation
+    decision of some layer's input lies within that value's error bound of
+    its threshold, decided the other way and the network re-run from that
+    layer.  Values: the encoded features (bound ``encoding_error_bound``) and
+    each hidden layer's output (single-precision accumulation bound
+    gamma_K sum |a w| plus a few units of the result).  Decisions: the E4M3
+    rounding of a value in its block's scaled units; the ReLU kink; and a
+    block's shared exponent floor(log2 amax), when amax lies within its
+    bound of a power of two (the whole block re-quantised one exponent up or
+    down).  Each decision alone, then all of a layer's together.  Returns
+    (ambiguity of clamp(mu_hat) [n], of sigmoid(z) [n], decisions [n])."""
+    from .mx import mx_quantize, hidden_blocks, encoded_blocks, mx_exponent
+    x = _features(model, o_l, d_l)
+    n = x.shape[0]
+    L = model.params["enc_L"]
+    W = [np.asarray(w, F64) for w in model.trunk.W]
+    b = [np.asarray(v, F64) for v in model.trunk.b]
+    nh = len(W) - 1
+    u = 2.0 ** -24
+    blocks = [encoded_blocks(6, L)] + [hidden_blocks(W[j].shape[1]) for j in range(1, nh)]
+    Wq = [mx_quantize(W[j], blocks[j])[0] for j in range(nh)]
+
+    def run_from(j, hq):
+        h = None
+        for jj in range(j, nh):
+            h = np.maximum(hq @ Wq[jj].T + b[jj], 0.0)
+            if jj + 1 < nh:
+                hq = mx_quantize(h, blocks[jj + 1])[0]
+        return h @ W[-1].T + b[-1]
+
+    # each layer's value before quantisation, its error bound, and (hidden)
+    # its pre-activation
+    vals = [x]
+    errs = [encoding_error_bound(coord_err, L, sin_err)]
+    pre = [None]
+    hq = mx_quantize(x, blocks[0])[0]
+    hqs = [hq]
+    for j in range(nh - 1):
+        z = hq @ Wq[j].T + b[j]
+        K = Wq[j].shape[1]
+        gam = K * u / (1.0 - K * u)
+        err = gam * (np.abs(hq) @ np.abs(Wq[j]).T) + 4 * u * (np.abs(z) + np.abs(b[j]))
+        y = np.maximum(z, 0.0)
+        vals.append(y)
+        errs.append(err)
+        pre.append(z)
+        hq = mx_quantize(y, blocks[j + 1])[0]
+        hqs.append(hq)
+    base = run_from(0, hqs[0])
+    amb = np.zeros(n)
+    amb_p = np.zeros(n)
+    count = np.zeros(n, np.int64)
+
+    def apply(j, rows, alts):
+        """Re-run from layer j with per-row altered quantised inputs."""
+        dmu, dp = _head_delta(run_from(j, alts), base[rows])
+        np.maximum.at(amb, rows, dmu)
+        np.maximum.at(amb_p, rows, dp)
+
+    for j in range(nh):
+        y, e, hq = vals[j], errs[j], hqs[j]
+        cand = []   # (row, column indices, their alternative dequantised values)
+        for blk in blocks[j]:
+            if blk.size == 0:
+                continue
+            v = y[:, blk]
+            ev = e[:, blk]
+            amax = np.max(np.abs(v), axis=1)
+            ex = mx_exponent(amax)
+            X = np.exp2(ex)[:, None]
+            r = v / X
+            # element roundings
+            with np.errstate(invalid="ignore"):
+                marg = np.where(r != 0, e4m3_rounding_margin(r) * np.abs(r), np.inf)
+            close = marg < ev / X
+            if pre[j] is not None:
+                close |= (np.abs(pre[j][:, blk]) <= ev) & (v == 0)
+            for row, col in zip(*np.nonzero(close)):
+                if v[row, col] == 0:
+                    alt = round_e4m3(ev[row, col] / X[row, 0]) * X[row, 0]
+                else:
+                    alt = _other_neighbour(r[row, col], marg[row, col], round_e4m3) * X[row, 0]
+                cand.append((row, blk[col:col + 1], np.array([alt])))
+            # shared exponent: amax within its bound of a power of two
+            k = np.floor(np.log2(np.where(amax > 0, amax, 1.0)))
+            emax = ev[np.arange(v.shape[0]), np.argmax(np.abs(v), axis=1)]
+            lo, hi = amax - np.exp2(k), np.exp2(k + 1) - amax
+            for row in np.nonzero((amax > 0) & (np.minimum(lo, hi) <= emax))[0]:
+                ex2 = ex[row] + (-1.0 if lo[row] <= hi[row] else 1.0)
+                X2 = np.exp2(ex2)
+                cand.append((row, blk, round_e4m3(v[row] / X2) * X2))
+        if not cand:
+            continue
+        rows = np.array([c[0] for c in cand])
+        count += np.bincount(rows, minlength=n)
+        # each decision alone (at most max_alternatives per ray and layer)
+        seen = {}
+        sel = []
+        for i, c in enumerate(cand):
+            seen[c[0]] = seen.get(c[0], 0) + 1
+            if seen[c[0]] <= max_alternatives:
+                sel.append(i)
+        alts = hq[rows[sel]].copy()
+        for a, i in enumerate(sel):
+            alts[a, cand[i][1]] = cand[i][2]
+        apply(j, rows[sel], alts)
+        # all of a ray's decisions of this layer together
+        ur = np.unique(rows)
+        pos = {r_: i for i, r_ in enumerate(ur)}
+        alls = hq[ur].copy()
+        for c in cand:
+            alls[pos[c[0]], c[1]] = c[2]
+        apply(j, ur, alls)
+    return amb, amb_p, count

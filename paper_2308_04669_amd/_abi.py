@@ -13,7 +13,7 @@ W2L_FLOATS = 16
 NEDF_OK = 0
 STATUS = {0: "OK", 1: "NULL", 2: "SHAPE", 3: "DTYPE", 4: "ALIGN", 5: "WORKSPACE", 6: "CAPACITY",
           7: "HIP", 8: "UNSUPPORTED"}
-DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "fp8mx": 3}
 FIELDS = {"sphere": 0, "slab": 1, "mlp": 2}
 SIGMA_MODES = {"softplus": 0, "softplus_masked": 1, "sdf": 2}
 IN_KINDS = {"xyz": 0, "pluecker": 1, "points16": 2}

@@ -241,8 +241,10 @@ int32_t prepare_scene(const nedf_scene* sc, int32_t dtype, Prepared& P) {
       if (!cls && (s.in_kind != NEDF_IN_PLUECKER || s.n_out != 2))
         return fail(NEDF_ERR_SHAPE, "intersection network must take Pluecker coordinates and output (mu, logit), "
                                     "or be a classifier-form network");
-      if (o.nedf.dtype != dtype && o.nedf.dtype != NEDF_FP8)
-        return fail(NEDF_ERR_DTYPE, "intersection network dtype must be the call's dtype or FP8");
+      if (o.nedf.dtype != dtype && o.nedf.dtype != NEDF_FP8 && o.nedf.dtype != NEDF_FP8_MX)
+        return fail(NEDF_ERR_DTYPE, "intersection network dtype must be the call's dtype, FP8 or FP8_MX");
+      if (cls && o.nedf.dtype == NEDF_FP8_MX)
+        return fail(NEDF_ERR_UNSUPPORTED, "MX FP8 covers the regression-form network");
       if (P.nedf_dtype >= 0 && o.nedf.dtype != P.nedf_dtype)
         return fail(NEDF_ERR_UNSUPPORTED, "all intersection networks of one call must share a dtype");
       if (P.nedf && cls != P.nedf_cls)
@@ -341,7 +343,9 @@ void run_infer_keys(const Prepared& P, int dtype, const nedf_infer_opts& o, hipS
   // analytic objects without a network are marched directly
   const uint32_t direct = P.analytic & ~P.nedf;
   if (direct) stage_march(k, s, false, direct, dtype, 0, 0, 0);
-  if (P.nedf) stage_nedf(k, s, P.nedf_dtype, P.nedf, tune_value(NEDF_TUNE_SLABS, P.nedf_dtype), P.nedf_cls);
+  // MX networks take the FP8 slab count
+  const int slab_dt = P.nedf_dtype == NEDF_FP8_MX ? NEDF_FP8 : P.nedf_dtype;
+  if (P.nedf) stage_nedf(k, s, P.nedf_dtype, P.nedf, tune_value(NEDF_TUNE_SLABS, slab_dt), P.nedf_cls);
   // uncertain pairs: marcher on list B
   stage_march(k, s, true, P.analytic, dtype, (P.mlp & P.nedf) ? P.W : 0, P.H, P.L);
 }

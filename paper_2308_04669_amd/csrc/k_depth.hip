@@ -995,6 +995,9 @@ void launch_nedf_net(const KArgs& k, hipStream_t s, int v) {
       case 1012: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 8>), g1, b8, 0, s, k); return;
       default: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 4>), g1, b4, 0, s, k); return;
     }
+  } else if constexpr (DT == 3) {
+    // MX: superchunks of four blocks, four waves (items of 128 pairs)
+    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1, 4>), g1, b4, 0, s, k);
   } else {
     hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 4>), g1, b4, 0, s, k);
   }
@@ -1018,7 +1021,7 @@ bool march_mlp_supported(int dtype, int width, int n_hidden, int L) {
 }
 
 bool nedf_net_supported(int dtype, int width, int n_hidden, int L) {
-  if (dtype != NEDF_F32 && dtype != NEDF_BF16 && dtype != NEDF_FP8) return false;
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16 && dtype != NEDF_FP8 && dtype != NEDF_FP8_MX) return false;
   return width == 256 && n_hidden == 8 && L == 8;
 }
 
@@ -1121,6 +1124,7 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
     prof_mark("net", s, true);
     if (classifier) launch_nedf_cls(k, s, dtype);
     else if (dtype == NEDF_FP8) launch_nedf_net<2>(k, s, v);
+    else if (dtype == NEDF_FP8_MX) launch_nedf_net<3>(k, s, v);
     else if (dtype == NEDF_BF16) launch_nedf_net<1>(k, s, v);
     else launch_nedf_net<0>(k, s, v);
     prof_mark("net", s, false);

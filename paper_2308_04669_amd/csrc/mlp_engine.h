@@ -70,13 +70,81 @@ template <> struct Tr<2> {  // OCP E4M3 inputs with per-layer scales, float32 ac
   }
 };
 
+// MX E4M3 (OCP Microscaling): E4M3 values with one E8M0 scale per 32 along
+// K, applied by the scaled matrix op.  In the operand registers a lane's
+// bytes 0..15 belong to the first 32-value block of the K-step (with the
+// other lane half's bytes 0..15) and bytes 16..31 to the second; the scale
+// of the first block comes from the lane in half 0 and that of the second
+// from the lane in half 1, each in byte 0 of its scale operand.
+template <> struct Tr<3> {
+  typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8_t;
+  struct frag {
+    i32x8_t v;  // 32 E4M3 values
+    int sc;     // this lane's block scale (E8M0 in byte 0)
+  };
+  static constexpr int KPS = 64;
+  static constexpr int FRAG = 2048;
+  static constexpr int KPR = 1;
+  static constexpr int NB = 1;
+  __device__ static __forceinline__ f32x16_t mma(const i32x8_t& a, int a_sc, const frag& b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b.v, c, 0, 0, 0, a_sc, 0, b.sc);
+  }
+  __device__ static __forceinline__ i32x8_t pick2(const u32x4& lo, const u32x4& hi) {
+    i32x8_t f;
+    f[0] = int(lo.x); f[1] = int(lo.y); f[2] = int(lo.z); f[3] = int(lo.w);
+    f[4] = int(hi.x); f[5] = int(hi.y); f[6] = int(hi.z); f[7] = int(hi.w);
+    return f;
+  }
+};
+
+// E8M0 block scale of a block whose largest magnitude is amax (>= 0):
+// exponent floor(log2 amax) - 8 (8: E4M3's largest exponent) as a biased
+// byte, and the power of two 2^-(that exponent) the values are multiplied by
+// before rounding to E4M3 (1 for an all-zero block, whose byte is 0).
+__device__ __forceinline__ void mx_scale(float amax, int& byte, float& inv) {
+  const int eb = int((__float_as_uint(amax) >> 23) & 0xFFu);  // biased exponent; 0 for zero and subnormals
+  if (eb == 0) {
+    byte = 0;
+    inv = 1.0f;
+    return;
+  }
+  const int e = eb - 127 - 8;  // scale exponent
+  byte = e + 127 < 0 ? 0 : (e + 127 > 254 ? 254 : e + 127);
+  inv = __builtin_amdgcn_ldexpf(1.0f, -(byte - 127));
+}
+
+// Quantise 16 values of one lane with a block scale: four packed E4M3 words.
+__device__ __forceinline__ void mx_pack16(const float (&v)[16], float inv, int (&w)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[j] = fminf(fmaxf(v[4 * q + j] * inv, -448.0f), 448.0f);
+    int x = __builtin_amdgcn_cvt_pk_fp8_f32(t[0], t[1], 0, false);
+    w[q] = __builtin_amdgcn_cvt_pk_fp8_f32(t[2], t[3], x, true);
+  }
+}
+
 // Matrix ops of one group of G consecutive 16-byte LDS reads (read r0..r0+G-1
 // of the chunk) against the B operand.
 template <int DT, int NB, int KS_IN, int G>
 __device__ __forceinline__ void mma_group(const u32x4 (&w)[G], int r0, int R,
-                                          const typename Tr<DT>::frag (&Bin)[NB][KS_IN], f32x16_t (&acc)[NB]) {
+                                          const typename Tr<DT>::frag (&Bin)[NB][KS_IN], f32x16_t (&acc)[NB],
+                                          uint32_t wsc = 0u) {
   using T = Tr<DT>;
-  if constexpr (DT == 2) {
+  if constexpr (DT == 3) {
+    // wsc: this lane's weight-block scales, byte ks for K-step ks
+#pragma unroll
+    for (int r = 0; r + 1 < G; r += 2) {
+      if (r0 + r + 1 < R) {
+        const int ks = (r0 + r) / 2;
+        const typename T::i32x8_t a = T::pick2(w[r], w[r + 1]);
+        const int asc = int((wsc >> (8 * ks)) & 0xFFu);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = T::mma(a, asc, Bin[nb][ks], acc[nb]);
+      }
+    }
+  } else if constexpr (DT == 2) {
 #pragma unroll
     for (int r = 0; r + 1 < G; r += 2) {
       if (r0 + r + 1 < R) {
@@ -104,12 +172,16 @@ __device__ __forceinline__ void mma_group(const u32x4 (&w)[G], int r0, int R,
 
 // Matrix ops per group (for scheduling hints).
 template <int DT, int NB, int G>
-constexpr int mma_per_group() { return DT == 2 ? (G / 2) * NB : G * Tr<DT>::KPR * NB; }
+constexpr int mma_per_group() { return DT >= 2 ? (G / 2) * NB : G * Tr<DT>::KPR * NB; }
 
 // Bytes of one chunk: K-steps of fragments, bias, head rows.
+// MX adds 1 KB of weight-block scales after the fragments ([lane][16] bytes,
+// byte ks of lane l the scale of K-step ks's block that lane supplies).
+template <int DT>
+constexpr int mx_scale_bytes() { return DT == 3 ? 1024 : 0; }
 template <int DT>
 constexpr int chunk_bytes(int ks, int heads) {
-  return ks * Tr<DT>::FRAG + 128 * (1 + heads);
+  return ks * Tr<DT>::FRAG + mx_scale_bytes<DT>() + 128 * (1 + heads);
 }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -193,7 +265,31 @@ __device__ __forceinline__ void epi_hidden(int fb, const f32x16_t (&acc)[NB],
                                            typename Tr<DT>::frag (&Bout)[NB][KSO], float2 qs) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    if constexpr (DT == 2) {
+    if constexpr (DT == 3) {
+      // ReLU; block fb (this sample's 32 features, 16 in each lane half) is
+      // one MX block of K-step fb / 2: its scale from the larger of the two
+      // halves' maxima, the lane's 16 values quantised into bytes
+      // 16 (fb % 2) .. + 15; the half whose turn it is (half fb % 2)
+      // carries the scale byte
+      float v[16];
+      float mx = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        v[r] = fmaxf(acc[nb][r], 0.0f);
+        mx = fmaxf(mx, v[r]);
+      }
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      int byte;
+      float inv;
+      mx_scale(mx, byte, inv);
+      int w[4];
+      mx_pack16(v, inv, w);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bout[nb][fb / 2].v[(fb % 2) * 4 + q] = w[q];
+      const int half = (threadIdx.x & 63) >> 5;
+      if (half == (fb % 2)) Bout[nb][fb / 2].sc = byte;
+      (void)qs;
+    } else if constexpr (DT == 2) {
       // real = acc * qs.x; ReLU; quantise real / a_next = acc * (qs.x * qs.y)
       // to E4M3 (saturating at +-448); block fb fills half of K-step fb / 2
       const float m = qs.x * qs.y;
@@ -288,7 +384,11 @@ template <int DT, int NB, int KSO>
 __device__ __forceinline__ void pin_block(int fb, typename Tr<DT>::frag (&Bout)[NB][KSO]) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    if constexpr (DT == 2) {
+    if constexpr (DT == 3) {
+      asm volatile("" ::"v"(Bout[nb][fb / 2].v[(fb % 2) * 4 + 0]), "v"(Bout[nb][fb / 2].v[(fb % 2) * 4 + 1]),
+                   "v"(Bout[nb][fb / 2].v[(fb % 2) * 4 + 2]), "v"(Bout[nb][fb / 2].v[(fb % 2) * 4 + 3]),
+                   "v"(Bout[nb][fb / 2].sc));
+    } else if constexpr (DT == 2) {
       asm volatile("" ::"v"(Bout[nb][fb / 2][(fb % 2) * 4 + 0]), "v"(Bout[nb][fb / 2][(fb % 2) * 4 + 1]),
                    "v"(Bout[nb][fb / 2][(fb % 2) * 4 + 2]), "v"(Bout[nb][fb / 2][(fb % 2) * 4 + 3]));
     } else if constexpr (DT == 1) {
@@ -364,10 +464,12 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   constexpr int G = 4;
   constexpr int NG = (R + G - 1) / G;
   constexpr int NH = (MODE == 1 || MODE == 2) ? NOUT : 0;
-  constexpr int PER = 1 + NG + NH;  // read groups per block
+  constexpr bool MX = (DT == 3);    // one more read per block: the weight-block scales
+  constexpr int PER = 1 + (MX ? 1 : 0) + NG + NH;  // read groups per block
   constexpr int E = SB * PER;       // read groups per superchunk
   constexpr int D = 3;              // groups issued ahead of consumption
-  constexpr int BIAS = KS_IN * T::FRAG;
+  constexpr int SCALES = KS_IN * T::FRAG;
+  constexpr int BIAS = SCALES + mx_scale_bytes<DT>();
   // hidden-layer epilogues are deferred by one block so that their vector
   // work overlaps the next block's matrix ops
   constexpr bool DEFER = (MODE == 0 || MODE == 3);
@@ -380,7 +482,8 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   // block, then per block k its fragment groups, with the bias of block k + 1
   // placed before block k's last fragment group (so that initialising the
   // next accumulator overlaps block k's last matrix ops), then block k's head
-  // rows.  kind 0 bias, 1 fragment group (idx g), 2 head row (idx o).
+  // rows.  kind 0 bias, 1 fragment group (idx g), 2 head row (idx o), 3 the
+  // block's weight-block scales (MX; one read, right after its bias).
   struct Grp {
     int kind, k, idx;
   };
@@ -390,11 +493,19 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
       if (k == 0) {
         if (n == e) return Grp{0, 0, 0};
         ++n;
+        if (MX) {
+          if (n == e) return Grp{3, 0, 0};
+          ++n;
+        }
       }
       for (int g = 0; g < NG; ++g) {
         if (g == NG - 1 && k + 1 < SB) {
           if (n == e) return Grp{0, k + 1, 0};
           ++n;
+          if (MX) {
+            if (n == e) return Grp{3, k + 1, 0};
+            ++n;
+          }
         }
         if (n == e) return Grp{1, k, g};
         ++n;
@@ -410,6 +521,7 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   constexpr auto cnt = [grp](int e) constexpr {
     if (e >= E) return 0;
     const Grp q = grp(e);
+    if (q.kind == 3) return 1;
     if (q.kind != 1) return 4;
     return R - q.idx * G < G ? R - q.idx * G : G;
   };
@@ -434,6 +546,8 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
           constexpr int r = decltype(rc)::value;
           dst[r] = lds_read16<k * CB_THIS + (g * G + r) * 1024>(fbase);
         });
+      } else if constexpr (q.kind == 3) {
+        dst[0] = lds_read16<k * CB_THIS + SCALES>(fbase);
       } else {
         constexpr int o = q.idx;
         static_for<4>([&](auto qc) __attribute__((always_inline)) {
@@ -445,6 +559,7 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
   };
   // accumulators alternate between consecutive blocks of a superchunk
   f32x16_t acc2[2][NB];
+  uint32_t wsc2[2] = {0u, 0u};  // MX: the lane's weight-block scales of those blocks
   // consume group e (already in registers cw) of superchunk sc
   auto consume = [&](auto ec, int sc, const u32x4(&cw)[G]) __attribute__((always_inline)) {
     constexpr int e = decltype(ec)::value;
@@ -463,7 +578,7 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
       for (int nb = 0; nb < NB; ++nb) acc[nb] = b0;
     } else if constexpr (q.kind == 1) {
       constexpr int g = q.idx;
-      mma_group<DT, NB, KS_IN, G>(cw, g * G, R, Bin, acc);
+      mma_group<DT, NB, KS_IN, G>(cw, g * G, R, Bin, acc, wsc2[k & 1]);
       if constexpr (DEFER && g == 0) {
         if (fb > 0) epi_deferred(fb - 1, prev);
       }
@@ -487,6 +602,8 @@ __device__ __forceinline__ void layer(const typename Tr<DT>::frag (&Bin)[NB][KS_
           epi_argmax<NB, NOUT>(fb, acc, partial);
         }
       }
+    } else if constexpr (q.kind == 3) {
+      wsc2[k & 1] = cw[0].x;
     } else {
       // head row o: partial[nb][o] += w . relu(real(acc))
       constexpr int o = q.idx;
@@ -678,7 +795,32 @@ __device__ __forceinline__ float enc_slot(const float (&p)[N], const float (&plo
 template <int DT, int N, int L, int KS0>
 __device__ __forceinline__ void encode_input(const float (&p)[N], const float (&plo)[N], int half,
                                              typename Tr<DT>::frag (&B)[KS0], float inv_scale = 1.0f) {
-  if constexpr (DT == 2) {
+  if constexpr (DT == 3) {
+    // MX: the 16 slots of each block from both lane halves share a scale
+#pragma unroll
+    for (int ks = 0; ks < KS0; ++ks) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        float v[16];
+        float mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          v[i] = enc_slot<N, L>(p, plo, 32 * ks + 16 * b + i, half);
+          mx = fmaxf(mx, fabsf(v[i]));
+        }
+        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        int byte;
+        float inv;
+        mx_scale(mx, byte, inv);
+        int w[4];
+        mx_pack16(v, inv, w);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[ks].v[4 * b + q] = w[q];
+        if (half == b) B[ks].sc = byte;
+      }
+    }
+    (void)inv_scale;
+  } else if constexpr (DT == 2) {
     // 32 slots per K-step and lane half, quantised to E4M3 with the
     // input's activation scale
 #pragma unroll
@@ -720,7 +862,7 @@ __device__ __forceinline__ void encode_input(const float (&p)[N], int half, type
 // K-steps of an encoded input with n components and L levels.
 template <int DT>
 constexpr int ks_for_slots(int slots) {
-  return DT == 2 ? (slots + 31) / 32 : DT == 1 ? (slots + 7) / 8 : (slots + 3) / 4 * 4;
+  return DT >= 2 ? (slots + 31) / 32 : DT == 1 ? (slots + 7) / 8 : (slots + 3) / 4 * 4;
 }
 
 }  // namespace eng

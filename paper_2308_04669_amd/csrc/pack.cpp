@@ -1,5 +1,6 @@
 // Host-side packing of float32 network weights into the blob layout read by
 // the matrix-core kernels (see blob_layout.h for the register layout).
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -62,7 +63,10 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
   Plan p;
   std::memset(&p.h, 0, sizeof(p.h));
   if (!s) { p.why = "shape is NULL"; return p; }
-  if (dtype != NEDF_F32 && dtype != NEDF_BF16 && dtype != NEDF_FP8) { p.why = "dtype not supported by the packer"; return p; }
+  if (dtype != NEDF_F32 && dtype != NEDF_BF16 && dtype != NEDF_FP8 && dtype != NEDF_FP8_MX) {
+    p.why = "dtype not supported by the packer";
+    return p;
+  }
   if (s->in_kind != NEDF_IN_XYZ && s->in_kind != NEDF_IN_PLUECKER) { p.why = "bad in_kind"; return p; }
   if (s->width != 64 && s->width != 256) { p.why = "width must be 64 or 256"; return p; }
   if (s->n_hidden < 2 || s->n_hidden > NEDF_MAX_LAYERS) { p.why = "n_hidden must be 2..16"; return p; }
@@ -73,8 +77,10 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
   if (s->rgb_width && s->in_kind != NEDF_IN_XYZ) { p.why = "colour branch needs an xyz input"; return p; }
   nedf_blob_header& h = p.h;
   const bool bf = dtype == NEDF_BF16;
-  const bool f8 = dtype == NEDF_FP8;
+  const bool mx = dtype == NEDF_FP8_MX;
+  const bool f8 = dtype == NEDF_FP8 || mx;
   if (f8 && s->rgb_width) { p.why = "FP8 packing covers networks without a colour branch"; return p; }
+  if (mx && s->in_kind != NEDF_IN_PLUECKER) { p.why = "MX FP8 packing covers the intersection network"; return p; }
   const int n = in_components(s->in_kind);
   h.magic = NEDF_BLOB_MAGIC;
   h.version = NEDF_BLOB_VERSION;
@@ -102,7 +108,7 @@ Plan plan_blob(const nedf_mlp_shape* s, int32_t dtype) {
   for (int i = 0; i < s->n_hidden; ++i) {
     const size_t ks = i == 0 ? h.ks_in : h.ks_hidden;
     const size_t heads = i == s->n_hidden - 1 ? size_t(s->n_out) : 0;
-    h.chunk_bytes[i] = uint32_t(ks * h.frag_bytes + 128 * (1 + heads));
+    h.chunk_bytes[i] = uint32_t(ks * h.frag_bytes + (mx ? 1024 : 0) + 128 * (1 + heads));
     h.off_layer[i] = off;
     off = align256(off + fbn * h.chunk_bytes[i]);
   }
@@ -130,7 +136,7 @@ int n_comp(const nedf_blob_header& h) { return h.in_kind == NEDF_IN_PLUECKER ? 6
 //         2 = colour layer (hidden features, then the direction encoding)
 int logical_to_feature(const nedf_blob_header& h, int part, int k) {
   const bool bf = h.dtype == NEDF_BF16;
-  const bool f8 = h.dtype == NEDF_FP8;
+  const bool f8 = h.dtype == NEDF_FP8 || h.dtype == NEDF_FP8_MX;
   int ks, hh, j;
   if (f8) { ks = k / 64; hh = (k % 64) / 32; j = k % 32; }
   else if (bf) { ks = k / 16; hh = (k % 16) / 8; j = k % 8; }
@@ -165,6 +171,48 @@ int logical_to_feature(const nedf_blob_header& h, int part, int k) {
 void pack_fragments(const nedf_blob_header& h, int part, const float* W, int rows, int cols,
                     int ks_count, size_t chunk_bytes, uint8_t* dst, float w_scale = 1.0f) {
   const bool bf = h.dtype == NEDF_BF16;
+  if (h.dtype == NEDF_FP8_MX) {
+    // MX: per output row and K-step two blocks of 32 weights (bytes 16 b ..
+    // 16 b + 15 of both lane halves), each with its own scale 2^e,
+    // e = floor(log2 amax) - 8; lane l keeps the byte of block l / 32 at
+    // [ks_count x 2 KB] + 16 l + ks
+    for (int fb = 0; fb < rows / 32; ++fb)
+      for (int ks = 0; ks < ks_count; ++ks) {
+        uint8_t* frag = dst + size_t(fb) * chunk_bytes + size_t(ks) * 2048;
+        uint8_t* scl = dst + size_t(fb) * chunk_bytes + size_t(ks_count) * 2048;
+        for (int rr = 0; rr < 32; ++rr) {
+          const int row = 32 * fb + rr;
+          for (int b = 0; b < 2; ++b) {
+            float vals[2][16];
+            double amax = 0.0;
+            for (int hh = 0; hh < 2; ++hh)
+              for (int i = 0; i < 16; ++i) {
+                const int k = 64 * ks + 32 * hh + 16 * b + i;
+                const int f = logical_to_feature(h, part, k);
+                const float v = (f >= 0 && f < cols) ? W[size_t(row) * cols + f] : 0.0f;
+                vals[hh][i] = v;
+                amax = std::max(amax, std::fabs(double(v)));
+              }
+            int byte = 0;
+            double X = 1.0;
+            if (amax > 0.0 && std::isfinite(amax)) {
+              int ex = 0;
+              std::frexp(amax, &ex);  // amax = m 2^ex, 0.5 <= m < 1: floor(log2 amax) = ex - 1
+              const int e = std::min(std::max(ex - 1 - 8, -127), 127);
+              byte = e + 127;
+              X = std::ldexp(1.0, e);
+            }
+            for (int hh = 0; hh < 2; ++hh) {
+              const int l = rr + 32 * hh;
+              for (int i = 0; i < 16; ++i)
+                frag[((16 * b + i) / 16) * 1024 + l * 16 + ((16 * b + i) % 16)] = e4m3_rne(float(vals[hh][i] / X));
+              if (hh == b) scl[l * 16 + ks] = uint8_t(byte);
+            }
+          }
+        }
+      }
+    return;
+  }
   if (h.dtype == NEDF_FP8) {
     // FP8: lane l of K-step ks holds 32 bytes k = 64 ks + 32 (l / 32) + j;
     // bytes 0..15 in the first 1 KB half of the fragment, 16..31 in the second
@@ -211,9 +259,9 @@ void pack_fragments(const nedf_blob_header& h, int part, const float* W, int row
 // Bias of every output block, placed after the block's fragments (divided by
 // the layer's to-real multiplier for FP8, whose accumulators are in scaled units).
 void pack_bias(const float* b, int rows, int ks_count, int frag_bytes, size_t chunk_bytes, uint8_t* dst,
-               float to_real = 1.0f) {
+               float to_real = 1.0f, int extra = 0) {
   for (int fb = 0; fb < rows / 32; ++fb) {
-    float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes);
+    float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes + extra);
     for (int hh = 0; hh < 2; ++hh)
       for (int r = 0; r < 16; ++r) out[hh * 16 + r] = b[nedf_acc_feature(fb, hh, r)] / to_real;
   }
@@ -222,10 +270,10 @@ void pack_bias(const float* b, int rows, int ks_count, int frag_bytes, size_t ch
 // Narrow head W [n_out][in_width]: row o's weights of input block fb follow
 // that block's bias, [h][16] in accumulator order.
 void pack_head(const float* W, int n_out, int in_width, int ks_count, int frag_bytes, size_t chunk_bytes,
-               uint8_t* dst) {
+               uint8_t* dst, int extra = 0) {
   for (int fb = 0; fb < in_width / 32; ++fb)
     for (int o = 0; o < n_out; ++o) {
-      float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes +
+      float* out = reinterpret_cast<float*>(dst + size_t(fb) * chunk_bytes + size_t(ks_count) * frag_bytes + extra +
                                             128 * (1 + o));
       for (int hh = 0; hh < 2; ++hh)
         for (int r = 0; r < 16; ++r) out[hh * 16 + r] = W[size_t(o) * in_width + nedf_acc_feature(fb, hh, r)];
@@ -407,6 +455,7 @@ extern "C" int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, con
   const int Wd = shape->width;
   const int fragb = int(h.frag_bytes);
   const bool f8 = dtype == NEDF_FP8;
+  const int extra = dtype == NEDF_FP8_MX ? 1024 : 0;  // MX weight-block scales after the fragments
   float* sc = reinterpret_cast<float*>(base + h.off_scales);
   if (f8) {
     // scales: [0] 1 / a_0, then per layer {a_L w_L (to real), 1 / a_{L+1}}
@@ -424,9 +473,9 @@ extern "C" int32_t nedf_pack_mlp(const nedf_mlp_shape* shape, int32_t dtype, con
     const int ks = int(i == 0 ? h.ks_in : h.ks_hidden);
     uint8_t* dst = base + h.off_layer[i];
     pack_fragments(h, i == 0 ? 0 : 1, W[i], Wd, cols, ks, h.chunk_bytes[i], dst, f8 ? fp8_scales[2 * i] : 1.0f);
-    pack_bias(b[i], Wd, ks, fragb, h.chunk_bytes[i], dst, f8 ? sc[1 + 2 * i] : 1.0f);
+    pack_bias(b[i], Wd, ks, fragb, h.chunk_bytes[i], dst, f8 ? sc[1 + 2 * i] : 1.0f, extra);
     if (i == shape->n_hidden - 1)
-      pack_head(W[shape->n_hidden], shape->n_out, Wd, ks, fragb, h.chunk_bytes[i], dst);
+      pack_head(W[shape->n_hidden], shape->n_out, Wd, ks, fragb, h.chunk_bytes[i], dst, extra);
   }
   std::memcpy(base + h.off_head_b, b[shape->n_hidden], sizeof(float) * shape->n_out);
   if (shape->rgb_width) {

@@ -115,7 +115,7 @@ def near_flags(r, band):
                 | (np.abs(r.A - 0.5) <= band) | r.geo)
 
 
-def pair_oracle(dens, net, rec, o, d, n_samples, dtype, scales=None, band=2e-2):
+def pair_oracle(dens, net, rec, o, d, n_samples, dtype, scales=None, band=2e-2, mx=False):
     """Oracle of one instance (through its single-precision record) on rays
     o, d, as a ``PairResult``.  ``amb`` is the world-depth change
     s l |delta clamp(mu_hat)| and ``amb_p`` the hit-probability change that a
@@ -134,8 +134,12 @@ def pair_oracle(dens, net, rec, o, d, n_samples, dtype, scales=None, band=2e-2):
     from oracle.render import march_instance
     gemm = None if dtype == "f32" else "bf16"
     n = o.shape[0]
+    net_fn = None
+    if mx:
+        from oracle.mx import nedf_eval_mx
+        net_fn = lambda ol, dl: nedf_eval_mx(net, ol, dl)  # noqa: E731
     hit, D, p, path = nedf_pair(net, dens, rec, o, d, p_lo=0.2, p_hi=0.8, n_samples=n_samples, gemm=gemm,
-                                net_scales=scales)
+                                net_scales=scales, net_fn=net_fn)
     A = np.full(n, np.nan)
     fb = np.nonzero(path == 1)[0]
     Dm = np.full(n, np.nan)
@@ -146,7 +150,21 @@ def pair_oracle(dens, net, rec, o, d, n_samples, dtype, scales=None, band=2e-2):
     # every pair on which the network ran (routed to it, or to the marcher
     # by its probability)
     sel = np.nonzero(np.isfinite(p))[0]
-    if net.kind == "nedf16" and sel.size:
+    if mx and sel.size:
+        # MX E4M3: every quantisation decision within its value's error
+        # bound of the threshold, taken the other way, and (doubled) the
+        # move under float32 instead of float64 summation
+        from oracle.mx import nedf_eval_mx
+        from oracle.fields import sigmoid
+        from oracle.ambiguity import nedf_mx_ambiguity
+        o_l, d_l = to_local(rec, o[sel], d[sel])
+        pl, _ = pluecker(o_l, d_l)
+        a_q, p_q, _ = nedf_mx_ambiguity(net, o_l, d_l, coord_err(o_l, pl), SIN_ERR)
+        m0, z0 = nedf_eval_mx(net, o_l, d_l)
+        m1, z1 = nedf_eval_mx(net, o_l, d_l, acc="f32")
+        amb[sel] = rec.s * net.bound * np.maximum(a_q, 2.0 * np.abs(np.clip(m1, -1, 1) - np.clip(m0, -1, 1)))
+        amb_p[sel] = np.maximum(p_q, 2.0 * np.abs(sigmoid(z1) - sigmoid(z0)))
+    elif net.kind == "nedf16" and sel.size:
         # classifier form: argmax decisions and the hit logit near a tie
         from oracle.ambiguity import classifier_decision_ambiguity
         o_l, d_l = to_local(rec, o[sel], d[sel])
@@ -184,7 +202,11 @@ def pair_oracle(dens, net, rec, o, d, n_samples, dtype, scales=None, band=2e-2):
     idx = np.nonzero(lo_b | hi_b)[0]
     if idx.size:
         o_i, d_i = o_l[idx], d_l[idx]
-        mu, _ = nedf_eval(net, o_i, d_i, gemm=gemm, scales=scales)
+        if mx:
+            from oracle.mx import nedf_eval_mx
+            mu, _ = nedf_eval_mx(net, o_i, d_i)
+        else:
+            mu, _ = nedf_eval(net, o_i, d_i, gemm=gemm, scales=scales)
         Dn = rec.s * (t_perp[idx] - l * np.clip(mu, -1.0, 1.0))
         _, Am, Dmi = march_instance(dens, rec, o[idx], d[idx], n_samples, None, gemm)
         march_alt = np.where(Am >= 0.5 - band, Dmi, np.inf)

@@ -492,6 +492,46 @@ def test_infer_fp8_network_and_refine_parity():
     assert np.all(err[chk] <= allow[chk])
 
 
+def test_infer_mx_fp8_network_and_refine_parity():
+    """MX block-scaled E4M3 intersection networks (one power-of-two scale
+    per 32 values, activation scales formed in the kernel) with bfloat16
+    fallback and 3-step refinement, element by element against the oracle
+    emulating MX: IDs must agree outside near-ties and bands, a refined
+    depth within 5e-3 of the oracle's refinement of its own start (where the
+    bracket decision is stable), an unrefined depth within 5e-3 plus its
+    ambiguity."""
+    need_gpu()
+    from paper_2308_04669_amd import api
+    models, nedfs, insts, cam = _nedf_scene()
+    log("case: infer MX FP8 networks, BF16 fallback, refinement")
+    objs = [api.object_from_model(m, "bf16", nedf_model=n, nedf_dtype="fp8mx") for m, n in zip(models, nedfs)]
+    sc = api.make_scene(objs, insts)
+    ws = api.Workspace()
+    o32, d32 = _f32_rays(cam)
+    depth, ident = api.infer_depth_id(sc, _gpu_rays(o32, d32), dtype="bf16", refine_steps=3, ws=ws)
+    depth, ident = _np(depth).astype(np.float64), _np(ident)
+    o, d = o32.astype(np.float64), d32.astype(np.float64)
+    recs = [f32_record(i) for i in insts]
+    res = [pair_oracle(models[r.model], nedfs[r.model], r, o, d, 128, "bf16", mx=True) for r in recs]
+    best, id_o, ex_id, win_amb = _oracle_depth_id(res, "bf16")
+    tol = DEPTH_TOL["bf16"]
+    ref, moved, unstable, spread = refine_with_stability(models, recs, id_o, o, d, np.where(id_o >= 0, best, 0.0),
+                                                         tol + win_amb)
+    bad = (ident != id_o) & ~ex_id
+    chk = (ident == id_o) & (id_o >= 0) & ~ex_id & ~unstable & (spread <= tol / 2)
+    allow = tol + np.where(moved, 0.0, win_amb)
+    err = np.abs(depth - ref)
+    hits = int((id_o >= 0).sum())
+    log(f"[infer mx+refine] hits={hits} exempt_id={int(ex_id.sum())} id_mismatch={int(bad.sum())} "
+        f"checked={int(chk.sum())} refined={int((chk & moved).sum())} "
+        f"max_err_refined={err[chk & moved].max() if (chk & moved).any() else 0:.3e} "
+        f"max_err_unrefined={err[chk & ~moved].max() if (chk & ~moved).any() else 0:.3e} "
+        f"median_amb={np.median(win_amb[id_o >= 0]):.3e} routing {api.ws_counters(ws)}")
+    assert bad.sum() == 0
+    assert chk.sum() >= 0.7 * hits
+    assert np.all(err[chk] <= allow[chk])
+
+
 def test_shade_outlier_resampling_parity():
     """Outlier processing in deferred shading (Sec. "Deferred Shading"): with
     an untrained intersection network many depths miss the surface; pixels
