@@ -63,8 +63,8 @@ typedef enum nedf_dtype {
   NEDF_FP8 = 2,   /* OCP E4M3FN inputs with per-layer scales, float32 accumulate */
   NEDF_FP8_MX = 3 /* OCP MX: E4M3FN inputs with one power-of-two (E8M0) scale per 32 values along the
                      reduction, float32 accumulate; weight scales packed per output row, activation
-                     scales formed in the kernel per sample (largest magnitude of the block,
-                     exponent floor(log2 amax) - 8, values saturating at +-448).  Intersection network
+                     scales formed in the kernel per sample (the smallest power of two that
+                     brings the block's largest magnitude to at most 448).  Intersection network
                      (regression form) only; needs no calibration. */
 } nedf_dtype;
 

@@ -269,9 +269,12 @@ def nedf_mx_ambiguity(model, o_l, d_l, coord_err, sin_err, max_alternatives=32):
     each hidden layer's output (single-precision accumulation bound
     gamma_K sum |a w| plus a few units of the result).  Decisions: the E4M3
     rounding of a value in its block's scaled units; the ReLU kink; and a
-    block's shared exponent floor(log2 amax), when amax lies within its
-    bound of a power of two (the whole block re-quantised one exponent up or
-    down).  Each decision alone, then all of a layer's together.  Returns
+    block's shared exponent, when amax lies within its bound of a step of it
+    (the whole block re-quantised one exponent up or
+    down; the exponent steps where amax crosses 448 times a power of two).
+    Each decision alone, and all of a layer's together, the ambiguity being
+    the larger of the largest such change and the sum over layers of the
+    all-together changes (first-order effect of several layers).  Returns
     (ambiguity of clamp(mu_hat) [n], of sigmoid(z) [n], decisions [n])."""
     from .mx import mx_quantize, hidden_blocks, encoded_blocks, mx_exponent
     x = _features(model, o_l, d_l)
@@ -313,6 +316,8 @@ def nedf_mx_ambiguity(model, o_l, d_l, coord_err, sin_err, max_alternatives=32):
     base = run_from(0, hqs[0])
     amb = np.zeros(n)
     amb_p = np.zeros(n)
+    sum_mu = np.zeros(n)
+    sum_p = np.zeros(n)
     count = np.zeros(n, np.int64)
 
     def apply(j, rows, alts):
@@ -345,10 +350,11 @@ def nedf_mx_ambiguity(model, o_l, d_l, coord_err, sin_err, max_alternatives=32):
                 else:
                     alt = _other_neighbour(r[row, col], marg[row, col], round_e4m3) * X[row, 0]
                 cand.append((row, blk[col:col + 1], np.array([alt])))
-            # shared exponent: amax within its bound of a power of two
-            k = np.floor(np.log2(np.where(amax > 0, amax, 1.0)))
+            # shared exponent: it steps where amax crosses 448 2^e, i.e.
+            # 1.75 times a power of two; amax within its bound of such a point
+            k = np.floor(np.log2(np.where(amax > 0, amax, 1.0) / 1.75))
             emax = ev[np.arange(v.shape[0]), np.argmax(np.abs(v), axis=1)]
-            lo, hi = amax - np.exp2(k), np.exp2(k + 1) - amax
+            lo, hi = amax - 1.75 * np.exp2(k), 1.75 * np.exp2(k + 1) - amax
             for row in np.nonzero((amax > 0) & (np.minimum(lo, hi) <= emax))[0]:
                 ex2 = ex[row] + (-1.0 if lo[row] <= hi[row] else 1.0)
                 X2 = np.exp2(ex2)
@@ -368,11 +374,16 @@ def nedf_mx_ambiguity(model, o_l, d_l, coord_err, sin_err, max_alternatives=32):
         for a, i in enumerate(sel):
             alts[a, cand[i][1]] = cand[i][2]
         apply(j, rows[sel], alts)
-        # all of a ray's decisions of this layer together
+        # all of a ray's decisions of this layer together; the layers'
+        # effects add up (to first order) when several layers have one
         ur = np.unique(rows)
         pos = {r_: i for i, r_ in enumerate(ur)}
         alls = hq[ur].copy()
         for c in cand:
             alls[pos[c[0]], c[1]] = c[2]
-        apply(j, ur, alls)
-    return amb, amb_p, count
+        dmu, dp = _head_delta(run_from(j, alls), base[ur])
+        np.maximum.at(amb, ur, dmu)
+        np.maximum.at(amb_p, ur, dp)
+        np.add.at(sum_mu, ur, dmu)
+        np.add.at(sum_p, ur, dp)
+    return np.maximum(amb, sum_mu), np.maximum(amb_p, sum_p), count

@@ -996,8 +996,9 @@ void launch_nedf_net(const KArgs& k, hipStream_t s, int v) {
       default: hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 2, 1, 1, 4>), g1, b4, 0, s, k); return;
     }
   } else if constexpr (DT == 3) {
-    // MX: superchunks of four blocks, four waves (items of 128 pairs)
-    hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1, 4>), g1, b4, 0, s, k);
+    // MX: superchunks of four blocks; eight waves (items of 256 pairs) or four
+    if (v >= 1000) hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1, 8>), g1, b8, 0, s, k);
+    else hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 4, 1, 1, 4>), g1, b4, 0, s, k);
   } else {
     hipLaunchKernelGGL((k_nedf<DT, 256, 8, 8, 1, 1, 1, 4>), g1, b4, 0, s, k);
   }
@@ -1114,7 +1115,7 @@ void stage_nedf(const KArgs& k0, hipStream_t s, int dtype, uint32_t nedf_mask, i
   k.pairs = k.pairsS;
   k.item_mask = nedf_mask;
   // launch shape from the tuning table, fixed for all slabs of the stage
-  const int v = dtype == NEDF_F32 ? 11 : tune_value(NEDF_TUNE_NEDF, dtype);
+  const int v = dtype == NEDF_F32 ? 11 : dtype == NEDF_FP8_MX ? 1014 : tune_value(NEDF_TUNE_NEDF, dtype);
   k.item_pairs = classifier ? 32 * 4 : 32 * tune_waves(v) * nedf_rows(v);
   for (int slab = 0; slab < n_slabs; ++slab) {
     hipLaunchKernelGGL(k_slab_begin, dim3(1), dim3(64), 0, s, k);

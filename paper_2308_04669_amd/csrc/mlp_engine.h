@@ -97,18 +97,21 @@ template <> struct Tr<3> {
   }
 };
 
-// E8M0 block scale of a block whose largest magnitude is amax (>= 0):
-// exponent floor(log2 amax) - 8 (8: E4M3's largest exponent) as a biased
-// byte, and the power of two 2^-(that exponent) the values are multiplied by
-// before rounding to E4M3 (1 for an all-zero block, whose byte is 0).
+// E8M0 block scale of a block whose largest magnitude is amax (>= 0): the
+// smallest power of two 2^e with amax / 2^e <= 448 (E4M3's largest value):
+// floor(log2 amax) - 8, plus one when the significand of amax exceeds 1.75
+// (amax / 2^e would pass 448); as a biased byte, and 2^-e, the factor the
+// values are multiplied by before rounding to E4M3 (1 for an all-zero block,
+// whose byte is 0).
 __device__ __forceinline__ void mx_scale(float amax, int& byte, float& inv) {
-  const int eb = int((__float_as_uint(amax) >> 23) & 0xFFu);  // biased exponent; 0 for zero and subnormals
+  const uint32_t bits = __float_as_uint(amax);
+  const int eb = int((bits >> 23) & 0xFFu);  // biased exponent; 0 for zero and subnormals
   if (eb == 0) {
     byte = 0;
     inv = 1.0f;
     return;
   }
-  const int e = eb - 127 - 8;  // scale exponent
+  const int e = eb - 127 - 8 + ((bits & 0x7FFFFFu) > 0x600000u ? 1 : 0);  // scale exponent
   byte = e + 127 < 0 ? 0 : (e + 127 > 254 ? 254 : e + 127);
   inv = __builtin_amdgcn_ldexpf(1.0f, -(byte - 127));
 }

@@ -173,8 +173,8 @@ void pack_fragments(const nedf_blob_header& h, int part, const float* W, int row
   const bool bf = h.dtype == NEDF_BF16;
   if (h.dtype == NEDF_FP8_MX) {
     // MX: per output row and K-step two blocks of 32 weights (bytes 16 b ..
-    // 16 b + 15 of both lane halves), each with its own scale 2^e,
-    // e = floor(log2 amax) - 8; lane l keeps the byte of block l / 32 at
+    // 16 b + 15 of both lane halves), each with its own scale 2^e, the
+    // smallest with amax / 2^e <= 448; lane l keeps the byte of block l / 32 at
     // [ks_count x 2 KB] + 16 l + ks
     for (int fb = 0; fb < rows / 32; ++fb)
       for (int ks = 0; ks < ks_count; ++ks) {
@@ -198,7 +198,9 @@ void pack_fragments(const nedf_blob_header& h, int part, const float* W, int row
             if (amax > 0.0 && std::isfinite(amax)) {
               int ex = 0;
               std::frexp(amax, &ex);  // amax = m 2^ex, 0.5 <= m < 1: floor(log2 amax) = ex - 1
-              const int e = std::min(std::max(ex - 1 - 8, -127), 127);
+              int e0 = ex - 1 - 8;
+              if (amax / std::ldexp(1.0, e0) > 448.0) ++e0;
+              const int e = std::min(std::max(e0, -127), 127);
               byte = e + 127;
               X = std::ldexp(1.0, e);
             }

@@ -527,9 +527,13 @@ def test_infer_mx_fp8_network_and_refine_parity():
         f"max_err_refined={err[chk & moved].max() if (chk & moved).any() else 0:.3e} "
         f"max_err_unrefined={err[chk & ~moved].max() if (chk & ~moved).any() else 0:.3e} "
         f"median_amb={np.median(win_amb[id_o >= 0]):.3e} routing {api.ws_counters(ws)}")
+    over = np.nonzero(chk & (err > allow))[0]
+    for i in over[:8]:
+        log(f"  over: pixel {i} err {err[i]:.3e} allow {allow[i]:.3e} amb {win_amb[i]:.3e} refined {bool(moved[i])} "
+            f"winner path {res[id_o[i]].path[i]} p {res[id_o[i]].p[i]:.4f}")
     assert bad.sum() == 0
     assert chk.sum() >= 0.7 * hits
-    assert np.all(err[chk] <= allow[chk])
+    assert over.size == 0
 
 
 def test_shade_outlier_resampling_parity():

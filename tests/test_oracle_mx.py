@@ -9,20 +9,20 @@ from oracle import mlp_forward
 
 
 def test_exponent_hand_values():
-    # floor(log2 amax) - 8
-    assert list(mx_exponent(np.array([448.0, 256.0, 255.9, 1.0, 0.3, 0.0, 2.0 ** 200]))) == \
-        [0.0, 0.0, -1.0, -8.0, -10.0, -127.0, 127.0]
+    # floor(log2 amax) - 8, one more when amax / 2^e would exceed 448
+    assert list(mx_exponent(np.array([448.0, 256.0, 255.9, 1.0, 0.3, 0.0, 2.0 ** 200, 448.5, 500.0, 1.76]))) == \
+        [0.0, 0.0, 0.0, -8.0, -10.0, -127.0, 127.0, 1.0, 1.0, -7.0]
 
 
 def test_quantize_hand_block():
     blk = [np.arange(32)]
     x = np.zeros((3, 32))
     x[0, :4] = [448.0, 1.0, -3.0, 0.5]          # scale 1: all representable
-    x[1, :3] = [500.0, 300.0, 17.0]             # scale 1: 500 saturates, 300 -> 288 or 320, 17 -> 16 or 18
+    x[1, :3] = [500.0, 300.0, 17.0]             # scale 2: 250 -> 256, 150 -> 144, 8.5 -> 8 (tie to even)
     x[2, :2] = [0.3, 0.01]                      # scale 2^-10: 307.2 -> 320, 10.24 -> 10
     q, e = mx_quantize(x, blk)
     assert np.array_equal(q[0, :4], x[0, :4]) and e[0, 0] == 0.0
-    assert q[1, 0] == 448.0 and q[1, 1] == 288.0 and q[1, 2] == 16.0 and e[1, 0] == 0.0
+    assert q[1, 0] == 512.0 and q[1, 1] == 288.0 and q[1, 2] == 16.0 and e[1, 0] == 1.0
     assert e[2, 0] == -10.0
     assert np.isclose(q[2, 0], 320.0 / 1024) and np.isclose(q[2, 1], 10.0 / 1024)
 
@@ -36,13 +36,14 @@ def test_quantize_scale_covariance_and_independent_blocks():
     q2, e2 = mx_quantize(x2, hidden_blocks(64))
     assert np.array_equal(q2[:, :32], q[:, :32]) and np.array_equal(e2[:, 0], e[:, 0])
     assert np.array_equal(q2[:, 32:], q[:, 32:] * 2.0 ** 7) and np.array_equal(e2[:, 1], e[:, 1] + 7)
-    # per block, v / X lies below 512; within E4M3's normal range a value is
-    # off by at most half a step (2^-4 relative), and above 448 it saturates
+    # per block, v / X stays within 448 (nothing saturates) and above 224
+    # for the largest value; in E4M3's normal range a value is off by at
+    # most half a step (2^-4 relative)
     X = np.repeat(np.exp2(e), 32, axis=1)
     r = np.abs(x) / X
-    normal = (r >= 2.0 ** -6) & (r <= 448.0)
+    assert np.all(r <= 448.0) and np.all(r.reshape(5, 2, 32).max(axis=2) > 224.0)
+    normal = r >= 2.0 ** -6
     assert np.all(np.abs(q - x)[normal] <= np.abs(x)[normal] * 2.0 ** -4)
-    assert np.all(np.abs(q[r > 448.0]) == 448.0 * X[r > 448.0]) and np.all(r < 512.0)
 
 
 def test_block_partitions_cover_every_feature_once():
