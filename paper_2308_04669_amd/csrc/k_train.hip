@@ -135,7 +135,19 @@ struct GemmArgs {
   const float* resid32;
   const uint16_t* resid16;
   uint16_t* out16b;
+  // EPI 6 (last hidden layer of the regression form, N = 256 = width):
+  // h = relu(acc + bias) rounded to bfloat16 (stored to out16 if set); the
+  // head (mu_hat, z) = head_w h + head_b and the loss terms of Eq. 6 per
+  // row; out16b = G = (g_mu head_w[0] + g_z head_w[1]) * (h > 0); part
+  // [tile][HEAD_PART] = this tile's head weight and bias gradients and loss
+  // sums
+  const float* head_w;   // [2][256]
+  const float* head_b;   // [2]
+  const float* mu;       // [M] target mu (0 for misses)
+  const float* alpha;    // [M] hit label
+  float w_hit;
 };
+constexpr int HEAD_PART = 520;  // 512 weight grads, 2 bias grads, 3 loss terms (total, mse, bce)
 
 // 8 x 8 transpose of bfloat16: v[j] holds 8 consecutive rows at k = j; w[r]
 // gets the 8 values of row r in k order.
@@ -213,8 +225,105 @@ struct Stage<RC, ROWS, NT> {
   }
 };
 
+// Head and loss of the regression form from the bfloat16 tile h [128][LO]
+// of the last hidden layer in LDS (all 256 features of 128 rows), followed
+// in LDS by the head weights (float [2][256]).  Four threads per row form
+// the two head outputs (a fixed pairing of their partial sums); the row's
+// loss terms (Eq. 6: alpha (mu_hat - mu)^2 and the logistic loss of the
+// hit logit) and gradients g = dLoss/d(mu_hat, z) go to LDS; then the
+// gradient G of the tile, the tile's head weight gradients (rows summed in
+// order) and its bias and loss sums.
+template <int NT, int LO>
+__device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* lds, int m0, int tile, int t) {
+  static_assert(NT == 512, "four threads per row of a 128-row tile, two per head weight");
+  const float* sW = reinterpret_cast<const float*>(lds + GT_BM * LO);
+  float* sg = const_cast<float*>(sW) + 512;  // [2][128]
+  float* sred = sg + 256;                    // [2][128]
+  const float invB = 1.0f / float(g.M);
+  {
+    const int r = t >> 2, p = t & 3;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int k = 64 * p + 8 * m;
+      const uint4 q = *reinterpret_cast<const uint4*>(lds + r * LO + k);
+      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
+        a0 = fmaf(sW[k + 2 * e], h0, a0);
+        a1 = fmaf(sW[256 + k + 2 * e], h0, a1);
+        a0 = fmaf(sW[k + 2 * e + 1], h1, a0);
+        a1 = fmaf(sW[256 + k + 2 * e + 1], h1, a1);
+      }
+    }
+    // (p0 + p1) + (p2 + p3)
+    a0 += __shfl_xor(a0, 1);
+    a1 += __shfl_xor(a1, 1);
+    a0 += __shfl_xor(a0, 2);
+    a1 += __shfl_xor(a1, 2);
+    if (p == 0) {
+      a0 += g.head_b[0];
+      a1 += g.head_b[1];
+      const float al = g.alpha[m0 + r], e = a0 - g.mu[m0 + r];
+      sred[r] = al * e * e;
+      sred[128 + r] = fmaxf(a1, 0.f) + log1pf(expf(-fabsf(a1))) - al * a1;
+      sg[r] = 2.0f * al * e * invB;
+      sg[128 + r] = g.w_hit * (1.0f / (1.0f + expf(-a1)) - al) * invB;
+    }
+  }
+  __syncthreads();
+  // G = (g_mu W_0 + g_z W_1) * (h > 0), 16-byte row pieces
+#pragma unroll
+  for (int i = 0; i < GT_BM * 256 / 8 / NT; ++i) {
+    const int c = t + NT * i;
+    const int r = c >> 5, c8 = 8 * (c & 31);
+    const uint4 q = *reinterpret_cast<const uint4*>(lds + r * LO + c8);
+    const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+    const float g0 = sg[r], g1 = sg[128 + r];
+    uint32_t o4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = c8 + 2 * e;
+      const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
+      const float v0 = h0 > 0.f ? fmaf(g0, sW[k], g1 * sW[256 + k]) : 0.f;
+      const float v1 = h1 > 0.f ? fmaf(g0, sW[k + 1], g1 * sW[256 + k + 1]) : 0.f;
+      o4[e] = uint32_t(bf16_bits(v0)) | (uint32_t(bf16_bits(v1)) << 16);
+    }
+    *reinterpret_cast<uint4*>(g.out16b + size_t(m0 + r) * g.ldo + c8) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+  }
+  // head weight gradients of the tile: thread (j, k) sums g_j h_k over the rows in order
+  float* P = g.part + size_t(tile) * HEAD_PART;
+  {
+    const int j = t >> 8, k = t & 255;
+    float acc = 0.f;
+    for (int r = 0; r < GT_BM; ++r) acc = fmaf(sg[128 * j + r], bf16_val(lds[r * LO + k]), acc);
+    P[256 * j + k] = acc;
+  }
+  // bias gradients and loss sums of the tile (one wave: lane l adds rows l
+  // and l + 64, then a fixed butterfly)
+  if (t < 64) {
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float* src = q < 2 ? sg + 128 * q : sred + 128 * (q - 2);
+      v[q] = src[t] + src[t + 64];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off);
+    }
+    if (t == 0) {
+      P[512] = v[0];
+      P[513] = v[1];
+      P[514] = (v[2] + g.w_hit * v[3]) * invB;
+      P[515] = v[2] * invB;
+      P[516] = v[3] * invB;
+    }
+  }
+}
+
+// One output tile (bx, by) of split bz.
 template <int AL, int BL, int EPI, bool COLSUM, int BN>
-__global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const int by, const int bz) {
   constexpr int NT = BN * 2;            // threads: (128 / 64) x (BN / 64) waves
   constexpr int WN = BN / 64;           // waves along N
   constexpr int SA = GT_BM * GT_LD, SB = BN * GT_LD;
@@ -223,8 +332,8 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[2 * (SA + SB)];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * GT_BM, n0 = blockIdx.y * BN;
-  const int kb = blockIdx.z * g.k_per_split;
+  const int m0 = bx * GT_BM, n0 = by * BN;
+  const int kb = bz * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
   const int n_stages = (ke - kb) / GT_BK;
   // row-contiguous operands: A's blocks by threads 0..127, B's by 128..255
@@ -298,7 +407,8 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
 #undef NEDF_GEMM_STAGE
   // accumulator r of block (i, j): row 64 wm + 32 i + lane % 32, column
   // 64 wn + 32 j + 8 (r / 4) + 4 (lane / 32) + r % 4 of the tile
-  if constexpr (EPI >= 3) {
+  static_assert(EPI >= 0 && EPI <= 6, "unknown epilogue");
+  if constexpr (EPI >= 3 && EPI <= 5) {
     // straight from the accumulators: four consecutive columns per store
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -329,7 +439,8 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
                   make_uint2(uint32_t(bf16_bits(m0v > 0.f ? v[0] : 0.f)) | (uint32_t(bf16_bits(m1v > 0.f ? v[1] : 0.f)) << 16),
                              uint32_t(bf16_bits(m2v > 0.f ? v[2] : 0.f)) | (uint32_t(bf16_bits(m3v > 0.f ? v[3] : 0.f)) << 16));
             }
-          } else {
+          } else {  // EPI 5
+            static_assert(EPI == 5, "residual epilogue");
             const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
             const float r0 = fmaxf(v[0] + bb.x, 0.f), r1 = fmaxf(v[1] + bb.y, 0.f);
             const float r2 = fmaxf(v[2] + bb.z, 0.f), r3 = fmaxf(v[3] + bb.w, 0.f);
@@ -354,12 +465,13 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int col = n0 + wn * 64 + 32 * j + 8 * q + 4 * (lane >> 5);
-          *reinterpret_cast<float4*>(g.part + (size_t(blockIdx.z) * g.M + row) * g.N + col) =
+          *reinterpret_cast<float4*>(g.part + (size_t(bz) * g.M + row) * g.N + col) =
               make_float4(acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]);
         }
     }
   } else {
-    // bfloat16 tile in LDS ([128][BN + 8]), then 16-byte row pieces
+    // EPI 0, 1, 6: bfloat16 tile in LDS ([128][BN + 8]), then 16-byte row pieces
+    static_assert(EPI == 0 || EPI == 1 || EPI == 6, "tile epilogues");
     constexpr int LO = BN + 8;
     static_assert(GT_BM * LO <= 2 * (SA + SB), "output tile must fit the stage buffers");
 #pragma unroll
@@ -373,7 +485,7 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
           float v[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * q + e];
-          if constexpr (EPI == 0) {
+          if constexpr (EPI == 0 || EPI == 6) {
             const float4 bb = *reinterpret_cast<const float4*>(g.bias + n0 + c);
             v[0] = fmaxf(v[0] + bb.x, 0.f); v[1] = fmaxf(v[1] + bb.y, 0.f);
             v[2] = fmaxf(v[2] + bb.z, 0.f); v[3] = fmaxf(v[3] + bb.w, 0.f);
@@ -383,8 +495,15 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
                          uint32_t(bf16_bits(v[2])) | (uint32_t(bf16_bits(v[3])) << 16));
         }
     }
+    if constexpr (EPI == 6) {
+      float* sW = reinterpret_cast<float*>(lds + GT_BM * LO);
+      for (int i = t; i < 512; i += NT) sW[i] = g.head_w[i];
+    }
     __syncthreads();
     constexpr int CH = GT_BM * BN / 8;  // 16-byte pieces of the tile
+    static_assert(EPI != 6 || (GT_BM * LO * 2 + 1024 * 4 <= 2 * (SA + SB) * 2 && BN == 256),
+                  "head epilogue: the tile and 4 KB of head data fit the stage buffers");
+    if (EPI != 6 || g.out16) {
 #pragma unroll
     for (int i = 0; i < CH / NT; ++i) {
       const int c = t + NT * i;
@@ -404,6 +523,8 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
       }
       *reinterpret_cast<uint4*>(g.out16 + size_t(m0 + r) * g.ldo + n0 + c8) = v;
     }
+    }
+    if constexpr (EPI == 6) head_loss_epilogue<NT, LO>(g, lds, m0, bx, t);
   }
   if constexpr (COLSUM) {
     // column sums of A over this split's k, one set per m tile (written by
@@ -415,13 +536,62 @@ __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
       for (int r = 0; r < 8; ++r) s_cs[8 * (rc % 16) + r][rc / 16] = cs[r];
     }
     __syncthreads();
-    if (blockIdx.y == 0 && t < 128) {
+    if (by == 0 && t < 128) {
       float s_ = 0.f;
 #pragma unroll
       for (int q = 0; q < 8; ++q) s_ += s_cs[t][q];
-      g.colsum[size_t(blockIdx.z) * g.M + m0 + t] = s_;
+      g.colsum[size_t(bz) * g.M + m0 + t] = s_;
     }
   }
+}
+
+template <int AL, int BL, int EPI, bool COLSUM, int BN>
+__global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
+  gemm_tile<AL, BL, EPI, COLSUM, BN>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Weight gradients of several layers in one launch: dW_p = G_p^T X_p over S
+// batch splits, with the column sums of G_p (bias gradients).  Both operands
+// are stored [batch][features] (row-contiguous in the product's terms);
+// M = width for every problem.  blockIdx.z = problem * S + split; the
+// workgroups of a problem's n tiles beyond its own N leave at once.  Two
+// workgroups of four waves share a compute unit (registers and LDS fit), so
+// a launch of more than one workgroup per compute unit keeps the matrix
+// cores busy while the other workgroup stages.
+struct WgradProb {
+  const uint16_t* G;  // [B][M]
+  const uint16_t* X;  // [B][ldx], N = padded input width
+  float* part;        // [S][M][N]
+  float* colsum;      // [S][M]
+  int ldx, N;
+};
+struct WgradBatch {
+  WgradProb p[NEDF_TRAIN_MAX_LAYERS];
+  int n, S, M, B;
+};
+__global__ __launch_bounds__(256, 2) void k_wgrad(WgradBatch wb) {
+  // The tiles of one (problem, split) read the same rows of both operands.
+  // Workgroups are handed to the 8 XCDs (each with its own L2) round-robin
+  // by linear id, so logical workgroup l = (id % 8) * (total / 8) + id / 8
+  // (a bijection when total is a multiple of 8) puts consecutive logical
+  // ids, and with them a slice's tiles, on one XCD: the second read of each
+  // operand row is an L2 hit instead of an HBM read.
+  const int nx = gridDim.x, ny = gridDim.y;
+  const int total = nx * ny * int(gridDim.z);
+  const int id = int(blockIdx.x) + nx * (int(blockIdx.y) + ny * int(blockIdx.z));
+  const int lid = total % 8 == 0 ? (id % 8) * (total / 8) + id / 8 : id;
+  const int bx = lid % nx, by = (lid / nx) % ny, bz = lid / (nx * ny);
+  const int prob = bz / wb.S, split = bz % wb.S;
+  const WgradProb& p = wb.p[prob];
+  if (by * 128 >= p.N) return;  // the whole workgroup
+  GemmArgs g{};
+  g.A = p.G; g.lda = wb.M;
+  g.B = p.X; g.ldb = p.ldx;
+  g.M = wb.M; g.N = p.N; g.K = wb.B;
+  g.k_per_split = wb.B / wb.S;
+  g.part = p.part;
+  g.colsum = p.colsum;
+  gemm_tile<RC, RC, 2, true, 128>(g, bx, by, split);
 }
 
 template <int AL, int BL, int EPI, bool COLSUM = false, int BN = 256>
@@ -440,7 +610,7 @@ struct ReduceLayer {
   int M, N, K;
 };
 struct ReduceArgs {
-  ReduceLayer L[NEDF_MAX_LAYERS];
+  ReduceLayer L[NEDF_TRAIN_MAX_LAYERS];
   int n_layers, S;
 };
 __global__ void k_reduce_grads(ReduceArgs r) {
@@ -463,93 +633,6 @@ __global__ void k_reduce_grads(ReduceArgs r) {
 }
 
 // ---- head and loss ------------------------------------------------------------
-// One block of 256 threads per HEAD_ROWS samples; width must be 256.  Phase 1
-// (one thread per sample): the (mu_hat, z) head and the loss terms; phase 2
-// (thread k owns feature k): the head weight gradients and
-// G = (g_mu W_h0 + g_z W_h1) * (H > 0).  Every block writes its partial sums
-// (head weight and bias gradients, loss terms) to its own row of `part`
-// [blocks][HEAD_PART]; k_reduce_head adds the rows in a fixed order.
-constexpr int HEAD_PART = 520;  // 512 weight grads, 2 bias grads, 3 loss terms (total, mse, bce)
-constexpr int HEAD_ROWS = 64;
-__global__ __launch_bounds__(256) void k_head_loss(const uint16_t* H, const float* Wh, const float* bh,
-                                                   const float* mu, const float* alpha, int B, float w_hit,
-                                                   uint16_t* G, float* part) {
-  __shared__ float sW[2][256];
-  __shared__ float sg[2][HEAD_ROWS];
-  __shared__ float red[2][HEAD_ROWS];
-  const int t = threadIdx.x;
-  const int s0 = blockIdx.x * HEAD_ROWS;
-  sW[0][t] = Wh[t];
-  sW[1][t] = Wh[256 + t];
-  __syncthreads();
-  if (t < HEAD_ROWS) {
-    const int s = s0 + t;
-    float lm = 0.f, lb = 0.f, g0 = 0.f, g1 = 0.f;
-    if (s < B) {
-      const uint4* row = reinterpret_cast<const uint4*>(H + size_t(s) * 256);
-      float a0 = bh[0], a1 = bh[1];
-      for (int k8 = 0; k8 < 32; ++k8) {
-        const uint4 q = row[k8];
-        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
-          const int k = 8 * k8 + 2 * e;
-          a0 = fmaf(sW[0][k], h0, a0);
-          a1 = fmaf(sW[1][k], h0, a1);
-          a0 = fmaf(sW[0][k + 1], h1, a0);
-          a1 = fmaf(sW[1][k + 1], h1, a1);
-        }
-      }
-      const float al = alpha[s], m = mu[s];
-      const float e = a0 - m;
-      lm = al * e * e;
-      lb = fmaxf(a1, 0.f) + log1pf(expf(-fabsf(a1))) - al * a1;
-      const float invB = 1.0f / float(B);
-      g0 = 2.0f * al * e * invB;
-      g1 = w_hit * (1.0f / (1.0f + expf(-a1)) - al) * invB;
-    }
-    sg[0][t] = g0;
-    sg[1][t] = g1;
-    red[0][t] = lm;
-    red[1][t] = lb;
-  }
-  __syncthreads();
-  for (int off = HEAD_ROWS / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      red[0][t] += red[0][t + off];
-      red[1][t] += red[1][t + off];
-    }
-    __syncthreads();
-  }
-  float* P = part + size_t(blockIdx.x) * HEAD_PART;
-  if (t == 0) {
-    const float invB = 1.0f / float(B);
-    P[514] = (red[0][0] + w_hit * red[1][0]) * invB;
-    P[515] = red[0][0] * invB;
-    P[516] = red[1][0] * invB;
-  }
-  // phase 2: thread t owns feature k = t
-  const int k = t;
-  float gw0 = 0.f, gw1 = 0.f;
-  const int ns = min(HEAD_ROWS, B - s0);
-  for (int i = 0; i < ns; ++i) {
-    const size_t idx = size_t(s0 + i) * 256 + k;
-    const float h = bf16_val(H[idx]);
-    const float g0 = sg[0][i], g1 = sg[1][i];
-    gw0 = fmaf(g0, h, gw0);
-    gw1 = fmaf(g1, h, gw1);
-    G[idx] = bf16_bits(h > 0.0f ? fmaf(g0, sW[0][k], g1 * sW[1][k]) : 0.0f);
-  }
-  P[k] = gw0;
-  P[256 + k] = gw1;
-  if (t < 2) {
-    float sum = 0.f;
-    for (int i = 0; i < ns; ++i) sum += sg[t][i];
-    P[512 + t] = sum;
-  }
-}
-
 // Head gradients and loss from the per-block partials: one wave per output,
 // lane l adding blocks l, l + 64, ... in order, then a fixed butterfly.
 __global__ void k_reduce_head(const float* part, int n_blocks, float* gWh, float* gbh, float* loss) {
@@ -771,20 +854,38 @@ int wgrad_splits(int B) {
   return S;
 }
 
+// Split count of a batched weight-gradient launch over `tiles` 128 x 128
+// output tiles: a power of two up to 64 giving at most 640 workgroups (two
+// per compute unit and a quarter more, so that the last wave of workgroups
+// is short), with the batch a multiple of 128 per split (an even number of
+// 64-deep stages; the batch is a multiple of 256).
+int wgrad_batch_splits(int B, int tiles) {
+  int S = 1;
+  while (S < 64 && tiles * S * 2 <= 640 && B % (S * 2 * 2 * GT_BK) == 0) S *= 2;
+  return S;
+}
+
+// 128 x 128 output tiles of the regression form's hidden-layer weight gradients.
+int regression_wgrad_tiles(const nedf_mlp_shape& sh, const nedf_train_layout& tl) {
+  int t = 0;
+  for (int l = 0; l < sh.n_hidden; ++l) t += (sh.width / 128) * (tl.L[l].Kpad / 128);
+  return t;
+}
+
 size_t train_ws_bytes_cls(const nedf_mlp_shape& sh, int B);
 
 size_t train_ws_bytes(const nedf_mlp_shape& sh, int B) {
   if (sh.in_kind == NEDF_IN_POINTS16) return train_ws_bytes_cls(sh, B);
   const nedf_train_layout tl = nedf_train_layout_of(sh);
-  const int S = wgrad_splits(B);
+  const int S = wgrad_batch_splits(B, regression_wgrad_tiles(sh, tl));
   size_t off = 0;
   off = nedf_tl_align(off + size_t(B) * tl.L[0].Kpad * 2);           // H_in
   off = nedf_tl_align(off + size_t(B) * sh.width * 2 * sh.n_hidden);  // H_0..H_{n-1}
-  off = nedf_tl_align(off + size_t(B) * sh.width * 2 * 2);            // G ping-pong
+  off = nedf_tl_align(off + size_t(B) * sh.width * 2 * sh.n_hidden);  // G_0..G_{n-1}
   off = nedf_tl_align(off + size_t(B) * 4 * 2);                       // mu, alpha
   for (int l = 0; l < sh.n_hidden; ++l)                                // weight-gradient partials
     off = nedf_tl_align(off + size_t(S) * sh.width * (tl.L[l].Kpad + 1) * 4);
-  off = nedf_tl_align(off + size_t((B + HEAD_ROWS - 1) / HEAD_ROWS) * HEAD_PART * 4);  // head partials
+  off = nedf_tl_align(off + size_t(B / GT_BM) * HEAD_PART * 4);  // head partials, per 128-row tile
   return off;
 }
 
@@ -818,15 +919,14 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   const nedf_train_layout tl = nedf_train_layout_of(sh);
   const int W = sh.width, NH = sh.n_hidden;
   const int K0p = tl.L[0].Kpad;
-  const int S = wgrad_splits(B);
+  const int S = wgrad_batch_splits(B, regression_wgrad_tiles(sh, tl));
   size_t off = 0;
   uint16_t* Hin = reinterpret_cast<uint16_t*>(ws + off);
   off = nedf_tl_align(off + size_t(B) * K0p * 2);
   uint16_t* Hs = reinterpret_cast<uint16_t*>(ws + off);
   off = nedf_tl_align(off + size_t(B) * W * 2 * NH);
-  uint16_t* G0 = reinterpret_cast<uint16_t*>(ws + off);
-  uint16_t* G1 = G0 + size_t(B) * W;
-  off = nedf_tl_align(off + size_t(B) * W * 2 * 2);
+  uint16_t* Gs = reinterpret_cast<uint16_t*>(ws + off);
+  off = nedf_tl_align(off + size_t(B) * W * 2 * NH);
   float* mu = reinterpret_cast<float*>(ws + off);
   float* alpha = mu + B;
   off = nedf_tl_align(off + size_t(B) * 4 * 2);
@@ -836,8 +936,9 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     off = nedf_tl_align(off + size_t(S) * W * (tl.L[l].Kpad + 1) * 4);
   }
   float* hpart = reinterpret_cast<float*>(ws + off);
-  const int hblocks = (B + HEAD_ROWS - 1) / HEAD_ROWS;
+  const int hblocks = B / GT_BM;  // tiles of the last forward layer
   auto Hl = [&](int l) { return Hs + size_t(l) * B * W; };
+  auto Gl = [&](int l) { return Gs + size_t(l) * B * W; };  // gradient at layer l's pre-activation
   auto F = [&](size_t o) { return reinterpret_cast<float*>(st + o); };
   auto U = [&](size_t o) { return reinterpret_cast<uint16_t*>(st + o); };
 
@@ -846,6 +947,9 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
                      sh.in_kind, sh.enc_L,
                      K0p, bound, Hin, mu, alpha);
   // forward: H_l = relu(H_{l-1} W_l^T + b_l)
+  // the last hidden layer's epilogue forms the head, the loss terms and
+  // G_{NH-1} (its activation is not stored)
+  const nedf_train_layer& hd = tl.L[NH];
   for (int l = 0; l < NH; ++l) {
     GemmArgs g{};
     g.A = l == 0 ? Hin : Hl(l - 1);
@@ -855,51 +959,50 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     g.M = B; g.N = W; g.K = tl.L[l].Kpad;
     g.k_per_split = g.K;
     g.bias = F(tl.L[l].b);
-    g.out16 = Hl(l);
     g.ldo = W;
-    gemm<KC, KC, 0>(g, 1, s);
-  }
-  // head, loss, G_{NH-1}
-  const nedf_train_layer& hd = tl.L[NH];
-  hipLaunchKernelGGL(k_head_loss, dim3(hblocks), dim3(256), 0, s, Hl(NH - 1), F(hd.W), F(hd.b), mu, alpha, B,
-                     w_hit, G0, hpart);
-  hipLaunchKernelGGL(k_reduce_head, dim3((517 + 3) / 4), dim3(256), 0, s, hpart, hblocks, F(hd.gW), F(hd.gb), loss);
-  // backward through the hidden layers
-  ReduceArgs ra{};
-  ra.n_layers = NH;
-  ra.S = S;
-  uint16_t* Gc = G0;
-  uint16_t* Gn = G1;
-  for (int l = NH - 1; l >= 0; --l) {
-    const nedf_train_layer& L = tl.L[l];
-    // weight gradient partials dW_l = G_l^T H_{l-1} over S batch splits, and
-    // the column sums of G_l (bias gradient) per split
-    GemmArgs w{};
-    w.A = Gc; w.lda = W;                            // stored [B][W] = [K][M]: row-contiguous
-    w.B = l == 0 ? Hin : Hl(l - 1);
-    w.ldb = l == 0 ? K0p : W;                       // stored [B][Kpad] = [K][N]: row-contiguous
-    w.M = W; w.N = L.Kpad; w.K = B;
-    w.k_per_split = B / S;
-    w.part = wpart[l];
-    w.colsum = wpart[l] + size_t(S) * W * L.Kpad;
-    gemm<RC, RC, 2, true, 128>(w, S, s);
-    ra.L[l] = ReduceLayer{w.part, w.colsum, F(L.gW), F(L.gb), W, L.Kpad, L.K};
-    if (l > 0) {
-      // data gradient G_{l-1} = (G_l W_l) * (H_{l-1} > 0)
-      GemmArgs d{};
-      d.A = Gc; d.lda = W;                          // [B][W]: k-contiguous
-      d.B = U(L.W16T); d.ldb = W;                   // W_l^T [Kpad][W] = [N][K]: k-contiguous
-      d.M = B; d.N = W; d.K = W;
-      d.k_per_split = W;
-      d.mask = Hl(l - 1); d.ldm = W;
-      d.out16 = Gn; d.ldo = W;
-      gemm<KC, KC, 1>(d, 1, s);
-      uint16_t* tmp = Gc; Gc = Gn; Gn = tmp;
+    if (l + 1 < NH) {
+      g.out16 = Hl(l);
+      gemm<KC, KC, 0>(g, 1, s);
+    } else {
+      g.out16b = Gl(NH - 1);
+      g.head_w = F(hd.W); g.head_b = F(hd.b);
+      g.mu = mu; g.alpha = alpha; g.w_hit = w_hit;
+      g.part = hpart;
+      gemm<KC, KC, 6>(g, 1, s);
     }
   }
+  hipLaunchKernelGGL(k_reduce_head, dim3((517 + 3) / 4), dim3(256), 0, s, hpart, hblocks, F(hd.gW), F(hd.gb), loss);
+  // backward through the hidden layers: data gradients
+  // G_{l-1} = (G_l W_l) * (H_{l-1} > 0), every G_l kept
+  for (int l = NH - 1; l > 0; --l) {
+    const nedf_train_layer& L = tl.L[l];
+    GemmArgs d{};
+    d.A = Gl(l); d.lda = W;                         // [B][W]: k-contiguous
+    d.B = U(L.W16T); d.ldb = W;                     // W_l^T [Kpad][W] = [N][K]: k-contiguous
+    d.M = B; d.N = W; d.K = W;
+    d.k_per_split = W;
+    d.mask = Hl(l - 1); d.ldm = W;
+    d.out16 = Gl(l - 1); d.ldo = W;
+    gemm<KC, KC, 1>(d, 1, s);
+  }
+  // weight-gradient partials dW_l = G_l^T H_{l-1} of every layer in one
+  // launch, then their sums over the splits in order
   {
-    int maxmn = 0;
-    for (int l = 0; l < NH; ++l) maxmn = std::max(maxmn, W * tl.L[l].Kpad + W);
+    WgradBatch wb{};
+    wb.n = NH; wb.S = S; wb.M = W; wb.B = B;
+    ReduceArgs ra{};
+    ra.n_layers = NH;
+    ra.S = S;
+    int maxmn = 0, ny = 1;
+    for (int l = 0; l < NH; ++l) {
+      const nedf_train_layer& L = tl.L[l];
+      wb.p[l] = WgradProb{Gl(l), l == 0 ? Hin : Hl(l - 1), wpart[l], wpart[l] + size_t(S) * W * L.Kpad,
+                          l == 0 ? K0p : W, L.Kpad};
+      ra.L[l] = ReduceLayer{wb.p[l].part, wb.p[l].colsum, F(L.gW), F(L.gb), W, L.Kpad, L.K};
+      maxmn = std::max(maxmn, W * L.Kpad + W);
+      ny = std::max(ny, L.Kpad / 128);
+    }
+    hipLaunchKernelGGL(k_wgrad, dim3(W / GT_BM, ny, NH * S), dim3(256), 0, s, wb);
     hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(maxmn), NH), dim3(256), 0, s, ra);
   }
   // Adam on every parameter array, one launch
@@ -923,14 +1026,23 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
 
 // ---- classifier-form training step ----------------------------------------------
 namespace {
+// 128 x 128 output tiles of every layer's weight gradient (the tail's N
+// padded to the width).
+int cls_wgrad_tiles(const nedf_train_layout& tl, int W) {
+  int t = 0;
+  for (int i = 0; i < tl.n_layers; ++i) t += (W / 128) * (tl.L[i].Kpad / 128);
+  return t;
+}
 struct ClsTrainWs {
-  uint16_t *X, *H, *A, *R, *G16a, *G16b;
+  uint16_t *X, *H, *A, *R, *G;
   float *LG, *Gh, *mu, *alpha, *wpart, *lpart;
+  size_t part_off[NEDF_TRAIN_MAX_LAYERS];  // each layer's split partials, floats from wpart
   size_t end;
 };
 ClsTrainWs cls_train_ws(const nedf_mlp_shape& sh, int B, uint8_t* base) {
   const nedf_train_layout tl = nedf_train_layout_of(sh);
-  const int W = sh.width, NB = sh.n_hidden, K0p = tl.L[0].Kpad, S = wgrad_splits(B);
+  const int W = sh.width, NB = sh.n_hidden, K0p = tl.L[0].Kpad;
+  const int S = wgrad_batch_splits(B, cls_wgrad_tiles(tl, W));
   ClsTrainWs w{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -942,13 +1054,19 @@ ClsTrainWs cls_train_ws(const nedf_mlp_shape& sh, int B, uint8_t* base) {
   w.H = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * (NB + 1)));
   w.A = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * NB));
   w.R = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * NB));
-  w.G16a = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2));
-  w.G16b = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2));
+  // the bfloat16 gradient at every layer's pre-activation
+  w.G = reinterpret_cast<uint16_t*>(take(size_t(B) * W * 2 * tl.n_layers));
   w.LG = reinterpret_cast<float*>(take(size_t(B) * W * 4));
   w.Gh = reinterpret_cast<float*>(take(size_t(B) * W * 4));
   w.mu = reinterpret_cast<float*>(take(size_t(B) * 4));
   w.alpha = reinterpret_cast<float*>(take(size_t(B) * 4));
-  w.wpart = reinterpret_cast<float*>(take(size_t(S) * W * (K0p + 1) * 4));
+  size_t nf = 0;
+  for (int i = 0; i < tl.n_layers; ++i) {
+    w.part_off[i] = nf;
+    nf += size_t(S) * W * (tl.L[i].Kpad + 1);
+    nf = (nf + 63) & ~size_t(63);
+  }
+  w.wpart = reinterpret_cast<float*>(take(nf * 4));
   w.lpart = reinterpret_cast<float*>(take(size_t(B / 4 + 1) * 3 * 4));
   w.end = off;
   return w;
@@ -969,13 +1087,14 @@ hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const fl
   const nedf_train_layout tl = nedf_train_layout_of(sh);
   const int W = sh.width, NB = sh.n_hidden;
   const int K0p = tl.L[0].Kpad;
-  const int S = wgrad_splits(B);
+  const int S = wgrad_batch_splits(B, cls_wgrad_tiles(tl, W));
   const ClsTrainWs w = cls_train_ws(sh, B, ws);
   auto F = [&](size_t o) { return reinterpret_cast<float*>(st + o); };
   auto U = [&](size_t o) { return reinterpret_cast<uint16_t*>(st + o); };
   auto Hk = [&](int k) { return w.H + size_t(k) * B * W; };
   auto Ak = [&](int k) { return w.A + size_t(k) * B * W; };
   auto Rk = [&](int k) { return w.R + size_t(k) * B * W; };
+  auto Gi = [&](int i) { return w.G + size_t(i) * B * W; };  // gradient at layer i's pre-activation
   const int tail = tl.n_layers - 1;
   prof_mark("train.step", s, true);
   hipLaunchKernelGGL(k_train_encode_points, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l, depth,
@@ -1018,63 +1137,63 @@ hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const fl
     gemm<KC, KC, 3>(g, 1, s);
   }
   const int lblocks = (B + 3) / 4;
-  hipLaunchKernelGGL(k_cls_loss, dim3(lblocks), dim3(256), 0, s, w.LG, W, w.mu, w.alpha, B, w_hit, w.G16a, w.lpart);
+  hipLaunchKernelGGL(k_cls_loss, dim3(lblocks), dim3(256), 0, s, w.LG, W, w.mu, w.alpha, B, w_hit, Gi(tail), w.lpart);
   hipLaunchKernelGGL(k_cls_loss_reduce, dim3(1), dim3(256), 0, s, w.lpart, lblocks, B, loss);
-  // weight gradient of layer i from its output gradient G and its input X
-  auto wgrad = [&](int i, const uint16_t* G, const uint16_t* X, int ldx) {
-    const nedf_train_layer& L = tl.L[i];
-    GemmArgs g{};
-    g.A = G; g.lda = W;
-    g.B = X; g.ldb = ldx;
-    g.M = W; g.N = L.Kpad; g.K = B;
-    g.k_per_split = B / S;
-    g.part = w.wpart;
-    g.colsum = w.wpart + size_t(S) * W * L.Kpad;
-    gemm<RC, RC, 2, true, 128>(g, S, s);
-    ReduceArgs ra{};
-    ra.n_layers = 1;
-    ra.S = S;
-    ra.L[0] = ReduceLayer{g.part, g.colsum, F(L.gW), F(L.gb), W, L.Kpad, L.K};
-    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(size_t(W) * L.Kpad + W), 1), dim3(256), 0, s, ra);
-  };
   // data gradient through layer i: out = G W_i, plus epilogue options
-  auto dgrad = [&](int i, const uint16_t* G) {
+  auto dgrad = [&](int i) {
     GemmArgs g{};
-    g.A = G; g.lda = W;
+    g.A = Gi(i); g.lda = W;
     g.B = U(tl.L[i].W16T); g.ldb = W;
     g.M = B; g.N = W; g.K = W; g.k_per_split = W;
     g.ldo = W; g.ldm = W;
     return g;
   };
   // tail
-  wgrad(tail, w.G16a, Hk(NB), W);
   {
-    GemmArgs g = dgrad(tail, w.G16a);
+    GemmArgs g = dgrad(tail);
     g.out32 = w.Gh;
     g.mask = Rk(NB - 1);
-    g.out16 = w.G16b;  // gradient at the last block's second pre-activation
+    g.out16 = Gi(2 * NB);  // gradient at the last block's second pre-activation
     gemm<KC, KC, 4>(g, 1, s);
   }
   for (int k = NB - 1; k >= 0; --k) {
     const int i1 = 1 + 2 * k, i2 = 2 + 2 * k;
-    wgrad(i2, w.G16b, Ak(k), W);
     {
-      GemmArgs g = dgrad(i2, w.G16b);
+      GemmArgs g = dgrad(i2);
       g.mask = Ak(k);
-      g.out16 = w.G16a;  // gradient at the first layer's pre-activation
+      g.out16 = Gi(i1);  // gradient at the first layer's pre-activation
       gemm<KC, KC, 1>(g, 1, s);
     }
-    wgrad(i1, w.G16a, Hk(k), W);
     {
-      GemmArgs g = dgrad(i1, w.G16a);
+      GemmArgs g = dgrad(i1);
       g.resid32 = w.Gh;
       g.out32 = w.Gh;                         // skip path plus the branch
       g.mask = k > 0 ? Rk(k - 1) : Hk(0);     // next: block k-1's second layer, or the head
-      g.out16 = w.G16b;
+      g.out16 = Gi(i1 - 1);
       gemm<KC, KC, 4>(g, 1, s);
     }
   }
-  wgrad(0, w.G16b, w.X, K0p);
+  // weight gradients of every layer from its pre-activation gradient and its
+  // input, in one launch, then their sums over the splits in order
+  {
+    WgradBatch wb{};
+    wb.n = tl.n_layers; wb.S = S; wb.M = W; wb.B = B;
+    ReduceArgs ra{};
+    ra.n_layers = tl.n_layers;
+    ra.S = S;
+    int maxmn = 0, ny = 1;
+    for (int i = 0; i < tl.n_layers; ++i) {
+      const nedf_train_layer& L = tl.L[i];
+      const uint16_t* X = i == 0 ? w.X : i == tail ? Hk(NB) : (i % 2 == 1 ? Hk((i - 1) / 2) : Ak((i - 2) / 2));
+      float* part = w.wpart + w.part_off[i];
+      wb.p[i] = WgradProb{Gi(i), X, part, part + size_t(S) * W * L.Kpad, i == 0 ? K0p : W, L.Kpad};
+      ra.L[i] = ReduceLayer{part, part + size_t(S) * W * L.Kpad, F(L.gW), F(L.gb), W, L.Kpad, L.K};
+      maxmn = std::max(maxmn, W * L.Kpad + W);
+      ny = std::max(ny, L.Kpad / 128);
+    }
+    hipLaunchKernelGGL(k_wgrad, dim3(W / GT_BM, ny, tl.n_layers * S), dim3(256), 0, s, wb);
+    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(maxmn), tl.n_layers), dim3(256), 0, s, ra);
+  }
   // Adam, in launches of at most one argument block of segments
   AdamArgs aa{};
   aa.step = reinterpret_cast<const int64_t*>(st);

@@ -43,7 +43,9 @@ static inline nedf_train_layout nedf_train_layout_of(const nedf_mlp_shape& s) {
     l.N = cls ? s.width : (last ? s.n_out : s.width);
     l.Nsrc = last ? s.n_out : l.N;
     l.K = i == 0 ? n_in : s.width;
-    l.Kpad = (l.K + 63) / 64 * 64;
+    // the GEMMs take K in pairs of 64-deep stages and weight-gradient
+    // tiles of 128 input columns
+    l.Kpad = (l.K + 127) / 128 * 128;
     const size_t nw = size_t(l.N) * l.K * 4, nb = size_t(l.N) * 4;
     l.W = off; off = nedf_tl_align(off + nw);
     l.mW = off; off = nedf_tl_align(off + nw);

@@ -30,19 +30,24 @@ def _tensor(x, dtype=None):
     return t.cuda()
 
 
-def test_train_gradients_and_adam_match_oracle():
+@pytest.mark.parametrize("enc_L,depth,B", [(8, 8, 2048), (4, 3, 1280)])
+def test_train_gradients_and_adam_match_oracle(enc_L, depth, B):
+    """gamma_8, 8 hidden layers (the benchmark's network), and a short input
+    (gamma_4: 54 features, padded to one 128-wide tile) with 3 hidden layers
+    and a batch that is not a power of two: other split counts of the
+    batched weight-gradient launch."""
     need_gpu()
     import torch
     from paper_2308_04669_amd import api
-    model = syn.nedf_model(4, 1)
+    model = syn.nedf_model(4, 1, enc_L=enc_L, depth=depth)
+    log(f"case: training step, enc_L {enc_L}, {depth} hidden layers, B = {B}")
     g = syn.rng(4, 2)
     for bb in model.trunk.b:
         bb[:] = (g.standard_normal(bb.shape) * 0.05).astype(np.float32)
-    B = 2048
     o, d = syn.training_rays(4, 3, B)
     D, hit = _sphere_labels(o.astype(np.float64), d.astype(np.float64))
     D32 = D.astype(np.float32)
-    tr = api.Trainer(model.trunk.W, model.trunk.b, enc_L=8)
+    tr = api.Trainer(model.trunk.W, model.trunk.b, enc_L=enc_L)
     loss = tr.step(_tensor(o), _tensor(d), _tensor(D32), _tensor(hit.astype(np.uint8)), lr=0.0)
     torch.cuda.synchronize()
     loss = loss.cpu().numpy().astype(np.float64)
