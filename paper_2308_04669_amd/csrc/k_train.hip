@@ -24,9 +24,11 @@ __device__ __forceinline__ float bf16_val(uint16_t u) { return __uint_as_float(u
 // mu* = (t_perp - D) / l and alpha = hit.  One thread per sample and group
 // of 8 features (one 16-byte store; a sample's row is written by
 // consecutive threads).
+// N: input components (6 Pluecker, 3 xyz), a constant so that the feature
+// index arithmetic divides by constants.
+template <int N>
 __global__ void k_train_encode(const float* o_l, const float* d_l, const float* depth, const uint8_t* hit,
-                               int B, int in_kind, int L, int Kpad, float bound, uint16_t* H, float* mu,
-                               float* alpha) {
+                               int B, int L, int Kpad, float bound, uint16_t* H, float* mu, float* alpha) {
   const int groups = Kpad / 8;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = tid / groups, grp = tid % groups;
@@ -34,15 +36,14 @@ __global__ void k_train_encode(const float* o_l, const float* d_l, const float* 
   const float o[3] = {o_l[3 * s], o_l[3 * s + 1], o_l[3 * s + 2]};
   const float d[3] = {d_l[3 * s], d_l[3 * s + 1], d_l[3 * s + 2]};
   float p[6], plo[6] = {0, 0, 0, 0, 0, 0}, tperp = 0.0f;
-  int n;
-  if (in_kind == NEDF_IN_PLUECKER) {
-    n = 6;
+  constexpr int n = N;
+  if constexpr (N == 6) {
     line_of_local(o, d, p, plo, tperp);
   } else {
-    n = 3;
     float pl[6], pllo[6];
     line_of_local(o, d, pl, pllo, tperp);
     p[0] = o[0]; p[1] = o[1]; p[2] = o[2];
+    p[3] = p[4] = p[5] = 0.0f;
   }
   uint32_t packed[4];
 #pragma unroll
@@ -146,6 +147,11 @@ struct GemmArgs {
   const float* mu;       // [M] target mu (0 for misses)
   const float* alpha;    // [M] hit label
   float w_hit;
+  // ReLU masks as bits, [M][ldo / 8] bytes, bit e of byte c of a row for
+  // column 8 c + e: EPI 0 writes them for its output (if set), EPI 1 reads
+  // them in place of the bfloat16 mask (if set)
+  uint8_t* bits_out;
+  const uint8_t* bits_in;
 };
 constexpr int HEAD_PART = 520;  // 512 weight grads, 2 bias grads, 3 loss terms (total, mse, bce)
 
@@ -292,13 +298,43 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
     }
     *reinterpret_cast<uint4*>(g.out16b + size_t(m0 + r) * g.ldo + c8) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
   }
-  // head weight gradients of the tile: thread (j, k) sums g_j h_k over the rows in order
+  // head weight gradients of the tile: thread (row group rg, features
+  // 8 kq .. 8 kq + 7) sums g_j h_k over its 8 rows in order; the 16 row
+  // groups' partials (LDS after the head data) are then added in order
   float* P = g.part + size_t(tile) * HEAD_PART;
   {
-    const int j = t >> 8, k = t & 255;
+    float* red = sred + 256;  // [16][512]
+    static_assert(GT_BM * LO * 2 + (1024 + 16 * 512) * 4 <= 2 * (GT_BM + 256) * GT_LD * 2,
+                  "head partials fit the stage buffers");
+    const int kq = t & 31, rg = t >> 5;
+    float a0[8], a1[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a0[e] = a1[e] = 0.f;
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) {
+      const int r = 8 * rg + rr;
+      const uint4 q = *reinterpret_cast<const uint4*>(lds + r * LO + 8 * kq);
+      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+      const float g0 = sg[r], g1 = sg[128 + r];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
+        a0[2 * e] = fmaf(g0, h0, a0[2 * e]);
+        a1[2 * e] = fmaf(g1, h0, a1[2 * e]);
+        a0[2 * e + 1] = fmaf(g0, h1, a0[2 * e + 1]);
+        a1[2 * e + 1] = fmaf(g1, h1, a1[2 * e + 1]);
+      }
+    }
+    float* dst = red + 512 * rg + 8 * kq;
+    *reinterpret_cast<float4*>(dst) = make_float4(a0[0], a0[1], a0[2], a0[3]);
+    *reinterpret_cast<float4*>(dst + 4) = make_float4(a0[4], a0[5], a0[6], a0[7]);
+    *reinterpret_cast<float4*>(dst + 256) = make_float4(a1[0], a1[1], a1[2], a1[3]);
+    *reinterpret_cast<float4*>(dst + 260) = make_float4(a1[4], a1[5], a1[6], a1[7]);
+    __syncthreads();
     float acc = 0.f;
-    for (int r = 0; r < GT_BM; ++r) acc = fmaf(sg[128 * j + r], bf16_val(lds[r * LO + k]), acc);
-    P[256 * j + k] = acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += red[512 * q + t];
+    P[t] = acc;  // t = 256 j + k
   }
   // bias gradients and loss sums of the tile (one wave: lane l adds rows l
   // and l + 64, then a fixed butterfly)
@@ -510,16 +546,34 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
       const int r = c / (BN / 8), c8 = 8 * (c % (BN / 8));
       uint4 v = *reinterpret_cast<const uint4*>(lds + r * LO + c8);
       if constexpr (EPI == 1) {
-        const uint4 mk = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
-        const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
         uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+        if (g.bits_in) {
+          const uint32_t mb = g.bits_in[size_t(m0 + r) * (g.ldm / 8) + (n0 + c8) / 8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t lo = __uint_as_float(mw[e] << 16) > 0.f ? 0x0000FFFFu : 0u;
-          const uint32_t hi = __uint_as_float(mw[e] & 0xFFFF0000u) > 0.f ? 0xFFFF0000u : 0u;
-          vw[e] &= lo | hi;
+          for (int e = 0; e < 4; ++e)
+            vw[e] &= ((mb >> (2 * e)) & 1u ? 0x0000FFFFu : 0u) | ((mb >> (2 * e + 1)) & 1u ? 0xFFFF0000u : 0u);
+        } else {
+          const uint4 mk = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
+          const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t lo = __uint_as_float(mw[e] << 16) > 0.f ? 0x0000FFFFu : 0u;
+            const uint32_t hi = __uint_as_float(mw[e] & 0xFFFF0000u) > 0.f ? 0xFFFF0000u : 0u;
+            vw[e] &= lo | hi;
+          }
         }
         v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+      }
+      if constexpr (EPI == 0) {
+        if (g.bits_out) {
+          const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+          uint32_t mb = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            mb |= (__uint_as_float(vw[e] << 16) > 0.f ? 1u : 0u) << (2 * e) |
+                  (__uint_as_float(vw[e] & 0xFFFF0000u) > 0.f ? 1u : 0u) << (2 * e + 1);
+          g.bits_out[size_t(m0 + r) * (g.ldo / 8) + (n0 + c8) / 8] = uint8_t(mb);
+        }
       }
       *reinterpret_cast<uint4*>(g.out16 + size_t(m0 + r) * g.ldo + n0 + c8) = v;
     }
@@ -709,6 +763,18 @@ __global__ void k_copy_w(const float* src, float* dst, uint16_t* w16, uint16_t* 
 
 unsigned blocks(size_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+void launch_train_encode(const nedf_mlp_shape& sh, const float* o_l, const float* d_l, const float* depth,
+                         const uint8_t* hit, int B, int K0p, float bound, uint16_t* H, float* mu, float* alpha,
+                         hipStream_t s) {
+  const dim3 grid(blocks(size_t(B) * (K0p / 8)));
+  if (sh.in_kind == NEDF_IN_PLUECKER)
+    hipLaunchKernelGGL(k_train_encode<6>, grid, dim3(256), 0, s, o_l, d_l, depth, hit, B, sh.enc_L, K0p, bound, H,
+                       mu, alpha);
+  else
+    hipLaunchKernelGGL(k_train_encode<3>, grid, dim3(256), 0, s, o_l, d_l, depth, hit, B, sh.enc_L, K0p, bound, H,
+                       mu, alpha);
+}
+
 // ---- classifier-form network (NEDF_IN_POINTS16) ---------------------------------
 // Encoded input of the 16 line points (natural order: point-major, each
 // [x, sin(2^0 pi x), cos(2^0 pi x), ...], 63 values) zero padded to Kpad, and
@@ -882,6 +948,7 @@ size_t train_ws_bytes(const nedf_mlp_shape& sh, int B) {
   off = nedf_tl_align(off + size_t(B) * tl.L[0].Kpad * 2);           // H_in
   off = nedf_tl_align(off + size_t(B) * sh.width * 2 * sh.n_hidden);  // H_0..H_{n-1}
   off = nedf_tl_align(off + size_t(B) * sh.width * 2 * sh.n_hidden);  // G_0..G_{n-1}
+  off = nedf_tl_align(off + size_t(B) * (sh.width / 8) * sh.n_hidden);  // ReLU mask bits of H_0..H_{n-1}
   off = nedf_tl_align(off + size_t(B) * 4 * 2);                       // mu, alpha
   for (int l = 0; l < sh.n_hidden; ++l)                                // weight-gradient partials
     off = nedf_tl_align(off + size_t(S) * sh.width * (tl.L[l].Kpad + 1) * 4);
@@ -927,6 +994,8 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   off = nedf_tl_align(off + size_t(B) * W * 2 * NH);
   uint16_t* Gs = reinterpret_cast<uint16_t*>(ws + off);
   off = nedf_tl_align(off + size_t(B) * W * 2 * NH);
+  uint8_t* bits = ws + off;
+  off = nedf_tl_align(off + size_t(B) * (W / 8) * NH);
   float* mu = reinterpret_cast<float*>(ws + off);
   float* alpha = mu + B;
   off = nedf_tl_align(off + size_t(B) * 4 * 2);
@@ -939,13 +1008,12 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   const int hblocks = B / GT_BM;  // tiles of the last forward layer
   auto Hl = [&](int l) { return Hs + size_t(l) * B * W; };
   auto Gl = [&](int l) { return Gs + size_t(l) * B * W; };  // gradient at layer l's pre-activation
+  auto Ml = [&](int l) { return bits + size_t(l) * B * (W / 8); };  // H_l > 0 as bits
   auto F = [&](size_t o) { return reinterpret_cast<float*>(st + o); };
   auto U = [&](size_t o) { return reinterpret_cast<uint16_t*>(st + o); };
 
   prof_mark("train.step", s, true);
-  hipLaunchKernelGGL(k_train_encode, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l, depth, hit, B,
-                     sh.in_kind, sh.enc_L,
-                     K0p, bound, Hin, mu, alpha);
+  launch_train_encode(sh, o_l, d_l, depth, hit, B, K0p, bound, Hin, mu, alpha, s);
   // forward: H_l = relu(H_{l-1} W_l^T + b_l)
   // the last hidden layer's epilogue forms the head, the loss terms and
   // G_{NH-1} (its activation is not stored)
@@ -962,6 +1030,7 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     g.ldo = W;
     if (l + 1 < NH) {
       g.out16 = Hl(l);
+      g.bits_out = Ml(l);
       gemm<KC, KC, 0>(g, 1, s);
     } else {
       g.out16b = Gl(NH - 1);
@@ -973,7 +1042,8 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
   }
   hipLaunchKernelGGL(k_reduce_head, dim3((517 + 3) / 4), dim3(256), 0, s, hpart, hblocks, F(hd.gW), F(hd.gb), loss);
   // backward through the hidden layers: data gradients
-  // G_{l-1} = (G_l W_l) * (H_{l-1} > 0), every G_l kept
+  // G_{l-1} = (G_l W_l) * (H_{l-1} > 0) (the mask from the forward pass's
+  // bits), every G_l kept
   for (int l = NH - 1; l > 0; --l) {
     const nedf_train_layer& L = tl.L[l];
     GemmArgs d{};
@@ -981,7 +1051,7 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     d.B = U(L.W16T); d.ldb = W;                     // W_l^T [Kpad][W] = [N][K]: k-contiguous
     d.M = B; d.N = W; d.K = W;
     d.k_per_split = W;
-    d.mask = Hl(l - 1); d.ldm = W;
+    d.bits_in = Ml(l - 1); d.ldm = W;       // the ReLU mask of H_{l-1}
     d.out16 = Gl(l - 1); d.ldo = W;
     gemm<KC, KC, 1>(d, 1, s);
   }
@@ -1239,9 +1309,7 @@ hipError_t launch_fp8_calibrate(const nedf_mlp_shape& sh, const float* const* W,
   uint16_t* Hin = reinterpret_cast<uint16_t*>(fw);
   uint16_t* Hs = reinterpret_cast<uint16_t*>(fw + nedf_tl_align(size_t(B) * K0p * 2));
   float* mu = nullptr;
-  hipLaunchKernelGGL(k_train_encode, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l,
-                     static_cast<const float*>(nullptr),
-                     static_cast<const uint8_t*>(nullptr), B, sh.in_kind, sh.enc_L, K0p, 1.0f, Hin, mu, mu);
+  launch_train_encode(sh, o_l, d_l, nullptr, nullptr, B, K0p, 1.0f, Hin, mu, mu, s);
   hipLaunchKernelGGL(k_amax16, dim3(256), dim3(256), 0, s, Hin, size_t(B) * K0p, amax + NEDF_MAX_LAYERS);
   for (int l = 0; l < NH; ++l) {
     GemmArgs g{};
