@@ -19,6 +19,10 @@ library-side HIP events, and the FP64 oracle timed on a bounded pixel sample.
 ``--workload marcher``: the plain-marcher composition scene (16 random NeRF
 objects, 800 x 800, 192 samples per pair), BF16 with an FP32 run beside it.
 
+``--workload train``: the intersection network's Adam step alone (Eq. 6),
+65,536 synthetic rays per step, the regression form (the frame's networks)
+and the classifier form beside it, with the step's HBM roofline.
+
 ``--workload precision``: 64 instances at 3840 x 2160; the depth+ID path
 with the intersection network in FP32, BF16 and FP8 (per-layer scales from
 the library's calibration pass), each with 3-step refinement on the density
@@ -67,7 +71,9 @@ NET_SOURCES = ["include/nedf.h"] + ["paper_2308_04669_amd/csrc/" + f for f in (
 TRAFFIC_RECORDS = {
     "infer.nedf/net": os.path.join(ROOT, "profiles", "nedf_net_bf16_batched_1000inst_1920x1080.md"),
     "fallback.mlp": os.path.join(ROOT, "profiles", "fallback_march_bf16_batched_1000inst_1920x1080.md"),
+    "train.step": os.path.join(ROOT, "profiles", "train_step_bf16_65536rays.md"),
 }
+TRAIN_SOURCES = ["include/nedf.h"] + ["paper_2308_04669_amd/csrc/" + f for f in ("k_train.hip", "train_layout.h")]
 
 
 def sources_hash(files) -> str:
@@ -96,9 +102,10 @@ def recorded_traffic(record: str, files):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--steps", type=int, default=None, help="timed steps (default 5; 200 for --workload train)")
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="frame", choices=["frame", "marcher", "precision", "nedf", "ablation"])
+    p.add_argument("--workload", default="frame", choices=["frame", "marcher", "precision", "nedf", "ablation",
+                                                            "train"])
     p.add_argument("--dtype", default="bf16", choices=["bf16", "f32"])
     # frame workload
     p.add_argument("--width", type=int, default=1920)
@@ -1102,10 +1109,124 @@ def marcher_cpu_baseline(n_pixels: int, n_samples: int, size: int):
                       f"FP64 NumPy, {dt:.1f} s"}
 
 
+# ---------------------------------------------------------------------------
+# training workload (the Adam step alone)
+# ---------------------------------------------------------------------------
+
+def sphere_labels(o, d, r=0.5):
+    """Synthetic labels: depth of a radius-r sphere at the origin along each
+    local ray, and whether the ray hits it."""
+    tp = -np.sum(o * d, axis=1)
+    b2 = np.sum(o * o, axis=1) - tp ** 2
+    hit = b2 < r * r
+    return np.where(hit, tp - np.sqrt(np.maximum(r * r - b2, 0.0)), 0.0), hit
+
+
+def train_step_bytes(B, k0=128, width=256, n_hidden=8, n_params=0, splits=16):
+    """Algorithmic HBM bytes of one regression-form step as the library runs
+    it: every bfloat16 activation and gradient written once and read by each
+    consumer (next layer, data gradient, weight gradient), ReLU masks as bits,
+    split-K weight-gradient partials written and summed, Adam over float32
+    state (read p, m, v, g; write p, m, v and two bfloat16 copies)."""
+    act, x = B * width * 2, B * k0 * 2
+    bits = B * width // 8
+    encode = B * (2 * 12 + 5) + x + B * 8
+    fwd = (x + (n_hidden - 1) * act) + (n_hidden - 1) * (act + bits) + act + B * 8
+    dgrad = (n_hidden - 1) * (act + bits + act)
+    wgrad = n_hidden * act + (n_hidden - 1) * act + x
+    partials = 2 * splits * width * ((k0 + 1) + (n_hidden - 1) * (width + 1)) * 4
+    adam = n_params * (4 * 4 + 3 * 4 + 2 * 2)
+    return encode + fwd + dgrad + wgrad + partials + adam
+
+
+def train_bench(args):
+    """Adam steps of the intersection network (Eq. 6) on one batch of
+    synthetic rays: local rays through the unit ball, sphere labels.  The
+    regression form is the frame's network; the classifier form (16 residual
+    blocks, 193 outputs) runs beside it."""
+    import torch
+    from paper_2308_04669_amd import api
+    import synthetic as syn
+    B = args.train_batch
+    o, d = syn.training_rays(3, 7, B)
+    D, hit = sphere_labels(o.astype(np.float64), d.astype(np.float64))
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ot, dt, Dt, ht = t(o), t(d), t(D.astype(np.float32)), t(hit.astype(np.uint8))
+
+    def run(model, L, kind, steps, warmup):
+        tr = api.Trainer(model.trunk.W, model.trunk.b, enc_L=L, in_kind=kind)
+        for _ in range(warmup):
+            loss = tr.step(ot, dt, Dt, ht, lr=5e-4)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            loss = tr.step(ot, dt, Dt, ht, lr=5e-4)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, loss.cpu().numpy()
+
+    steps = args.steps
+    reg = syn.nedf_model(3, 200)
+    ms, loss = run(reg, 8, "pluecker", steps, max(args.warmup, 20))
+    n_params = sum(w.size + b.size for w, b in zip(reg.trunk.W, reg.trunk.b))
+    nbytes = train_step_bytes(B, n_params=n_params)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    flops = 3.0 * 2.0 * MAC_NEDF * B
+    traffic, traffic_src = recorded_traffic(TRAFFIC_RECORDS["train.step"], TRAIN_SOURCES)
+    cls = syn.classifier_model(3, 500)
+    cls_steps = max(steps // 10, 5)
+    ms_c, loss_c = run(cls, 10, "points16", cls_steps, 3)
+    return {
+        "metric": "training rays/s (Adam steps of the intersection network, Eq. 6)",
+        "value": B / (ms * 1e-3),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(args.warmup, 20),
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded local rays through the unit ball, radius-0.5 sphere labels; He-initialised "
+                "networks)",
+        "config": {"workload": f"regression-form intersection network (gamma8 Pluecker -> 8 x 256 -> 2), "
+                               f"{B} rays per step, BF16 matrix cores, FP32 master weights, Adam",
+                   "batch": B, "loss_last": [float(x) for x in loss]},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                     "traffic": traffic, "traffic_unit": "bytes per step", "traffic_source": traffic_src,
+                     "kernel": "train.step (all kernels of one step)", "algorithmic_bytes_per_step": nbytes,
+                     "mfma_tflops": flops / (ms * 1e-3) / 1e12,
+                     "mfma_frac_of_bf16_peak": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"]},
+        "classifier_form": {"ms_per_step": ms_c, "rays_per_s": B / (ms_c * 1e-3), "steps": cls_steps,
+                            "tflops": 3.0 * 2.0 * MAC_CLS * B / (ms_c * 1e-3) / 1e12,
+                            "loss_last": [float(x) for x in loss_c]},
+    }
+
+
+def train_cpu_baseline(n_rays):
+    """The FP64 oracle's loss and gradients (Eq. 6, regression form) on
+    n_rays of the same synthetic rays and labels, one step (no update)."""
+    import synthetic as syn
+    from oracle import nedf_loss_and_grads
+    o, d = syn.training_rays(3, 7, n_rays)
+    o, d = o.astype(np.float64), d.astype(np.float64)
+    D, hit = sphere_labels(o, d)
+    tp = -np.sum(o * d, axis=1)
+    mu = np.where(hit, tp - D, 0.0)
+    t0 = time.perf_counter()
+    nedf_loss_and_grads(syn.nedf_model(3, 200), o, d, mu, hit.astype(np.float64))
+    dt = time.perf_counter() - t0
+    return {"value": n_rays / dt, "unit": "rays/s", "cores": int(host_threads()), "kind": "oracle",
+            "sample": f"{n_rays} of the same synthetic rays, loss and all gradients in FP64 NumPy (no update), "
+                      f"{dt:.1f} s"}
+
+
 def main():
     args = parse()
     if args.sources_hash:
-        print(sources_hash(NET_SOURCES))
+        print(sources_hash(TRAIN_SOURCES if args.workload == "train" else NET_SOURCES))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
@@ -1115,6 +1236,8 @@ def main():
     torch.cuda.set_device(0)
     if args.train_steps is None:
         args.train_steps = 20000 if args.workload == "nedf" else 6000
+    if args.steps is None:
+        args.steps = 200 if args.workload == "train" else 5
     if args.workload == "frame":
         line, ctx = frame_bench(args)
     elif args.workload == "precision":
@@ -1126,6 +1249,8 @@ def main():
     elif args.workload == "ablation":
         line, ctx = ablation_bench(args), None
         args.no_cpu_baseline = True
+    elif args.workload == "train":
+        line, ctx = train_bench(args), None
     else:
         line, ctx = marcher_bench(args), None
     if args.copy_mib > 0:
@@ -1138,6 +1263,8 @@ def main():
         if args.workload == "frame":
             line["cpu_baseline"] = frame_cpu_baseline(ctx, args.cpu_pixels or 2000, args.fp64_pixels)
             line["quality_fp64"] = line["cpu_baseline"].pop("quality_fp64")
+        elif args.workload == "train":
+            line["cpu_baseline"] = train_cpu_baseline(args.cpu_pixels or args.train_batch)
         else:
             line["cpu_baseline"] = marcher_cpu_baseline(args.cpu_pixels or 6000, args.samples, args.size)
     print(json.dumps(line), flush=True)

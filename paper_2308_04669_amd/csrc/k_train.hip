@@ -113,6 +113,18 @@ __global__ void k_fp8_scales(const uint32_t* amax_w, const uint32_t* amax_a, int
 // N of BN and K of 64 per split.
 enum { KC = 0, RC = 1 };
 constexpr int GT_BM = 128, GT_BK = 64, GT_LD = 72;  // rows per tile, K stage, LDS row stride (bf16)
+// A stage row holds 8 chunks of 16 bytes.  LDS serves 16 lanes of a 16-byte
+// access per cycle over 64 banks; a row is 36 words (9 groups of 4 banks)
+// long, so the fragment reads (16 consecutive rows, one chunk: 9 j mod 16
+// distinct) are conflict-free.  The transposed stores of a row-contiguous
+// (RC) operand write rows 8 apart from 16 lanes (8 j mod 16: two groups, an
+// 8-way conflict), so there chunk c of row r sits at position
+// c ^ ((r / 16) % 8), which spreads them over 16 groups and keeps the reads
+// conflict-free; k-contiguous operands keep the plain layout.
+template <int LAYOUT>
+__device__ __forceinline__ int stage_chunk(int row, int chunk) {
+  return LAYOUT == RC ? chunk ^ ((row >> 4) & 7) : chunk;
+}
 
 struct GemmArgs {
   const uint16_t* A;
@@ -219,7 +231,7 @@ struct Stage<RC, ROWS, NT> {
     transpose8x8(v, w);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      *reinterpret_cast<uint4*>(S + (8 * rb + r) * GT_LD + 8 * kb) = w[r];
+      *reinterpret_cast<uint4*>(S + (8 * rb + r) * GT_LD + 8 * stage_chunk<RC>(8 * rb + r, kb)) = w[r];
       if (colsum8) {
         const uint32_t* q = reinterpret_cast<const uint32_t*>(&w[r]);
         float s = 0.f;
@@ -239,15 +251,23 @@ struct Stage<RC, ROWS, NT> {
 // hit logit) and gradients g = dLoss/d(mu_hat, z) go to LDS; then the
 // gradient G of the tile, the tile's head weight gradients (rows summed in
 // order) and its bias and loss sums.
+// Head weights in LDS: weight k (0..511, row-major [2][256]) at k + k / 64,
+// so that reads 64 weights apart fall on different banks.
+__device__ __forceinline__ int head_w_slot(int k) { return k + (k >> 6); }
+constexpr int HEAD_W_SLOTS = 520;  // 512 + 8 pads (a multiple of 4 floats)
+
 template <int NT, int LO>
 __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* lds, int m0, int tile, int t) {
   static_assert(NT == 512, "four threads per row of a 128-row tile, two per head weight");
   const float* sW = reinterpret_cast<const float*>(lds + GT_BM * LO);
-  float* sg = const_cast<float*>(sW) + 512;  // [2][128]
+  float* sg = const_cast<float*>(sW) + HEAD_W_SLOTS;  // [2][128]
   float* sred = sg + 256;                    // [2][128]
   const float invB = 1.0f / float(g.M);
   {
-    const int r = t >> 2, p = t & 3;
+    // wave w takes rows 16 w .. 16 w + 15; a row's four threads (quarters p
+    // of its 256 features) are 16 lanes apart, so that the 8 lanes of an LDS
+    // cycle read 8 different rows (distinct banks)
+    const int r = 16 * (t >> 6) + (t & 15), p = (t >> 4) & 3;
     float a0 = 0.f, a1 = 0.f;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -257,17 +277,17 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
-        a0 = fmaf(sW[k + 2 * e], h0, a0);
-        a1 = fmaf(sW[256 + k + 2 * e], h0, a1);
-        a0 = fmaf(sW[k + 2 * e + 1], h1, a0);
-        a1 = fmaf(sW[256 + k + 2 * e + 1], h1, a1);
+        a0 = fmaf(sW[head_w_slot(k + 2 * e)], h0, a0);
+        a1 = fmaf(sW[head_w_slot(256 + k + 2 * e)], h0, a1);
+        a0 = fmaf(sW[head_w_slot(k + 2 * e + 1)], h1, a0);
+        a1 = fmaf(sW[head_w_slot(256 + k + 2 * e + 1)], h1, a1);
       }
     }
     // (p0 + p1) + (p2 + p3)
-    a0 += __shfl_xor(a0, 1);
-    a1 += __shfl_xor(a1, 1);
-    a0 += __shfl_xor(a0, 2);
-    a1 += __shfl_xor(a1, 2);
+    a0 += __shfl_xor(a0, 16);
+    a1 += __shfl_xor(a1, 16);
+    a0 += __shfl_xor(a0, 32);
+    a1 += __shfl_xor(a1, 32);
     if (p == 0) {
       a0 += g.head_b[0];
       a1 += g.head_b[1];
@@ -292,8 +312,8 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
     for (int e = 0; e < 4; ++e) {
       const int k = c8 + 2 * e;
       const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
-      const float v0 = h0 > 0.f ? fmaf(g0, sW[k], g1 * sW[256 + k]) : 0.f;
-      const float v1 = h1 > 0.f ? fmaf(g0, sW[k + 1], g1 * sW[256 + k + 1]) : 0.f;
+      const float v0 = h0 > 0.f ? fmaf(g0, sW[head_w_slot(k)], g1 * sW[head_w_slot(256 + k)]) : 0.f;
+      const float v1 = h1 > 0.f ? fmaf(g0, sW[head_w_slot(k + 1)], g1 * sW[head_w_slot(256 + k + 1)]) : 0.f;
       o4[e] = uint32_t(bf16_bits(v0)) | (uint32_t(bf16_bits(v1)) << 16);
     }
     *reinterpret_cast<uint4*>(g.out16b + size_t(m0 + r) * g.ldo + c8) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
@@ -304,7 +324,7 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
   float* P = g.part + size_t(tile) * HEAD_PART;
   {
     float* red = sred + 256;  // [16][512]
-    static_assert(GT_BM * LO * 2 + (1024 + 16 * 512) * 4 <= 2 * (GT_BM + 256) * GT_LD * 2,
+    static_assert(GT_BM * LO * 2 + (HEAD_W_SLOTS + 512 + 16 * 512) * 4 <= 2 * (GT_BM + 256) * GT_LD * 2,
                   "head partials fit the stage buffers");
     const int kq = t & 31, rg = t >> 5;
     float a0[8], a1[8];
@@ -412,13 +432,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
       RA_CUR.load(g.A, g.lda, m0, kl, ta, a_mine);                                                        \
       RB_CUR.load(g.B, g.ldb, n0, kl, tb, b_mine);                                                        \
     }                                                                                                     \
-    const uint16_t* A_ = lds + (BUF) * (SA + SB) + (wm * 64 + (lane & 31)) * GT_LD + 8 * (lane >> 5);      \
-    const uint16_t* B_ = lds + (BUF) * (SA + SB) + SA + (wn * 64 + (lane & 31)) * GT_LD + 8 * (lane >> 5); \
+    const uint16_t* A_ = lds + (BUF) * (SA + SB) + (wm * 64 + (lane & 31)) * GT_LD;                        \
+    const uint16_t* B_ = lds + (BUF) * (SA + SB) + SA + (wn * 64 + (lane & 31)) * GT_LD;                   \
     _Pragma("unroll") for (int ks = 0; ks < GT_BK / 16; ++ks) {                                           \
       bf16x8_t a[2], b[2];                                                                                \
       _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                     \
-        a[i] = *reinterpret_cast<const bf16x8_t*>(A_ + 32 * i * GT_LD + 16 * ks);                         \
-        b[i] = *reinterpret_cast<const bf16x8_t*>(B_ + 32 * i * GT_LD + 16 * ks);                         \
+        /* row 64 w + 32 i + lane % 32: (row / 16) % 8 = (4 w + 2 i + bit 4 of lane) % 8 */               \
+        const int c_ = 2 * ks + (lane >> 5), l4 = (lane >> 4) & 1;                                        \
+        const int ca = AL == RC ? c_ ^ ((4 * wm + 2 * i + l4) & 7) : c_;                                  \
+        const int cb = BL == RC ? c_ ^ ((4 * wn + 2 * i + l4) & 7) : c_;                                  \
+        a[i] = *reinterpret_cast<const bf16x8_t*>(A_ + 32 * i * GT_LD + 8 * ca);                          \
+        b[i] = *reinterpret_cast<const bf16x8_t*>(B_ + 32 * i * GT_LD + 8 * cb);                          \
       }                                                                                                   \
       _Pragma("unroll") for (int i = 0; i < 2; ++i)                                                       \
       _Pragma("unroll") for (int j = 0; j < 2; ++j)                                                       \
@@ -533,12 +557,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
     }
     if constexpr (EPI == 6) {
       float* sW = reinterpret_cast<float*>(lds + GT_BM * LO);
-      for (int i = t; i < 512; i += NT) sW[i] = g.head_w[i];
+      for (int i = t; i < 512; i += NT) sW[head_w_slot(i)] = g.head_w[i];
     }
     __syncthreads();
     constexpr int CH = GT_BM * BN / 8;  // 16-byte pieces of the tile
-    static_assert(EPI != 6 || (GT_BM * LO * 2 + 1024 * 4 <= 2 * (SA + SB) * 2 && BN == 256),
-                  "head epilogue: the tile and 4 KB of head data fit the stage buffers");
+    static_assert(EPI != 6 || BN == 256, "head epilogue: whole rows in one tile");
     if (EPI != 6 || g.out16) {
 #pragma unroll
     for (int i = 0; i < CH / NT; ++i) {
