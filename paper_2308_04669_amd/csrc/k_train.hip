@@ -251,13 +251,18 @@ struct Stage<RC, ROWS, NT> {
 // hit logit) and gradients g = dLoss/d(mu_hat, z) go to LDS; then the
 // gradient G of the tile, the tile's head weight gradients (rows summed in
 // order) and its bias and loss sums.
-// Head weights in LDS: weight k (0..511, row-major [2][256]) at k + k / 64,
-// so that reads 64 weights apart fall on different banks.
-__device__ __forceinline__ int head_w_slot(int k) { return k + (k >> 6); }
-constexpr int HEAD_W_SLOTS = 520;  // 512 + 8 pads (a multiple of 4 floats)
+// Head weights in LDS: weight k (0..511, row-major [2][256]) at
+// k + 4 (k / 64), so that reads 64 weights apart fall on different banks and
+// groups of 4 stay 16-byte aligned.
+__device__ __forceinline__ int head_w_slot(int k) { return k + 4 * (k >> 6); }
+constexpr int HEAD_W_SLOTS = 544;  // 512 + 8 pads of 4
+__device__ __forceinline__ float4 head_w4(const float* sW, int k) {  // weights k .. k + 3, k a multiple of 4
+  return *reinterpret_cast<const float4*>(sW + head_w_slot(k));
+}
 
 template <int NT, int LO>
-__device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* lds, int m0, int tile, int t) {
+__device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* lds, int m0, int tile, int t,
+                                                   float mu_r, float alpha_r) {
   static_assert(NT == 512, "four threads per row of a 128-row tile, two per head weight");
   const float* sW = reinterpret_cast<const float*>(lds + GT_BM * LO);
   float* sg = const_cast<float*>(sW) + HEAD_W_SLOTS;  // [2][128]
@@ -274,13 +279,17 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
       const int k = 64 * p + 8 * m;
       const uint4 q = *reinterpret_cast<const uint4*>(lds + r * LO + k);
       const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+      const float4 u0 = head_w4(sW, k), u1 = head_w4(sW, k + 4);
+      const float4 v0 = head_w4(sW, 256 + k), v1 = head_w4(sW, 256 + k + 4);
+      const float wa[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      const float wb[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
-        a0 = fmaf(sW[head_w_slot(k + 2 * e)], h0, a0);
-        a1 = fmaf(sW[head_w_slot(256 + k + 2 * e)], h0, a1);
-        a0 = fmaf(sW[head_w_slot(k + 2 * e + 1)], h1, a0);
-        a1 = fmaf(sW[head_w_slot(256 + k + 2 * e + 1)], h1, a1);
+        a0 = fmaf(wa[2 * e], h0, a0);
+        a1 = fmaf(wb[2 * e], h0, a1);
+        a0 = fmaf(wa[2 * e + 1], h1, a0);
+        a1 = fmaf(wb[2 * e + 1], h1, a1);
       }
     }
     // (p0 + p1) + (p2 + p3)
@@ -291,7 +300,7 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
     if (p == 0) {
       a0 += g.head_b[0];
       a1 += g.head_b[1];
-      const float al = g.alpha[m0 + r], e = a0 - g.mu[m0 + r];
+      const float al = alpha_r, e = a0 - mu_r;  // labels of row r, loaded before the K loop
       sred[r] = al * e * e;
       sred[128 + r] = fmaxf(a1, 0.f) + log1pf(expf(-fabsf(a1))) - al * a1;
       sg[r] = 2.0f * al * e * invB;
@@ -307,13 +316,16 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
     const uint4 q = *reinterpret_cast<const uint4*>(lds + r * LO + c8);
     const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
     const float g0 = sg[r], g1 = sg[128 + r];
+    const float4 u0 = head_w4(sW, c8), u1 = head_w4(sW, c8 + 4);
+    const float4 z0 = head_w4(sW, 256 + c8), z1 = head_w4(sW, 256 + c8 + 4);
+    const float wa[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    const float wb[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
     uint32_t o4[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int k = c8 + 2 * e;
       const float h0 = __uint_as_float(w4[e] << 16), h1 = __uint_as_float(w4[e] & 0xFFFF0000u);
-      const float v0 = h0 > 0.f ? fmaf(g0, sW[head_w_slot(k)], g1 * sW[head_w_slot(256 + k)]) : 0.f;
-      const float v1 = h1 > 0.f ? fmaf(g0, sW[head_w_slot(k + 1)], g1 * sW[head_w_slot(256 + k + 1)]) : 0.f;
+      const float v0 = h0 > 0.f ? fmaf(g0, wa[2 * e], g1 * wb[2 * e]) : 0.f;
+      const float v1 = h1 > 0.f ? fmaf(g0, wa[2 * e + 1], g1 * wb[2 * e + 1]) : 0.f;
       o4[e] = uint32_t(bf16_bits(v0)) | (uint32_t(bf16_bits(v1)) << 16);
     }
     *reinterpret_cast<uint4*>(g.out16b + size_t(m0 + r) * g.ldo + c8) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
@@ -392,6 +404,31 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
   const int kb = bz * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
   const int n_stages = (ke - kb) / GT_BK;
+  // epilogue inputs loaded before the K loop, which hides their latency:
+  // the masks of this thread's output pieces (EPI 1; loaded in the store
+  // loop they would wait one by one behind the stores, which the compiler
+  // may not move them past), and the head weights plus this thread's row
+  // labels (EPI 6)
+  constexpr int PIECES = GT_BM * BN / 8 / NT;
+  uint32_t pre_bits[EPI == 1 ? PIECES : 1];
+  uint4 pre_mask[EPI == 1 ? PIECES : 1];
+  if constexpr (EPI == 1) {
+#pragma unroll
+    for (int i = 0; i < PIECES; ++i) {
+      const int c = t + NT * i;
+      const int r = c / (BN / 8), c8 = 8 * (c % (BN / 8));
+      if (g.bits_in) pre_bits[i] = g.bits_in[size_t(m0 + r) * (g.ldm / 8) + (n0 + c8) / 8];
+      else pre_mask[i] = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
+    }
+  }
+  float pre_w = 0.f, pre_mu = 0.f, pre_al = 0.f;
+  if constexpr (EPI == 6) {
+    static_assert(NT == 512, "one head weight per thread");
+    pre_w = g.head_w[t];
+    const int r = 16 * (t >> 6) + (t & 15);  // the row whose labels this thread uses in the head epilogue
+    pre_mu = g.mu[m0 + r];
+    pre_al = g.alpha[m0 + r];
+  }
   // row-contiguous operands: A's blocks by threads 0..127, B's by 128..255
   const int rc = t & 127;
   const bool a_mine = AL == KC || t < 128;
@@ -469,10 +506,28 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
   // 64 wn + 32 j + 8 (r / 4) + 4 (lane / 32) + r % 4 of the tile
   static_assert(EPI >= 0 && EPI <= 6, "unknown epilogue");
   if constexpr (EPI >= 3 && EPI <= 5) {
-    // straight from the accumulators: four consecutive columns per store
+    // straight from the accumulators: four consecutive columns per store.
+    // Per accumulator row block, every input of its 8 column groups is
+    // loaded first: a load placed after a store would wait for it (the
+    // compiler may not move a load past a store to memory that can alias).
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int row = m0 + wm * 64 + 32 * i + (lane & 31);
+      float4 in4[2][4];  // bias (EPI 3, 5) or the float32 stream (EPI 4)
+      uint2 in2[2][4];   // the bfloat16 mask (EPI 4) or the residual input (EPI 5)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = n0 + wn * 64 + 32 * j + 8 * q + 4 * (lane >> 5);
+          const size_t o = size_t(row) * g.ldo + col;
+          if constexpr (EPI == 3 || EPI == 5) in4[j][q] = *reinterpret_cast<const float4*>(g.bias + col);
+          if constexpr (EPI == 4) {
+            in4[j][q] = g.resid32 ? *reinterpret_cast<const float4*>(g.resid32 + o) : make_float4(0.f, 0.f, 0.f, 0.f);
+            in2[j][q] = g.out16 ? *reinterpret_cast<const uint2*>(g.mask + size_t(row) * g.ldm + col) : make_uint2(0u, 0u);
+          }
+          if constexpr (EPI == 5) in2[j][q] = *reinterpret_cast<const uint2*>(g.resid16 + o);
+        }
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -483,16 +538,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
 #pragma unroll
           for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * q + e];
           if constexpr (EPI == 3) {
-            const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
+            const float4 bb = in4[j][q];
             *reinterpret_cast<float4*>(g.out32 + o) = make_float4(v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w);
           } else if constexpr (EPI == 4) {
             if (g.resid32) {
-              const float4 r = *reinterpret_cast<const float4*>(g.resid32 + o);
+              const float4 r = in4[j][q];
               v[0] += r.x; v[1] += r.y; v[2] += r.z; v[3] += r.w;
             }
             if (g.out32) *reinterpret_cast<float4*>(g.out32 + o) = make_float4(v[0], v[1], v[2], v[3]);
             if (g.out16) {
-              const uint2 mk = *reinterpret_cast<const uint2*>(g.mask + size_t(row) * g.ldm + col);
+              const uint2 mk = in2[j][q];
               const float m0v = __uint_as_float(mk.x << 16), m1v = __uint_as_float(mk.x & 0xFFFF0000u);
               const float m2v = __uint_as_float(mk.y << 16), m3v = __uint_as_float(mk.y & 0xFFFF0000u);
               *reinterpret_cast<uint2*>(g.out16 + o) =
@@ -501,10 +556,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
             }
           } else {  // EPI 5
             static_assert(EPI == 5, "residual epilogue");
-            const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
+            const float4 bb = in4[j][q];
             const float r0 = fmaxf(v[0] + bb.x, 0.f), r1 = fmaxf(v[1] + bb.y, 0.f);
             const float r2 = fmaxf(v[2] + bb.z, 0.f), r3 = fmaxf(v[3] + bb.w, 0.f);
-            const uint2 h = *reinterpret_cast<const uint2*>(g.resid16 + o);
+            const uint2 h = in2[j][q];
             const float h0 = __uint_as_float(h.x << 16), h1 = __uint_as_float(h.x & 0xFFFF0000u);
             const float h2 = __uint_as_float(h.y << 16), h3 = __uint_as_float(h.y & 0xFFFF0000u);
             *reinterpret_cast<uint2*>(g.out16 + o) =
@@ -557,7 +612,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
     }
     if constexpr (EPI == 6) {
       float* sW = reinterpret_cast<float*>(lds + GT_BM * LO);
-      for (int i = t; i < 512; i += NT) sW[head_w_slot(i)] = g.head_w[i];
+      sW[head_w_slot(t)] = pre_w;
     }
     __syncthreads();
     constexpr int CH = GT_BM * BN / 8;  // 16-byte pieces of the tile
@@ -571,12 +626,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
       if constexpr (EPI == 1) {
         uint32_t vw[4] = {v.x, v.y, v.z, v.w};
         if (g.bits_in) {
-          const uint32_t mb = g.bits_in[size_t(m0 + r) * (g.ldm / 8) + (n0 + c8) / 8];
+          const uint32_t mb = pre_bits[i];
 #pragma unroll
           for (int e = 0; e < 4; ++e)
             vw[e] &= ((mb >> (2 * e)) & 1u ? 0x0000FFFFu : 0u) | ((mb >> (2 * e + 1)) & 1u ? 0xFFFF0000u : 0u);
         } else {
-          const uint4 mk = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
+          const uint4 mk = pre_mask[i];
           const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -601,7 +656,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
       *reinterpret_cast<uint4*>(g.out16 + size_t(m0 + r) * g.ldo + n0 + c8) = v;
     }
     }
-    if constexpr (EPI == 6) head_loss_epilogue<NT, LO>(g, lds, m0, bx, t);
+    if constexpr (EPI == 6) head_loss_epilogue<NT, LO>(g, lds, m0, bx, t, pre_mu, pre_al);
   }
   if constexpr (COLSUM) {
     // column sums of A over this split's k, one set per m tile (written by
@@ -933,15 +988,6 @@ __global__ void k_cls_loss_reduce(const float* part, int n_blocks, int B, float*
 
 
 }  // namespace
-
-// Split-K count of the weight-gradient GEMMs (batch dimension).
-int wgrad_splits(int B) {
-  int S = B / 1024;
-  if (S < 1) S = 1;
-  if (S > 64) S = 64;
-  while (S > 1 && (B % (S * GT_BK) != 0)) --S;
-  return S;
-}
 
 // Split count of a batched weight-gradient launch over `tiles` 128 x 128
 // output tiles: a power of two up to 64 giving at most 640 workgroups (two
