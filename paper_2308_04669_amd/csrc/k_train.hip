@@ -858,9 +858,10 @@ void launch_train_encode(const nedf_mlp_shape& sh, const float* o_l, const float
 // [x, sin(2^0 pi x), cos(2^0 pi x), ...], 63 values) zero padded to Kpad, and
 // labels mu* = (t_perp - D) / l, alpha = hit.  The points come from the
 // compensated frame of the inference kernel, applied to the local ray.
+template <int L>
 __global__ void k_train_encode_points(const float* o_l, const float* d_l, const float* depth, const uint8_t* hit,
-                                      int B, int L, int Kpad, float bound, uint16_t* H, float* mu,
-                                      float* alpha) {
+                                      int B, int Kpad, float bound, uint16_t* H, float* mu, float* alpha) {
+  constexpr int per = 3 * (1 + 2 * L);  // features per point
   const int groups = Kpad / 8;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = tid / groups, grp = tid % groups;
@@ -874,7 +875,23 @@ __global__ void k_train_encode_points(const float* o_l, const float* d_l, const 
   f2 q[3], dv[3];
   float tperp, ol[3];
   local_points_frame(id, o, d, zero, bound, q, dv, tperp, ol);
-  const int per = 3 * (1 + 2 * L);
+  // point p of the line (compensated: value and low part), for the at most
+  // two points this thread's 8 features belong to
+  auto point = [&](int p, float (&x)[3], float (&xlo)[3]) {
+    const float cp = float(2 * p + 1) * 0.0625f - 1.0f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma clang fp contract(off)
+      const f2 pp = two_prod(cp, dv[r].hi);
+      const f2 sm = two_sum(q[r].hi, pp.hi);
+      x[r] = sm.hi;
+      xlo[r] = sm.lo + ((pp.lo + q[r].lo) + cp * dv[r].lo);
+    }
+  };
+  const int pa = (8 * grp) / per;
+  float xa[3], xla[3], xb[3], xlb[3];
+  point(pa, xa, xla);
+  point(pa + 1, xb, xlb);
   uint32_t packed[4];
 #pragma unroll
   for (int e = 0; e < 8; e += 2) {
@@ -884,22 +901,21 @@ __global__ void k_train_encode_points(const float* o_l, const float* d_l, const 
       const int f = 8 * grp + e + u;
       float v = 0.0f;
       if (f < NEDF_CLS_POINTS * per) {
-        const int p = f / per, e2 = f % per;
-        const float cp = float(2 * p + 1) * 0.0625f - 1.0f;
+        const bool second = f >= (pa + 1) * per;
+        const int e2 = f - (second ? pa + 1 : pa) * per;
         float x[3], xlo[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-#pragma clang fp contract(off)
-          const f2 pp = two_prod(cp, dv[r].hi);
-          const f2 sm = two_sum(q[r].hi, pp.hi);
-          x[r] = sm.hi;
-          xlo[r] = sm.lo + ((pp.lo + q[r].lo) + cp * dv[r].lo);
+          x[r] = second ? xb[r] : xa[r];
+          xlo[r] = second ? xlb[r] : xla[r];
         }
         if (e2 < 3) {
-          v = x[e2];
+          v = e2 == 0 ? x[0] : e2 == 1 ? x[1] : x[2];
         } else {
           const int qq = e2 - 3, level = qq / 6, w = qq % 6, c = w % 3;
-          v = sinpi_hw(float(1 << level) * x[c], float(1 << level) * xlo[c], w >= 3 ? 1 : 0);
+          const float xc = c == 0 ? x[0] : c == 1 ? x[1] : x[2];
+          const float xlc = c == 0 ? xlo[0] : c == 1 ? xlo[1] : xlo[2];
+          v = sinpi_hw(float(1 << level) * xc, float(1 << level) * xlc, w >= 3 ? 1 : 0);
         }
       }
       v2[u] = v;
@@ -1236,8 +1252,9 @@ hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const fl
   auto Gi = [&](int i) { return w.G + size_t(i) * B * W; };  // gradient at layer i's pre-activation
   const int tail = tl.n_layers - 1;
   prof_mark("train.step", s, true);
-  hipLaunchKernelGGL(k_train_encode_points, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l, depth,
-                     hit, B, sh.enc_L, K0p, bound, w.X, w.mu, w.alpha);
+  // gamma_10 (the only classifier encoding training accepts)
+  hipLaunchKernelGGL(k_train_encode_points<10>, dim3(blocks(size_t(B) * (K0p / 8))), dim3(256), 0, s, o_l, d_l, depth,
+                     hit, B, K0p, bound, w.X, w.mu, w.alpha);
   // forward
   {
     GemmArgs g{};
