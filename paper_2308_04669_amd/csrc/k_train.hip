@@ -389,18 +389,23 @@ __device__ __forceinline__ void head_loss_epilogue(const GemmArgs& g, uint16_t* 
   }
 }
 
-// One output tile (bx, by) of split bz.
-template <int AL, int BL, int EPI, bool COLSUM, int BN>
+// One output tile (bx, by) of split bz, BM rows (128, or 256 for
+// k-contiguous operands: half the re-reads of the B operand from L2 and
+// six fragment reads per eight matrix ops instead of four per four).
+template <int AL, int BL, int EPI, bool COLSUM, int BN, int BM>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const int by, const int bz) {
-  constexpr int NT = BN * 2;            // threads: (128 / 64) x (BN / 64) waves
+  constexpr int NT = BN * 2;            // threads: 2 x (BN / 64) waves
   constexpr int WN = BN / 64;           // waves along N
-  constexpr int SA = GT_BM * GT_LD, SB = BN * GT_LD;
+  constexpr int MI = BM / 64;           // 32-row blocks per wave (a wave takes BM / 2 rows)
+  constexpr int SA = BM * GT_LD, SB = BN * GT_LD;
   static_assert(AL == KC || BN == 128, "row-contiguous operands need BN = 128");
   static_assert(BL == KC || BN == 128, "row-contiguous operands need BN = 128");
+  static_assert(BM == GT_BM || (BM == 256 && AL == KC && BL == KC && !COLSUM && (EPI == 0 || EPI == 1)),
+                "256-row tiles: k-contiguous operands, bias/ReLU or bit-mask epilogues");
   __shared__ __attribute__((aligned(16))) uint16_t lds[2 * (SA + SB)];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = bx * GT_BM, n0 = by * BN;
+  const int m0 = bx * BM, n0 = by * BN;
   const int kb = bz * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
   const int n_stages = (ke - kb) / GT_BK;
@@ -409,16 +414,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
   // loop they would wait one by one behind the stores, which the compiler
   // may not move them past), and the head weights plus this thread's row
   // labels (EPI 6)
-  constexpr int PIECES = GT_BM * BN / 8 / NT;
+  constexpr int PIECES = BM * BN / 8 / NT;
   uint32_t pre_bits[EPI == 1 ? PIECES : 1];
-  uint4 pre_mask[EPI == 1 ? PIECES : 1];
+  uint4 pre_mask[EPI == 1 && BM == GT_BM ? PIECES : 1];  // 256-row tiles take bit masks only
   if constexpr (EPI == 1) {
 #pragma unroll
     for (int i = 0; i < PIECES; ++i) {
       const int c = t + NT * i;
       const int r = c / (BN / 8), c8 = 8 * (c % (BN / 8));
       if (g.bits_in) pre_bits[i] = g.bits_in[size_t(m0 + r) * (g.ldm / 8) + (n0 + c8) / 8];
-      else pre_mask[i] = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
+      else if constexpr (BM == GT_BM) pre_mask[i] = *reinterpret_cast<const uint4*>(g.mask + size_t(m0 + r) * g.ldm + n0 + c8);
     }
   }
   float pre_w = 0.f, pre_mu = 0.f, pre_al = 0.f;
@@ -435,12 +440,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
   const bool b_mine = BL == KC || (AL == RC ? t >= 128 : t < 128);
   const int ta = AL == KC ? t : rc, tb = BL == KC ? t : rc;
   // two register sets, named (not indexed) so that they stay in registers
-  Stage<AL, GT_BM, NT> ra0, ra1;
+  Stage<AL, BM, NT> ra0, ra1;
   Stage<BL, BN, NT> rb0, rb1;
   float cs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  f32x16_t acc[2][2];
+  f32x16_t acc[MI][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x16_t{};
   if (n_stages <= 0) return;  // never launched so (K a multiple of 64 per split)
@@ -469,19 +474,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
       RA_CUR.load(g.A, g.lda, m0, kl, ta, a_mine);                                                        \
       RB_CUR.load(g.B, g.ldb, n0, kl, tb, b_mine);                                                        \
     }                                                                                                     \
-    const uint16_t* A_ = lds + (BUF) * (SA + SB) + (wm * 64 + (lane & 31)) * GT_LD;                        \
+    const uint16_t* A_ = lds + (BUF) * (SA + SB) + (wm * (BM / 2) + (lane & 31)) * GT_LD;                  \
     const uint16_t* B_ = lds + (BUF) * (SA + SB) + SA + (wn * 64 + (lane & 31)) * GT_LD;                   \
     _Pragma("unroll") for (int ks = 0; ks < GT_BK / 16; ++ks) {                                           \
-      bf16x8_t a[2], b[2];                                                                                \
-      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                     \
-        /* row 64 w + 32 i + lane % 32: (row / 16) % 8 = (4 w + 2 i + bit 4 of lane) % 8 */               \
-        const int c_ = 2 * ks + (lane >> 5), l4 = (lane >> 4) & 1;                                        \
+      bf16x8_t a[MI], b[2];                                                                               \
+      /* row 64 w + 32 i + lane % 32 (RC: 128-row tiles): (row / 16) % 8 = (4 w + 2 i + bit 4 of lane) % 8 */ \
+      const int c_ = 2 * ks + (lane >> 5), l4 = (lane >> 4) & 1;                                          \
+      _Pragma("unroll") for (int i = 0; i < MI; ++i) {                                                    \
         const int ca = AL == RC ? c_ ^ ((4 * wm + 2 * i + l4) & 7) : c_;                                  \
-        const int cb = BL == RC ? c_ ^ ((4 * wn + 2 * i + l4) & 7) : c_;                                  \
         a[i] = *reinterpret_cast<const bf16x8_t*>(A_ + 32 * i * GT_LD + 8 * ca);                          \
+      }                                                                                                   \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                     \
+        const int cb = BL == RC ? c_ ^ ((4 * wn + 2 * i + l4) & 7) : c_;                                  \
         b[i] = *reinterpret_cast<const bf16x8_t*>(B_ + 32 * i * GT_LD + 8 * cb);                          \
       }                                                                                                   \
-      _Pragma("unroll") for (int i = 0; i < 2; ++i)                                                       \
+      _Pragma("unroll") for (int i = 0; i < MI; ++i)                                                      \
       _Pragma("unroll") for (int j = 0; j < 2; ++j)                                                       \
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j], a[i], acc[i][j], 0, 0, 0);              \
     }                                                                                                     \
@@ -511,8 +518,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
     // loaded first: a load placed after a store would wait for it (the
     // compiler may not move a load past a store to memory that can alias).
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int row = m0 + wm * 64 + 32 * i + (lane & 31);
+    for (int i = 0; i < MI; ++i) {
+      const int row = m0 + wm * (BM / 2) + 32 * i + (lane & 31);
       float4 in4[2][4];  // bias (EPI 3, 5) or the float32 stream (EPI 4)
       uint2 in2[2][4];   // the bfloat16 mask (EPI 4) or the residual input (EPI 5)
 #pragma unroll
@@ -573,8 +580,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
     }
   } else if constexpr (EPI == 2) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int row = m0 + wm * 64 + 32 * i + (lane & 31);
+    for (int i = 0; i < MI; ++i) {
+      const int row = m0 + wm * (BM / 2) + 32 * i + (lane & 31);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -588,10 +595,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
     // EPI 0, 1, 6: bfloat16 tile in LDS ([128][BN + 8]), then 16-byte row pieces
     static_assert(EPI == 0 || EPI == 1 || EPI == 6, "tile epilogues");
     constexpr int LO = BN + 8;
-    static_assert(GT_BM * LO <= 2 * (SA + SB), "output tile must fit the stage buffers");
+    static_assert(BM * LO <= 2 * (SA + SB), "output tile must fit the stage buffers");
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = wm * 64 + 32 * i + (lane & 31);
+    for (int i = 0; i < MI; ++i) {
+      const int r = wm * (BM / 2) + 32 * i + (lane & 31);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -611,11 +618,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
         }
     }
     if constexpr (EPI == 6) {
-      float* sW = reinterpret_cast<float*>(lds + GT_BM * LO);
+      float* sW = reinterpret_cast<float*>(lds + BM * LO);
       sW[head_w_slot(t)] = pre_w;
     }
     __syncthreads();
-    constexpr int CH = GT_BM * BN / 8;  // 16-byte pieces of the tile
+    constexpr int CH = BM * BN / 8;  // 16-byte pieces of the tile
     static_assert(EPI != 6 || BN == 256, "head epilogue: whole rows in one tile");
     if (EPI != 6 || g.out16) {
 #pragma unroll
@@ -630,7 +637,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
 #pragma unroll
           for (int e = 0; e < 4; ++e)
             vw[e] &= ((mb >> (2 * e)) & 1u ? 0x0000FFFFu : 0u) | ((mb >> (2 * e + 1)) & 1u ? 0xFFFF0000u : 0u);
-        } else {
+        } else if constexpr (BM == GT_BM) {
           const uint4 mk = pre_mask[i];
           const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
 #pragma unroll
@@ -677,9 +684,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const
   }
 }
 
-template <int AL, int BL, int EPI, bool COLSUM, int BN>
+template <int AL, int BL, int EPI, bool COLSUM, int BN, int BM>
 __global__ __launch_bounds__(BN * 2) void k_gemm(GemmArgs g) {
-  gemm_tile<AL, BL, EPI, COLSUM, BN>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+  gemm_tile<AL, BL, EPI, COLSUM, BN, BM>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Weight gradients of several layers in one launch: dW_p = G_p^T X_p over S
@@ -723,13 +730,13 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(WgradBatch wb) {
   g.k_per_split = wb.B / wb.S;
   g.part = p.part;
   g.colsum = p.colsum;
-  gemm_tile<RC, RC, 2, true, 128>(g, bx, by, split);
+  gemm_tile<RC, RC, 2, true, 128, GT_BM>(g, bx, by, split);
 }
 
-template <int AL, int BL, int EPI, bool COLSUM = false, int BN = 256>
+template <int AL, int BL, int EPI, bool COLSUM = false, int BN = 256, int BM = GT_BM>
 void gemm(const GemmArgs& g, int splits, hipStream_t s) {
-  dim3 grid(g.M / GT_BM, g.N / BN, splits);
-  hipLaunchKernelGGL((k_gemm<AL, BL, EPI, COLSUM, BN>), grid, dim3(BN * 2), 0, s, g);
+  dim3 grid(g.M / BM, g.N / BN, splits);
+  hipLaunchKernelGGL((k_gemm<AL, BL, EPI, COLSUM, BN, BM>), grid, dim3(BN * 2), 0, s, g);
 }
 
 // Weight and bias gradients of every hidden layer from the split partials,
@@ -1116,7 +1123,7 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     if (l + 1 < NH) {
       g.out16 = Hl(l);
       g.bits_out = Ml(l);
-      gemm<KC, KC, 0>(g, 1, s);
+      gemm<KC, KC, 0, false, 256, 256>(g, 1, s);  // B is a multiple of 256
     } else {
       g.out16b = Gl(NH - 1);
       g.head_w = F(hd.W); g.head_b = F(hd.b);
@@ -1136,9 +1143,9 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     d.B = U(L.W16T); d.ldb = W;                     // W_l^T [Kpad][W] = [N][K]: k-contiguous
     d.M = B; d.N = W; d.K = W;
     d.k_per_split = W;
-    d.bits_in = Ml(l - 1); d.ldm = W;       // the ReLU mask of H_{l-1}
+    d.bits_in = Ml(l - 1); d.ldm = W;       // the ReLU mask of H_{l-1} (256-row tiles take bits only)
     d.out16 = Gl(l - 1); d.ldo = W;
-    gemm<KC, KC, 1>(d, 1, s);
+    gemm<KC, KC, 1, false, 256, 256>(d, 1, s);
   }
   // weight-gradient partials dW_l = G_l^T H_{l-1} of every layer in one
   // launch, then their sums over the splits in order
