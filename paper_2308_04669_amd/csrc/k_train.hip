@@ -741,6 +741,11 @@ void gemm(const GemmArgs& g, int splits, hipStream_t s) {
 
 // Weight and bias gradients of every hidden layer from the split partials,
 // summed over the splits in order (deterministic): gW[m][k] for k < K, gb[m].
+// With head partials (regression form), the slice blockIdx.y = n_layers
+// sums them too: one wave per output (512 head weight gradients, 2 bias
+// gradients, 3 loss terms), lane l adding tiles l, l + 64, ... in order, then
+// a fixed butterfly.  The first thread also counts the update in the Adam
+// step counter, which the Adam launch after this one reads.
 struct ReduceLayer {
   const float* part;   // [S][M][N]
   const float* csum;   // [S][M]
@@ -751,8 +756,26 @@ struct ReduceLayer {
 struct ReduceArgs {
   ReduceLayer L[NEDF_TRAIN_MAX_LAYERS];
   int n_layers, S;
+  int64_t* step;
+  const float* hpart;  // [h_blocks][HEAD_PART] or null
+  int h_blocks;
+  float *gWh, *gbh, *loss;
 };
 __global__ void k_reduce_grads(ReduceArgs r) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *r.step += 1;
+  if (int(blockIdx.y) == r.n_layers) {
+    const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= 517) return;
+    float s = 0.f;
+    for (int q = lane; q < r.h_blocks; q += 64) s += r.hpart[size_t(q) * HEAD_PART + j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane != 0) return;
+    if (j < 512) r.gWh[j] = s;
+    else if (j < 514) r.gbh[j - 512] = s;
+    else r.loss[j - 514] = s;
+    return;
+  }
   const ReduceLayer& L = r.L[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int MN = L.M * L.N;
@@ -771,28 +794,13 @@ __global__ void k_reduce_grads(ReduceArgs r) {
   }
 }
 
-// ---- head and loss ------------------------------------------------------------
-// Head gradients and loss from the per-block partials: one wave per output,
-// lane l adding blocks l, l + 64, ... in order, then a fixed butterfly.
-__global__ void k_reduce_head(const float* part, int n_blocks, float* gWh, float* gbh, float* loss) {
-  const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= 517) return;
-  float s = 0.f;
-  for (int q = lane; q < n_blocks; q += 64) s += part[size_t(q) * HEAD_PART + j];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane != 0) return;
-  if (j < 512) gWh[j] = s;
-  else if (j < 514) gbh[j - 512] = s;
-  else loss[j - 514] = s;
-}
-
 __global__ void k_zero_f32(float* p, size_t n) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
 }
 
-// Adam (Kingma & Ba 2015) with bias correction, step t = *step + 1, over every
+// Adam (Kingma & Ba 2015) with bias correction, step t = *step (counted by
+// the gradient reduction just before), over every
 // parameter array of the network in one launch (segments listed in AdamArgs;
 // a block never spans two segments); the bfloat16 copy of weight matrices is
 // refreshed in the same pass.
@@ -816,7 +824,7 @@ __global__ void k_adam(AdamArgs a) {
   const AdamSeg& S = a.seg[si];
   const int i = (int(blockIdx.x) - S.block0) * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
-  const float t = float(*a.step + 1);
+  const float t = float(*a.step);
   const float bc1 = 1.0f - powf(a.b1, t), bc2 = 1.0f - powf(a.b2, t);
   const float gi = S.g[i];
   const float mi = a.b1 * S.m[i] + (1.0f - a.b1) * gi;
@@ -827,10 +835,6 @@ __global__ void k_adam(AdamArgs a) {
   S.p[i] = pi;
   if (S.w16) S.w16[size_t(i / S.K) * S.Kpad + (i % S.K)] = bf16_bits(pi);
   if (S.w16t) S.w16t[size_t(i % S.K) * S.N + (i / S.K)] = bf16_bits(pi);
-}
-
-__global__ void k_step_inc(int64_t* step) {
-  if (threadIdx.x == 0) *step += 1;
 }
 
 // Initial state: master weights from float32 arrays, moments and gradients
@@ -1132,7 +1136,6 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
       gemm<KC, KC, 6>(g, 1, s);
     }
   }
-  hipLaunchKernelGGL(k_reduce_head, dim3((517 + 3) / 4), dim3(256), 0, s, hpart, hblocks, F(hd.gW), F(hd.gb), loss);
   // backward through the hidden layers: data gradients
   // G_{l-1} = (G_l W_l) * (H_{l-1} > 0) (the mask from the forward pass's
   // bits), every G_l kept
@@ -1155,7 +1158,10 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     ReduceArgs ra{};
     ra.n_layers = NH;
     ra.S = S;
-    int maxmn = 0, ny = 1;
+    ra.step = reinterpret_cast<int64_t*>(st);
+    ra.hpart = hpart; ra.h_blocks = hblocks;
+    ra.gWh = F(hd.gW); ra.gbh = F(hd.gb); ra.loss = loss;
+    int maxmn = 517, ny = 1;
     for (int l = 0; l < NH; ++l) {
       const nedf_train_layer& L = tl.L[l];
       wb.p[l] = WgradProb{Gl(l), l == 0 ? Hin : Hl(l - 1), wpart[l], wpart[l] + size_t(S) * W * L.Kpad,
@@ -1165,7 +1171,7 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
       ny = std::max(ny, L.Kpad / 128);
     }
     hipLaunchKernelGGL(k_wgrad, dim3(W / GT_BM, ny, NH * S), dim3(256), 0, s, wb);
-    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(maxmn), NH), dim3(256), 0, s, ra);
+    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(maxmn), NH + 1), dim3(256), 0, s, ra);
   }
   // Adam on every parameter array, one launch
   AdamArgs aa{};
@@ -1181,7 +1187,6 @@ hipError_t launch_train_step(const nedf_mlp_shape& sh, uint8_t* st, const float*
     nb += int(blocks(size_t(L.N)));
   }
   hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, s, aa);
-  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, reinterpret_cast<int64_t*>(st));
   prof_mark("train.step", s, false);
   return hipGetLastError();
 }
@@ -1344,6 +1349,7 @@ hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const fl
     ReduceArgs ra{};
     ra.n_layers = tl.n_layers;
     ra.S = S;
+    ra.step = reinterpret_cast<int64_t*>(st);
     int maxmn = 0, ny = 1;
     for (int i = 0; i < tl.n_layers; ++i) {
       const nedf_train_layer& L = tl.L[i];
@@ -1378,7 +1384,6 @@ hipError_t launch_train_step_cls(const nedf_mlp_shape& sh, uint8_t* st, const fl
     nb += int(blocks(size_t(L.N)));
   }
   flush();
-  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, reinterpret_cast<int64_t*>(st));
   prof_mark("train.step", s, false);
   return hipGetLastError();
 }
