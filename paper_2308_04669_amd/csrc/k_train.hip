@@ -99,8 +99,9 @@ __global__ void k_fp8_scales(const uint32_t* amax_w, const uint32_t* amax_a, int
 
 // ---- GEMM ---------------------------------------------------------------------
 // C[M][N] = sum_k A(m, k) B(n, k) on 32x32x16 bf16 matrix cores with float32
-// accumulation.  A workgroup computes a 128 x BN tile (BN = 128 or 256) with
-// one wave per 64 x 64 block (2 x 2 blocks of 32 x 32); K runs in stages of
+// accumulation.  A workgroup computes a BM x BN tile (BM = 128 or 256, BN =
+// 128 or 256) with one wave per (BM / 2) x 64 block (BM / 64 x 2 blocks of
+// 32 x 32); K runs in stages of
 // 64, staged in LDS as [row][k] (k contiguous; rows padded to 72 elements, so
 // that the 16-byte fragment reads of a wave's 16-lane groups fall on distinct
 // banks) and double-buffered.  Global loads run two stages ahead of the
@@ -109,8 +110,8 @@ __global__ void k_fp8_scales(const uint32_t* amax_w, const uint32_t* amax_a, int
 // X[row][k], copied 16 bytes at a time) or row-contiguous (RC: X[k][row],
 // loaded as 8 x 8 blocks and transposed in registers by byte permutes on the
 // way to LDS; only with BN = 128).  bfloat16 outputs go through LDS after the
-// last stage and leave as whole 16-byte row pieces.  M is a multiple of 128,
-// N of BN and K of 64 per split.
+// last stage and leave as whole 16-byte row pieces.  M is a multiple of BM,
+// N of BN and K of 128 per split.
 enum { KC = 0, RC = 1 };
 constexpr int GT_BM = 128, GT_BK = 64, GT_LD = 72;  // rows per tile, K stage, LDS row stride (bf16)
 // A stage row holds 8 chunks of 16 bytes.  LDS serves 16 lanes of a 16-byte
